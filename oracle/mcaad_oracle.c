@@ -26,7 +26,8 @@
  * They are drawn here from Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11),
  * counter (floor(q/4), path, instance, 0), key (seed lo, seed hi), where q is
  * the index of the normal within the path; words map to uniforms
- * u = ((w >> 8) + 0.5) * 2^-24 and pairs of uniforms to normals by
+ * u = ((w >> 9) + 0.5) * 2^-23 (exactly representable in FP32 and FP64,
+ * so both precisions see the same uniforms) and pairs of uniforms to normals by
  * Box-Muller: rho = sqrt(-2 ln u0), z0 = rho cos(2 pi u1), z1 = rho sin(2 pi u1).
  *
  * Models (all step the log-price x = ln(S/S0), "standard Euler" read as
@@ -97,7 +98,7 @@ void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t ou
 
 static double orc_uniform(uint32_t w)
 {
-    return ((double)(w >> 8) + 0.5) * (1.0 / 16777216.0);
+    return ((double)(w >> 9) + 0.5) * (1.0 / 8388608.0);
 }
 
 /* Four normals from one Philox call: pairs (u0,u1) and (u2,u3). */
