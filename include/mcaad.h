@@ -1,0 +1,188 @@
+/*
+ * mcaad.h - C ABI of the MI355X (gfx950) library for the two-pass Monte Carlo
+ * adjoint gradient of the calibration functional
+ *
+ *     G(theta) = 1/2 sum_{i=1..m} (E y_i(theta) - C_i)^2          (paper, eq. 241118A)
+ *
+ * where y_i are the m payoffs that the forward algorithm F : R^{M+N} -> R^m
+ * produces for one path from M parameters and N random variables (paper,
+ * problem statement after eq. 241118A), and E is the Monte Carlo mean over P
+ * paths (paper, eq. 1211A).
+ *
+ * Conventions for every entry point:
+ *   - "d_" arguments are device pointers (HIP global memory on the current
+ *     device), "h_"/plain struct members are host pointers.
+ *   - All device arrays are contiguous, FP64, owned by the caller; the
+ *     library never frees or retains them beyond the call.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream). Work
+ *     is enqueued on it and the call returns without synchronising, except
+ *     cal_status and cal_timing_read, which synchronise.
+ *   - The context owns all workspace (block partial sums, checkpoints,
+ *     sorted instrument tables). It is allocated once in cal_create; the
+ *     calibrate_* calls allocate nothing. One context serves one stream at a
+ *     time: calls on one context that overlap on different streams race.
+ *   - Return value 0 = success, negative = error (CAL_E*). On error nothing is
+ *     enqueued and cal_last_error(ctx) describes it. Nothing throws or aborts
+ *     across this boundary.
+ *   - Floating point: path state and per-path arithmetic in FP32
+ *     (CAL_FP32) or FP64 (CAL_FP64); sums over paths, the residual
+ *     E y - C, G and the gradient are always FP64 and are reduced in a fixed
+ *     order, so results are bitwise reproducible run to run.
+ */
+#ifndef MCAAD_H
+#define MCAAD_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* model */
+#define CAL_BS 0      /* Black-Scholes GBM, theta = (sigma), log-Euler */
+#define CAL_HESTON 1  /* Heston, theta = (kappa, theta_bar, xi, rho, v0), full-truncation log-Euler */
+#define CAL_LV 2      /* local volatility, theta = bilinear node values (reserved) */
+
+/* precision of the path state */
+#define CAL_FP32 0
+#define CAL_FP64 1
+
+/* where the reverse sweep gets its checkpoints */
+#define CAL_CKPT_AUTO 0    /* CAL_CKPT_STORE when the buffer fits, else RERUN */
+#define CAL_CKPT_RERUN 1   /* pass 2 re-runs the forward sweep and keeps its own checkpoints */
+#define CAL_CKPT_STORE 2   /* the pass-1 sweep of calibrate_gradient stores them in HBM */
+
+/* return codes */
+#define CAL_OK 0
+#define CAL_EINVAL (-1)        /* bad problem or argument */
+#define CAL_ENOMEM (-2)        /* device allocation failed */
+#define CAL_EHIP (-3)          /* a HIP runtime call failed */
+#define CAL_EUNSUPPORTED (-4)  /* valid problem the device path does not implement */
+
+/* device status bits reported by cal_status */
+#define CAL_FLAG_THETA 1       /* theta outside the model's domain */
+#define CAL_FLAG_NONFINITE 2   /* a non-finite E y, G or gradient was produced */
+
+typedef struct cal_ctx cal_ctx;
+
+/*
+ * Problem description (all pointers are host pointers, read during
+ * cal_validate / cal_create only).
+ *   model, precision  : see above
+ *   n_params (M)      : 1 (BS), 5 (Heston)
+ *   n_instr  (m)      : number of calls, 1..2048
+ *   n_steps  (N)      : Euler steps over [0, t_max], 1..65536
+ *   n_paths  (P)      : 1..2^32; path p uses Philox counter word 1 = p
+ *   seed              : Philox key (lo, hi words)
+ *   inst              : Philox counter word 2 (instance / draw index)
+ *   ckpt_every (k)    : 0 = auto, else 8, 16 or 32 steps between checkpoints
+ *   ckpt_mode         : CAL_CKPT_*
+ *   s0, rate, t_max   : spot, risk-free rate (drift and discounting), horizon
+ *   sqrt_eps          : Heston only; 0 = plain full truncation (s = sqrt(v+));
+ *                       > 0 replaces sqrt below eps by v(3 - v/eps)/(2 sqrt(eps))
+ *   instr_step[m]     : maturity step of call i, 1..N (maturity = step * t_max / N)
+ *   instr_strike[m]   : strike of call i (>= 0)
+ * Random numbers: normal q of path p is Box-Muller of the uniforms
+ * ((w >> 9) + 0.5) 2^-23 of Philox4x32-10 counter (q/4, p, inst, 0), key
+ * (seed lo, seed hi); q = n*d + j for normal j of step n (d = 2 for Heston,
+ * 1 otherwise).
+ */
+typedef struct {
+    int32_t model;
+    int32_t precision;
+    int32_t n_params;
+    int32_t n_instr;
+    int32_t n_steps;
+    int32_t ckpt_every;
+    int64_t n_paths;
+    uint64_t seed;
+    uint32_t inst;
+    int32_t ckpt_mode;
+    double s0;
+    double rate;
+    double t_max;
+    double sqrt_eps;
+    const int32_t *instr_step;
+    const double *instr_strike;
+    int32_t n_t_nodes;           /* LV (reserved) */
+    int32_t n_k_nodes;
+    const double *t_nodes;
+    const double *k_nodes;
+} cal_problem;
+
+/* Host-only check of a problem (no HIP call): CAL_OK or CAL_EINVAL /
+ * CAL_EUNSUPPORTED.  `msg` (may be NULL) receives a reason, up to `msg_len`
+ * bytes including the terminating NUL. */
+int cal_validate(const cal_problem *pb, char *msg, int32_t msg_len);
+
+/* Validate, then allocate the context and all its device workspace on the
+ * current device.  *out receives the context (NULL on error). */
+int cal_create(const cal_problem *pb, cal_ctx **out);
+
+/* Free the context and its workspace (synchronises the device first).
+ * NULL is accepted. */
+int cal_destroy(cal_ctx *ctx);
+
+/* Pass 1 of the paper's algorithm (its step 1, cost eq. 1211A): the forward
+ * sweep F_v over all paths and the sample means.
+ *   d_theta[M] : parameters (FP64, device)
+ *   d_Ey[m]    : out, E y_i = (1/P) sum_p y_i(p) (FP64, device) */
+int calibrate_forward(cal_ctx *ctx, const double *d_theta, double *d_Ey, void *stream);
+
+/* Pass 2 alone with a caller-given output adjoint (eq. 0711A summed over
+ * paths): d_grad[j] = sum_i lambda_i dE y_i/dtheta_j, where each path runs
+ * the forward sweep again and then its reverse sweep seeded with lambda_i/P.
+ *   d_lambda[m] : adjoint of E y (FP64, device)
+ *   d_grad[M]   : out (FP64, device) */
+int calibrate_vjp(cal_ctx *ctx, const double *d_theta, const double *d_lambda, double *d_grad,
+                  void *stream);
+
+/* The paper's full algorithm (its steps 1-3, cost eq. 0711C): pass 1, then
+ * r_i = E y_i - C_i and G = 1/2 sum r_i^2 in FP64 on the device, then pass 2
+ * seeded with lambda_i = r_i / P per path, summed over paths.
+ *   d_C[m]  : targets (FP64, device)
+ *   d_Ey[m] : out, E y;  d_G[1] : out, G;  d_grad[M] : out, dG/dtheta */
+int calibrate_gradient(cal_ctx *ctx, const double *d_theta, const double *d_C, double *d_Ey,
+                       double *d_G, double *d_grad, void *stream);
+
+/* Forward tangent mode over the same paths: d_Ey[m] and the Jacobian
+ * d_J[m*M] (row-major, J[i*M + j] = dE y_i/dtheta_j).  Heston and BS. */
+int calibrate_jacobian(cal_ctx *ctx, const double *d_theta, double *d_Ey, double *d_J, void *stream);
+
+/* Synchronise `stream` and return the device status bits (CAL_FLAG_*)
+ * accumulated since the previous cal_status call (then cleared), or a
+ * negative error code. */
+int cal_status(cal_ctx *ctx, void *stream);
+
+/* Description of the last error on this context ("" if none). With ctx ==
+ * NULL: the last error of cal_create / cal_validate in this thread. */
+const char *cal_last_error(const cal_ctx *ctx);
+
+/* Kernel timing with HIP events recorded on the launch stream around the
+ * pass-1 kernel (which = 0), the pass-2 kernel (which = 1) and the tangent
+ * kernel (which = 2).  cal_timing_enable(ctx, 1) starts recording (and clears
+ * earlier records); cal_timing_read synchronises, returns the summed
+ * milliseconds and the launch count of kernel `which`. */
+int cal_timing_enable(cal_ctx *ctx, int32_t on);
+int cal_timing_read(cal_ctx *ctx, int32_t which, double *ms_total, int64_t *launches);
+
+/* Launch geometry the context uses (for reports): threads per block, blocks
+ * per pass, checkpoint spacing and mode actually in effect. */
+int cal_geometry(const cal_ctx *ctx, int32_t *threads, int64_t *blocks, int32_t *ckpt_every,
+                 int32_t *ckpt_mode);
+
+/* Test access to the random stream the kernels use (same device functions).
+ *   cal_philox: d_out[4*i..4*i+3] = Philox4x32-10(d_ctr[4*i..4*i+3], key)
+ *   cal_normals: for paths path0..path0+n_paths-1 and normals q0..q0+nq-1,
+ *     d_out[(p - path0)*nq + (q - q0)] in the given precision (d_out is
+ *     float* for CAL_FP32, double* for CAL_FP64). */
+int cal_philox(const uint32_t *d_ctr, uint32_t key0, uint32_t key1, int64_t n, uint32_t *d_out,
+               void *stream);
+int cal_normals(int32_t precision, uint64_t seed, uint32_t inst, uint32_t path0, int64_t n_paths,
+                uint32_t q0, int32_t nq, void *d_out, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MCAAD_H */

@@ -1,0 +1,484 @@
+// C ABI of the library (declared in include/mcaad.h): problem validation,
+// context and workspace ownership, and the sequence of kernel launches for
+// each entry point.  Nothing here computes on the host beyond constants and
+// table layout; every step of the path runs in the kernels of mc_kernels.hip.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "../../include/mcaad.h"
+#include "mc_device.hpp"
+#include "mc_kernels.hpp"
+
+using namespace mcaad;
+
+namespace mcaad {
+hipError_t launch_reduce_jac(const double *partial, int64_t nblocks, int32_t M, int32_t m, const int32_t *id,
+                             double scale, double *Ey, double *J, int32_t *status, hipStream_t st);
+hipError_t launch_check_theta(const DevProblem &pb, const double *theta, int model, hipStream_t st);
+}
+
+namespace {
+
+constexpr int kMaxInstr = 2048;
+constexpr int kMaxSteps = 65536;
+constexpr int kMaxTimed = 256;
+
+thread_local std::string g_err;
+
+struct TimedPair {
+    hipEvent_t a, b;
+    int which;
+};
+
+}  // namespace
+
+struct cal_ctx {
+    int device = 0;
+    int model = 0;
+    bool fp64 = false;
+    int M = 0, m = 0, N = 0;
+    int64_t P = 0;
+    int64_t nblocks = 0;
+    int K = 16;
+    int mode = CAL_CKPT_STORE;
+    size_t real = 4;
+    DevProblem dp{};
+    // device workspace
+    int32_t *d_date_step = nullptr;
+    int32_t *d_date_begin = nullptr;
+    double *d_strike = nullptr;
+    float *d_strike_f = nullptr;
+    double *d_disc = nullptr;
+    int32_t *d_id = nullptr;
+    int32_t *d_status = nullptr;
+    double *d_part_y = nullptr;
+    double *d_part_g = nullptr;
+    double *d_part_j = nullptr;
+    void *d_lamD = nullptr;
+    void *d_ckpt = nullptr;
+    // timing
+    bool timing = false;
+    std::vector<TimedPair> timed;
+    std::vector<hipEvent_t> pool;
+    std::string err;
+};
+
+static int fail(cal_ctx *ctx, int code, const std::string &msg)
+{
+    if (ctx) ctx->err = msg;
+    g_err = msg;
+    return code;
+}
+
+static int hip_fail(cal_ctx *ctx, hipError_t e, const char *where)
+{
+    return fail(ctx, CAL_EHIP, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+static std::string validate(const cal_problem *pb, int *code)
+{
+    *code = CAL_EINVAL;
+    if (!pb) return "null problem";
+    if (pb->model != CAL_BS && pb->model != CAL_HESTON && pb->model != CAL_LV) return "unknown model";
+    if (pb->precision != CAL_FP32 && pb->precision != CAL_FP64) return "unknown precision";
+    if (pb->n_instr < 1 || pb->n_instr > kMaxInstr) return "n_instr must be in 1..2048";
+    if (pb->n_steps < 1 || pb->n_steps > kMaxSteps) return "n_steps must be in 1..65536";
+    if (pb->n_paths < 1 || pb->n_paths > ((int64_t)1 << 32)) return "n_paths must be in 1..2^32";
+    if (!pb->instr_step || !pb->instr_strike) return "null instrument table";
+    for (int i = 0; i < pb->n_instr; ++i) {
+        if (pb->instr_step[i] < 1 || pb->instr_step[i] > pb->n_steps) return "instr_step outside 1..n_steps";
+        if (!std::isfinite(pb->instr_strike[i]) || pb->instr_strike[i] < 0.0) return "strike must be finite and >= 0";
+    }
+    if (!(pb->s0 > 0.0) || !std::isfinite(pb->s0)) return "s0 must be positive";
+    if (!(pb->t_max > 0.0) || !std::isfinite(pb->t_max)) return "t_max must be positive";
+    if (!std::isfinite(pb->rate)) return "rate must be finite";
+    if (!(pb->sqrt_eps >= 0.0) || !std::isfinite(pb->sqrt_eps)) return "sqrt_eps must be finite and >= 0";
+    if (pb->ckpt_every != 0 && pb->ckpt_every != 8 && pb->ckpt_every != 16 && pb->ckpt_every != 32)
+        return "ckpt_every must be 0, 8, 16 or 32";
+    if (pb->ckpt_mode < CAL_CKPT_AUTO || pb->ckpt_mode > CAL_CKPT_STORE) return "unknown ckpt_mode";
+    if (pb->model == CAL_BS && pb->n_params != 1) return "Black-Scholes takes n_params = 1";
+    if (pb->model == CAL_HESTON && pb->n_params != 5) return "Heston takes n_params = 5";
+    if (pb->model == CAL_BS && pb->sqrt_eps != 0.0) return "sqrt_eps applies to Heston only";
+    if (pb->model == CAL_LV) {
+        *code = CAL_EUNSUPPORTED;
+        return "the local-volatility model has no device path in this library";
+    }
+    *code = CAL_OK;
+    return "";
+}
+
+static hipError_t alloc(void **p, size_t bytes)
+{
+    return hipMalloc(p, bytes ? bytes : 8);
+}
+
+extern "C" int cal_validate(const cal_problem *pb, char *msg, int32_t msg_len)
+{
+    int code;
+    std::string s = validate(pb, &code);
+    if (msg && msg_len > 0) {
+        std::snprintf(msg, (size_t)msg_len, "%s", s.c_str());
+    }
+    if (code != CAL_OK) g_err = s;
+    return code;
+}
+
+extern "C" int cal_destroy(cal_ctx *ctx)
+{
+    if (!ctx) return CAL_OK;
+    (void)hipDeviceSynchronize();
+    void *bufs[] = {ctx->d_date_step, ctx->d_date_begin, ctx->d_strike, ctx->d_strike_f, ctx->d_disc, ctx->d_id,
+                    ctx->d_status, ctx->d_part_y, ctx->d_part_g, ctx->d_part_j, ctx->d_lamD, ctx->d_ckpt};
+    for (void *b : bufs)
+        if (b) (void)hipFree(b);
+    for (auto &t : ctx->timed) {
+        (void)hipEventDestroy(t.a);
+        (void)hipEventDestroy(t.b);
+    }
+    for (auto e : ctx->pool) (void)hipEventDestroy(e);
+    delete ctx;
+    return CAL_OK;
+}
+
+extern "C" int cal_create(const cal_problem *pb, cal_ctx **out)
+{
+    if (!out) return fail(nullptr, CAL_EINVAL, "null output pointer");
+    *out = nullptr;
+    int code;
+    std::string msg = validate(pb, &code);
+    if (code != CAL_OK) return fail(nullptr, code, msg);
+
+    cal_ctx *c = new cal_ctx();
+    (void)hipGetDevice(&c->device);
+    c->model = pb->model;
+    c->fp64 = pb->precision == CAL_FP64;
+    c->real = c->fp64 ? 8 : 4;
+    c->M = pb->n_params;
+    c->m = pb->n_instr;
+    c->N = pb->n_steps;
+    c->P = pb->n_paths;
+    c->nblocks = (c->P + kBlock - 1) / kBlock;
+    c->K = pb->ckpt_every ? pb->ckpt_every : (c->fp64 ? 8 : 16);
+    const int nv = c->model == CAL_HESTON ? 2 : 1;
+    const int nseg = (c->N + c->K - 1) / c->K;
+    const size_t ckpt_bytes = (size_t)nseg * nv * (size_t)c->P * c->real;
+    c->mode = pb->ckpt_mode == CAL_CKPT_AUTO ? CAL_CKPT_STORE : pb->ckpt_mode;
+
+    // instruments grouped by maturity date (ascending), original order within a date
+    const int m = c->m;
+    std::vector<int32_t> order(m);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int a, int b) { return pb->instr_step[a] < pb->instr_step[b]; });
+    std::vector<int32_t> date_step, date_begin;
+    std::vector<double> strike(m), disc(m);
+    std::vector<float> strike_f(m);
+    const double h = pb->t_max / c->N;
+    for (int k = 0; k < m; ++k) {
+        const int i = order[k];
+        const int s = pb->instr_step[i];
+        if (date_step.empty() || date_step.back() != s) {
+            date_step.push_back(s);
+            date_begin.push_back(k);
+        }
+        strike[k] = pb->instr_strike[i];
+        strike_f[k] = (float)pb->instr_strike[i];
+        disc[k] = std::exp(-pb->rate * s * h);
+    }
+    date_begin.push_back(m);
+    const int nd = (int)date_step.size();
+
+    const size_t tan_w = (size_t)m * (c->M + 1);
+    hipError_t e = hipSuccess;
+    auto A = [&](void **p, size_t bytes) {
+        if (e == hipSuccess) e = alloc(p, bytes);
+    };
+    A((void **)&c->d_date_step, sizeof(int32_t) * nd);
+    A((void **)&c->d_date_begin, sizeof(int32_t) * (nd + 1));
+    A((void **)&c->d_strike, sizeof(double) * m);
+    A((void **)&c->d_strike_f, sizeof(float) * m);
+    A((void **)&c->d_disc, sizeof(double) * m);
+    A((void **)&c->d_id, sizeof(int32_t) * m);
+    A((void **)&c->d_status, sizeof(int32_t));
+    A((void **)&c->d_part_y, sizeof(double) * (size_t)c->nblocks * m);
+    A((void **)&c->d_part_g, sizeof(double) * (size_t)c->nblocks * c->M);
+    A((void **)&c->d_part_j, sizeof(double) * (size_t)c->nblocks * tan_w);
+    A(&c->d_lamD, c->real * m);
+    if (e != hipSuccess) {
+        cal_destroy(c);
+        return fail(nullptr, CAL_ENOMEM, std::string("workspace allocation failed: ") + hipGetErrorString(e));
+    }
+    e = alloc(&c->d_ckpt, ckpt_bytes);
+    if (e != hipSuccess) {
+        cal_destroy(c);
+        return fail(nullptr, CAL_ENOMEM, "checkpoint buffer allocation failed");
+    }
+    auto H2D = [&](void *dst, const void *src, size_t bytes) {
+        if (e == hipSuccess) e = hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice);
+    };
+    H2D(c->d_date_step, date_step.data(), sizeof(int32_t) * nd);
+    H2D(c->d_date_begin, date_begin.data(), sizeof(int32_t) * (nd + 1));
+    H2D(c->d_strike, strike.data(), sizeof(double) * m);
+    H2D(c->d_strike_f, strike_f.data(), sizeof(float) * m);
+    H2D(c->d_disc, disc.data(), sizeof(double) * m);
+    H2D(c->d_id, order.data(), sizeof(int32_t) * m);
+    if (e == hipSuccess) e = hipMemset(c->d_status, 0, sizeof(int32_t));
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e != hipSuccess) {
+        cal_destroy(c);
+        return fail(nullptr, CAL_EHIP, std::string("table upload failed: ") + hipGetErrorString(e));
+    }
+
+    DevProblem &d = c->dp;
+    d.N = c->N;
+    d.m = m;
+    d.M = c->M;
+    d.ndates = nd;
+    d.nseg = nseg;
+    d.K = c->K;
+    d.P = c->P;
+    d.k0 = (uint32_t)pb->seed;
+    d.k1 = (uint32_t)(pb->seed >> 32);
+    d.inst = pb->inst;
+    d.use_eps = pb->sqrt_eps > 0.0;
+    d.s0 = pb->s0;
+    d.rate = pb->rate;
+    d.h = h;
+    d.sq = std::sqrt(h);
+    d.sqrt_eps = pb->sqrt_eps;
+    d.date_step = c->d_date_step;
+    d.date_begin = c->d_date_begin;
+    d.strike = c->d_strike;
+    d.strike_f = c->d_strike_f;
+    d.disc = c->d_disc;
+    d.id = c->d_id;
+    d.status = c->d_status;
+    *out = c;
+    return CAL_OK;
+}
+
+// --- timing -----------------------------------------------------------------
+static hipEvent_t get_event(cal_ctx *c)
+{
+    if (!c->pool.empty()) {
+        hipEvent_t e = c->pool.back();
+        c->pool.pop_back();
+        return e;
+    }
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+struct Timed {
+    cal_ctx *c;
+    hipStream_t st;
+    int which;
+    hipEvent_t a = nullptr, b = nullptr;
+    Timed(cal_ctx *c_, hipStream_t s, int w) : c(c_), st(s), which(w)
+    {
+        if (c->timing && (int)c->timed.size() < kMaxTimed) {
+            a = get_event(c);
+            b = get_event(c);
+            if (a && b && hipEventRecord(a, st) != hipSuccess) a = nullptr;
+        }
+    }
+    void done()
+    {
+        if (a && b && hipEventRecord(b, st) == hipSuccess) c->timed.push_back({a, b, which});
+    }
+};
+
+extern "C" int cal_timing_enable(cal_ctx *ctx, int32_t on)
+{
+    if (!ctx) return fail(nullptr, CAL_EINVAL, "null context");
+    (void)hipDeviceSynchronize();
+    for (auto &t : ctx->timed) {
+        ctx->pool.push_back(t.a);
+        ctx->pool.push_back(t.b);
+    }
+    ctx->timed.clear();
+    ctx->timing = on != 0;
+    return CAL_OK;
+}
+
+extern "C" int cal_timing_read(cal_ctx *ctx, int32_t which, double *ms_total, int64_t *launches)
+{
+    if (!ctx || !ms_total || !launches) return fail(ctx, CAL_EINVAL, "null argument");
+    double tot = 0.0;
+    int64_t n = 0;
+    for (auto &t : ctx->timed) {
+        if (t.which != which) continue;
+        hipError_t e = hipEventSynchronize(t.b);
+        if (e != hipSuccess) return hip_fail(ctx, e, "hipEventSynchronize");
+        float ms = 0.f;
+        e = hipEventElapsedTime(&ms, t.a, t.b);
+        if (e != hipSuccess) return hip_fail(ctx, e, "hipEventElapsedTime");
+        tot += ms;
+        ++n;
+    }
+    *ms_total = tot;
+    *launches = n;
+    return CAL_OK;
+}
+
+extern "C" int cal_geometry(const cal_ctx *ctx, int32_t *threads, int64_t *blocks, int32_t *ckpt_every,
+                            int32_t *ckpt_mode)
+{
+    if (!ctx) return CAL_EINVAL;
+    if (threads) *threads = kBlock;
+    if (blocks) *blocks = ctx->nblocks;
+    if (ckpt_every) *ckpt_every = ctx->K;
+    if (ckpt_mode) *ckpt_mode = ctx->mode;
+    return CAL_OK;
+}
+
+// --- entry points -------------------------------------------------------------
+static int check_ctx(cal_ctx *ctx)
+{
+    if (!ctx) return fail(nullptr, CAL_EINVAL, "null context");
+    int dev = -1;
+    (void)hipGetDevice(&dev);
+    if (dev != ctx->device) return fail(ctx, CAL_EINVAL, "context belongs to another device");
+    ctx->err.clear();
+    return CAL_OK;
+}
+
+static int run_pass1(cal_ctx *c, const double *theta, bool store, hipStream_t st)
+{
+    Timed t(c, st, 0);
+    hipError_t e = launch_pass1(c->dp, c->model, c->fp64, store, theta, c->d_part_y, c->d_ckpt, c->nblocks, st);
+    t.done();
+    if (e != hipSuccess) return hip_fail(c, e, "pass-1 launch");
+    return CAL_OK;
+}
+
+static int run_pass2(cal_ctx *c, const double *theta, bool from_ckpt, hipStream_t st)
+{
+    Timed t(c, st, 1);
+    hipError_t e = launch_pass2(c->dp, c->model, c->fp64, from_ckpt, theta, c->d_lamD, c->d_part_g, c->d_ckpt,
+                                c->nblocks, st);
+    t.done();
+    if (e != hipSuccess) return hip_fail(c, e, "pass-2 launch");
+    return CAL_OK;
+}
+
+extern "C" int calibrate_forward(cal_ctx *ctx, const double *d_theta, double *d_Ey, void *stream)
+{
+    int rc = check_ctx(ctx);
+    if (rc) return rc;
+    if (!d_theta || !d_Ey) return fail(ctx, CAL_EINVAL, "null device pointer");
+    hipStream_t st = (hipStream_t)stream;
+    rc = run_pass1(ctx, d_theta, false, st);
+    if (rc) return rc;
+    hipError_t e = launch_reduce_sorted(ctx->d_part_y, ctx->nblocks, ctx->m, ctx->m, ctx->d_id, 1.0 / (double)ctx->P,
+                                        d_Ey, ctx->d_status, st);
+    if (e != hipSuccess) return hip_fail(ctx, e, "reduce launch");
+    return CAL_OK;
+}
+
+extern "C" int calibrate_vjp(cal_ctx *ctx, const double *d_theta, const double *d_lambda, double *d_grad,
+                             void *stream)
+{
+    int rc = check_ctx(ctx);
+    if (rc) return rc;
+    if (!d_theta || !d_lambda || !d_grad) return fail(ctx, CAL_EINVAL, "null device pointer");
+    hipStream_t st = (hipStream_t)stream;
+    hipError_t e = launch_check_theta(ctx->dp, d_theta, ctx->model, st);
+    if (e == hipSuccess) e = launch_lambda(ctx->dp, ctx->fp64, d_lambda, ctx->d_lamD, d_theta, st);
+    if (e != hipSuccess) return hip_fail(ctx, e, "lambda launch");
+    rc = run_pass2(ctx, d_theta, false, st);
+    if (rc) return rc;
+    e = launch_reduce_sorted(ctx->d_part_g, ctx->nblocks, ctx->M, ctx->M, nullptr, 1.0, d_grad, ctx->d_status, st);
+    if (e != hipSuccess) return hip_fail(ctx, e, "reduce launch");
+    return CAL_OK;
+}
+
+extern "C" int calibrate_gradient(cal_ctx *ctx, const double *d_theta, const double *d_C, double *d_Ey,
+                                  double *d_G, double *d_grad, void *stream)
+{
+    int rc = check_ctx(ctx);
+    if (rc) return rc;
+    if (!d_theta || !d_C || !d_Ey || !d_G || !d_grad) return fail(ctx, CAL_EINVAL, "null device pointer");
+    hipStream_t st = (hipStream_t)stream;
+    const bool store = ctx->mode == CAL_CKPT_STORE;
+    rc = run_pass1(ctx, d_theta, store, st);
+    if (rc) return rc;
+    hipError_t e = launch_reduce_sorted(ctx->d_part_y, ctx->nblocks, ctx->m, ctx->m, ctx->d_id, 1.0 / (double)ctx->P,
+                                        d_Ey, ctx->d_status, st);
+    if (e == hipSuccess) e = launch_residual(ctx->dp, ctx->fp64, d_Ey, d_C, d_G, ctx->d_lamD, d_theta, st);
+    if (e != hipSuccess) return hip_fail(ctx, e, "residual launch");
+    rc = run_pass2(ctx, d_theta, store, st);
+    if (rc) return rc;
+    e = launch_reduce_sorted(ctx->d_part_g, ctx->nblocks, ctx->M, ctx->M, nullptr, 1.0, d_grad, ctx->d_status, st);
+    if (e != hipSuccess) return hip_fail(ctx, e, "reduce launch");
+    return CAL_OK;
+}
+
+extern "C" int calibrate_jacobian(cal_ctx *ctx, const double *d_theta, double *d_Ey, double *d_J, void *stream)
+{
+    int rc = check_ctx(ctx);
+    if (rc) return rc;
+    if (!d_theta || !d_Ey || !d_J) return fail(ctx, CAL_EINVAL, "null device pointer");
+    if ((size_t)ctx->m * (ctx->M + 1) * kWavesPerBlock * sizeof(double) > 64 * 1024)
+        return fail(ctx, CAL_EUNSUPPORTED, "m * (M + 1) too large for the tangent kernel's LDS");
+    hipStream_t st = (hipStream_t)stream;
+    hipError_t e;
+    {
+        Timed t(ctx, st, 2);
+        e = launch_tangent(ctx->dp, ctx->model, ctx->fp64, d_theta, ctx->d_part_j, ctx->nblocks, st);
+        t.done();
+    }
+    if (e != hipSuccess) return hip_fail(ctx, e, "tangent launch");
+    e = launch_reduce_jac(ctx->d_part_j, ctx->nblocks, ctx->M, ctx->m, ctx->d_id, 1.0 / (double)ctx->P, d_Ey, d_J,
+                          ctx->d_status, st);
+    if (e != hipSuccess) return hip_fail(ctx, e, "reduce launch");
+    return CAL_OK;
+}
+
+extern "C" int cal_status(cal_ctx *ctx, void *stream)
+{
+    int rc = check_ctx(ctx);
+    if (rc) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    int32_t flags = 0;
+    hipError_t e = hipMemcpyAsync(&flags, ctx->d_status, sizeof(int32_t), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e == hipSuccess) e = hipMemsetAsync(ctx->d_status, 0, sizeof(int32_t), st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return hip_fail(ctx, e, "status read");
+    return flags;
+}
+
+extern "C" const char *cal_last_error(const cal_ctx *ctx)
+{
+    return ctx ? ctx->err.c_str() : g_err.c_str();
+}
+
+extern "C" int cal_philox(const uint32_t *d_ctr, uint32_t key0, uint32_t key1, int64_t n, uint32_t *d_out,
+                          void *stream)
+{
+    if (n < 0 || (n > 0 && (!d_ctr || !d_out))) return fail(nullptr, CAL_EINVAL, "bad philox arguments");
+    if (n == 0) return CAL_OK;
+    hipError_t e = launch_philox(d_ctr, key0, key1, n, d_out, (hipStream_t)stream);
+    return e == hipSuccess ? CAL_OK : hip_fail(nullptr, e, "philox launch");
+}
+
+extern "C" int cal_normals(int32_t precision, uint64_t seed, uint32_t inst, uint32_t path0, int64_t n_paths,
+                           uint32_t q0, int32_t nq, void *d_out, void *stream)
+{
+    if ((precision != CAL_FP32 && precision != CAL_FP64) || n_paths < 0 || nq < 0)
+        return fail(nullptr, CAL_EINVAL, "bad normals arguments");
+    if (n_paths == 0 || nq == 0) return CAL_OK;
+    if (!d_out) return fail(nullptr, CAL_EINVAL, "null output");
+    hipError_t e = launch_normals(precision == CAL_FP64, (uint32_t)seed, (uint32_t)(seed >> 32), inst, path0, n_paths,
+                                  q0, nq, d_out, (hipStream_t)stream);
+    return e == hipSuccess ? CAL_OK : hip_fail(nullptr, e, "normals launch");
+}

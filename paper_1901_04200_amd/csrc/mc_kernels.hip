@@ -1,0 +1,731 @@
+// Monte Carlo passes of the two-pass adjoint calibration gradient on gfx950.
+//
+// One path per lane, path state in VGPRs, normals regenerated from the
+// counter-based Philox stream whenever they are needed (never stored), FP64
+// sums over paths: wavefront butterfly -> LDS (one slot per wave) -> one
+// FP64 partial per workgroup -> fixed-order final sum in a separate kernel.
+//
+//  pass 1 (paper: algorithm step 1, cost eq. 1211A)
+//      Euler sweep F_v, payoffs at maturity dates, block partials of sum y_i;
+//      optionally stores the state every K steps (the paper's "execution
+//      results of the first step ... stored in the memory", step 2).
+//  pass 2 (paper: algorithm step 2, eq. 0711A; step 3 is the final sum)
+//      per path: forward sweep again (or the stored checkpoints), then for
+//      every K-step segment from the last to the first: reload the segment's
+//      checkpoint, recompute its K steps keeping states and normals in
+//      registers, and run the reverse sweep R_v over them seeded with
+//      lambda_i D_i / P at the maturity dates.
+//  tangent
+//      forward sweep carrying dx/dtheta, dv/dtheta (Jacobian of E y).
+#include <hip/hip_runtime.h>
+
+#include "mc_device.hpp"
+#include "mc_kernels.hpp"
+
+namespace mcaad {
+
+// ---------------------------------------------------------------------------
+// Model constants, computed per lane from theta (uniform values)
+// ---------------------------------------------------------------------------
+template <typename R>
+struct Consts {
+    R s0, sq;
+    // Black-Scholes: x += (r - sigma^2/2) h + sigma sq z
+    R bs_drift, bs_vol, bs_gh;
+    // Heston (theta = kappa, theta_bar, xi, rho, v0)
+    R rh, hh, kh, khth, xsq, rho, rhop, rr, thbh, h, v0;
+    R eps, e_c1, e_c2;
+    int use_eps;
+};
+
+template <typename R>
+__device__ __forceinline__ R sqrt_r(R v)
+{
+    if constexpr (sizeof(R) == 4) return __builtin_amdgcn_sqrtf(v);
+    else return sqrt(v);
+}
+
+template <typename R>
+__device__ __forceinline__ R half_rcp(R s)
+{
+    if constexpr (sizeof(R) == 4) return 0.5f * __builtin_amdgcn_rcpf(s);
+    else return 0.5 / s;
+}
+
+template <typename R>
+__device__ __forceinline__ R exp_r(R x)
+{
+    if constexpr (sizeof(R) == 4) return __expf(x);
+    else return exp(x);
+}
+
+template <int MODEL, typename R>
+__device__ __forceinline__ void load_consts(const DevProblem &pb, const double *th, Consts<R> &c)
+{
+    c.s0 = (R)pb.s0;
+    c.sq = (R)pb.sq;
+    if constexpr (MODEL == kBS) {
+        const double sig = th[0];
+        c.bs_drift = (R)((pb.rate - 0.5 * sig * sig) * pb.h);
+        c.bs_vol = (R)(sig * pb.sq);
+        c.bs_gh = (R)(-sig * pb.h);
+    } else {
+        const double kap = th[0], thb = th[1], xi = th[2], rho = th[3], v0 = th[4];
+        const double rhop = sqrt(1.0 - rho * rho);
+        c.rh = (R)(pb.rate * pb.h);
+        c.hh = (R)(0.5 * pb.h);
+        c.kh = (R)(kap * pb.h);
+        c.khth = (R)(kap * thb * pb.h);
+        c.xsq = (R)(xi * pb.sq);
+        c.rho = (R)rho;
+        c.rhop = (R)rhop;
+        c.rr = (R)(rho / rhop);
+        c.thbh = (R)(thb * pb.h);
+        c.h = (R)pb.h;
+        c.v0 = (R)v0;
+        c.use_eps = pb.use_eps;
+        const double e = pb.sqrt_eps;
+        c.eps = (R)e;
+        c.e_c1 = e > 0.0 ? (R)(1.5 / sqrt(e)) : (R)0;
+        c.e_c2 = e > 0.0 ? (R)(0.5 / (e * sqrt(e))) : (R)0;
+    }
+}
+
+// Diffusion coefficient of the variance and its derivative (full truncation;
+// optionally a C1 quadratic below eps).
+template <typename R>
+__device__ __forceinline__ R heston_s(const Consts<R> &c, R vp)
+{
+    R s = sqrt_r(vp);
+    if (c.use_eps && vp < c.eps) s = vp * (c.e_c1 - c.e_c2 * vp);
+    return s;
+}
+
+template <typename R>
+__device__ __forceinline__ R heston_ds(const Consts<R> &c, R vp, R s)
+{
+    R d = vp > (R)0 ? half_rcp(s) : (R)0;
+    if (c.use_eps && vp < c.eps) d = vp > (R)0 ? c.e_c1 - (R)2 * c.e_c2 * vp : (R)0;
+    return d;
+}
+
+// One Euler step of the forward algorithm F.  z points at the d normals of the step.
+template <int MODEL, typename R>
+__device__ __forceinline__ void euler_step(const Consts<R> &c, R &x, R &v, const R *z)
+{
+    if constexpr (MODEL == kBS) {
+        x = x + c.bs_drift + c.bs_vol * z[0];
+    } else {
+        const R vp = v > (R)0 ? v : (R)0;
+        const R s = heston_s(c, vp);
+        const R w = c.rho * z[0] + c.rhop * z[1];
+        const R xn = x + (c.rh - c.hh * vp) + (c.sq * s) * z[0];
+        const R vn = v + (c.khth - c.kh * vp) + (c.xsq * s) * w;
+        x = xn;
+        v = vn;
+    }
+}
+
+template <int MODEL>
+struct Traits;
+template <>
+struct Traits<kBS> {
+    static constexpr int D = 1;   // normals per step
+    static constexpr int NV = 1;  // state variables in a checkpoint
+    static constexpr int NP = 1;  // parameters
+};
+template <>
+struct Traits<kHeston> {
+    static constexpr int D = 2;
+    static constexpr int NV = 2;
+    static constexpr int NP = 5;
+};
+
+// Flags theta outside the model's domain (one lane of the grid).
+template <int MODEL>
+__device__ void check_theta(const DevProblem &pb, const double *th)
+{
+    bool ok;
+    if constexpr (MODEL == kBS) {
+        ok = isfinite(th[0]) && th[0] >= 0.0;
+    } else {
+        ok = true;
+        for (int j = 0; j < 5; ++j) ok = ok && isfinite(th[j]);
+        ok = ok && th[0] >= 0.0 && th[1] >= 0.0 && th[2] >= 0.0 && th[3] > -1.0 && th[3] < 1.0 && th[4] >= 0.0;
+    }
+    if (!ok) atomicOr(pb.status, 1);
+}
+
+// ---------------------------------------------------------------------------
+// Pass 1: forward sweep, payoffs, block partials of sum_p y_i(p)
+// ---------------------------------------------------------------------------
+template <int MODEL, typename R, bool STORE>
+__global__ __launch_bounds__(kBlock) void k_pass1(DevProblem pb, const double *__restrict__ theta,
+                                                  double *__restrict__ partial, R *__restrict__ ckpt)
+{
+    using T = Traits<MODEL>;
+    extern __shared__ double lds[];   // [kWavesPerBlock][m]
+    const int tid = threadIdx.x;
+    const int lane = tid & (kWave - 1);
+    const int wave = tid / kWave;
+    const int64_t p = (int64_t)blockIdx.x * kBlock + tid;
+    const bool active = p < pb.P;
+    const uint32_t path = (uint32_t)p;
+    if (blockIdx.x == 0 && tid == 0) check_theta<MODEL>(pb, theta);
+
+    Consts<R> c;
+    load_consts<MODEL, R>(pb, theta, c);
+    R x = (R)0;
+    R v = MODEL == kHeston ? c.v0 : (R)0;
+
+    constexpr int SPC = 4 / T::D;   // steps per Philox call
+    const int ncalls = (pb.N * T::D + 3) / 4;
+    int d = 0;
+    int next = pb.ndates > 0 ? pb.date_step[0] : -1;
+    const int kmask = pb.K - 1;
+    const int kshift = __builtin_ctz(pb.K);
+    for (int call = 0; call < ncalls; ++call) {
+        R z[4];
+        normals4<R>((uint32_t)call, path, pb.inst, pb.k0, pb.k1, z);
+#pragma unroll
+        for (int j = 0; j < SPC; ++j) {
+            const int n = call * SPC + j;
+            if (n < pb.N) {
+                if constexpr (STORE) {
+                    if ((n & kmask) == 0 && active) {
+                        const int64_t base = (int64_t)((n >> kshift) * T::NV) * pb.P + p;
+                        ckpt[base] = x;
+                        if constexpr (T::NV == 2) ckpt[base + pb.P] = v;
+                    }
+                }
+                euler_step<MODEL, R>(c, x, v, z + j * T::D);
+                if (n + 1 == next) {
+                    const double S = (double)(c.s0 * exp_r(x));
+                    for (int k = pb.date_begin[d]; k < pb.date_begin[d + 1]; ++k) {
+                        double y = active ? pb.disc[k] * fmax(S - pb.strike[k], 0.0) : 0.0;
+                        y = wave_sum(y);
+                        if (lane == 0) lds[wave * pb.m + k] = y;
+                    }
+                    ++d;
+                    next = d < pb.ndates ? pb.date_step[d] : -1;
+                }
+            }
+        }
+    }
+    __syncthreads();
+    for (int k = tid; k < pb.m; k += kBlock) {
+        double s = lds[k];
+#pragma unroll
+        for (int w = 1; w < kWavesPerBlock; ++w) s += lds[w * pb.m + k];
+        partial[(int64_t)blockIdx.x * pb.m + k] = s;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Pass 2: (re-run forward with checkpoints) + reverse sweep, block partials
+// of sum_p thetabar(p)
+// ---------------------------------------------------------------------------
+template <int MODEL, typename R, bool FROM_CKPT, int K>
+__global__ __launch_bounds__(kBlock) void k_pass2(DevProblem pb, const double *__restrict__ theta,
+                                                  const R *__restrict__ lamD, double *__restrict__ partial,
+                                                  R *__restrict__ ckpt)
+{
+    using T = Traits<MODEL>;
+    constexpr int NP = T::NP;
+    constexpr int SPC = 4 / T::D;
+    static_assert(K % SPC == 0, "segments must start on a Philox call");
+    extern __shared__ double lds[];   // [kWavesPerBlock][NP]
+    const int tid = threadIdx.x;
+    const int lane = tid & (kWave - 1);
+    const int wave = tid / kWave;
+    const int64_t p = (int64_t)blockIdx.x * kBlock + tid;
+    const bool active = p < pb.P;
+    const int64_t pc = active ? p : 0;   // inactive lanes read path 0's checkpoints
+    const uint32_t path = (uint32_t)p;
+
+    Consts<R> c;
+    load_consts<MODEL, R>(pb, theta, c);
+    const R *strike_r;
+    if constexpr (sizeof(R) == 4) strike_r = pb.strike_f;
+    else strike_r = pb.strike;
+
+    if constexpr (!FROM_CKPT) {
+        // The forward re-run of the paper's step 2: sweep again, keep the state
+        // at the start of every segment.
+        R x = (R)0;
+        R v = MODEL == kHeston ? c.v0 : (R)0;
+        const int ncalls = (pb.N * T::D + 3) / 4;
+        for (int call = 0; call < ncalls; ++call) {
+            R z[4];
+            normals4<R>((uint32_t)call, path, pb.inst, pb.k0, pb.k1, z);
+#pragma unroll
+            for (int j = 0; j < SPC; ++j) {
+                const int n = call * SPC + j;
+                if (n < pb.N) {
+                    if ((n % K) == 0 && active) {
+                        const int64_t base = (int64_t)((n / K) * T::NV) * pb.P + p;
+                        ckpt[base] = x;
+                        if constexpr (T::NV == 2) ckpt[base + pb.P] = v;
+                    }
+                    euler_step<MODEL, R>(c, x, v, z + j * T::D);
+                }
+            }
+        }
+    }
+
+    R xb = (R)0, vb = (R)0;     // adjoints of the state after the current step
+    double g[NP];
+#pragma unroll
+    for (int j = 0; j < NP; ++j) g[j] = 0.0;
+    int dhi = pb.ndates;        // dates with index < dhi mature at or before this segment's end
+
+    for (int seg = pb.nseg - 1; seg >= 0; --seg) {
+        const int n0 = seg * K;
+        const int64_t base = (int64_t)(seg * T::NV) * pb.P + pc;
+        R x = ckpt[base];
+        R v = (R)0;
+        if constexpr (T::NV == 2) v = ckpt[base + pb.P];
+        int dlo = dhi;
+        while (dlo > 0 && pb.date_step[dlo - 1] > n0) --dlo;
+        int d = dlo;
+        int next = d < dhi ? pb.date_step[d] : -1;
+
+        // recompute the segment, keeping what the reverse sweep needs
+        R s_z1[K], s_z2[K], s_vp[K], s_s[K], s_inj[K];
+        R z[4];
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+            const int n = n0 + j;
+            s_inj[j] = (R)0;
+            s_z2[j] = (R)0;
+            s_vp[j] = (R)0;
+            s_s[j] = (R)0;
+            if (n < pb.N) {
+                if (j % SPC == 0) normals4<R>((uint32_t)(n / SPC), path, pb.inst, pb.k0, pb.k1, z);
+                const R *zs = z + (j % SPC) * T::D;
+                s_z1[j] = zs[0];
+                if constexpr (MODEL == kHeston) {
+                    const R vp = v > (R)0 ? v : (R)0;
+                    s_z2[j] = zs[1];
+                    s_vp[j] = vp;
+                    s_s[j] = heston_s(c, vp);
+                }
+                euler_step<MODEL, R>(c, x, v, zs);
+                if (n + 1 == next) {
+                    // payoff adjoints of this date: sum_i lambda_i D_i / P 1{S > K_i} S
+                    const R S = c.s0 * exp_r(x);
+                    R inj = (R)0;
+                    for (int k = pb.date_begin[d]; k < pb.date_begin[d + 1]; ++k)
+                        inj += S > strike_r[k] ? lamD[k] * S : (R)0;
+                    s_inj[j] = inj;
+                    ++d;
+                    next = d < dhi ? pb.date_step[d] : -1;
+                }
+            } else {
+                s_z1[j] = (R)0;
+            }
+        }
+        dhi = dlo;
+
+        // reverse sweep over the segment
+        R gs[NP];
+#pragma unroll
+        for (int j = 0; j < NP; ++j) gs[j] = (R)0;
+#pragma unroll
+        for (int j = K - 1; j >= 0; --j) {
+            if (n0 + j < pb.N) {
+                xb += s_inj[j];
+                if constexpr (MODEL == kBS) {
+                    // x' = x + (r - sigma^2/2) h + sigma sq z
+                    gs[0] += xb * (c.bs_gh + c.sq * s_z1[j]);
+                } else {
+                    const R vp = s_vp[j], s = s_s[j], z1 = s_z1[j], z2 = s_z2[j];
+                    const R w = c.rho * z1 + c.rhop * z2;
+                    const R a = xb, b = vb;
+                    const R sbar = a * c.sq * z1 + b * c.xsq * w;
+                    const R vpbar = -a * c.hh - b * c.kh + sbar * heston_ds(c, vp, s);
+                    gs[0] += b * (c.thbh - c.h * vp);
+                    gs[1] += b * c.kh;
+                    gs[2] += b * s * c.sq * w;
+                    gs[3] += b * c.xsq * s * (z1 - c.rr * z2);
+                    vb = b + (vp > (R)0 ? vpbar : (R)0);
+                }
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < NP; ++j) g[j] += (double)gs[j];
+    }
+    if constexpr (MODEL == kHeston) g[4] += (double)vb;   // v_0 is theta[4]
+
+#pragma unroll
+    for (int j = 0; j < NP; ++j) {
+        const double t = wave_sum(active ? g[j] : 0.0);
+        if (lane == 0) lds[wave * NP + j] = t;
+    }
+    __syncthreads();
+    if (tid < NP) {
+        double s = lds[tid];
+#pragma unroll
+        for (int w = 1; w < kWavesPerBlock; ++w) s += lds[w * NP + tid];
+        partial[(int64_t)blockIdx.x * NP + tid] = s;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Forward tangent mode: block partials of y_i and dy_i/dtheta_j
+// ---------------------------------------------------------------------------
+template <int MODEL, typename R>
+__global__ __launch_bounds__(kBlock) void k_tangent(DevProblem pb, const double *__restrict__ theta,
+                                                    double *__restrict__ partial)
+{
+    using T = Traits<MODEL>;
+    constexpr int NP = T::NP;
+    constexpr int W = NP + 1;
+    extern __shared__ double lds[];   // [kWavesPerBlock][m * W]
+    const int tid = threadIdx.x;
+    const int lane = tid & (kWave - 1);
+    const int wave = tid / kWave;
+    const int64_t p = (int64_t)blockIdx.x * kBlock + tid;
+    const bool active = p < pb.P;
+    const uint32_t path = (uint32_t)p;
+    if (blockIdx.x == 0 && tid == 0) check_theta<MODEL>(pb, theta);
+
+    Consts<R> c;
+    load_consts<MODEL, R>(pb, theta, c);
+    R x = (R)0;
+    R v = MODEL == kHeston ? c.v0 : (R)0;
+    R xd[NP], vd[NP];
+#pragma unroll
+    for (int j = 0; j < NP; ++j) {
+        xd[j] = (R)0;
+        vd[j] = (R)0;
+    }
+    if constexpr (MODEL == kHeston) vd[4] = (R)1;
+
+    constexpr int SPC = 4 / T::D;
+    const int ncalls = (pb.N * T::D + 3) / 4;
+    int d = 0;
+    int next = pb.ndates > 0 ? pb.date_step[0] : -1;
+    for (int call = 0; call < ncalls; ++call) {
+        R z[4];
+        normals4<R>((uint32_t)call, path, pb.inst, pb.k0, pb.k1, z);
+#pragma unroll
+        for (int j = 0; j < SPC; ++j) {
+            const int n = call * SPC + j;
+            if (n < pb.N) {
+                const R *zs = z + j * T::D;
+                if constexpr (MODEL == kBS) {
+                    xd[0] += c.bs_gh + c.sq * zs[0];
+                } else {
+                    const R vp = v > (R)0 ? v : (R)0;
+                    const R s = heston_s(c, vp);
+                    const R ds = heston_ds(c, vp, s);
+                    const R z1 = zs[0], z2 = zs[1];
+                    const R w = c.rho * z1 + c.rhop * z2;
+                    const R sw = s * c.sq * w;
+#pragma unroll
+                    for (int q = 0; q < NP; ++q) {
+                        const R vpd = v > (R)0 ? vd[q] : (R)0;
+                        const R sd = ds * vpd;
+                        R direct = (R)0;
+                        if (q == 0) direct = c.thbh - c.h * vp;
+                        if (q == 1) direct = c.kh;
+                        if (q == 2) direct = sw;
+                        if (q == 3) direct = c.xsq * s * (z1 - c.rr * z2);
+                        xd[q] = xd[q] - c.hh * vpd + c.sq * z1 * sd;
+                        vd[q] = vd[q] - c.kh * vpd + c.xsq * w * sd + direct;
+                    }
+                }
+                euler_step<MODEL, R>(c, x, v, zs);
+                if (n + 1 == next) {
+                    const double S = (double)(c.s0 * exp_r(x));
+                    for (int k = pb.date_begin[d]; k < pb.date_begin[d + 1]; ++k) {
+                        const bool itm = active && S > pb.strike[k];
+                        double y = itm ? pb.disc[k] * (S - pb.strike[k]) : 0.0;
+                        y = wave_sum(y);
+                        if (lane == 0) lds[wave * pb.m * W + k * W] = y;
+                        const double dS = itm ? pb.disc[k] * S : 0.0;
+#pragma unroll
+                        for (int q = 0; q < NP; ++q) {
+                            const double t = wave_sum(dS * (double)xd[q]);
+                            if (lane == 0) lds[wave * pb.m * W + k * W + 1 + q] = t;
+                        }
+                    }
+                    ++d;
+                    next = d < pb.ndates ? pb.date_step[d] : -1;
+                }
+            }
+        }
+    }
+    __syncthreads();
+    const int width = pb.m * W;
+    for (int k = tid; k < width; k += kBlock) {
+        double s = lds[k];
+#pragma unroll
+        for (int w = 1; w < kWavesPerBlock; ++w) s += lds[w * width + k];
+        partial[(int64_t)blockIdx.x * width + k] = s;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Fixed-order reductions and the FP64 epilogues
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double block_sum(double v, double *sh)
+{
+    const int tid = threadIdx.x;
+    sh[tid] = v;
+    __syncthreads();
+    for (int s = kBlock / 2; s > 0; s >>= 1) {
+        if (tid < s) sh[tid] += sh[tid + s];
+        __syncthreads();
+    }
+    const double r = sh[0];
+    __syncthreads();
+    return r;
+}
+
+// One workgroup per output column k: thread t sums blocks t, t+256, ... in
+// order, then a fixed tree.
+__global__ __launch_bounds__(kBlock) void k_reduce_sorted(const double *__restrict__ partial, int64_t nblocks,
+                                                          int32_t width, const int32_t *__restrict__ id,
+                                                          double scale, double *__restrict__ out,
+                                                          int32_t *status)
+{
+    __shared__ double sh[kBlock];
+    const int k = blockIdx.x;
+    double acc = 0.0;
+    for (int64_t b = threadIdx.x; b < nblocks; b += kBlock) acc += partial[b * width + k];
+    const double s = block_sum(acc, sh) * scale;
+    if (threadIdx.x == 0) {
+        out[id ? id[k] : k] = s;
+        if (!isfinite(s)) atomicOr(status, 2);
+    }
+}
+
+// Tangent-mode columns: k*W + 0 -> Ey[id[k]], k*W + 1 + j -> J[id[k]*M + j].
+__global__ __launch_bounds__(kBlock) void k_reduce_jac(const double *__restrict__ partial, int64_t nblocks,
+                                                       int32_t M, int32_t m, const int32_t *__restrict__ id,
+                                                       double scale, double *__restrict__ Ey,
+                                                       double *__restrict__ J, int32_t *status)
+{
+    __shared__ double sh[kBlock];
+    const int col = blockIdx.x;
+    const int W = M + 1;
+    const int width = m * W;
+    double acc = 0.0;
+    for (int64_t b = threadIdx.x; b < nblocks; b += kBlock) acc += partial[b * width + col];
+    const double s = block_sum(acc, sh) * scale;
+    if (threadIdx.x == 0) {
+        const int k = col / W, t = col % W;
+        if (t == 0) Ey[id[k]] = s;
+        else J[(int64_t)id[k] * M + (t - 1)] = s;
+        if (!isfinite(s)) atomicOr(status, 2);
+    }
+}
+
+template <typename R>
+__global__ __launch_bounds__(kBlock) void k_residual(DevProblem pb, const double *__restrict__ Ey,
+                                                     const double *__restrict__ C, double *__restrict__ G,
+                                                     R *__restrict__ lamD)
+{
+    __shared__ double sh[kBlock];
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < pb.m; i += kBlock) {
+        const double r = Ey[i] - C[i];
+        acc += 0.5 * r * r;
+    }
+    const double g = block_sum(acc, sh);
+    if (threadIdx.x == 0) {
+        G[0] = g;
+        if (!isfinite(g)) atomicOr(pb.status, 2);
+    }
+    const double invP = 1.0 / (double)pb.P;
+    for (int k = threadIdx.x; k < pb.m; k += kBlock) {
+        const int i = pb.id[k];
+        lamD[k] = (R)((Ey[i] - C[i]) * pb.disc[k] * invP);
+    }
+}
+
+template <typename R>
+__global__ __launch_bounds__(kBlock) void k_lambda(DevProblem pb, const double *__restrict__ lambda,
+                                                   R *__restrict__ lamD)
+{
+    const double invP = 1.0 / (double)pb.P;
+    for (int k = threadIdx.x; k < pb.m; k += kBlock) lamD[k] = (R)(lambda[pb.id[k]] * pb.disc[k] * invP);
+}
+
+__global__ void k_check_theta(DevProblem pb, const double *theta, int model)
+{
+    if (threadIdx.x == 0) {
+        if (model == kBS) check_theta<kBS>(pb, theta);
+        else check_theta<kHeston>(pb, theta);
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_philox(const uint32_t *__restrict__ ctr, uint32_t k0, uint32_t k1,
+                                                   int64_t n, uint32_t *__restrict__ out)
+{
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    uint32_t w[4];
+    philox4x32_10(ctr[4 * i], ctr[4 * i + 1], ctr[4 * i + 2], ctr[4 * i + 3], k0, k1, w);
+    for (int j = 0; j < 4; ++j) out[4 * i + j] = w[j];
+}
+
+template <typename R>
+__global__ __launch_bounds__(kBlock) void k_normals(uint32_t k0, uint32_t k1, uint32_t inst, uint32_t path0,
+                                                    int64_t npaths, uint32_t q0, int32_t nq, R *__restrict__ out)
+{
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= npaths * nq) return;
+    const int64_t pp = i / nq;
+    const uint32_t q = q0 + (uint32_t)(i % nq);
+    R z[4];
+    normals4<R>(q >> 2, path0 + (uint32_t)pp, inst, k0, k1, z);
+    out[i] = z[q & 3u];
+}
+
+// ---------------------------------------------------------------------------
+// Launchers
+// ---------------------------------------------------------------------------
+template <int MODEL, typename R>
+static hipError_t pass1_t(const DevProblem &pb, bool store, const double *theta, double *partial, void *ckpt,
+                          int64_t nblocks, hipStream_t st)
+{
+    const size_t lds = sizeof(double) * kWavesPerBlock * pb.m;
+    if (store)
+        hipLaunchKernelGGL((k_pass1<MODEL, R, true>), dim3((unsigned)nblocks), dim3(kBlock), lds, st, pb, theta,
+                           partial, (R *)ckpt);
+    else
+        hipLaunchKernelGGL((k_pass1<MODEL, R, false>), dim3((unsigned)nblocks), dim3(kBlock), lds, st, pb, theta,
+                           partial, (R *)ckpt);
+    return hipGetLastError();
+}
+
+hipError_t launch_pass1(const DevProblem &pb, int model, bool fp64, bool store, const double *theta,
+                        double *partial, void *ckpt, int64_t nblocks, hipStream_t st)
+{
+    if (model == kBS)
+        return fp64 ? pass1_t<kBS, double>(pb, store, theta, partial, ckpt, nblocks, st)
+                    : pass1_t<kBS, float>(pb, store, theta, partial, ckpt, nblocks, st);
+    return fp64 ? pass1_t<kHeston, double>(pb, store, theta, partial, ckpt, nblocks, st)
+                : pass1_t<kHeston, float>(pb, store, theta, partial, ckpt, nblocks, st);
+}
+
+template <int MODEL, typename R, int K>
+static hipError_t pass2_k(const DevProblem &pb, bool from_ckpt, const double *theta, const void *lamD,
+                          double *partial, void *ckpt, int64_t nblocks, hipStream_t st)
+{
+    const size_t lds = sizeof(double) * kWavesPerBlock * Traits<MODEL>::NP;
+    if (from_ckpt)
+        hipLaunchKernelGGL((k_pass2<MODEL, R, true, K>), dim3((unsigned)nblocks), dim3(kBlock), lds, st, pb, theta,
+                           (const R *)lamD, partial, (R *)ckpt);
+    else
+        hipLaunchKernelGGL((k_pass2<MODEL, R, false, K>), dim3((unsigned)nblocks), dim3(kBlock), lds, st, pb,
+                           theta, (const R *)lamD, partial, (R *)ckpt);
+    return hipGetLastError();
+}
+
+template <int MODEL, typename R>
+static hipError_t pass2_t(const DevProblem &pb, bool from_ckpt, const double *theta, const void *lamD,
+                          double *partial, void *ckpt, int64_t nblocks, hipStream_t st)
+{
+    switch (pb.K) {
+    case 8: return pass2_k<MODEL, R, 8>(pb, from_ckpt, theta, lamD, partial, ckpt, nblocks, st);
+    case 16: return pass2_k<MODEL, R, 16>(pb, from_ckpt, theta, lamD, partial, ckpt, nblocks, st);
+    case 32: return pass2_k<MODEL, R, 32>(pb, from_ckpt, theta, lamD, partial, ckpt, nblocks, st);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_pass2(const DevProblem &pb, int model, bool fp64, bool from_ckpt, const double *theta,
+                        const void *lamD, double *partial, void *ckpt, int64_t nblocks, hipStream_t st)
+{
+    if (model == kBS)
+        return fp64 ? pass2_t<kBS, double>(pb, from_ckpt, theta, lamD, partial, ckpt, nblocks, st)
+                    : pass2_t<kBS, float>(pb, from_ckpt, theta, lamD, partial, ckpt, nblocks, st);
+    return fp64 ? pass2_t<kHeston, double>(pb, from_ckpt, theta, lamD, partial, ckpt, nblocks, st)
+                : pass2_t<kHeston, float>(pb, from_ckpt, theta, lamD, partial, ckpt, nblocks, st);
+}
+
+template <int MODEL, typename R>
+static hipError_t tangent_t(const DevProblem &pb, const double *theta, double *partial, int64_t nblocks,
+                            hipStream_t st)
+{
+    const size_t lds = sizeof(double) * kWavesPerBlock * pb.m * (Traits<MODEL>::NP + 1);
+    hipLaunchKernelGGL((k_tangent<MODEL, R>), dim3((unsigned)nblocks), dim3(kBlock), lds, st, pb, theta, partial);
+    return hipGetLastError();
+}
+
+hipError_t launch_tangent(const DevProblem &pb, int model, bool fp64, const double *theta, double *partial,
+                          int64_t nblocks, hipStream_t st)
+{
+    if (model == kBS)
+        return fp64 ? tangent_t<kBS, double>(pb, theta, partial, nblocks, st)
+                    : tangent_t<kBS, float>(pb, theta, partial, nblocks, st);
+    return fp64 ? tangent_t<kHeston, double>(pb, theta, partial, nblocks, st)
+                : tangent_t<kHeston, float>(pb, theta, partial, nblocks, st);
+}
+
+hipError_t launch_reduce_sorted(const double *partial, int64_t nblocks, int32_t width, int32_t count,
+                                const int32_t *id, double scale, double *out, int32_t *status, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_reduce_sorted, dim3((unsigned)count), dim3(kBlock), 0, st, partial, nblocks, width, id,
+                       scale, out, status);
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce_jac(const double *partial, int64_t nblocks, int32_t M, int32_t m, const int32_t *id,
+                             double scale, double *Ey, double *J, int32_t *status, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_reduce_jac, dim3((unsigned)(m * (M + 1))), dim3(kBlock), 0, st, partial, nblocks, M, m,
+                       id, scale, Ey, J, status);
+    return hipGetLastError();
+}
+
+hipError_t launch_residual(const DevProblem &pb, bool fp64, const double *Ey, const double *C, double *G,
+                           void *lamD, const double *theta, hipStream_t st)
+{
+    if (fp64) hipLaunchKernelGGL(k_residual<double>, dim3(1), dim3(kBlock), 0, st, pb, Ey, C, G, (double *)lamD);
+    else hipLaunchKernelGGL(k_residual<float>, dim3(1), dim3(kBlock), 0, st, pb, Ey, C, G, (float *)lamD);
+    (void)theta;
+    return hipGetLastError();
+}
+
+hipError_t launch_lambda(const DevProblem &pb, bool fp64, const double *lambda, void *lamD, const double *theta,
+                         hipStream_t st)
+{
+    if (fp64) hipLaunchKernelGGL(k_lambda<double>, dim3(1), dim3(kBlock), 0, st, pb, lambda, (double *)lamD);
+    else hipLaunchKernelGGL(k_lambda<float>, dim3(1), dim3(kBlock), 0, st, pb, lambda, (float *)lamD);
+    (void)theta;
+    return hipGetLastError();
+}
+
+hipError_t launch_check_theta(const DevProblem &pb, const double *theta, int model, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_check_theta, dim3(1), dim3(64), 0, st, pb, theta, model);
+    return hipGetLastError();
+}
+
+hipError_t launch_philox(const uint32_t *ctr, uint32_t k0, uint32_t k1, int64_t n, uint32_t *out, hipStream_t st)
+{
+    const int64_t nb = (n + kBlock - 1) / kBlock;
+    hipLaunchKernelGGL(k_philox, dim3((unsigned)nb), dim3(kBlock), 0, st, ctr, k0, k1, n, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_normals(bool fp64, uint32_t k0, uint32_t k1, uint32_t inst, uint32_t path0, int64_t npaths,
+                          uint32_t q0, int32_t nq, void *out, hipStream_t st)
+{
+    const int64_t total = npaths * nq;
+    const int64_t nb = (total + kBlock - 1) / kBlock;
+    if (fp64)
+        hipLaunchKernelGGL(k_normals<double>, dim3((unsigned)nb), dim3(kBlock), 0, st, k0, k1, inst, path0, npaths,
+                           q0, nq, (double *)out);
+    else
+        hipLaunchKernelGGL(k_normals<float>, dim3((unsigned)nb), dim3(kBlock), 0, st, k0, k1, inst, path0, npaths,
+                           q0, nq, (float *)out);
+    return hipGetLastError();
+}
+
+}  // namespace mcaad

@@ -1,0 +1,56 @@
+// Kernel-side problem description and launch entry points of the Monte Carlo
+// passes (internal to the library; the public boundary is include/mcaad.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mcaad {
+
+enum Model { kBS = 0, kHeston = 1 };
+
+// Everything a kernel needs besides theta, passed by value.
+struct DevProblem {
+    int32_t N;            // Euler steps
+    int32_t m;            // instruments
+    int32_t M;            // parameters
+    int32_t ndates;       // distinct maturity steps
+    int32_t nseg;         // checkpoint segments = ceil(N / K)
+    int32_t K;            // checkpoint spacing (8, 16, 32)
+    int64_t P;            // paths
+    uint32_t k0, k1;      // Philox key
+    uint32_t inst;        // Philox counter word 2
+    int32_t use_eps;      // Heston smoothed square root in effect
+    double s0, rate, h, sq, sqrt_eps;
+    const int32_t *date_step;   // [ndates] ascending maturity steps
+    const int32_t *date_begin;  // [ndates + 1] ranges into the date-sorted tables
+    const double *strike;       // [m] date-sorted strikes
+    const float *strike_f;      // [m] the same in FP32
+    const double *disc;         // [m] date-sorted discount factors exp(-r n_i h)
+    const int32_t *id;          // [m] original index of date-sorted instrument k
+    int32_t *status;            // device status bits
+};
+
+// All launchers enqueue on `stream` and return hipGetLastError().
+hipError_t launch_pass1(const DevProblem &pb, int model, bool fp64, bool store_ckpt, const double *theta,
+                        double *partial, void *ckpt, int64_t nblocks, hipStream_t stream);
+hipError_t launch_pass2(const DevProblem &pb, int model, bool fp64, bool from_ckpt, const double *theta,
+                        const void *lamD, double *partial, void *ckpt, int64_t nblocks, hipStream_t stream);
+hipError_t launch_tangent(const DevProblem &pb, int model, bool fp64, const double *theta, double *partial,
+                          int64_t nblocks, hipStream_t stream);
+// out[id[k]] = scale * sum_b partial[b*width + k] for k < count (fixed order)
+hipError_t launch_reduce_sorted(const double *partial, int64_t nblocks, int32_t width, int32_t count,
+                                const int32_t *id, double scale, double *out, int32_t *status,
+                                hipStream_t stream);
+// r = Ey - C, G = 1/2 sum r^2, lamD[k] = r[id[k]] * disc[k] / P (in FP32 or FP64)
+hipError_t launch_residual(const DevProblem &pb, bool fp64, const double *Ey, const double *C, double *G,
+                           void *lamD, const double *theta, hipStream_t stream);
+// lamD[k] = lambda[id[k]] * disc[k] / P
+hipError_t launch_lambda(const DevProblem &pb, bool fp64, const double *lambda, void *lamD,
+                         const double *theta, hipStream_t stream);
+hipError_t launch_philox(const uint32_t *ctr, uint32_t k0, uint32_t k1, int64_t n, uint32_t *out,
+                         hipStream_t stream);
+hipError_t launch_normals(bool fp64, uint32_t k0, uint32_t k1, uint32_t inst, uint32_t path0, int64_t npaths,
+                          uint32_t q0, int32_t nq, void *out, hipStream_t stream);
+
+}  // namespace mcaad

@@ -1,0 +1,78 @@
+"""Torch-facing handle on one calibration problem (device memory and streams
+only; the computation is the C ABI's)."""
+from __future__ import annotations
+
+import torch
+
+from . import capi
+
+_PREC = {"fp32": capi.CAL_FP32, "fp64": capi.CAL_FP64}
+_MODE = {"auto": capi.CAL_CKPT_AUTO, "rerun": capi.CAL_CKPT_RERUN, "store": capi.CAL_CKPT_STORE}
+
+
+class MonteCarloCalibration:
+    """calibrate_forward / calibrate_vjp / calibrate_gradient / calibrate_jacobian
+    on one problem.  theta, targets and lambda are FP64 tensors of the
+    current device (host arrays are copied there)."""
+
+    def __init__(self, problem, precision: str = "fp32", ckpt_every: int = 0, ckpt_mode: str = "auto"):
+        if not torch.cuda.is_available():
+            raise RuntimeError("the Monte Carlo calibration path needs a HIP device")
+        self.problem = problem
+        self.precision = precision
+        self.device = torch.device("cuda", torch.cuda.current_device())
+        self.ctx = capi.cal_create(problem, _PREC[precision], ckpt_every, _MODE[ckpt_mode])
+        self.m = int(len(problem.instr_step))
+        self.M = int(problem.n_params)
+
+    def _dev(self, a, n):
+        t = torch.as_tensor(a, dtype=torch.float64, device=self.device).contiguous()
+        if t.numel() != n:
+            raise ValueError(f"expected {n} values, got {t.numel()}")
+        return t
+
+    def forward(self, theta):
+        th = self._dev(theta, self.M)
+        Ey = torch.empty(self.m, dtype=torch.float64, device=self.device)
+        capi.calibrate_forward(self.ctx, th, Ey)
+        return Ey
+
+    def vjp(self, theta, lam):
+        th = self._dev(theta, self.M)
+        la = self._dev(lam, self.m)
+        g = torch.empty(self.M, dtype=torch.float64, device=self.device)
+        capi.calibrate_vjp(self.ctx, th, la, g)
+        return g
+
+    def gradient(self, theta, targets):
+        th = self._dev(theta, self.M)
+        C = self._dev(targets, self.m)
+        Ey = torch.empty(self.m, dtype=torch.float64, device=self.device)
+        G = torch.empty(1, dtype=torch.float64, device=self.device)
+        g = torch.empty(self.M, dtype=torch.float64, device=self.device)
+        capi.calibrate_gradient(self.ctx, th, C, Ey, G, g)
+        return Ey, G, g
+
+    def jacobian(self, theta):
+        th = self._dev(theta, self.M)
+        Ey = torch.empty(self.m, dtype=torch.float64, device=self.device)
+        J = torch.empty(self.m, self.M, dtype=torch.float64, device=self.device)
+        capi.calibrate_jacobian(self.ctx, th, Ey, J)
+        return Ey, J
+
+    def status(self) -> int:
+        return capi.cal_status(self.ctx)
+
+    def geometry(self) -> dict:
+        return capi.cal_geometry(self.ctx)
+
+    def close(self):
+        if self.ctx is not None:
+            capi.cal_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,340 @@
+"""GPU parity: the HIP library through its C ABI against the FP64 CPU oracle
+on identical random streams.
+
+Tolerances (floating point, relative):
+  E y  : max_i |dEy_i| / max(|Ey_i|, 1e-2)  <= 1e-5 (FP32 state), 1e-12 (FP64)
+  grad : max_j |dg_j| / max_j |g_j|          <= 1e-4 (FP32 state), FP64 below
+Both precisions are held to these bounds where the problem is well
+conditioned (Heston draws with 2 kappa theta_bar > xi^2).  At the first
+Heston draw (2 kappa theta_bar << xi^2) a handful of paths whose variance
+nears zero carry most of the exact pathwise gradient and amplify rounding;
+there the errors against FP64 are stated and only loosely bounded.
+Integer work (Philox words) is compared bit for bit.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from paper_1901_04200_amd import capi
+from paper_1901_04200_amd import workloads as W
+from paper_1901_04200_amd.mc import MonteCarloCalibration
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    capi.lib()
+    return torch.device("cuda", 0)
+
+
+def ey_err(a, b):
+    a, b = np.asarray(a), np.asarray(b)
+    return float(np.max(np.abs(a - b) / np.maximum(np.abs(b), 1e-2)))
+
+
+def g_err(a, b):
+    a, b = np.asarray(a), np.asarray(b)
+    return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300))
+
+
+def run_all(pb, theta, C, precision="fp32", **kw):
+    mc = MonteCarloCalibration(pb, precision=precision, **kw)
+    Ey_f = mc.forward(theta).cpu().numpy()
+    Ey, G, g = mc.gradient(theta, C)
+    out = dict(Ey_f=Ey_f, Ey=Ey.cpu().numpy(), G=float(G.item()), g=g.cpu().numpy())
+    assert mc.status() == 0
+    mc.close()
+    return out
+
+
+# ---------------------------------------------------------------------------
+# random stream
+# ---------------------------------------------------------------------------
+def test_philox_words_bitwise(orc):
+    rng = np.random.default_rng(3)
+    ctr = rng.integers(0, 2 ** 32, size=(20000, 4), dtype=np.uint64)
+    ctr[:8] = [[0, 0, 0, 0], [2 ** 32 - 1] * 4, [1, 0, 0, 0], [0, 1, 0, 0], [0, 0, 1, 0], [0, 0, 0, 1],
+               [5, 7, 0, 0], [2 ** 31, 2 ** 31, 2 ** 31, 2 ** 31]]
+    key = (0x9ABCDEF0, 0x13579BDF)
+    d_ctr = torch.tensor(ctr.astype(np.int64).astype(np.uint32).view(np.int32), device="cuda")
+    d_out = torch.empty_like(d_ctr)
+    say("philox: 20000 counters")
+    capi.cal_philox(d_ctr, key[0], key[1], d_out)
+    torch.cuda.synchronize()
+    got = d_out.cpu().numpy().view(np.uint32).reshape(-1, 4)
+    ref = np.array([orc.philox(c, key) for c in ctr], dtype=np.uint32)
+    np.testing.assert_array_equal(got, ref)
+
+
+def _normals(precision, seed, inst, path0, npaths, q0, nq):
+    dt = torch.float64 if precision == capi.CAL_FP64 else torch.float32
+    out = torch.empty(npaths * nq, dtype=dt, device="cuda")
+    capi.cal_normals(precision, seed, inst, path0, npaths, q0, nq, out)
+    torch.cuda.synchronize()
+    return out.cpu().numpy().astype(np.float64).reshape(npaths, nq)
+
+
+def test_normals_fp64(orc):
+    say("normals fp64: 512 paths x 64")
+    got = _normals(capi.CAL_FP64, 11, 3, 1000, 512, 5, 64)
+    ref = np.stack([orc.normals(11, 3, 1000 + p, 5, 64) for p in range(512)])
+    assert np.max(np.abs(got - ref)) <= 1e-14
+
+
+def test_normals_fp32(orc):
+    say("normals fp32: 4096 paths x 64")
+    got = _normals(capi.CAL_FP32, 11, 0, 0, 4096, 0, 64)
+    ref = np.stack([orc.normals(11, 0, p, 0, 64) for p in range(4096)])
+    d = got - ref
+    say("fp32 normals: max|dz| %.3g  mean dz %.3g  max rel %.3g" % (
+        np.abs(d).max(), d.mean(), np.max(np.abs(d) / np.maximum(np.abs(ref), 1e-3))))
+    assert np.abs(d).max() < 2e-5
+    assert abs(d.mean()) < 1e-7
+
+
+# ---------------------------------------------------------------------------
+# Black-Scholes problem (sigma, m = 4), FP64 and FP32
+# ---------------------------------------------------------------------------
+def test_bs_fp64_matches_oracle(orc):
+    pb, th, C = W.bs_problem()
+    say("bs fp64 P=2^14 N=16")
+    r = run_all(pb, th, C, "fp64")
+    Ey, G, g = orc.gradient(pb, th, C)
+    assert ey_err(r["Ey_f"], Ey) <= 1e-12
+    assert ey_err(r["Ey"], Ey) <= 1e-12
+    assert abs(r["G"] - G) <= 1e-12 * G
+    assert g_err(r["g"], g) <= 1e-11
+
+
+def test_bs_fp32_matches_oracle(orc):
+    pb, th, C = W.bs_problem()
+    say("bs fp32 P=2^14 N=16")
+    r = run_all(pb, th, C, "fp32")
+    Ey, G, g = orc.gradient(pb, th, C)
+    say("bs fp32 errors: Ey %.3g grad %.3g" % (ey_err(r["Ey"], Ey), g_err(r["g"], g)))
+    assert ey_err(r["Ey"], Ey) <= 1e-5
+    assert g_err(r["g"], g) <= 1e-4
+
+
+# ---------------------------------------------------------------------------
+# Heston problem (M = 5, m = 40), several tiles plus a ragged tail
+# ---------------------------------------------------------------------------
+@pytest.fixture(scope="module")
+def heston_small(orc):
+    pb, th0, tht, eps = W.heston_problem(n_paths=(1 << 14) + 37)
+    C = W.noisy_targets(orc.forward(pb, tht), eps)
+    return pb, th0, tht, C
+
+
+def test_heston_fp32_well_conditioned(orc, heston_small):
+    pb, th0, tht, C = heston_small
+    th = W.heston_draws(2, 10)[9]   # satisfies 2 kappa theta_bar > xi^2
+    assert 2 * th[0] * th[1] > th[2] ** 2
+    say("heston fp32 P=2^14+37 N=256 (Feller draw)")
+    r = run_all(pb, th, C, "fp32")
+    Ey, G, g = orc.gradient(pb, th, C)
+    say("heston fp32 errors: Ey %.3g grad %.3g" % (ey_err(r["Ey"], Ey), g_err(r["g"], g)))
+    assert ey_err(r["Ey_f"], Ey) <= 1e-5
+    assert ey_err(r["Ey"], Ey) <= 1e-5
+    assert abs(r["G"] - G) <= 1e-4 * G
+    assert g_err(r["g"], g) <= 1e-4
+
+
+def test_heston_fp32_target_draw(orc, heston_small):
+    pb, th0, tht, C = heston_small
+    say("heston fp32 at the target draw")
+    r = run_all(pb, tht, C * 1.01, "fp32")
+    Ey, G, g = orc.gradient(pb, tht, C * 1.01)
+    say("heston fp32 (target) errors: Ey %.3g grad %.3g" % (ey_err(r["Ey"], Ey), g_err(r["g"], g)))
+    assert ey_err(r["Ey"], Ey) <= 1e-5
+    assert g_err(r["g"], g) <= 1e-4
+
+
+def test_heston_fp64_well_conditioned(orc, heston_small):
+    pb, th0, tht, C = heston_small
+    th = W.heston_draws(2, 10)[9]
+    say("heston fp64 at a Feller draw")
+    r = run_all(pb, th, C, "fp64")
+    Ey, G, g = orc.gradient(pb, th, C)
+    say("heston fp64 errors: Ey %.3g grad %.3g" % (ey_err(r["Ey"], Ey), g_err(r["g"], g)))
+    assert ey_err(r["Ey"], Ey) <= 1e-12
+    assert g_err(r["g"], g) <= 1e-9
+
+
+def test_heston_fp64_first_draw(orc, heston_small):
+    """At the first draw (2 kappa theta_bar << xi^2) last-bit differences
+    between the GPU's and the CPU's FP64 arithmetic are amplified by the
+    paths whose variance nears zero: prices still agree to ~1e-9, the exact
+    pathwise gradient does not (its value hinges on those few paths).  The
+    errors are reported; prices are asserted."""
+    pb, th0, tht, C = heston_small
+    say("heston fp64 at the first draw (Feller violated)")
+    r = run_all(pb, th0, C, "fp64")
+    Ey, G, g = orc.gradient(pb, th0, C)
+    say("heston fp64 first-draw errors: Ey %.3g grad %.3g" % (ey_err(r["Ey"], Ey), g_err(r["g"], g)))
+    assert ey_err(r["Ey"], Ey) <= 1e-8
+    assert np.all(np.isfinite(r["g"]))
+
+
+def test_heston_fp32_first_draw_stated(orc, heston_small):
+    """At the first draw the Euler variance recursion amplifies rounding along
+    paths whose variance nears zero (the tangent of v is multiplied by about
+    1 + xi sqrt(h) w / (2 sqrt(v)) per step), so an FP32 trajectory drifts
+    from the FP64 one.  The errors are stated; the bound only guards against
+    regressions (measured: Ey 4e-4, gradient 0.6 at this size)."""
+    pb, th0, tht, C = heston_small
+    say("heston fp32 at the first draw")
+    r = run_all(pb, th0, C, "fp32")
+    Ey, G, g = orc.gradient(pb, th0, C)
+    say("heston fp32 (first draw) errors: Ey %.3g grad %.3g" % (ey_err(r["Ey"], Ey), g_err(r["g"], g)))
+    assert ey_err(r["Ey"], Ey) <= 2e-3
+    assert np.all(np.isfinite(r["g"]))
+
+
+def test_heston_jacobian_and_vjp(orc, heston_small):
+    pb, th0, tht, C = heston_small
+    th = W.heston_draws(2, 10)[9]
+    say("heston fp32 jacobian + vjp")
+    mc = MonteCarloCalibration(pb, precision="fp32")
+    Ey_g, J_g = mc.jacobian(th)
+    lam = np.linspace(-1.0, 1.0, pb.n_instr)
+    g_g = mc.vjp(th, lam).cpu().numpy()
+    mc.close()
+    Ey, J = orc.jacobian(pb, th)
+    assert ey_err(Ey_g.cpu().numpy(), Ey) <= 1e-5
+    Jg = J_g.cpu().numpy()
+    scale = np.max(np.abs(J), axis=0)
+    assert np.max(np.abs(Jg - J) / scale) <= 1e-4
+    g = orc.vjp(pb, th, lam)
+    assert g_err(g_g, g) <= 1e-4
+
+
+def test_heston_fp64_jacobian(orc, heston_small):
+    pb, th0, tht, C = heston_small
+    pb = pb.with_(n_paths=4096 + 5)
+    th = W.heston_draws(2, 10)[9]
+    mc = MonteCarloCalibration(pb, precision="fp64")
+    Ey_g, J_g = mc.jacobian(th)
+    mc.close()
+    Ey, J = orc.jacobian(pb, th)
+    assert ey_err(Ey_g.cpu().numpy(), Ey) <= 1e-12
+    assert np.max(np.abs(J_g.cpu().numpy() - J)) <= 1e-8 * np.max(np.abs(J))
+
+
+# ---------------------------------------------------------------------------
+# invariants and edge cases
+# ---------------------------------------------------------------------------
+def test_checkpoint_modes_and_spacing(orc, heston_small):
+    pb, th0, tht, C = heston_small
+    th = W.heston_draws(2, 10)[9]
+    res = {}
+    for mode in ("store", "rerun"):
+        for k in (8, 16, 32):
+            say(f"heston fp32 ckpt mode={mode} k={k}")
+            res[(mode, k)] = run_all(pb, th, C, "fp32", ckpt_every=k, ckpt_mode=mode)
+    base = res[("store", 16)]
+    for key, r in res.items():
+        np.testing.assert_array_equal(r["Ey"], base["Ey"])
+        assert g_err(r["g"], base["g"]) <= 1e-5, key
+    for k in (8, 16, 32):
+        np.testing.assert_array_equal(res[("store", k)]["g"], res[("rerun", k)]["g"])
+
+
+def test_bitwise_reproducible(heston_small):
+    pb, th0, tht, C = heston_small
+    a = run_all(pb, tht, C, "fp32")
+    b = run_all(pb, tht, C, "fp32")
+    for k in ("Ey", "g"):
+        np.testing.assert_array_equal(a[k], b[k])
+    assert a["G"] == b["G"]
+
+
+def test_zero_residual(heston_small):
+    pb, th0, tht, C = heston_small
+    mc = MonteCarloCalibration(pb, precision="fp32")
+    Ey = mc.forward(tht)
+    Ey2, G, g = mc.gradient(tht, Ey)
+    assert torch.equal(Ey, Ey2)
+    assert G.item() == 0.0
+    assert torch.all(g == 0)
+    mc.close()
+
+
+def test_invalid_theta_sets_status(heston_small):
+    pb, th0, tht, C = heston_small
+    mc = MonteCarloCalibration(pb.with_(n_paths=256), precision="fp32")
+    bad = tht.copy()
+    bad[3] = 1.5   # |rho| >= 1
+    mc.gradient(bad, C)
+    assert mc.status() & capi.CAL_FLAG_THETA
+    assert mc.status() == 0   # cleared by the previous read
+    mc.close()
+
+
+@pytest.mark.parametrize("P,N,steps,k", [
+    (1, 16, [16, 16, 8], 8),
+    (63, 3, [1, 2, 3, 3], 8),
+    (257, 37, [37, 5, 20, 5, 1], 16),
+    (1000, 40, [40, 33, 17], 32),
+])
+def test_edge_shapes_fp64(orc, P, N, steps, k):
+    """Ragged path counts, step counts that are not a multiple of the
+    checkpoint spacing or of the Philox call, unsorted maturities."""
+    steps = np.array(steps, dtype=np.int32)
+    strikes = np.linspace(85.0, 115.0, len(steps))
+    C = np.linspace(3.0, 9.0, len(steps))
+    for model, th in ((W.MODEL_BS, np.array([0.3])), (W.MODEL_HESTON, np.array([2.0, 0.05, 0.4, -0.6, 0.04]))):
+        pb = W.Problem(model=model, n_params=len(th), n_steps=N, n_paths=P, t_max=N / 64.0,
+                       instr_step=steps, instr_strike=strikes, seed=77, inst=2)
+        say(f"edge fp64 model={model} P={P} N={N} k={k}")
+        for mode in ("store", "rerun"):
+            r = run_all(pb, th, C, "fp64", ckpt_every=k, ckpt_mode=mode)
+            Ey, G, g = orc.gradient(pb, th, C)
+            assert ey_err(r["Ey"], Ey) <= 1e-12
+            assert g_err(r["g"], g) <= 1e-10
+
+
+def test_single_instrument_first_step(orc):
+    pb = W.Problem(model=W.MODEL_HESTON, n_params=5, n_steps=8, n_paths=300, t_max=0.1,
+                   instr_step=np.array([1], dtype=np.int32), instr_strike=np.array([100.0]), seed=3)
+    th = np.array([1.0, 0.04, 0.3, -0.3, 0.05])
+    r = run_all(pb, th, np.array([0.5]), "fp64")
+    Ey, G, g = orc.gradient(pb, th, np.array([0.5]))
+    assert ey_err(r["Ey"], Ey) <= 1e-12
+    assert g_err(r["g"], g) <= 1e-10
+
+
+# ---------------------------------------------------------------------------
+# full size: Heston, 2^20 paths x 256 steps, the launch configuration the
+# benchmark times
+# ---------------------------------------------------------------------------
+def test_heston_full_size(orc):
+    pb, th0, tht, eps = W.heston_problem()
+    th = W.heston_draws(2, 10)[9]
+    say("full size: oracle targets at the target draw, 2^20 paths (seed 2)")
+    C = W.noisy_targets(orc.forward(pb.with_(seed=2), tht), eps)
+    say("full size: fp32 gradient at a Feller draw")
+    r = run_all(pb, th, C, "fp32")
+    Ey, G, g = orc.gradient(pb, th, C)
+    say("full-size fp32 errors: Ey %.3g grad %.3g" % (ey_err(r["Ey"], Ey), g_err(r["g"], g)))
+    assert ey_err(r["Ey"], Ey) <= 1e-5
+    assert g_err(r["g"], g) <= 1e-4
+    say("full size: fp32 forward at the first draw")
+    mc = MonteCarloCalibration(pb, precision="fp32")
+    Ey0_g = mc.forward(th0).cpu().numpy()
+    mc.close()
+    Ey0 = orc.forward(pb, th0)
+    say("full-size fp32 first-draw Ey error %.3g" % ey_err(Ey0_g, Ey0))
+    # ill-conditioned point (see test_heston_fp32_first_draw_stated): stated, guarded loosely
+    assert ey_err(Ey0_g, Ey0) <= 5e-4
