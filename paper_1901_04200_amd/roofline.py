@@ -1,0 +1,65 @@
+"""Algorithmic work per path-step of the Monte Carlo kernels and MI355X peaks.
+
+The path is bound by VALU issue (integer multiplies, transcendentals and
+FP32 arithmetic in registers; HBM traffic is only the checkpoints).  Work is
+counted from the algorithm, not from compiled code, in VALU issue slots.
+
+Peak: the published FP32 vector rate, 157.3 TFLOP/s = 256 CU x 128 FMA
+lanes per clock x 2 flops x 2.4 GHz, i.e. 128 lane-slots per CU per clock,
+7.86e13 lane-slots/s.  A throughput probe on gfx950 (independent chains,
+4096 x 256 threads) measured, in lane-ops per CU per clock: FP32 mul 104,
+FP32 fma 93, xor/shift 103, FP64 fma 52, v_mad_u64_u32 ~32, transcendentals
+(v_log/v_sqrt/v_sin/v_rcp/v_exp_f32) 29-30.  Issue costs in slots:
+  plain 32-bit VALU op (add, mul, fma, xor3, shift, cvt, cmp, select): 1
+  32x32->64 integer multiply (v_mad_u64_u32):                           COST_MAD64 = 4
+  transcendental (log2, sqrt, sin, cos, rcp, exp2):                     COST_TRANS = 4
+
+Per path-step, Heston (d = 2 normals per step), FP32 state:
+  Philox4x32-10, half a call: 10 rounds x (2 wide multiplies + 2 three-way xors) / 2
+                                          = 10 mad64 + 10 valu
+  two uniforms (shift, convert, fma)       = 6 valu
+  Box-Muller pair                          = 3 valu + 4 trans
+  Euler step (truncation, sqrt, w, x, v)   = 11 valu + 1 trans
+  forward step F                           = 10 mad64 + 30 valu + 5 trans  (90 slots)
+  reverse step R (adjoints of x, v; theta-bar accumulation)
+                                           = 24 valu + 1 trans             (28 slots)
+  pass 1 (F)                               = F
+  pass 2 from stored checkpoints (F + R)   = 10 mad64 + 54 valu + 6 trans  (118 slots)
+FP32 flops (FMA = 2) per path-step: F 22, R 31.
+"""
+
+CUS = 256
+LANE_SLOTS_PER_CU_CLOCK = 128   # 157.3 TFLOP/s / (2 flops x 256 CU x 2.4 GHz)
+CLOCK_HZ = 2.4e9
+PEAK_SLOTS = CUS * LANE_SLOTS_PER_CU_CLOCK * CLOCK_HZ   # 7.86e13 lane-slots/s
+PEAK_FP32_TFLOPS = 157.3        # published packed-FP32 vector peak
+PEAK_FP32_NONPACKED_TFLOPS = 78.6
+
+COST_MAD64 = 4.0
+COST_TRANS = 4.0
+
+HESTON_F = {"mad64": 10, "valu": 30, "trans": 5, "flops": 22}
+HESTON_R = {"mad64": 0, "valu": 24, "trans": 1, "flops": 31}
+BS_F = {"mad64": 5, "valu": 11, "trans": 2, "flops": 6}     # quarter call + one normal per step
+BS_R = {"mad64": 0, "valu": 4, "trans": 0, "flops": 4}
+
+
+def slots(op: dict) -> float:
+    return op["valu"] + COST_MAD64 * op["mad64"] + COST_TRANS * op["trans"]
+
+
+def add(a: dict, b: dict) -> dict:
+    return {k: a[k] + b[k] for k in a}
+
+
+def per_path_step(model: str, kernel: str) -> dict:
+    """Algorithmic work per path-step of 'pass1' or 'pass2' (from stored
+    checkpoints) or 'pass2_rerun' (forward re-run + recompute + reverse)."""
+    F, R = (HESTON_F, HESTON_R) if model == "heston" else (BS_F, BS_R)
+    if kernel == "pass1":
+        return dict(F)
+    if kernel == "pass2":
+        return add(F, R)
+    if kernel == "pass2_rerun":
+        return add(add(F, F), R)
+    raise ValueError(kernel)
