@@ -11,11 +11,23 @@ constexpr int kWave = 64;
 constexpr int kBlock = 256;          // 4 waves per workgroup
 constexpr int kWavesPerBlock = kBlock / kWave;
 
+// a ^ b ^ k in one VALU instruction (k uniform, in a scalar register).
+__device__ __forceinline__ uint32_t xor3_vvs(uint32_t a, uint32_t b, uint32_t k)
+{
+    uint32_t r;
+    asm("v_xor3_b32 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "s"(k));
+    return r;
+}
+
 // Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of two
 // 32x32->64 multiplies on the even words, the high halves xor-ed with the odd
 // words and the round key, the key bumped by the Weyl constants after every
 // round.  The key is uniform across the wavefront, so its schedule lives in
-// scalar registers; only the counter words that differ per lane use VALU.
+// scalar registers.  With counter (call, path, inst, 0) only the path word
+// differs per lane, so the first rounds are partly uniform and are left to
+// the compiler's scalar/vector split; from the fourth round on every word
+// differs per lane and each new word is one v_mad_u64_u32 half plus one
+// three-way xor.
 __device__ __forceinline__ void philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
                                               uint32_t k0, uint32_t k1, uint32_t out[4])
 {
@@ -23,8 +35,14 @@ __device__ __forceinline__ void philox4x32_10(uint32_t c0, uint32_t c1, uint32_t
     for (int r = 0; r < 10; ++r) {
         const uint64_t p0 = (uint64_t)0xD2511F53u * (uint64_t)c0;
         const uint64_t p1 = (uint64_t)0xCD9E8D57u * (uint64_t)c2;
-        const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
-        const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+        uint32_t n0, n2;
+        if (r >= 3) {
+            n0 = xor3_vvs((uint32_t)(p1 >> 32), c1, k0);
+            n2 = xor3_vvs((uint32_t)(p0 >> 32), c3, k1);
+        } else {
+            n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+            n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+        }
         c1 = (uint32_t)p1;
         c3 = (uint32_t)p0;
         c0 = n0;

@@ -1,0 +1,87 @@
+"""Pins for the surrogate oracle: the input Jacobian against central
+differences of the forward, and the double-backprop weight gradient against
+torch.autograd in FP64 on the CPU (a library routine) and central
+differences of the loss."""
+import numpy as np
+import pytest
+
+from oracle import mlp_oracle as MO
+
+SIZES = [5, 16, 12, 9, 7]
+
+
+@pytest.fixture(scope="module")
+def case():
+    rng = np.random.default_rng(1)
+    params = MO.init_params(SIZES, 3)
+    params = [(W, rng.normal(0, 0.1, b.shape)) for W, b in params]
+    X = rng.uniform(-1, 1, (6, 5))
+    Yl = rng.normal(0, 1, (6, 7))
+    Jl = rng.normal(0, 1, (6, 7, 5))
+    return params, X, Yl, Jl
+
+
+def test_silu_derivatives():
+    z = np.linspace(-6, 6, 101)
+    h = 1e-6
+    np.testing.assert_allclose(MO.dsilu(z), (MO.silu(z + h) - MO.silu(z - h)) / (2 * h), atol=1e-9)
+    np.testing.assert_allclose(MO.d2silu(z), (MO.dsilu(z + h) - MO.dsilu(z - h)) / (2 * h), atol=1e-8)
+
+
+def test_jacobian_matches_central_differences(case):
+    params, X, _, _ = case
+    Y, J = MO.forward_tangent(params, X)
+    h = 1e-6
+    for j in range(5):
+        e = np.zeros(5)
+        e[j] = h
+        fd = (MO.forward_tangent(params, X + e)[0] - MO.forward_tangent(params, X - e)[0]) / (2 * h)
+        np.testing.assert_allclose(J[:, :, j], fd, atol=1e-8)
+
+
+def test_grads_match_torch_autograd(case):
+    torch = pytest.importorskip("torch")
+    params, X, Yl, Jl = case
+    w = 0.7
+    L, g = MO.grads(params, X, Yl, Jl, w)
+    tp = [(torch.tensor(W, requires_grad=True), torch.tensor(b, requires_grad=True)) for W, b in params]
+    Xt = torch.tensor(X, requires_grad=True)
+
+    def net(x):
+        h = x
+        for l, (W, b) in enumerate(tp):
+            h = h @ W + b
+            if l < len(tp) - 1:
+                h = torch.nn.functional.silu(h)
+        return h
+
+    Y = net(Xt)
+    cols = [torch.autograd.grad(Y[:, i].sum(), Xt, create_graph=True)[0] for i in range(Y.shape[1])]
+    J = torch.stack(cols, dim=1)                       # [B, m, n_in]
+    Lt = torch.mean((Y - torch.tensor(Yl)) ** 2) + w * torch.mean((J - torch.tensor(Jl)) ** 2)
+    Lt.backward()
+    assert abs(L - Lt.item()) < 1e-13 * abs(L)
+    for (dW, db), (W, b) in zip(g, tp):
+        np.testing.assert_allclose(dW, W.grad.numpy(), rtol=1e-11, atol=1e-14)
+        np.testing.assert_allclose(db, b.grad.numpy(), rtol=1e-11, atol=1e-14)
+
+
+def test_grads_match_central_differences(case):
+    params, X, Yl, Jl = case
+    w = 1.3
+    _, g = MO.grads(params, X, Yl, Jl, w)
+    rng = np.random.default_rng(4)
+    h = 1e-6
+    for _ in range(20):
+        l = int(rng.integers(len(params)))
+        W, b = params[l]
+        i, j = int(rng.integers(W.shape[0])), int(rng.integers(W.shape[1]))
+        Wp, Wm = W.copy(), W.copy()
+        Wp[i, j] += h
+        Wm[i, j] -= h
+        pp = list(params)
+        pp[l] = (Wp, b)
+        Lp = MO.loss(pp, X, Yl, Jl, w)
+        pp[l] = (Wm, b)
+        Lm = MO.loss(pp, X, Yl, Jl, w)
+        assert abs((Lp - Lm) / (2 * h) - g[l][0][i, j]) < 1e-7 * max(1.0, abs(g[l][0][i, j]))
