@@ -98,6 +98,8 @@ typedef struct {
     uint64_t seed;
     uint32_t inst;
     int32_t ckpt_mode;
+    int32_t max_batch;           /* instances per calibrate_jacobian_batch call (0 = 1) */
+    int32_t reserved0;
     double s0;
     double rate;
     double t_max;
@@ -146,8 +148,17 @@ int calibrate_gradient(cal_ctx *ctx, const double *d_theta, const double *d_C, d
                        double *d_G, double *d_grad, void *stream);
 
 /* Forward tangent mode over the same paths: d_Ey[m] and the Jacobian
- * d_J[m*M] (row-major, J[i*M + j] = dE y_i/dtheta_j).  Heston and BS. */
+ * d_J[m*M] (row-major, J[i*M + j] = dE y_i/dtheta_j).  Heston and BS.  By
+ * the paper's eq. 0711A the same numbers follow from m reverse sweeps; with
+ * M < m the tangent sweep is the cheaper route to the whole matrix. */
 int calibrate_jacobian(cal_ctx *ctx, const double *d_theta, double *d_Ey, double *d_J, void *stream);
+
+/* calibrate_jacobian for n_inst parameter vectors in one launch (the
+ * surrogate's training labels): instance i reads d_theta[i*M .. i*M+M-1],
+ * draws its normals with Philox counter word 2 = inst0 + i, and writes
+ * d_Ey[i*m ..] and d_J[i*m*M ..].  1 <= n_inst <= the problem's max_batch. */
+int calibrate_jacobian_batch(cal_ctx *ctx, const double *d_theta, int32_t n_inst, uint32_t inst0, double *d_Ey,
+                             double *d_J, void *stream);
 
 /* Synchronise `stream` and return the device status bits (CAL_FLAG_*)
  * accumulated since the previous cal_status call (then cleared), or a

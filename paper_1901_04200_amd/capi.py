@@ -22,7 +22,7 @@ CAL_FLAG_THETA, CAL_FLAG_NONFINITE = 1, 2
 
 EXPORTED = (
     "cal_validate", "cal_create", "cal_destroy", "calibrate_forward", "calibrate_vjp",
-    "calibrate_gradient", "calibrate_jacobian", "cal_status", "cal_last_error",
+    "calibrate_gradient", "calibrate_jacobian", "calibrate_jacobian_batch", "cal_status", "cal_last_error",
     "cal_timing_enable", "cal_timing_read", "cal_geometry", "cal_philox", "cal_normals",
 )
 
@@ -31,7 +31,7 @@ class cal_problem(C.Structure):
     _fields_ = [
         ("model", C.c_int32), ("precision", C.c_int32), ("n_params", C.c_int32), ("n_instr", C.c_int32),
         ("n_steps", C.c_int32), ("ckpt_every", C.c_int32), ("n_paths", C.c_int64), ("seed", C.c_uint64),
-        ("inst", C.c_uint32), ("ckpt_mode", C.c_int32),
+        ("inst", C.c_uint32), ("ckpt_mode", C.c_int32), ("max_batch", C.c_int32), ("reserved0", C.c_int32),
         ("s0", C.c_double), ("rate", C.c_double), ("t_max", C.c_double), ("sqrt_eps", C.c_double),
         ("instr_step", C.POINTER(C.c_int32)), ("instr_strike", C.POINTER(C.c_double)),
         ("n_t_nodes", C.c_int32), ("n_k_nodes", C.c_int32),
@@ -65,6 +65,7 @@ def lib():
             "calibrate_vjp": ([vp, dp, dp, dp, vp], C.c_int),
             "calibrate_gradient": ([vp, dp, dp, dp, dp, dp, vp], C.c_int),
             "calibrate_jacobian": ([vp, dp, dp, dp, vp], C.c_int),
+            "calibrate_jacobian_batch": ([vp, dp, i32, C.c_uint32, dp, dp, vp], C.c_int),
             "cal_status": ([vp, vp], C.c_int),
             "cal_last_error": ([vp], C.c_char_p),
             "cal_timing_enable": ([vp, i32], C.c_int),
@@ -102,7 +103,7 @@ def _check(rc, ctx=None):
 class Packed:
     """A cal_problem plus the host arrays it points at."""
 
-    def __init__(self, pb, precision=CAL_FP32, ckpt_every=0, ckpt_mode=CAL_CKPT_AUTO):
+    def __init__(self, pb, precision=CAL_FP32, ckpt_every=0, ckpt_mode=CAL_CKPT_AUTO, max_batch=0):
         import numpy as np
         self.step = np.ascontiguousarray(pb.instr_step, dtype=np.int32)
         self.strike = np.ascontiguousarray(pb.instr_strike, dtype=np.float64)
@@ -119,6 +120,7 @@ class Packed:
         s.seed = int(pb.seed)
         s.inst = int(pb.inst)
         s.ckpt_mode = int(ckpt_mode)
+        s.max_batch = int(max_batch)
         s.s0 = float(pb.s0)
         s.rate = float(pb.rate)
         s.t_max = float(pb.t_max)
@@ -140,8 +142,8 @@ def cal_validate(pb, precision=CAL_FP32, ckpt_every=0, ckpt_mode=CAL_CKPT_AUTO):
     return rc, buf.value.decode()
 
 
-def cal_create(pb, precision=CAL_FP32, ckpt_every=0, ckpt_mode=CAL_CKPT_AUTO):
-    pk = Packed(pb, precision, ckpt_every, ckpt_mode)
+def cal_create(pb, precision=CAL_FP32, ckpt_every=0, ckpt_mode=CAL_CKPT_AUTO, max_batch=0):
+    pk = Packed(pb, precision, ckpt_every, ckpt_mode, max_batch)
     h = C.c_void_p()
     _check(lib().cal_create(C.byref(pk.s), C.byref(h)))
     return h
@@ -166,6 +168,11 @@ def calibrate_gradient(ctx, theta, C_, Ey, G, grad, stream=None):
 
 def calibrate_jacobian(ctx, theta, Ey, J, stream=None):
     return _check(lib().calibrate_jacobian(ctx, _ptr(theta), _ptr(Ey), _ptr(J), _stream(stream)), ctx)
+
+
+def calibrate_jacobian_batch(ctx, theta, n_inst, inst0, Ey, J, stream=None):
+    return _check(lib().calibrate_jacobian_batch(ctx, _ptr(theta), int(n_inst), int(inst0), _ptr(Ey), _ptr(J),
+                                                 _stream(stream)), ctx)
 
 
 def cal_status(ctx, stream=None):

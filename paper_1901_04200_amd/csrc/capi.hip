@@ -18,12 +18,6 @@
 
 using namespace mcaad;
 
-namespace mcaad {
-hipError_t launch_reduce_jac(const double *partial, int64_t nblocks, int32_t M, int32_t m, const int32_t *id,
-                             double scale, double *Ey, double *J, int32_t *status, hipStream_t st);
-hipError_t launch_check_theta(const DevProblem &pb, const double *theta, int model, hipStream_t st);
-}
-
 namespace {
 
 constexpr int kMaxInstr = 2048;
@@ -46,6 +40,7 @@ struct cal_ctx {
     int M = 0, m = 0, N = 0;
     int64_t P = 0;
     int64_t nblocks = 0;
+    int max_batch = 1;
     int K = 16;
     int mode = CAL_CKPT_STORE;
     size_t real = 4;
@@ -103,6 +98,7 @@ static std::string validate(const cal_problem *pb, int *code)
     if (pb->ckpt_every != 0 && pb->ckpt_every != 8 && pb->ckpt_every != 16 && pb->ckpt_every != 32)
         return "ckpt_every must be 0, 8, 16 or 32";
     if (pb->ckpt_mode < CAL_CKPT_AUTO || pb->ckpt_mode > CAL_CKPT_STORE) return "unknown ckpt_mode";
+    if (pb->max_batch < 0 || pb->max_batch > 65535) return "max_batch must be in 0..65535";
     if (pb->model == CAL_BS && pb->n_params != 1) return "Black-Scholes takes n_params = 1";
     if (pb->model == CAL_HESTON && pb->n_params != 5) return "Heston takes n_params = 5";
     if (pb->model == CAL_BS && pb->sqrt_eps != 0.0) return "sqrt_eps applies to Heston only";
@@ -165,6 +161,7 @@ extern "C" int cal_create(const cal_problem *pb, cal_ctx **out)
     c->N = pb->n_steps;
     c->P = pb->n_paths;
     c->nblocks = (c->P + kBlock - 1) / kBlock;
+    c->max_batch = pb->max_batch > 0 ? pb->max_batch : 1;
     c->K = pb->ckpt_every ? pb->ckpt_every : (c->fp64 ? 8 : 16);
     const int nv = c->model == CAL_HESTON ? 2 : 1;
     const int nseg = (c->N + c->K - 1) / c->K;
@@ -209,7 +206,7 @@ extern "C" int cal_create(const cal_problem *pb, cal_ctx **out)
     A((void **)&c->d_status, sizeof(int32_t));
     A((void **)&c->d_part_y, sizeof(double) * (size_t)c->nblocks * m);
     A((void **)&c->d_part_g, sizeof(double) * (size_t)c->nblocks * c->M);
-    A((void **)&c->d_part_j, sizeof(double) * (size_t)c->nblocks * tan_w);
+    A((void **)&c->d_part_j, sizeof(double) * (size_t)c->nblocks * tan_w * c->max_batch);
     A(&c->d_lamD, c->real * m);
     if (e != hipSuccess) {
         cal_destroy(c);
@@ -422,25 +419,35 @@ extern "C" int calibrate_gradient(cal_ctx *ctx, const double *d_theta, const dou
     return CAL_OK;
 }
 
-extern "C" int calibrate_jacobian(cal_ctx *ctx, const double *d_theta, double *d_Ey, double *d_J, void *stream)
+extern "C" int calibrate_jacobian_batch(cal_ctx *ctx, const double *d_theta, int32_t n_inst, uint32_t inst0,
+                                        double *d_Ey, double *d_J, void *stream)
 {
     int rc = check_ctx(ctx);
     if (rc) return rc;
     if (!d_theta || !d_Ey || !d_J) return fail(ctx, CAL_EINVAL, "null device pointer");
+    if (n_inst < 1 || n_inst > ctx->max_batch) return fail(ctx, CAL_EINVAL, "n_inst outside 1..max_batch");
     if ((size_t)ctx->m * (ctx->M + 1) * kWavesPerBlock * sizeof(double) > 64 * 1024)
         return fail(ctx, CAL_EUNSUPPORTED, "m * (M + 1) too large for the tangent kernel's LDS");
     hipStream_t st = (hipStream_t)stream;
+    DevProblem dp = ctx->dp;
+    dp.inst = inst0;
     hipError_t e;
     {
         Timed t(ctx, st, 2);
-        e = launch_tangent(ctx->dp, ctx->model, ctx->fp64, d_theta, ctx->d_part_j, ctx->nblocks, st);
+        e = launch_tangent(dp, ctx->model, ctx->fp64, d_theta, ctx->d_part_j, ctx->nblocks, n_inst, st);
         t.done();
     }
     if (e != hipSuccess) return hip_fail(ctx, e, "tangent launch");
     e = launch_reduce_jac(ctx->d_part_j, ctx->nblocks, ctx->M, ctx->m, ctx->d_id, 1.0 / (double)ctx->P, d_Ey, d_J,
-                          ctx->d_status, st);
+                          ctx->d_status, n_inst, st);
     if (e != hipSuccess) return hip_fail(ctx, e, "reduce launch");
     return CAL_OK;
+}
+
+extern "C" int calibrate_jacobian(cal_ctx *ctx, const double *d_theta, double *d_Ey, double *d_J, void *stream)
+{
+    if (!ctx) return fail(nullptr, CAL_EINVAL, "null context");
+    return calibrate_jacobian_batch(ctx, d_theta, 1, ctx->dp.inst, d_Ey, d_J, stream);
 }
 
 extern "C" int cal_status(cal_ctx *ctx, void *stream)

@@ -11,11 +11,13 @@ constexpr int kWave = 64;
 constexpr int kBlock = 256;          // 4 waves per workgroup
 constexpr int kWavesPerBlock = kBlock / kWave;
 
-// a ^ b ^ k in one VALU instruction (k uniform, in a scalar register).
+// a ^ b ^ k in one VALU instruction (k uniform, in a scalar register):
+// gfx950's three-input bitwise op with truth table 0x96 (odd parity), which
+// is symmetric in its operands.  (gfx9 has no v_xor3_b32.)
 __device__ __forceinline__ uint32_t xor3_vvs(uint32_t a, uint32_t b, uint32_t k)
 {
     uint32_t r;
-    asm("v_xor3_b32 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "s"(k));
+    asm("v_bitop3_b32 %0, %1, %2, %3 bitop3:0x96" : "=v"(r) : "v"(a), "v"(b), "s"(k));
     return r;
 }
 

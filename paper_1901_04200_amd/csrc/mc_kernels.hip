@@ -374,9 +374,11 @@ __global__ __launch_bounds__(kBlock) void k_pass2(DevProblem pb, const double *_
 // ---------------------------------------------------------------------------
 // Forward tangent mode: block partials of y_i and dy_i/dtheta_j
 // ---------------------------------------------------------------------------
+// blockIdx.y selects an instance: its parameters theta + y*M and Philox
+// counter word 2 = inst + y; its partials start at partial + y*gridDim.x*m*W.
 template <int MODEL, typename R>
-__global__ __launch_bounds__(kBlock) void k_tangent(DevProblem pb, const double *__restrict__ theta,
-                                                    double *__restrict__ partial)
+__global__ __launch_bounds__(kBlock) void k_tangent(DevProblem pb, const double *__restrict__ theta_all,
+                                                    double *__restrict__ partial_all)
 {
     using T = Traits<MODEL>;
     constexpr int NP = T::NP;
@@ -388,6 +390,9 @@ __global__ __launch_bounds__(kBlock) void k_tangent(DevProblem pb, const double 
     const int64_t p = (int64_t)blockIdx.x * kBlock + tid;
     const bool active = p < pb.P;
     const uint32_t path = (uint32_t)p;
+    const double *theta = theta_all + (int64_t)blockIdx.y * NP;
+    double *partial = partial_all + (int64_t)blockIdx.y * gridDim.x * pb.m * W;
+    pb.inst += blockIdx.y;
     if (blockIdx.x == 0 && tid == 0) check_theta<MODEL>(pb, theta);
 
     Consts<R> c;
@@ -502,16 +507,20 @@ __global__ __launch_bounds__(kBlock) void k_reduce_sorted(const double *__restri
     }
 }
 
-// Tangent-mode columns: k*W + 0 -> Ey[id[k]], k*W + 1 + j -> J[id[k]*M + j].
-__global__ __launch_bounds__(kBlock) void k_reduce_jac(const double *__restrict__ partial, int64_t nblocks,
+// Tangent-mode columns: k*W + 0 -> Ey[id[k]], k*W + 1 + j -> J[id[k]*M + j];
+// blockIdx.y is the instance.
+__global__ __launch_bounds__(kBlock) void k_reduce_jac(const double *__restrict__ partial_all, int64_t nblocks,
                                                        int32_t M, int32_t m, const int32_t *__restrict__ id,
-                                                       double scale, double *__restrict__ Ey,
-                                                       double *__restrict__ J, int32_t *status)
+                                                       double scale, double *__restrict__ Ey_all,
+                                                       double *__restrict__ J_all, int32_t *status)
 {
     __shared__ double sh[kBlock];
     const int col = blockIdx.x;
     const int W = M + 1;
     const int width = m * W;
+    const double *partial = partial_all + (int64_t)blockIdx.y * nblocks * width;
+    double *Ey = Ey_all + (int64_t)blockIdx.y * m;
+    double *J = J_all + (int64_t)blockIdx.y * m * M;
     double acc = 0.0;
     for (int64_t b = threadIdx.x; b < nblocks; b += kBlock) acc += partial[b * width + col];
     const double s = block_sum(acc, sh) * scale;
@@ -650,21 +659,22 @@ hipError_t launch_pass2(const DevProblem &pb, int model, bool fp64, bool from_ck
 
 template <int MODEL, typename R>
 static hipError_t tangent_t(const DevProblem &pb, const double *theta, double *partial, int64_t nblocks,
-                            hipStream_t st)
+                            int ninst, hipStream_t st)
 {
     const size_t lds = sizeof(double) * kWavesPerBlock * pb.m * (Traits<MODEL>::NP + 1);
-    hipLaunchKernelGGL((k_tangent<MODEL, R>), dim3((unsigned)nblocks), dim3(kBlock), lds, st, pb, theta, partial);
+    hipLaunchKernelGGL((k_tangent<MODEL, R>), dim3((unsigned)nblocks, (unsigned)ninst), dim3(kBlock), lds, st, pb,
+                       theta, partial);
     return hipGetLastError();
 }
 
 hipError_t launch_tangent(const DevProblem &pb, int model, bool fp64, const double *theta, double *partial,
-                          int64_t nblocks, hipStream_t st)
+                          int64_t nblocks, int ninst, hipStream_t st)
 {
     if (model == kBS)
-        return fp64 ? tangent_t<kBS, double>(pb, theta, partial, nblocks, st)
-                    : tangent_t<kBS, float>(pb, theta, partial, nblocks, st);
-    return fp64 ? tangent_t<kHeston, double>(pb, theta, partial, nblocks, st)
-                : tangent_t<kHeston, float>(pb, theta, partial, nblocks, st);
+        return fp64 ? tangent_t<kBS, double>(pb, theta, partial, nblocks, ninst, st)
+                    : tangent_t<kBS, float>(pb, theta, partial, nblocks, ninst, st);
+    return fp64 ? tangent_t<kHeston, double>(pb, theta, partial, nblocks, ninst, st)
+                : tangent_t<kHeston, float>(pb, theta, partial, nblocks, ninst, st);
 }
 
 hipError_t launch_reduce_sorted(const double *partial, int64_t nblocks, int32_t width, int32_t count,
@@ -676,10 +686,10 @@ hipError_t launch_reduce_sorted(const double *partial, int64_t nblocks, int32_t 
 }
 
 hipError_t launch_reduce_jac(const double *partial, int64_t nblocks, int32_t M, int32_t m, const int32_t *id,
-                             double scale, double *Ey, double *J, int32_t *status, hipStream_t st)
+                             double scale, double *Ey, double *J, int32_t *status, int ninst, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_reduce_jac, dim3((unsigned)(m * (M + 1))), dim3(kBlock), 0, st, partial, nblocks, M, m,
-                       id, scale, Ey, J, status);
+    hipLaunchKernelGGL(k_reduce_jac, dim3((unsigned)(m * (M + 1)), (unsigned)ninst), dim3(kBlock), 0, st, partial,
+                       nblocks, M, m, id, scale, Ey, J, status);
     return hipGetLastError();
 }
 

@@ -36,8 +36,12 @@ hipError_t launch_pass1(const DevProblem &pb, int model, bool fp64, bool store_c
                         double *partial, void *ckpt, int64_t nblocks, hipStream_t stream);
 hipError_t launch_pass2(const DevProblem &pb, int model, bool fp64, bool from_ckpt, const double *theta,
                         const void *lamD, double *partial, void *ckpt, int64_t nblocks, hipStream_t stream);
+// ninst instances along the grid's y dimension (theta and partials per instance)
 hipError_t launch_tangent(const DevProblem &pb, int model, bool fp64, const double *theta, double *partial,
-                          int64_t nblocks, hipStream_t stream);
+                          int64_t nblocks, int ninst, hipStream_t stream);
+hipError_t launch_reduce_jac(const double *partial, int64_t nblocks, int32_t M, int32_t m, const int32_t *id,
+                             double scale, double *Ey, double *J, int32_t *status, int ninst, hipStream_t st);
+hipError_t launch_check_theta(const DevProblem &pb, const double *theta, int model, hipStream_t st);
 // out[id[k]] = scale * sum_b partial[b*width + k] for k < count (fixed order)
 hipError_t launch_reduce_sorted(const double *partial, int64_t nblocks, int32_t width, int32_t count,
                                 const int32_t *id, double scale, double *out, int32_t *status,

@@ -1,0 +1,665 @@
+// Learned surrogate of the calibration map theta -> E y on gfx950: forward
+// pass with input tangents (the network's Jacobian), price + gradient loss,
+// double backpropagation and Adam.  Matrix products run on bf16 MFMA
+// (v_mfma_f32_32x32x16_bf16) with FP32 accumulation; everything elementwise
+// is FP32; the loss is summed in FP64 in a fixed order.  C ABI declared in
+// include/mcaad_surrogate.h.
+//
+// Row layout of every activation matrix: R = (n_in + 1) * Bp rows, row
+// t * Bp + b holds the primal values of sample b (t = 0) or its tangent
+// along input t - 1 (t >= 1); columns are the layer's units.  One product
+// with the layer's weights therefore advances the primal pass and all n_in
+// tangent passes together.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/mcaad_surrogate.h"
+
+namespace {
+
+typedef __attribute__((ext_vector_type(8))) __bf16 bf16x8;
+typedef __attribute__((ext_vector_type(16))) float f32x16;
+
+constexpr int kThreads = 256;
+constexpr int BM = 128, BN = 64, BK = 32, LDK = BK + 8;   // LDS row stride 80 bytes
+constexpr int kOutPad = 64;                               // output units padded to one N tile
+constexpr int kMaxSplits = 64;
+
+// FP32 -> bf16 with round-to-nearest-even (finite inputs).
+__device__ __forceinline__ uint16_t f2bf(float f)
+{
+    uint32_t u = __float_as_uint(f);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+__device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+__device__ __forceinline__ float sigm(float z) { return 1.0f / (1.0f + __expf(-z)); }
+
+// ---------------------------------------------------------------------------
+// C[z] (M x N, FP32) = sum over split z of A(m,k) B(k,n), bf16 operands.
+//   A(m,k) = A_KC ? A[m*lda + k] : A[k*lda + m]
+//   B(k,n) = B_KC ? B[n*ldb + k] : B[k*ldb + n]
+// Tiles 128 x 64 x 32; wave w owns rows 32w..32w+31 and both 32-column
+// blocks.  Operands are staged in LDS with k contiguous, so every MFMA
+// operand is one 16-byte LDS read (8 bf16 along k for one row / column).
+// Requires M % 128 == 0, N % 64 == 0, K % 32 == 0, k_split % 32 == 0.
+// ---------------------------------------------------------------------------
+template <bool A_KC, bool B_KC>
+__global__ __launch_bounds__(kThreads) void k_gemm(const uint16_t *__restrict__ A, int lda,
+                                                   const uint16_t *__restrict__ B, int ldb, float *__restrict__ C,
+                                                   int ldc, int64_t split_stride, int K, int k_split)
+{
+    __shared__ __attribute__((aligned(16))) uint16_t sA[BM * LDK];
+    __shared__ __attribute__((aligned(16))) uint16_t sB[BN * LDK];
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+    const int m0 = blockIdx.x * BM;
+    const int n0 = blockIdx.y * BN;
+    const int kbeg = blockIdx.z * k_split;
+    const int kend = min(K, kbeg + k_split);
+    f32x16 acc0, acc1;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        acc0[i] = 0.f;
+        acc1[i] = 0.f;
+    }
+    for (int k0 = kbeg; k0 < kend; k0 += BK) {
+#pragma unroll
+        for (int c = tid; c < BM * BK / 8; c += kThreads) {
+            if constexpr (A_KC) {
+                const int r = c / (BK / 8), kc = c % (BK / 8);
+                const uint4 v = *(const uint4 *)(A + (int64_t)(m0 + r) * lda + k0 + kc * 8);
+                *(uint4 *)(sA + r * LDK + kc * 8) = v;
+            } else {
+                const int kr = c / (BM / 8), mc = c % (BM / 8);
+                const uint4 v = *(const uint4 *)(A + (int64_t)(k0 + kr) * lda + m0 + mc * 8);
+                const uint16_t *e = (const uint16_t *)&v;
+#pragma unroll
+                for (int i = 0; i < 8; ++i) sA[(mc * 8 + i) * LDK + kr] = e[i];
+            }
+        }
+        {
+            const int c = tid;   // BN * BK / 8 == kThreads
+            if constexpr (B_KC) {
+                const int r = c / (BK / 8), kc = c % (BK / 8);
+                const uint4 v = *(const uint4 *)(B + (int64_t)(n0 + r) * ldb + k0 + kc * 8);
+                *(uint4 *)(sB + r * LDK + kc * 8) = v;
+            } else {
+                const int kr = c / (BN / 8), nc = c % (BN / 8);
+                const uint4 v = *(const uint4 *)(B + (int64_t)(k0 + kr) * ldb + n0 + nc * 8);
+                const uint16_t *e = (const uint16_t *)&v;
+#pragma unroll
+                for (int i = 0; i < 8; ++i) sB[(nc * 8 + i) * LDK + kr] = e[i];
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < BK; kk += 16) {
+            const int ko = kk + 8 * (lane >> 5);
+            const bf16x8 a = *(const bf16x8 *)(sA + (wave * 32 + (lane & 31)) * LDK + ko);
+            const bf16x8 b0 = *(const bf16x8 *)(sB + (lane & 31) * LDK + ko);
+            const bf16x8 b1 = *(const bf16x8 *)(sB + (32 + (lane & 31)) * LDK + ko);
+            acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b0, acc0, 0, 0, 0);
+            acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b1, acc1, 0, 0, 0);
+        }
+        __syncthreads();
+    }
+    float *Cz = C + (int64_t)blockIdx.z * split_stride;
+    const int col = n0 + (lane & 31);
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        const int row = m0 + wave * 32 + (i >> 2) * 8 + (lane >> 5) * 4 + (i & 3);
+        Cz[(int64_t)row * ldc + col] = acc0[i];
+        Cz[(int64_t)row * ldc + col + 32] = acc1[i];
+    }
+}
+
+// out[i*ldo + j] = sum_z part[z][i][j] (fixed order), j < ncols
+__global__ void k_split_reduce(const float *__restrict__ part, int S, int M, int N, float *__restrict__ out,
+                               int ldo, int ncols)
+{
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (int64_t)M * ncols) return;
+    const int i = (int)(idx / ncols), j = (int)(idx % ncols);
+    float s = 0.f;
+    for (int z = 0; z < S; ++z) s += part[(int64_t)z * M * N + (int64_t)i * N + j];
+    out[(int64_t)i * ldo + j] = s;
+}
+
+// ---------------------------------------------------------------------------
+// elementwise kernels
+// ---------------------------------------------------------------------------
+__global__ void k_normalize(const float *__restrict__ th, int B, int Bp, int nin, const float *__restrict__ shift,
+                            const float *__restrict__ scale, float *__restrict__ X)
+{
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= Bp * nin) return;
+    const int b = idx / nin, j = idx % nin;
+    X[idx] = b < B ? (th[idx] - shift[j]) * scale[j] : 0.f;
+}
+
+// Layer 1 (n_in -> H): z = x W1 + b1; the tangent pre-activations are the
+// rows of W1 (the input tangents are unit vectors).
+__global__ void k_l1_fwd(const float *__restrict__ X, const float *__restrict__ W1, const float *__restrict__ b1,
+                         int Bp, int nin, int H, float *__restrict__ Z, uint16_t *__restrict__ A)
+{
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= Bp * H) return;
+    const int b = idx / H, j = idx % H;
+    float z = b1[j];
+    for (int k = 0; k < nin; ++k) z += X[b * nin + k] * W1[k * H + j];
+    const float s = sigm(z);
+    const float d1 = s * (1.f + z * (1.f - s));
+    Z[(int64_t)b * H + j] = z;
+    A[(int64_t)b * H + j] = f2bf(z * s);
+    for (int t = 0; t < nin; ++t) {
+        const float u = W1[t * H + j];
+        const int64_t r = (int64_t)(t + 1) * Bp + b;
+        Z[r * H + j] = u;
+        A[r * H + j] = f2bf(d1 * u);
+    }
+}
+
+// Hidden layers 2, 3: add the bias to the primal rows, SiLU, tangents.
+__global__ void k_act_fwd(float *__restrict__ Z, const float *__restrict__ bias, int Bp, int nin, int H,
+                          uint16_t *__restrict__ A)
+{
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= Bp * H) return;
+    const int b = idx / H, j = idx % H;
+    const float z = Z[(int64_t)b * H + j] + bias[j];
+    const float s = sigm(z);
+    const float d1 = s * (1.f + z * (1.f - s));
+    Z[(int64_t)b * H + j] = z;
+    A[(int64_t)b * H + j] = f2bf(z * s);
+    for (int t = 0; t < nin; ++t) {
+        const int64_t r = (int64_t)(t + 1) * Bp + b;
+        A[r * H + j] = f2bf(d1 * Z[r * H + j]);
+    }
+}
+
+// Output layer: prices and price Jacobian in physical units.
+__global__ void k_out_fwd(const float *__restrict__ Z4, const float *__restrict__ b4, int B, int Bp, int nin,
+                          int nout, const float *__restrict__ in_scale, const float *__restrict__ out_shift,
+                          const float *__restrict__ out_scale, float *__restrict__ Y, float *__restrict__ J)
+{
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= B * nout) return;
+    const int b = idx / nout, i = idx % nout;
+    Y[idx] = (Z4[(int64_t)b * kOutPad + i] + b4[i]) * out_scale[i] + out_shift[i];
+    for (int t = 0; t < nin; ++t)
+        J[(int64_t)idx * nin + t] = Z4[((int64_t)(t + 1) * Bp + b) * kOutPad + i] * out_scale[i] * in_scale[t];
+}
+
+// Differential loss, its adjoint G4 (bf16, network units) and FP64 block partials.
+__global__ __launch_bounds__(kThreads) void k_loss(const float *__restrict__ Z4, const float *__restrict__ b4,
+                                                   const float *__restrict__ Ylab, const float *__restrict__ Jlab,
+                                                   int B, int nin, int nout, float w,
+                                                   const float *__restrict__ in_scale,
+                                                   const float *__restrict__ out_shift,
+                                                   const float *__restrict__ out_scale, uint16_t *__restrict__ G4,
+                                                   float *__restrict__ dYP, double *__restrict__ partial)
+{
+    __shared__ double sh[kThreads];
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    double acc = 0.0;
+    if (idx < B * kOutPad) {
+        const int b = idx / kOutPad, i = idx % kOutPad;
+        if (i < nout) {
+            const float cy = 2.f / (float)(B * nout);
+            const float cj = 2.f * w / (float)(B * nout * nin);
+            const float z = Z4[(int64_t)b * kOutPad + i] + b4[i];
+            const float zl = (Ylab[(int64_t)b * nout + i] - out_shift[i]) / out_scale[i];
+            const float dz = z - zl;
+            G4[(int64_t)b * kOutPad + i] = f2bf(cy * dz);
+            dYP[(int64_t)b * kOutPad + i] = cy * dz;
+            acc = (double)dz * dz / (double)(B * nout);
+            for (int t = 0; t < nin; ++t) {
+                const int64_t r = (int64_t)(t + 1) * B + b;
+                const float jl = Jlab[((int64_t)b * nout + i) * nin + t] / (out_scale[i] * in_scale[t]);
+                const float dj = Z4[r * kOutPad + i] - jl;
+                G4[r * kOutPad + i] = f2bf(cj * dj);
+                acc += (double)w * dj * dj / (double)(B * nout * nin);
+            }
+        } else {
+            G4[(int64_t)b * kOutPad + i] = 0;
+            dYP[(int64_t)b * kOutPad + i] = 0.f;
+            for (int t = 0; t < nin; ++t) G4[((int64_t)(t + 1) * B + b) * kOutPad + i] = 0;
+        }
+    }
+    sh[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s = kThreads / 2; s > 0; s >>= 1) {
+        if (threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[blockIdx.x] = sh[0];
+}
+
+__global__ void k_sum_partials(const double *__restrict__ p, int n, double *__restrict__ out)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        double s = 0.0;
+        for (int i = 0; i < n; ++i) s += p[i];
+        out[0] = s;
+    }
+}
+
+// Adjoint through a hidden layer's activation (double backprop):
+//   primal:  zbar   = hbar s'(z) + sum_t tbar_t u_t s''(z)
+//   tangent: ubar_t = tbar_t s'(z)
+__global__ void k_act_bwd(const float *__restrict__ Hbar, const float *__restrict__ Z, int B, int nin, int H,
+                          uint16_t *__restrict__ Zbar, float *__restrict__ ZbarP)
+{
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= B * H) return;
+    const int b = idx / H, j = idx % H;
+    const float z = Z[(int64_t)b * H + j];
+    const float s = sigm(z);
+    const float d1 = s * (1.f + z * (1.f - s));
+    const float d2 = s * (1.f - s) * (2.f + z * (1.f - 2.f * s));
+    float zb = Hbar[(int64_t)b * H + j] * d1;
+    for (int t = 0; t < nin; ++t) {
+        const int64_t r = (int64_t)(t + 1) * B + b;
+        const float tb = Hbar[r * H + j];
+        zb += tb * Z[r * H + j] * d2;
+        Zbar[r * H + j] = f2bf(tb * d1);
+    }
+    Zbar[(int64_t)b * H + j] = f2bf(zb);
+    ZbarP[(int64_t)b * H + j] = zb;
+}
+
+// out[j] = sum_b X[b*ld + j], b in order.
+__global__ void k_colsum(const float *__restrict__ X, int B, int ld, int ncols, float *__restrict__ out)
+{
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= ncols) return;
+    float s = 0.f;
+    for (int b = 0; b < B; ++b) s += X[(int64_t)b * ld + j];
+    out[j] = s;
+}
+
+// Layer-1 gradients: W1bar[t][j] = sum_b x_bt zbar_bj + sum_b ubar_t,bj, b1bar[j] = sum_b zbar_bj.
+__global__ void k_l1_bwd(const float *__restrict__ Hbar, const float *__restrict__ Z, const float *__restrict__ X,
+                         int B, int nin, int H, float *__restrict__ gW1, float *__restrict__ gb1)
+{
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (nin + 1) * H) return;
+    const int t = idx / H, j = idx % H;
+    float acc = 0.f;
+    for (int b = 0; b < B; ++b) {
+        const float z = Z[(int64_t)b * H + j];
+        const float s = sigm(z);
+        const float d1 = s * (1.f + z * (1.f - s));
+        const float d2 = s * (1.f - s) * (2.f + z * (1.f - 2.f * s));
+        float zb = Hbar[(int64_t)b * H + j] * d1;
+        for (int q = 0; q < nin; ++q) {
+            const int64_t r = (int64_t)(q + 1) * B + b;
+            zb += Hbar[r * H + j] * Z[r * H + j] * d2;
+        }
+        if (t < nin) acc += X[b * nin + t] * zb + Hbar[((int64_t)(t + 1) * B + b) * H + j] * d1;
+        else acc += zb;
+    }
+    if (t < nin) gW1[t * H + j] = acc;
+    else gb1[j] = acc;
+}
+
+__global__ void k_adam(float *__restrict__ p, const float *__restrict__ g, float *__restrict__ m,
+                       float *__restrict__ v, int64_t n, float lr, float b1, float b2, float eps, float bc1, float bc2)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.f - b1) * gi;
+    const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    p[i] -= lr * (mi / bc1) / (sqrtf(vi / bc2) + eps);
+}
+
+// bf16 copies of W [in x out]: WT [out_pad x in] (forward operand, k = in
+// contiguous) and Wb [in x out_pad] (backward operand, k = out contiguous).
+__global__ void k_refresh(const float *__restrict__ W, int in, int out, int out_pad, uint16_t *__restrict__ WT,
+                          uint16_t *__restrict__ Wb)
+{
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= in * out_pad) return;
+    const int i = idx / out_pad, o = idx % out_pad;
+    const uint16_t h = o < out ? f2bf(W[i * out + o]) : (uint16_t)0;
+    WT[(int64_t)o * in + i] = h;
+    Wb[(int64_t)i * out_pad + o] = h;
+}
+
+// Surrogate calibration functional per sample: r = y - C, G = 1/2 sum r^2,
+// grad_j = sum_i J_ij r_i (FP64; one workgroup per sample, fixed-order sums).
+__global__ __launch_bounds__(kThreads) void k_calib_grad(const float *__restrict__ Y, const float *__restrict__ J,
+                                                         const double *__restrict__ C, int nout, int nin,
+                                                         double *__restrict__ G, double *__restrict__ grad)
+{
+    __shared__ double r[kOutPad];
+    const int b = blockIdx.x;
+    const int t = threadIdx.x;
+    if (t < nout) r[t] = (double)Y[(int64_t)b * nout + t] - C[t];
+    __syncthreads();
+    if (t == 0) {
+        double s = 0.0;
+        for (int i = 0; i < nout; ++i) s += 0.5 * r[i] * r[i];
+        G[b] = s;
+    }
+    if (t < nin) {
+        double s = 0.0;
+        for (int i = 0; i < nout; ++i) s += (double)J[((int64_t)b * nout + i) * nin + t] * r[i];
+        grad[(int64_t)b * nin + t] = s;
+    }
+}
+
+__global__ void k_fill(float *p, int64_t n, float v)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+inline unsigned nb(int64_t n) { return (unsigned)((n + kThreads - 1) / kThreads); }
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// context and C ABI
+// ---------------------------------------------------------------------------
+struct mlp_ctx {
+    int nin = 0, H = 0, nout = 0, Bmax = 0;
+    int64_t np = 0;
+    int64_t off[8] = {0};
+    float *p = nullptr, *m = nullptr, *v = nullptr;
+    uint16_t *WT[4] = {nullptr}, *Wb[4] = {nullptr};   // layers 2..4 used
+    float *in_shift = nullptr, *in_scale = nullptr, *out_shift = nullptr, *out_scale = nullptr;
+    float *Z[5] = {nullptr};      // Z[1..3]: R x H, Z[4]: R x kOutPad
+    uint16_t *A[4] = {nullptr};   // A[1..3]: R x H
+    uint16_t *G4 = nullptr;       // R x kOutPad
+    float *Hbar = nullptr;        // R x H
+    uint16_t *Zbar = nullptr;     // R x H
+    float *ZbarP = nullptr;       // Bmax x H
+    float *Xn = nullptr;          // Bmax x nin
+    float *split = nullptr;       // kMaxSplits x H x H
+    double *lossp = nullptr;
+    std::vector<void *> allocs;
+    std::string err;
+};
+
+static thread_local std::string g_mlp_err;
+
+static int mfail(mlp_ctx *c, int code, const std::string &m)
+{
+    if (c) c->err = m;
+    g_mlp_err = m;
+    return code;
+}
+
+static hipError_t launch_gemm(bool akc, bool bkc, const uint16_t *A, int lda, const uint16_t *B, int ldb, float *C,
+                              int ldc, int M, int N, int K, int splits, hipStream_t st)
+{
+    const int ks = ((K + splits - 1) / splits + BK - 1) / BK * BK;
+    const dim3 grid(M / BM, N / BN, splits);
+    const int64_t ss = (int64_t)M * N;
+    if (akc && bkc) hipLaunchKernelGGL((k_gemm<true, true>), grid, dim3(kThreads), 0, st, A, lda, B, ldb, C, ldc, ss, K, ks);
+    else if (!akc && !bkc)
+        hipLaunchKernelGGL((k_gemm<false, false>), grid, dim3(kThreads), 0, st, A, lda, B, ldb, C, ldc, ss, K, ks);
+    else if (akc)
+        hipLaunchKernelGGL((k_gemm<true, false>), grid, dim3(kThreads), 0, st, A, lda, B, ldb, C, ldc, ss, K, ks);
+    else
+        hipLaunchKernelGGL((k_gemm<false, true>), grid, dim3(kThreads), 0, st, A, lda, B, ldb, C, ldc, ss, K, ks);
+    return hipGetLastError();
+}
+
+extern "C" int mlp_destroy(mlp_ctx *c)
+{
+    if (!c) return 0;
+    (void)hipDeviceSynchronize();
+    for (void *p : c->allocs) (void)hipFree(p);
+    delete c;
+    return 0;
+}
+
+extern "C" int mlp_create(int32_t n_in, int32_t n_hidden, int32_t n_out, int32_t max_batch, mlp_ctx **out)
+{
+    if (!out) return mfail(nullptr, -1, "null output pointer");
+    *out = nullptr;
+    if (n_in < 1 || n_in > 16) return mfail(nullptr, -1, "n_in must be in 1..16");
+    if (n_hidden < 128 || n_hidden > 1024 || n_hidden % 128)
+        return mfail(nullptr, -1, "n_hidden must be a multiple of 128 in 128..1024");
+    if (n_out < 1 || n_out > kOutPad) return mfail(nullptr, -1, "n_out must be in 1..64");
+    if (max_batch < 1 || max_batch > 65536) return mfail(nullptr, -1, "max_batch must be in 1..65536");
+    mlp_ctx *c = new mlp_ctx();
+    c->nin = n_in;
+    c->H = n_hidden;
+    c->nout = n_out;
+    c->Bmax = (max_batch + 127) / 128 * 128;
+    const int H = n_hidden;
+    const int64_t sizes[8] = {(int64_t)n_in * H, H, (int64_t)H * H, H, (int64_t)H * H, H, (int64_t)H * n_out, n_out};
+    int64_t o = 0;
+    for (int i = 0; i < 8; ++i) {
+        c->off[i] = o;
+        o += sizes[i];
+    }
+    c->np = o;
+    const int64_t R = (int64_t)(n_in + 1) * c->Bmax;
+    hipError_t e = hipSuccess;
+    auto A = [&](void **p, int64_t bytes) {
+        if (e != hipSuccess) return;
+        e = hipMalloc(p, (size_t)(bytes > 0 ? bytes : 16));
+        if (e == hipSuccess) c->allocs.push_back(*p);
+    };
+    A((void **)&c->p, 4 * c->np);
+    A((void **)&c->m, 4 * c->np);
+    A((void **)&c->v, 4 * c->np);
+    for (int l = 2; l <= 4; ++l) {
+        const int64_t opad = l == 4 ? kOutPad : H;
+        A((void **)&c->WT[l - 1], 2 * opad * H);
+        A((void **)&c->Wb[l - 1], 2 * opad * H);
+    }
+    A((void **)&c->in_shift, 4 * 16);
+    A((void **)&c->in_scale, 4 * 16);
+    A((void **)&c->out_shift, 4 * kOutPad);
+    A((void **)&c->out_scale, 4 * kOutPad);
+    for (int l = 1; l <= 3; ++l) {
+        A((void **)&c->Z[l], 4 * R * H);
+        A((void **)&c->A[l], 2 * R * H);
+    }
+    A((void **)&c->Z[4], 4 * R * kOutPad);
+    A((void **)&c->G4, 2 * R * kOutPad);
+    A((void **)&c->Hbar, 4 * R * H);
+    A((void **)&c->Zbar, 2 * R * H);
+    A((void **)&c->ZbarP, 4 * (int64_t)c->Bmax * H);
+    A((void **)&c->Xn, 4 * (int64_t)c->Bmax * n_in);
+    A((void **)&c->split, 4 * (int64_t)kMaxSplits * H * H);
+    A((void **)&c->lossp, 8 * (int64_t)((c->Bmax * kOutPad + kThreads - 1) / kThreads));
+    if (e != hipSuccess) {
+        mlp_destroy(c);
+        return mfail(nullptr, -2, std::string("allocation failed: ") + hipGetErrorString(e));
+    }
+    hipLaunchKernelGGL(k_fill, dim3(nb(c->np)), dim3(kThreads), 0, 0, c->p, c->np, 0.f);
+    hipLaunchKernelGGL(k_fill, dim3(nb(c->np)), dim3(kThreads), 0, 0, c->m, c->np, 0.f);
+    hipLaunchKernelGGL(k_fill, dim3(nb(c->np)), dim3(kThreads), 0, 0, c->v, c->np, 0.f);
+    hipLaunchKernelGGL(k_fill, dim3(1), dim3(kThreads), 0, 0, c->in_shift, (int64_t)16, 0.f);
+    hipLaunchKernelGGL(k_fill, dim3(1), dim3(kThreads), 0, 0, c->in_scale, (int64_t)16, 1.f);
+    hipLaunchKernelGGL(k_fill, dim3(1), dim3(kThreads), 0, 0, c->out_shift, (int64_t)kOutPad, 0.f);
+    hipLaunchKernelGGL(k_fill, dim3(1), dim3(kThreads), 0, 0, c->out_scale, (int64_t)kOutPad, 1.f);
+    for (int l = 2; l <= 4; ++l) {
+        const int opad = l == 4 ? kOutPad : H;
+        const int outd = l == 4 ? n_out : H;
+        hipLaunchKernelGGL(k_refresh, dim3(nb((int64_t)H * opad)), dim3(kThreads), 0, 0, c->p + c->off[2 * (l - 1)],
+                           H, outd, opad, c->WT[l - 1], c->Wb[l - 1]);
+    }
+    e = hipDeviceSynchronize();
+    if (e != hipSuccess) {
+        mlp_destroy(c);
+        return mfail(nullptr, -3, std::string("initialisation failed: ") + hipGetErrorString(e));
+    }
+    *out = c;
+    return 0;
+}
+
+extern "C" int64_t mlp_num_params(const mlp_ctx *c) { return c ? c->np : -1; }
+
+static hipError_t refresh_all(mlp_ctx *c, hipStream_t st)
+{
+    for (int l = 2; l <= 4; ++l) {
+        const int opad = l == 4 ? kOutPad : c->H;
+        const int outd = l == 4 ? c->nout : c->H;
+        hipLaunchKernelGGL(k_refresh, dim3(nb((int64_t)c->H * opad)), dim3(kThreads), 0, st, c->p + c->off[2 * (l - 1)],
+                           c->H, outd, opad, c->WT[l - 1], c->Wb[l - 1]);
+    }
+    return hipGetLastError();
+}
+
+extern "C" int mlp_set_params(mlp_ctx *c, const float *d_params, void *stream)
+{
+    if (!c || !d_params) return mfail(c, -1, "null argument");
+    hipStream_t st = (hipStream_t)stream;
+    hipError_t e = hipMemcpyAsync(c->p, d_params, 4 * c->np, hipMemcpyDeviceToDevice, st);
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(k_fill, dim3(nb(c->np)), dim3(kThreads), 0, st, c->m, c->np, 0.f);
+        hipLaunchKernelGGL(k_fill, dim3(nb(c->np)), dim3(kThreads), 0, st, c->v, c->np, 0.f);
+        e = refresh_all(c, st);
+    }
+    return e == hipSuccess ? 0 : mfail(c, -3, hipGetErrorString(e));
+}
+
+extern "C" int mlp_get_params(const mlp_ctx *c, float *d_params, void *stream)
+{
+    if (!c || !d_params) return mfail(nullptr, -1, "null argument");
+    hipError_t e = hipMemcpyAsync(d_params, c->p, 4 * c->np, hipMemcpyDeviceToDevice, (hipStream_t)stream);
+    return e == hipSuccess ? 0 : mfail(nullptr, -3, hipGetErrorString(e));
+}
+
+extern "C" int mlp_set_scaling(mlp_ctx *c, const float *d_in_shift, const float *d_in_scale, const float *d_out_shift,
+                               const float *d_out_scale, void *stream)
+{
+    if (!c || !d_in_shift || !d_in_scale || !d_out_shift || !d_out_scale) return mfail(c, -1, "null argument");
+    hipStream_t st = (hipStream_t)stream;
+    hipError_t e = hipMemcpyAsync(c->in_shift, d_in_shift, 4 * c->nin, hipMemcpyDeviceToDevice, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(c->in_scale, d_in_scale, 4 * c->nin, hipMemcpyDeviceToDevice, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(c->out_shift, d_out_shift, 4 * c->nout, hipMemcpyDeviceToDevice, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(c->out_scale, d_out_scale, 4 * c->nout, hipMemcpyDeviceToDevice, st);
+    return e == hipSuccess ? 0 : mfail(c, -3, hipGetErrorString(e));
+}
+
+// Forward over Bp rows of normalised inputs already in c->Xn.
+static hipError_t forward_core(mlp_ctx *c, int Bp, hipStream_t st)
+{
+    const int H = c->H, nin = c->nin;
+    const int R = (nin + 1) * Bp;
+    const float *p = c->p;
+    hipLaunchKernelGGL(k_l1_fwd, dim3(nb((int64_t)Bp * H)), dim3(kThreads), 0, st, c->Xn, p + c->off[0], p + c->off[1],
+                       Bp, nin, H, c->Z[1], c->A[1]);
+    hipError_t e = hipGetLastError();
+    for (int l = 2; l <= 3 && e == hipSuccess; ++l) {
+        e = launch_gemm(true, true, c->A[l - 1], H, c->WT[l - 1], H, c->Z[l], H, R, H, H, 1, st);
+        if (e != hipSuccess) break;
+        hipLaunchKernelGGL(k_act_fwd, dim3(nb((int64_t)Bp * H)), dim3(kThreads), 0, st, c->Z[l], p + c->off[2 * l - 1],
+                           Bp, nin, H, c->A[l]);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = launch_gemm(true, true, c->A[3], H, c->WT[3], H, c->Z[4], kOutPad, R, kOutPad, H, 1, st);
+    return e;
+}
+
+extern "C" int mlp_forward(mlp_ctx *c, const float *d_theta, int32_t B, float *d_Y, float *d_J, void *stream)
+{
+    if (!c || !d_theta || !d_Y || !d_J) return mfail(c, -1, "null argument");
+    if (B < 1 || B > c->Bmax) return mfail(c, -1, "batch outside 1..max_batch");
+    hipStream_t st = (hipStream_t)stream;
+    const int Bp = (B + 127) / 128 * 128;
+    hipLaunchKernelGGL(k_normalize, dim3(nb((int64_t)Bp * c->nin)), dim3(kThreads), 0, st, d_theta, B, Bp, c->nin,
+                       c->in_shift, c->in_scale, c->Xn);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = forward_core(c, Bp, st);
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(k_out_fwd, dim3(nb((int64_t)B * c->nout)), dim3(kThreads), 0, st, c->Z[4],
+                           c->p + c->off[7], B, Bp, c->nin, c->nout, c->in_scale, c->out_shift, c->out_scale, d_Y, d_J);
+        e = hipGetLastError();
+    }
+    return e == hipSuccess ? 0 : mfail(c, -3, hipGetErrorString(e));
+}
+
+extern "C" int mlp_loss_grad(mlp_ctx *c, const float *d_theta, const float *d_Ylab, const float *d_Jlab, int32_t B,
+                             float w, double *d_loss, float *d_grad, void *stream)
+{
+    if (!c || !d_theta || !d_Ylab || !d_Jlab || !d_loss || !d_grad) return mfail(c, -1, "null argument");
+    if (B < 128 || B > c->Bmax || B % 128) return mfail(c, -1, "training batch must be a multiple of 128 up to max_batch");
+    hipStream_t st = (hipStream_t)stream;
+    const int H = c->H, nin = c->nin, R = (nin + 1) * B;
+    float *g = d_grad;
+    hipLaunchKernelGGL(k_normalize, dim3(nb((int64_t)B * nin)), dim3(kThreads), 0, st, d_theta, B, B, nin, c->in_shift,
+                       c->in_scale, c->Xn);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = forward_core(c, B, st);
+    if (e != hipSuccess) return mfail(c, -3, hipGetErrorString(e));
+    // loss and the output-layer adjoint
+    const unsigned nlb = nb((int64_t)B * kOutPad);
+    hipLaunchKernelGGL(k_loss, dim3(nlb), dim3(kThreads), 0, st, c->Z[4], c->p + c->off[7], d_Ylab, d_Jlab, B, nin,
+                       c->nout, w, c->in_scale, c->out_shift, c->out_scale, c->G4, c->ZbarP, c->lossp);
+    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(64), 0, st, c->lossp, (int)nlb, d_loss);
+    hipLaunchKernelGGL(k_colsum, dim3(1), dim3(kThreads), 0, st, c->ZbarP, B, kOutPad, c->nout, g + c->off[7]);
+    // output layer: W4bar = A3^T G4 (split over rows), H3bar = G4 W4^T
+    const int S = std::min(kMaxSplits, std::max(1, R / 512));
+    e = launch_gemm(false, false, c->A[3], H, c->G4, kOutPad, c->split, kOutPad, H, kOutPad, R, S, st);
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(k_split_reduce, dim3(nb((int64_t)H * c->nout)), dim3(kThreads), 0, st, c->split, S, H, kOutPad,
+                           g + c->off[6], c->nout, c->nout);
+        e = launch_gemm(true, true, c->G4, kOutPad, c->Wb[3], kOutPad, c->Hbar, H, R, H, kOutPad, 1, st);
+    }
+    // hidden layers 3 and 2
+    for (int l = 3; l >= 2 && e == hipSuccess; --l) {
+        hipLaunchKernelGGL(k_act_bwd, dim3(nb((int64_t)B * H)), dim3(kThreads), 0, st, c->Hbar, c->Z[l], B, nin, H,
+                           c->Zbar, c->ZbarP);
+        hipLaunchKernelGGL(k_colsum, dim3(nb(H)), dim3(kThreads), 0, st, c->ZbarP, B, H, H, g + c->off[2 * l - 1]);
+        e = launch_gemm(false, false, c->A[l - 1], H, c->Zbar, H, c->split, H, H, H, R, S, st);
+        if (e != hipSuccess) break;
+        hipLaunchKernelGGL(k_split_reduce, dim3(nb((int64_t)H * H)), dim3(kThreads), 0, st, c->split, S, H, H,
+                           g + c->off[2 * l - 2], H, H);
+        e = launch_gemm(true, true, c->Zbar, H, c->Wb[l - 1], H, c->Hbar, H, R, H, H, 1, st);
+    }
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(k_l1_bwd, dim3(nb((int64_t)(nin + 1) * H)), dim3(kThreads), 0, st, c->Hbar, c->Z[1], c->Xn,
+                           B, nin, H, g + c->off[0], g + c->off[1]);
+        e = hipGetLastError();
+    }
+    return e == hipSuccess ? 0 : mfail(c, -3, hipGetErrorString(e));
+}
+
+extern "C" int mlp_adam_step(mlp_ctx *c, const float *d_grad, float lr, float beta1, float beta2, float eps, int32_t t,
+                             void *stream)
+{
+    if (!c || !d_grad) return mfail(c, -1, "null argument");
+    if (t < 1) return mfail(c, -1, "Adam step count starts at 1");
+    hipStream_t st = (hipStream_t)stream;
+    const float bc1 = 1.f - std::pow(beta1, (float)t), bc2 = 1.f - std::pow(beta2, (float)t);
+    hipLaunchKernelGGL(k_adam, dim3(nb(c->np)), dim3(kThreads), 0, st, c->p, d_grad, c->m, c->v, c->np, lr, beta1,
+                       beta2, eps, bc1, bc2);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = refresh_all(c, st);
+    return e == hipSuccess ? 0 : mfail(c, -3, hipGetErrorString(e));
+}
+
+extern "C" int mlp_calibration_gradient(mlp_ctx *c, const float *d_theta, int32_t B, const double *d_C, float *d_Y,
+                                        float *d_J, double *d_G, double *d_grad, void *stream)
+{
+    int rc = mlp_forward(c, d_theta, B, d_Y, d_J, stream);
+    if (rc) return rc;
+    if (!d_C || !d_G || !d_grad) return mfail(c, -1, "null argument");
+    hipLaunchKernelGGL(k_calib_grad, dim3((unsigned)B), dim3(kThreads), 0, (hipStream_t)stream, d_Y, d_J, d_C, c->nout,
+                       c->nin, d_G, d_grad);
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? 0 : mfail(c, -3, hipGetErrorString(e));
+}
+
+extern "C" const char *mlp_last_error(const mlp_ctx *c) { return c ? c->err.c_str() : g_mlp_err.c_str(); }

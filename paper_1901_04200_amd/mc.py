@@ -15,13 +15,14 @@ class MonteCarloCalibration:
     on one problem.  theta, targets and lambda are FP64 tensors of the
     current device (host arrays are copied there)."""
 
-    def __init__(self, problem, precision: str = "fp32", ckpt_every: int = 0, ckpt_mode: str = "auto"):
+    def __init__(self, problem, precision: str = "fp32", ckpt_every: int = 0, ckpt_mode: str = "auto",
+                 max_batch: int = 0):
         if not torch.cuda.is_available():
             raise RuntimeError("the Monte Carlo calibration path needs a HIP device")
         self.problem = problem
         self.precision = precision
         self.device = torch.device("cuda", torch.cuda.current_device())
-        self.ctx = capi.cal_create(problem, _PREC[precision], ckpt_every, _MODE[ckpt_mode])
+        self.ctx = capi.cal_create(problem, _PREC[precision], ckpt_every, _MODE[ckpt_mode], max_batch)
         self.m = int(len(problem.instr_step))
         self.M = int(problem.n_params)
 

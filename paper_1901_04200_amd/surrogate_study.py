@@ -1,0 +1,126 @@
+"""The surrogate against the plain Monte Carlo adjoint step, on one GPU.
+
+  1. labels: E y and dE y/dtheta for n_train parameter draws (each draw its
+     own Philox instance), by the Monte Carlo tangent kernel;
+  2. training: the differential loss, bf16 MFMA kernels, Adam;
+  3. accuracy: on held-out draws, the surrogate's gradient of
+     G = 1/2 |y - C|^2 against a Monte Carlo reference gradient at
+     ref_paths paths gives eps_s (median relative error);
+  4. the Monte Carlo gradient's own error at P paths (independent seeds)
+     falls like P^-1/2; P* is where it equals eps_s;
+  5. cost of one gradient step: surrogate (network forward, batch 1) vs the
+     Monte Carlo adjoint (calibrate_gradient) at P* paths.
+Everything is on the Feller-satisfying part of the Heston box, where the
+pathwise gradient is well conditioned.
+"""
+from __future__ import annotations
+
+import math
+import time
+
+import numpy as np
+
+from . import capi
+from . import surrogate as S
+from . import workloads as W
+from .mc import MonteCarloCalibration
+
+
+def _time_call(fn, reps):
+    import torch
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / reps
+
+
+def run(n_train=1 << 14, train_paths=1 << 14, n_heldout=32, ref_paths=1 << 20, epochs=200, batch=4096,
+        lr=2e-3, lr_final=5e-5, w=1.0, seeds_mc=8, log=print):
+    import torch
+    out = {}
+    pb, th0, tht, eps = W.heston_problem()
+    lo, hi = W.HESTON_LO, W.HESTON_HI
+
+    # ---- 1. labels -------------------------------------------------------
+    draws = W.surrogate_draws(n_train, rng_seed=6)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    Ey, J = S.generate_labels(pb, draws, n_paths=train_paths, seed=4, chunk=256)
+    torch.cuda.synchronize()
+    t_lab = time.perf_counter() - t0
+    out["labels"] = {"draws": n_train, "paths_per_draw": train_paths, "seconds": t_lab,
+                     "path_steps_per_s": n_train * train_paths * pb.n_steps / t_lab}
+    log(f"surrogate: labels for {n_train} draws x {train_paths} paths in {t_lab:.2f} s")
+
+    # ---- 2. training -----------------------------------------------------
+    net = S.MLP(5, 256, pb.n_instr, max_batch=batch)
+    net.init_params(0)
+    sh, sc, mu, sd = S.standard_scaling(lo, hi, Ey.cpu().numpy())
+    net.set_scaling(sh, sc, mu, sd)
+    thd = torch.as_tensor(draws, dtype=torch.float32, device="cuda")
+    t0 = time.perf_counter()
+    hist = S.fit(net, thd, Ey.float(), J.float(), epochs=epochs, batch=min(batch, n_train), lr=lr,
+                 lr_final=lr_final, w=w, log_every=max(1, epochs // 10))
+    t_fit = time.perf_counter() - t0
+    out["training"] = {"epochs": epochs, "seconds": t_fit, "loss_first": hist[0].loss, "loss_last": hist[-1].loss,
+                       "steps": epochs * (n_train // min(batch, n_train))}
+    log(f"surrogate: {epochs} epochs in {t_fit:.2f} s, loss {hist[0].loss:.4g} -> {hist[-1].loss:.4g}")
+
+    # ---- 3. accuracy on held-out draws -------------------------------------
+    # targets: prices at the target draw (seed 2) plus 0.1 % noise
+    gen = MonteCarloCalibration(pb.with_(seed=2))
+    C = torch.as_tensor(W.noisy_targets(gen.forward(tht).cpu().numpy(), eps), device="cuda")
+    gen.close()
+    ho = W.heston_feller_draws(99, n_heldout)
+    ref = MonteCarloCalibration(pb.with_(n_paths=ref_paths, seed=7))
+    g_ref = []
+    for th in ho:
+        _, _, g = ref.gradient(th, C)
+        g_ref.append(g.cpu().numpy())
+    ref.close()
+    g_ref = np.array(g_ref)
+    _, g_s = net.calibration_gradient(torch.as_tensor(ho, dtype=torch.float32, device="cuda"), C)
+    g_s = g_s.cpu().numpy()
+    err_s = np.linalg.norm(g_s - g_ref, axis=1) / np.linalg.norm(g_ref, axis=1)
+    eps_s = float(np.median(err_s))
+    out["surrogate_grad_rel_err"] = {"median": eps_s, "p90": float(np.quantile(err_s, 0.9)),
+                                     "heldout": n_heldout, "ref_paths": ref_paths}
+    log(f"surrogate: held-out gradient error median {eps_s:.3g} (vs MC at {ref_paths} paths)")
+
+    # ---- 4. Monte Carlo gradient error vs paths -----------------------------
+    curve = []
+    for lp in range(10, 19, 2):
+        P = 1 << lp
+        errs = []
+        for s in range(seeds_mc):
+            mc = MonteCarloCalibration(pb.with_(n_paths=P, seed=1000 + s))
+            for k in range(min(8, n_heldout)):
+                _, _, g = mc.gradient(ho[k], C)
+                errs.append(np.linalg.norm(g.cpu().numpy() - g_ref[k]) / np.linalg.norm(g_ref[k]))
+            mc.close()
+        curve.append((P, float(np.median(errs))))
+    out["mc_grad_rel_err_vs_paths"] = curve
+    # fit err = a P^-1/2 on the curve, solve for eps_s
+    a = float(np.median([e * math.sqrt(P) for P, e in curve]))
+    p_star = max(1, int(round((a / eps_s) ** 2)))
+    out["p_star"] = p_star
+    log(f"surrogate: MC gradient error ~ {a:.3g}/sqrt(P); equal to eps_s at P* = {p_star}")
+
+    # ---- 5. step costs ------------------------------------------------------
+    th1 = torch.as_tensor(ho[:1], dtype=torch.float32, device="cuda")
+
+    def sur_step():
+        net.calibration_gradient(th1, C)
+
+    t_sur = _time_call(sur_step, 50)
+    P_time = max(256, p_star)
+    mcs = MonteCarloCalibration(pb.with_(n_paths=P_time))
+    t_mc = _time_call(lambda: mcs.gradient(ho[0], C), 20)
+    mcs.close()
+    out["step_seconds"] = {"surrogate": t_sur, "mc_at_p_star": t_mc, "p_star_paths_timed": P_time,
+                           "mc_over_surrogate": t_mc / t_sur}
+    log(f"surrogate: step {t_sur * 1e6:.1f} us vs MC adjoint at {P_time} paths {t_mc * 1e6:.1f} us")
+    net.close()
+    return out

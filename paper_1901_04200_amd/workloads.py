@@ -152,7 +152,20 @@ def lv_problem(n_paths: int = 1 << 22, seed: int = 1, n_steps: int = 256, t_max:
 # Surrogate training set: uniform draws in the Heston box
 # --------------------------------------------------------------------------
 def surrogate_draws(n: int, rng_seed: int = 6) -> np.ndarray:
-    return heston_draws(rng_seed, n)
+    return heston_feller_draws(rng_seed, n)
+
+
+def heston_feller_draws(rng_seed: int, n: int) -> np.ndarray:
+    """Uniform draws on the part of the Heston box where Feller's condition
+    2 kappa theta_bar >= xi^2 holds (rejection from uniform box draws, in
+    the generator's order)."""
+    rng = np.random.default_rng(rng_seed)
+    out = []
+    while len(out) < n:
+        d = HESTON_LO + (HESTON_HI - HESTON_LO) * rng.random((max(4 * n, 64), 5))
+        d = d[2.0 * d[:, 0] * d[:, 1] >= d[:, 2] ** 2]
+        out.extend(d[: n - len(out)])
+    return np.array(out)
 
 
 # --------------------------------------------------------------------------

@@ -16,9 +16,13 @@ HEADER = os.path.join(ROOT, "include", "mcaad.h")
 
 
 def _declared():
-    text = open(HEADER).read()
-    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"^\s*(?:const\s+)?\w+\s*\*?\s*(\w+)\s*\(", text, flags=re.M)))
+    names = set()
+    for h in sorted(os.listdir(os.path.join(ROOT, "include"))):
+        if h.endswith(".h"):
+            text = open(os.path.join(ROOT, "include", h)).read()
+            text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+            names |= set(re.findall(r"^\s*(?:const\s+)?\w+\s*\*?\s*(\w+)\s*\(", text, flags=re.M))
+    return sorted(names)
 
 
 @pytest.fixture(scope="module")
@@ -29,8 +33,9 @@ def L():
 
 
 def test_header_declarations_are_exported(L):
+    from paper_1901_04200_amd import surrogate
     names = _declared()
-    assert set(names) == set(capi.EXPORTED), names
+    assert set(names) == set(capi.EXPORTED) | set(surrogate.EXPORTED), names
     out = subprocess.run(["nm", "-D", "--defined-only", capi.LIB_PATH], capture_output=True, text=True,
                          check=True).stdout
     exported = {l.split()[-1] for l in out.splitlines() if l.strip()}

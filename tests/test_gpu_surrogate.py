@@ -1,0 +1,197 @@
+"""GPU parity of the surrogate kernels against the FP64 MLP oracle, and of
+its training labels against the FP64 Monte Carlo oracle.
+
+Tolerance (derived from the arithmetic): the oracle is given the device's
+bf16-rounded weights, so the remaining difference is the bf16 rounding of
+activations and adjoints where they enter the products (relative 2^-9 per
+rounding, a few roundings deep) plus FP32 accumulation: outputs within
+2e-2 of their largest magnitude, weight gradients within 5e-2 in relative
+norm per parameter block.  Labels (FP32 Monte Carlo) follow the Monte Carlo
+bounds: 1e-5 on prices, 1e-4 on the Jacobian.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import mlp_oracle as MO
+from paper_1901_04200_amd import surrogate as S
+from paper_1901_04200_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+
+
+def bf16(x):
+    u = np.asarray(x, np.float32).copy().view(np.uint32)
+    u = (u + np.uint32(0x7FFF) + ((u >> np.uint32(16)) & np.uint32(1))) & np.uint32(0xFFFF0000)
+    return u.view(np.float32).astype(np.float64)
+
+
+def rand_params(sizes, seed):
+    rng = np.random.default_rng(seed)
+    ps = []
+    for a, c in zip(sizes[:-1], sizes[1:]):
+        lim = np.sqrt(6.0 / a)
+        ps.append((rng.uniform(-lim, lim, (a, c)).astype(np.float32), rng.normal(0, 0.1, c).astype(np.float32)))
+    return ps
+
+
+def device_view(params):
+    """The weights the device multiplies with: bf16 copies of W (first layer
+    and biases stay FP32)."""
+    out = []
+    for l, (Wt, b) in enumerate(params):
+        out.append((Wt.astype(np.float64) if l == 0 else bf16(Wt), b.astype(np.float64)))
+    return out
+
+
+@pytest.mark.parametrize("H,nout,B", [(128, 7, 128), (128, 7, 5), (256, 40, 4096)])
+def test_forward_and_jacobian(H, nout, B):
+    say(f"mlp forward H={H} n_out={nout} B={B}")
+    net = S.MLP(5, H, nout, max_batch=max(B, 128))
+    params = rand_params([5, H, H, H, nout], 1)
+    net.set_params(net.pack(params))
+    X = np.random.default_rng(2).uniform(-1, 1, (B, 5)).astype(np.float32)
+    Y, J = net.forward(torch.as_tensor(X, device="cuda"))
+    Y, J = Y.cpu().numpy(), J.cpu().numpy()
+    Yo, Jo = MO.forward_tangent(device_view(params), X.astype(np.float64))
+    ey = np.max(np.abs(Y - Yo)) / np.max(np.abs(Yo))
+    ej = np.max(np.abs(J - Jo)) / np.max(np.abs(Jo))
+    say(f"  rel err Y {ey:.2e} J {ej:.2e}")
+    assert ey < 2e-2 and ej < 2e-2
+    net.close()
+
+
+def test_scaling_maps_units():
+    net = S.MLP(5, 128, 7, max_batch=128)
+    params = rand_params([5, 128, 128, 128, 7], 3)
+    net.set_params(net.pack(params))
+    lo, hi = W.HESTON_LO, W.HESTON_HI
+    shift, scale = (lo + hi) / 2, 2 / (hi - lo)
+    oshift, oscale = np.linspace(1, 7, 7), np.linspace(0.5, 2, 7)
+    net.set_scaling(shift, scale, oshift, oscale)
+    th = W.heston_draws(9, 128).astype(np.float32)
+    Y, J = net.forward(torch.as_tensor(th, device="cuda"))
+    Yo, Jo = MO.forward_tangent(device_view(params), (th.astype(np.float64) - shift) * scale)
+    Yo = Yo * oscale + oshift
+    Jo = Jo * oscale[None, :, None] * scale[None, None, :]
+    assert np.max(np.abs(Y.cpu().numpy() - Yo)) < 2e-2 * np.max(np.abs(Yo))
+    assert np.max(np.abs(J.cpu().numpy() - Jo)) < 2e-2 * np.max(np.abs(Jo))
+    net.close()
+
+
+@pytest.mark.parametrize("H,nout,B", [(128, 7, 256), (256, 40, 4096)])
+def test_loss_and_double_backprop(H, nout, B):
+    say(f"mlp loss/grad H={H} n_out={nout} B={B}")
+    net = S.MLP(5, H, nout, max_batch=B)
+    params = rand_params([5, H, H, H, nout], 5)
+    net.set_params(net.pack(params))
+    rng = np.random.default_rng(6)
+    X = rng.uniform(-1, 1, (B, 5)).astype(np.float32)
+    Yl = rng.normal(0, 1, (B, nout)).astype(np.float32)
+    Jl = rng.normal(0, 1, (B, nout, 5)).astype(np.float32)
+    w = 0.8
+    loss, grad = net.loss_grad(*(torch.as_tensor(a, device="cuda") for a in (X, Yl, Jl)), w)
+    L, go = MO.grads(device_view(params), X.astype(np.float64), Yl.astype(np.float64), Jl.astype(np.float64), w)
+    say(f"  loss gpu {loss.item():.6g} oracle {L:.6g}")
+    assert abs(loss.item() - L) < 2e-2 * L
+    gg = net.unpack(grad.cpu().numpy())
+    for l in range(4):
+        for k in range(2):
+            a, b = gg[l][k], go[l][k]
+            e = np.linalg.norm(a - b) / np.linalg.norm(b)
+            say(f"  layer {l + 1} {'W' if k == 0 else 'b'} rel err {e:.2e}")
+            assert e < 5e-2, (l, k, e)
+    net.close()
+
+
+def test_adam_step_matches_reference():
+    net = S.MLP(5, 128, 7, max_batch=128)
+    params = rand_params([5, 128, 128, 128, 7], 8)
+    p0 = net.pack(params)
+    net.set_params(p0)
+    rng = np.random.default_rng(9)
+    m = np.zeros_like(p0, dtype=np.float64)
+    v = np.zeros_like(p0, dtype=np.float64)
+    p = p0.astype(np.float64)
+    lr, b1, b2, eps = 1e-3, 0.9, 0.999, 1e-8
+    for t in range(1, 4):
+        g = rng.normal(0, 1, p0.size).astype(np.float32)
+        net.adam_step(torch.as_tensor(g, device="cuda"), lr, b1, b2, eps)
+        m = b1 * m + (1 - b1) * g
+        v = b2 * v + (1 - b2) * g.astype(np.float64) ** 2
+        p = p - lr * (m / (1 - b1 ** t)) / (np.sqrt(v / (1 - b2 ** t)) + eps)
+    np.testing.assert_allclose(net.get_params(), p, rtol=1e-5, atol=1e-7)
+    net.close()
+
+
+def test_calibration_gradient_kernel():
+    """G = 1/2 |y - C|^2 and J^T (y - C) from the network's own outputs."""
+    net = S.MLP(5, 128, 7, max_batch=128)
+    net.set_params(net.pack(rand_params([5, 128, 128, 128, 7], 4)))
+    th = torch.as_tensor(np.random.default_rng(5).uniform(-1, 1, (9, 5)), dtype=torch.float32, device="cuda")
+    C = torch.linspace(-1.0, 1.0, 7, dtype=torch.float64, device="cuda")
+    G, g = net.calibration_gradient(th, C)
+    Y, J = net.forward(th)
+    r = Y.double().cpu().numpy() - C.cpu().numpy()
+    np.testing.assert_allclose(G.cpu().numpy(), 0.5 * np.sum(r * r, axis=1), rtol=1e-12)
+    np.testing.assert_allclose(g.cpu().numpy(), np.einsum("bij,bi->bj", J.double().cpu().numpy(), r), rtol=1e-10,
+                               atol=1e-12)
+    net.close()
+
+
+def test_labels_match_oracle_jacobian(orc):
+    """calibrate_jacobian_batch on 4 draws (own Philox instance each) against
+    the oracle's tangent mode with the same streams."""
+    pb, _, _, _ = W.heston_problem(n_paths=1 << 14)
+    draws = W.heston_feller_draws(6, 4)
+    Ey, J = S.generate_labels(pb, draws, n_paths=1 << 14, seed=4, inst0=100, chunk=4)
+    Ey, J = Ey.cpu().numpy(), J.cpu().numpy()
+    Ey64, J64 = S.generate_labels(pb, draws, n_paths=1 << 14, seed=4, inst0=100, chunk=4, precision="fp64")
+    Ey64, J64 = Ey64.cpu().numpy(), J64.cpu().numpy()
+    n_checked = 0
+    for i, th in enumerate(draws):
+        sub = pb.with_(seed=4, inst=100 + i)
+        Eo, Jo, _, dyp = orc.jacobian(sub, th, per_path=True)
+        # conditioning: the largest share of one path in any Jacobian column
+        col = dyp.sum(axis=1)
+        share = float(np.max(np.abs(col).max(0) / np.abs(col.sum(0))))
+        ey = np.max(np.abs(Ey[i] - Eo) / np.maximum(np.abs(Eo), 1e-2))
+        ej = np.max(np.abs(J[i] - Jo)) / np.max(np.abs(Jo))
+        ej64 = np.max(np.abs(J64[i] - Jo)) / np.max(np.abs(Jo))
+        say(f"  draw {i}: one-path share {share:.3f}; fp32 Ey {ey:.2e} J {ej:.2e}; fp64 J {ej64:.2e}")
+        assert np.max(np.abs(Ey64[i] - Eo) / np.maximum(np.abs(Eo), 1e-2)) <= 1e-12
+        assert ej64 <= 1e-9
+        assert ey <= 1e-5
+        if share <= 0.05:
+            assert ej <= 1e-4
+            n_checked += 1
+    assert n_checked >= 2
+
+
+def test_training_reduces_loss():
+    """A short fit on Monte Carlo labels lowers the differential loss."""
+    pb, _, _, _ = W.heston_problem(n_paths=1 << 12)
+    draws = W.heston_feller_draws(12, 1024)
+    Ey, J = S.generate_labels(pb, draws, n_paths=1 << 12, seed=4, chunk=256)
+    net = S.MLP(5, 256, 40, max_batch=512)
+    net.init_params(0)
+    sh, sc, mu, sd = S.standard_scaling(W.HESTON_LO, W.HESTON_HI, Ey.cpu().numpy())
+    net.set_scaling(sh, sc, mu, sd)
+    th = torch.as_tensor(draws, dtype=torch.float32, device="cuda")
+    hist = S.fit(net, th, Ey.float(), J.float(), epochs=30, batch=512, lr=2e-3, w=0.1)
+    say(f"  loss {hist[0].loss:.4g} -> {hist[-1].loss:.4g}")
+    assert hist[-1].loss < 0.1 * hist[0].loss
+    net.close()
