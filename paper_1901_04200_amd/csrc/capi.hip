@@ -58,6 +58,7 @@ struct cal_ctx {
     double *d_part_j = nullptr;
     void *d_lamD = nullptr;
     void *d_ckpt = nullptr;
+    double *d_t_nodes = nullptr;
     // timing
     bool timing = false;
     std::vector<TimedPair> timed;
@@ -103,8 +104,19 @@ static std::string validate(const cal_problem *pb, int *code)
     if (pb->model == CAL_HESTON && pb->n_params != 5) return "Heston takes n_params = 5";
     if (pb->model == CAL_BS && pb->sqrt_eps != 0.0) return "sqrt_eps applies to Heston only";
     if (pb->model == CAL_LV) {
-        *code = CAL_EUNSUPPORTED;
-        return "the local-volatility model has no device path in this library";
+        if (pb->sqrt_eps != 0.0) return "sqrt_eps applies to Heston only";
+        const int nT = pb->n_t_nodes, nK = pb->n_k_nodes;
+        if (nT < 2 || nK < 2 || nT > 64 || nK > 64) return "local vol needs 2..64 time and spot nodes";
+        if (!pb->t_nodes || !pb->k_nodes) return "null node arrays";
+        if (pb->n_params != nT * nK) return "local vol takes n_params = n_t_nodes * n_k_nodes";
+        for (int a = 0; a < nT; ++a)
+            if (!std::isfinite(pb->t_nodes[a]) || (a > 0 && !(pb->t_nodes[a] > pb->t_nodes[a - 1])))
+                return "t_nodes must be finite and increasing";
+        const double K0 = pb->k_nodes[0], dK = (pb->k_nodes[nK - 1] - K0) / (nK - 1);
+        if (!std::isfinite(K0) || !(dK > 0.0) || !std::isfinite(dK)) return "k_nodes must be finite and increasing";
+        for (int k = 0; k < nK; ++k)
+            if (std::fabs(pb->k_nodes[k] - (K0 + k * dK)) > 1e-9 * (std::fabs(K0) + nK * dK))
+                return "k_nodes must be uniformly spaced";
     }
     *code = CAL_OK;
     return "";
@@ -131,7 +143,8 @@ extern "C" int cal_destroy(cal_ctx *ctx)
     if (!ctx) return CAL_OK;
     (void)hipDeviceSynchronize();
     void *bufs[] = {ctx->d_date_step, ctx->d_date_begin, ctx->d_strike, ctx->d_strike_f, ctx->d_disc, ctx->d_id,
-                    ctx->d_status, ctx->d_part_y, ctx->d_part_g, ctx->d_part_j, ctx->d_lamD, ctx->d_ckpt};
+                    ctx->d_status, ctx->d_part_y, ctx->d_part_g, ctx->d_part_j, ctx->d_lamD, ctx->d_ckpt,
+                    ctx->d_t_nodes};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
     for (auto &t : ctx->timed) {
@@ -192,7 +205,24 @@ extern "C" int cal_create(const cal_problem *pb, cal_ctx **out)
     date_begin.push_back(m);
     const int nd = (int)date_step.size();
 
-    const size_t tan_w = (size_t)m * (c->M + 1);
+    // tangent mode serves Black-Scholes and Heston (labels); not the local-vol grid
+    const size_t tan_w = c->model == CAL_LV ? 0 : (size_t)m * (c->M + 1);
+    if (c->model == CAL_LV) {
+        DevProblem probe{};
+        probe.N = c->N;
+        probe.m = m;
+        probe.nT = pb->n_t_nodes;
+        probe.nK = pb->n_k_nodes;
+        int max_lds = 0;
+        (void)hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, c->device);
+        const size_t need = std::max(lv_lds_bytes(probe, c->fp64, 1), lv_lds_bytes(probe, c->fp64, 2));
+        if (need > (size_t)max_lds) {
+            delete c;
+            return fail(nullptr, CAL_EUNSUPPORTED,
+                        "local vol grid x steps too large for one workgroup's LDS (" + std::to_string(need) + " > " +
+                            std::to_string(max_lds) + " bytes)");
+        }
+    }
     hipError_t e = hipSuccess;
     auto A = [&](void **p, size_t bytes) {
         if (e == hipSuccess) e = alloc(p, bytes);
@@ -208,6 +238,7 @@ extern "C" int cal_create(const cal_problem *pb, cal_ctx **out)
     A((void **)&c->d_part_g, sizeof(double) * (size_t)c->nblocks * c->M);
     A((void **)&c->d_part_j, sizeof(double) * (size_t)c->nblocks * tan_w * c->max_batch);
     A(&c->d_lamD, c->real * m);
+    if (c->model == CAL_LV) A((void **)&c->d_t_nodes, sizeof(double) * pb->n_t_nodes);
     if (e != hipSuccess) {
         cal_destroy(c);
         return fail(nullptr, CAL_ENOMEM, std::string("workspace allocation failed: ") + hipGetErrorString(e));
@@ -226,6 +257,7 @@ extern "C" int cal_create(const cal_problem *pb, cal_ctx **out)
     H2D(c->d_strike_f, strike_f.data(), sizeof(float) * m);
     H2D(c->d_disc, disc.data(), sizeof(double) * m);
     H2D(c->d_id, order.data(), sizeof(int32_t) * m);
+    if (c->model == CAL_LV) H2D(c->d_t_nodes, pb->t_nodes, sizeof(double) * pb->n_t_nodes);
     if (e == hipSuccess) e = hipMemset(c->d_status, 0, sizeof(int32_t));
     if (e == hipSuccess) e = hipDeviceSynchronize();
     if (e != hipSuccess) {
@@ -257,6 +289,13 @@ extern "C" int cal_create(const cal_problem *pb, cal_ctx **out)
     d.disc = c->d_disc;
     d.id = c->d_id;
     d.status = c->d_status;
+    if (c->model == CAL_LV) {
+        d.nT = pb->n_t_nodes;
+        d.nK = pb->n_k_nodes;
+        d.K0 = pb->k_nodes[0];
+        d.dK = (pb->k_nodes[d.nK - 1] - pb->k_nodes[0]) / (d.nK - 1);
+        d.t_nodes = c->d_t_nodes;
+    }
     *out = c;
     return CAL_OK;
 }
@@ -350,8 +389,14 @@ static int check_ctx(cal_ctx *ctx)
 
 static int run_pass1(cal_ctx *c, const double *theta, bool store, hipStream_t st)
 {
+    if (c->model == CAL_LV) {
+        hipError_t ec = launch_check_theta(c->dp, theta, c->model, st);
+        if (ec != hipSuccess) return hip_fail(c, ec, "theta check launch");
+    }
     Timed t(c, st, 0);
-    hipError_t e = launch_pass1(c->dp, c->model, c->fp64, store, theta, c->d_part_y, c->d_ckpt, c->nblocks, st);
+    hipError_t e = c->model == CAL_LV
+                       ? launch_lv_pass1(c->dp, c->fp64, store, theta, c->d_part_y, c->d_ckpt, c->nblocks, st)
+                       : launch_pass1(c->dp, c->model, c->fp64, store, theta, c->d_part_y, c->d_ckpt, c->nblocks, st);
     t.done();
     if (e != hipSuccess) return hip_fail(c, e, "pass-1 launch");
     return CAL_OK;
@@ -360,8 +405,11 @@ static int run_pass1(cal_ctx *c, const double *theta, bool store, hipStream_t st
 static int run_pass2(cal_ctx *c, const double *theta, bool from_ckpt, hipStream_t st)
 {
     Timed t(c, st, 1);
-    hipError_t e = launch_pass2(c->dp, c->model, c->fp64, from_ckpt, theta, c->d_lamD, c->d_part_g, c->d_ckpt,
-                                c->nblocks, st);
+    hipError_t e = c->model == CAL_LV
+                       ? launch_lv_pass2(c->dp, c->fp64, from_ckpt, theta, c->d_lamD, c->d_part_g, c->d_ckpt,
+                                         c->nblocks, st)
+                       : launch_pass2(c->dp, c->model, c->fp64, from_ckpt, theta, c->d_lamD, c->d_part_g, c->d_ckpt,
+                                      c->nblocks, st);
     t.done();
     if (e != hipSuccess) return hip_fail(c, e, "pass-2 launch");
     return CAL_OK;
@@ -425,6 +473,7 @@ extern "C" int calibrate_jacobian_batch(cal_ctx *ctx, const double *d_theta, int
     int rc = check_ctx(ctx);
     if (rc) return rc;
     if (!d_theta || !d_Ey || !d_J) return fail(ctx, CAL_EINVAL, "null device pointer");
+    if (ctx->model == CAL_LV) return fail(ctx, CAL_EUNSUPPORTED, "tangent mode serves Black-Scholes and Heston");
     if (n_inst < 1 || n_inst > ctx->max_batch) return fail(ctx, CAL_EINVAL, "n_inst outside 1..max_batch");
     if ((size_t)ctx->m * (ctx->M + 1) * kWavesPerBlock * sizeof(double) > 64 * 1024)
         return fail(ctx, CAL_EUNSUPPORTED, "m * (M + 1) too large for the tangent kernel's LDS");

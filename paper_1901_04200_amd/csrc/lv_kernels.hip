@@ -1,0 +1,368 @@
+// Local-volatility model on gfx950: sigma(t, S) bilinear on a grid of node
+// values theta[a*nK + k] at times t_nodes[a] and spots K0 + k dK, flat
+// outside the grid; log-Euler x' = x + (r - sigma^2/2) h + sigma sqrt(h) z.
+//
+// The time weights of step n are the same for every path, so each
+// workgroup first interpolates the grid in time once per step into LDS:
+// row_n[k] = (1 - al_n) theta[a_n][k] + al_n theta[a_n + 1][k].  A path-step
+// then needs its spot cell b, the weight be and two LDS reads.
+//
+// Reverse sweep: sigmabar_n = xbar (-sigma h + sqrt(h) z); the node adjoints
+// get sigmabar (1-al)(1-be), (1-al) be, al (1-be), al be at (a, b), (a, b+1),
+// (a+1, b), (a+1, b+1).  b differs per lane, a and al do not: each lane
+// accumulates sum (1-al) w_k and sum al w_k over the steps of one time cell in
+// its own LDS slice (FP32), and when the time cell changes the workgroup sums
+// the slices over lanes in a fixed tree into FP64 node sums.
+#include <hip/hip_runtime.h>
+
+#include "mc_device.hpp"
+#include "mc_kernels.hpp"
+
+namespace mcaad {
+namespace {
+
+template <typename R>
+__device__ __forceinline__ R exp_t(R x)
+{
+    if constexpr (sizeof(R) == 4) return __expf(x);
+    else return exp(x);
+}
+
+// LDS carve-up shared by both passes: [dbl area][al_n: R N][rows: R N*nK][a_n: int N][slices]
+template <typename R>
+struct LvLds {
+    double *dbl;   // pass 1: [waves][m] payoff sums; pass 2: [nT*nK] node sums
+    R *al;
+    R *rows;
+    int *an;
+    float *slices;   // pass 2: [2*nK][kBlock]
+};
+
+template <typename R>
+__device__ LvLds<R> carve(const DevProblem &pb, unsigned char *base, int ndbl)
+{
+    LvLds<R> L;
+    size_t o = 0;
+    L.dbl = (double *)(base + o);
+    o += sizeof(double) * ndbl;
+    L.al = (R *)(base + o);
+    o += sizeof(R) * pb.N;
+    L.rows = (R *)(base + o);
+    o += sizeof(R) * pb.N * pb.nK;
+    o = (o + 15) & ~(size_t)15;
+    L.an = (int *)(base + o);
+    o += sizeof(int) * pb.N;
+    o = (o + 15) & ~(size_t)15;
+    L.slices = (float *)(base + o);
+    return L;
+}
+
+// time cell and weight of every step, then the time-interpolated rows
+template <typename R>
+__device__ void build_rows(const DevProblem &pb, const double *theta, LvLds<R> &L)
+{
+    const int tid = threadIdx.x;
+    for (int n = tid; n < pb.N; n += kBlock) {
+        const double t = n * pb.h;
+        int a = 0;
+        while (a + 1 < pb.nT - 1 && pb.t_nodes[a + 1] <= t) ++a;
+        double al = (t - pb.t_nodes[a]) / (pb.t_nodes[a + 1] - pb.t_nodes[a]);
+        al = al < 0.0 ? 0.0 : (al > 1.0 ? 1.0 : al);
+        L.an[n] = a;
+        L.al[n] = (R)al;
+    }
+    __syncthreads();
+    const int total = pb.N * pb.nK;
+    for (int i = tid; i < total; i += kBlock) {
+        const int n = i / pb.nK, k = i % pb.nK;
+        const int a = L.an[n];
+        const double al = (double)L.al[n];
+        L.rows[i] = (R)((1.0 - al) * theta[a * pb.nK + k] + al * theta[(a + 1) * pb.nK + k]);
+    }
+    __syncthreads();
+}
+
+template <typename R>
+struct Cell {
+    int b;
+    R be, r0, r1, sig;
+    bool inside;
+};
+
+template <typename R>
+__device__ __forceinline__ Cell<R> locate(const DevProblem &pb, const R *row, R S, R K0, R invdK, R Klast)
+{
+    Cell<R> c;
+    const R u = (S - K0) * invdK;
+    int b = (int)floor(u);
+    b = b < 0 ? 0 : (b > pb.nK - 2 ? pb.nK - 2 : b);
+    R be = u - (R)b;
+    be = be < (R)0 ? (R)0 : (be > (R)1 ? (R)1 : be);
+    c.b = b;
+    c.be = be;
+    c.r0 = row[b];
+    c.r1 = row[b + 1];
+    c.sig = c.r0 + be * (c.r1 - c.r0);
+    c.inside = S >= K0 && S <= Klast;
+    return c;
+}
+
+template <typename R, bool STORE>
+__global__ __launch_bounds__(kBlock) void k_lv_pass1(DevProblem pb, const double *__restrict__ theta,
+                                                     double *__restrict__ partial, R *__restrict__ ckpt)
+{
+    extern __shared__ __attribute__((aligned(16))) unsigned char lds_raw[];
+    LvLds<R> L = carve<R>(pb, lds_raw, kWavesPerBlock * pb.m);
+    const int tid = threadIdx.x;
+    const int lane = tid & (kWave - 1);
+    const int wave = tid / kWave;
+    const int64_t p = (int64_t)blockIdx.x * kBlock + tid;
+    const bool active = p < pb.P;
+    const uint32_t path = (uint32_t)p;
+    build_rows<R>(pb, theta, L);
+
+    const R s0 = (R)pb.s0, rh = (R)(pb.rate * pb.h), hh = (R)(0.5 * pb.h), sq = (R)pb.sq;
+    const R K0 = (R)pb.K0, invdK = (R)(1.0 / pb.dK), Klast = (R)(pb.K0 + (pb.nK - 1) * pb.dK);
+    R x = (R)0;
+    int d = 0;
+    int next = pb.ndates > 0 ? pb.date_step[0] : -1;
+    const int kmask = pb.K - 1;
+    const int kshift = __builtin_ctz(pb.K);
+    const int ncalls = (pb.N + 3) / 4;
+    for (int call = 0; call < ncalls; ++call) {
+        R z[4];
+        normals4<R>((uint32_t)call, path, pb.inst, pb.k0, pb.k1, z);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int n = call * 4 + j;
+            if (n < pb.N) {
+                if constexpr (STORE) {
+                    if ((n & kmask) == 0 && active) ckpt[(int64_t)(n >> kshift) * pb.P + p] = x;
+                }
+                const R S = s0 * exp_t(x);
+                const Cell<R> c = locate<R>(pb, L.rows + n * pb.nK, S, K0, invdK, Klast);
+                x = x + (rh - hh * c.sig * c.sig) + (sq * c.sig) * z[j];
+                if (n + 1 == next) {
+                    const double Sd = (double)(s0 * exp_t(x));
+                    for (int k = pb.date_begin[d]; k < pb.date_begin[d + 1]; ++k) {
+                        double y = active ? pb.disc[k] * fmax(Sd - pb.strike[k], 0.0) : 0.0;
+                        y = wave_sum(y);
+                        if (lane == 0) L.dbl[wave * pb.m + k] = y;
+                    }
+                    ++d;
+                    next = d < pb.ndates ? pb.date_step[d] : -1;
+                }
+            }
+        }
+    }
+    __syncthreads();
+    for (int k = tid; k < pb.m; k += kBlock) {
+        double s = L.dbl[k];
+#pragma unroll
+        for (int w = 1; w < kWavesPerBlock; ++w) s += L.dbl[w * pb.m + k];
+        partial[(int64_t)blockIdx.x * pb.m + k] = s;
+    }
+}
+
+// Sum the lane slices of time cell `a` over the workgroup (fixed tree) into
+// the FP64 node sums, then clear them.  Called by every thread (uniform).
+template <typename R>
+__device__ void flush_cell(const DevProblem &pb, LvLds<R> &L, int a)
+{
+    const int tid = threadIdx.x;
+    const int rows2 = 2 * pb.nK;
+    __syncthreads();
+    for (int stride = kBlock / 2; stride > 0; stride >>= 1) {
+        if (tid < stride)
+            for (int q = 0; q < rows2; ++q) L.slices[q * kBlock + tid] += L.slices[q * kBlock + tid + stride];
+        __syncthreads();
+    }
+    if (tid < rows2) {
+        const int half = tid / pb.nK, k = tid % pb.nK;   // half 0: cell a, half 1: cell a + 1
+        L.dbl[(a + half) * pb.nK + k] += (double)L.slices[tid * kBlock];
+    }
+    __syncthreads();
+    for (int i = tid; i < rows2 * kBlock; i += kBlock) L.slices[i] = 0.f;
+    __syncthreads();
+}
+
+template <typename R, bool FROM_CKPT, int K>
+__global__ __launch_bounds__(kBlock) void k_lv_pass2(DevProblem pb, const double *__restrict__ theta,
+                                                     const R *__restrict__ lamD, double *__restrict__ partial,
+                                                     R *__restrict__ ckpt)
+{
+    static_assert(K % 4 == 0, "segments start on a Philox call");
+    extern __shared__ __attribute__((aligned(16))) unsigned char lds_raw[];
+    LvLds<R> L = carve<R>(pb, lds_raw, pb.nT * pb.nK);
+    const int tid = threadIdx.x;
+    const int64_t p = (int64_t)blockIdx.x * kBlock + tid;
+    const bool active = p < pb.P;
+    const int64_t pc = active ? p : 0;
+    const uint32_t path = (uint32_t)p;
+    build_rows<R>(pb, theta, L);
+    for (int i = tid; i < pb.nT * pb.nK; i += kBlock) L.dbl[i] = 0.0;
+    for (int i = tid; i < 2 * pb.nK * kBlock; i += kBlock) L.slices[i] = 0.f;
+    __syncthreads();
+
+    const R s0 = (R)pb.s0, rh = (R)(pb.rate * pb.h), hh = (R)(0.5 * pb.h), sq = (R)pb.sq, h = (R)pb.h;
+    const R K0 = (R)pb.K0, invdK = (R)(1.0 / pb.dK), Klast = (R)(pb.K0 + (pb.nK - 1) * pb.dK);
+    const R *strike_r;
+    if constexpr (sizeof(R) == 4) strike_r = pb.strike_f;
+    else strike_r = pb.strike;
+
+    if constexpr (!FROM_CKPT) {
+        R x = (R)0;
+        const int ncalls = (pb.N + 3) / 4;
+        for (int call = 0; call < ncalls; ++call) {
+            R z[4];
+            normals4<R>((uint32_t)call, path, pb.inst, pb.k0, pb.k1, z);
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int n = call * 4 + j;
+                if (n < pb.N) {
+                    if ((n % K) == 0 && active) ckpt[(int64_t)(n / K) * pb.P + p] = x;
+                    const R S = s0 * exp_t(x);
+                    const Cell<R> c = locate<R>(pb, L.rows + n * pb.nK, S, K0, invdK, Klast);
+                    x = x + (rh - hh * c.sig * c.sig) + (sq * c.sig) * z[j];
+                }
+            }
+        }
+    }
+
+    R xb = (R)0;
+    int cur_a = L.an[pb.N - 1];
+    int dhi = pb.ndates;
+    float *my0 = L.slices + tid;   // this lane's column of the slices
+    for (int seg = pb.nseg - 1; seg >= 0; --seg) {
+        const int n0 = seg * K;
+        R x = active ? ckpt[(int64_t)seg * pb.P + pc] : (R)0;   // inactive lanes run a harmless path
+        int dlo = dhi;
+        while (dlo > 0 && pb.date_step[dlo - 1] > n0) --dlo;
+        int d = dlo;
+        int next = d < dhi ? pb.date_step[d] : -1;
+        R s_S[K], s_z[K], s_inj[K];
+        R z[4];
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+            const int n = n0 + j;
+            s_inj[j] = (R)0;
+            s_z[j] = (R)0;
+            s_S[j] = (R)0;
+            if (n < pb.N) {
+                if (j % 4 == 0) normals4<R>((uint32_t)(n / 4), path, pb.inst, pb.k0, pb.k1, z);
+                const R S = s0 * exp_t(x);
+                const Cell<R> c = locate<R>(pb, L.rows + n * pb.nK, S, K0, invdK, Klast);
+                s_S[j] = S;
+                s_z[j] = z[j % 4];
+                x = x + (rh - hh * c.sig * c.sig) + (sq * c.sig) * z[j % 4];
+                if (n + 1 == next) {
+                    const R Sn = s0 * exp_t(x);
+                    R inj = (R)0;
+                    for (int k = pb.date_begin[d]; k < pb.date_begin[d + 1]; ++k)
+                        inj += Sn > strike_r[k] ? lamD[k] * Sn : (R)0;
+                    s_inj[j] = active ? inj : (R)0;
+                    ++d;
+                    next = d < dhi ? pb.date_step[d] : -1;
+                }
+            }
+        }
+        dhi = dlo;
+#pragma unroll
+        for (int j = K - 1; j >= 0; --j) {
+            const int n = n0 + j;
+            if (n < pb.N) {
+                xb += s_inj[j];
+                const int a = L.an[n];
+                if (a != cur_a) {
+                    flush_cell<R>(pb, L, cur_a);
+                    cur_a = a;
+                }
+                const R S = s_S[j];
+                const Cell<R> c = locate<R>(pb, L.rows + n * pb.nK, S, K0, invdK, Klast);
+                const R sbar = xb * (-c.sig * h + sq * s_z[j]);
+                const R dsdS = c.inside ? (c.r1 - c.r0) * invdK : (R)0;
+                xb = xb + sbar * dsdS * S;
+                const R al = (R)L.al[n];
+                const R w1 = sbar * c.be, w0 = sbar - w1;
+                my0[c.b * kBlock] += (float)((1 - al) * w0);
+                my0[(c.b + 1) * kBlock] += (float)((1 - al) * w1);
+                my0[(pb.nK + c.b) * kBlock] += (float)(al * w0);
+                my0[(pb.nK + c.b + 1) * kBlock] += (float)(al * w1);
+            }
+        }
+    }
+    flush_cell<R>(pb, L, cur_a);
+    const int M = pb.nT * pb.nK;
+    for (int i = tid; i < M; i += kBlock) partial[(int64_t)blockIdx.x * M + i] = L.dbl[i];
+}
+
+template <typename R>
+hipError_t pass1_t(const DevProblem &pb, bool store, const double *theta, double *partial, void *ckpt, int64_t nb,
+                   hipStream_t st)
+{
+    const size_t lds = lv_lds_bytes(pb, sizeof(R) == 8, 1);
+    if (store)
+        hipLaunchKernelGGL((k_lv_pass1<R, true>), dim3((unsigned)nb), dim3(kBlock), lds, st, pb, theta, partial,
+                           (R *)ckpt);
+    else
+        hipLaunchKernelGGL((k_lv_pass1<R, false>), dim3((unsigned)nb), dim3(kBlock), lds, st, pb, theta, partial,
+                           (R *)ckpt);
+    return hipGetLastError();
+}
+
+template <typename R, int K>
+hipError_t pass2_k(const DevProblem &pb, bool from_ckpt, const double *theta, const void *lamD, double *partial,
+                   void *ckpt, int64_t nb, hipStream_t st)
+{
+    const size_t lds = lv_lds_bytes(pb, sizeof(R) == 8, 2);
+    if (from_ckpt)
+        hipLaunchKernelGGL((k_lv_pass2<R, true, K>), dim3((unsigned)nb), dim3(kBlock), lds, st, pb, theta,
+                           (const R *)lamD, partial, (R *)ckpt);
+    else
+        hipLaunchKernelGGL((k_lv_pass2<R, false, K>), dim3((unsigned)nb), dim3(kBlock), lds, st, pb, theta,
+                           (const R *)lamD, partial, (R *)ckpt);
+    return hipGetLastError();
+}
+
+template <typename R>
+hipError_t pass2_t(const DevProblem &pb, bool from_ckpt, const double *theta, const void *lamD, double *partial,
+                   void *ckpt, int64_t nb, hipStream_t st)
+{
+    switch (pb.K) {
+    case 8: return pass2_k<R, 8>(pb, from_ckpt, theta, lamD, partial, ckpt, nb, st);
+    case 16: return pass2_k<R, 16>(pb, from_ckpt, theta, lamD, partial, ckpt, nb, st);
+    case 32: return pass2_k<R, 32>(pb, from_ckpt, theta, lamD, partial, ckpt, nb, st);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace
+
+size_t lv_lds_bytes(const DevProblem &pb, bool fp64, int pass)
+{
+    const size_t real = fp64 ? 8 : 4;
+    size_t o = sizeof(double) * (pass == 1 ? (size_t)kWavesPerBlock * pb.m : (size_t)pb.nT * pb.nK);
+    o += real * (size_t)pb.N;
+    o += real * (size_t)pb.N * pb.nK;
+    o = (o + 15) & ~(size_t)15;
+    o += sizeof(int) * (size_t)pb.N;
+    o = (o + 15) & ~(size_t)15;
+    if (pass == 2) o += sizeof(float) * 2 * (size_t)pb.nK * kBlock;
+    return o;
+}
+
+hipError_t launch_lv_pass1(const DevProblem &pb, bool fp64, bool store, const double *theta, double *partial,
+                           void *ckpt, int64_t nb, hipStream_t st)
+{
+    return fp64 ? pass1_t<double>(pb, store, theta, partial, ckpt, nb, st)
+                : pass1_t<float>(pb, store, theta, partial, ckpt, nb, st);
+}
+
+hipError_t launch_lv_pass2(const DevProblem &pb, bool fp64, bool from_ckpt, const double *theta, const void *lamD,
+                           double *partial, void *ckpt, int64_t nb, hipStream_t st)
+{
+    return fp64 ? pass2_t<double>(pb, from_ckpt, theta, lamD, partial, ckpt, nb, st)
+                : pass2_t<float>(pb, from_ckpt, theta, lamD, partial, ckpt, nb, st);
+}
+
+}  // namespace mcaad

@@ -565,9 +565,15 @@ __global__ __launch_bounds__(kBlock) void k_lambda(DevProblem pb, const double *
 
 __global__ void k_check_theta(DevProblem pb, const double *theta, int model)
 {
-    if (threadIdx.x == 0) {
-        if (model == kBS) check_theta<kBS>(pb, theta);
-        else check_theta<kHeston>(pb, theta);
+    if (model == kBS) {
+        if (threadIdx.x == 0) check_theta<kBS>(pb, theta);
+    } else if (model == kHeston) {
+        if (threadIdx.x == 0) check_theta<kHeston>(pb, theta);
+    } else {
+        // local volatility: every node value finite and >= 0
+        bool ok = true;
+        for (int i = threadIdx.x; i < pb.M; i += blockDim.x) ok = ok && isfinite(theta[i]) && theta[i] >= 0.0;
+        if (!ok) atomicOr(pb.status, 1);
     }
 }
 

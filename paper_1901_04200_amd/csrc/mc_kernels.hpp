@@ -29,7 +29,19 @@ struct DevProblem {
     const double *disc;         // [m] date-sorted discount factors exp(-r n_i h)
     const int32_t *id;          // [m] original index of date-sorted instrument k
     int32_t *status;            // device status bits
+    // local volatility: bilinear grid on time nodes t_nodes[nT] and uniformly
+    // spaced spot nodes K0 + k dK, k < nK; theta[a*nK + k] is the node value
+    int32_t nT, nK;
+    double K0, dK;
+    const double *t_nodes;
 };
+
+// Local-volatility passes (lv_kernels.hip).
+hipError_t launch_lv_pass1(const DevProblem &pb, bool fp64, bool store_ckpt, const double *theta, double *partial,
+                           void *ckpt, int64_t nblocks, hipStream_t stream);
+hipError_t launch_lv_pass2(const DevProblem &pb, bool fp64, bool from_ckpt, const double *theta, const void *lamD,
+                           double *partial, void *ckpt, int64_t nblocks, hipStream_t stream);
+size_t lv_lds_bytes(const DevProblem &pb, bool fp64, int pass);
 
 // All launchers enqueue on `stream` and return hipGetLastError().
 hipError_t launch_pass1(const DevProblem &pb, int model, bool fp64, bool store_ckpt, const double *theta,

@@ -88,6 +88,15 @@ def test_validate_rejects_bad_options(L):
     assert _ok(pb.with_(instr_step=np.full(big, 1, np.int32), instr_strike=np.ones(big)))[0] == capi.CAL_EINVAL
 
 
-def test_local_vol_reports_unsupported(L):
+def test_local_vol_validation(L):
     pb = W.lv_problem(n_paths=1024)[0]
-    assert _ok(pb)[0] == capi.CAL_EUNSUPPORTED
+    assert _ok(pb)[0] == capi.CAL_OK
+    k = pb.k_nodes.copy()
+    k[3] += 0.5
+    rc, msg = _ok(pb.with_(k_nodes=k))
+    assert rc == capi.CAL_EINVAL and "uniformly" in msg
+    t = pb.t_nodes.copy()
+    t[2] = t[1]
+    assert _ok(pb.with_(t_nodes=t))[0] == capi.CAL_EINVAL
+    assert _ok(pb.with_(n_params=199))[0] == capi.CAL_EINVAL
+    assert _ok(pb.with_(sqrt_eps=1e-4))[0] == capi.CAL_EINVAL

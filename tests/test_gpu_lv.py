@@ -1,0 +1,150 @@
+"""Local-volatility model on the GPU (M = 200 bilinear node values), its
+torch.autograd wrapper, and the central-difference check of the adjoint.
+
+Parity bounds as for the other models: E y 1e-5 (FP32) / 1e-12 (FP64),
+gradient 1e-4 (FP32) / 1e-9 (FP64), relative, against the FP64 oracle on the
+same streams.  The pathwise derivative of this model is bounded (the grid is
+Lipschitz), so every draw is well conditioned.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from paper_1901_04200_amd import autograd as AG
+from paper_1901_04200_amd import workloads as W
+from paper_1901_04200_amd.mc import MonteCarloCalibration
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+
+
+def ey_err(a, b):
+    return float(np.max(np.abs(np.asarray(a) - b) / np.maximum(np.abs(b), 1e-2)))
+
+
+def g_err(a, b):
+    return float(np.max(np.abs(np.asarray(a) - b)) / np.max(np.abs(b)))
+
+
+def run(pb, th, C, precision, **kw):
+    mc = MonteCarloCalibration(pb, precision=precision, **kw)
+    Ey_f = mc.forward(th).cpu().numpy()
+    Ey, G, g = mc.gradient(th, C)
+    st = mc.status()
+    mc.close()
+    assert st == 0
+    return Ey_f, Ey.cpu().numpy(), float(G.item()), g.cpu().numpy()
+
+
+@pytest.fixture(scope="module")
+def lv_small(orc):
+    pb, g0, gt, eps, coords = W.lv_problem(n_paths=(1 << 14) + 37)
+    C = W.noisy_targets(orc.forward(pb, gt), eps)
+    return pb, g0, gt, C, coords
+
+
+def test_lv_fp32_matches_oracle(orc, lv_small):
+    pb, g0, gt, C, _ = lv_small
+    say("lv fp32 P=2^14+37 N=256 M=200")
+    Ey_f, Ey, G, g = run(pb, g0, C, "fp32")
+    Eo, Go, go = orc.gradient(pb, g0, C)
+    say(f"  errors Ey {ey_err(Ey, Eo):.2e} grad {g_err(g, go):.2e}")
+    assert ey_err(Ey_f, Eo) <= 1e-5 and ey_err(Ey, Eo) <= 1e-5
+    assert abs(G - Go) <= 1e-4 * Go
+    assert g_err(g, go) <= 1e-4
+
+
+def test_lv_fp64_matches_oracle(orc, lv_small):
+    pb, g0, gt, C, _ = lv_small
+    pb = pb.with_(n_paths=4096 + 3, n_steps=64)
+    say("lv fp64 P=4099 N=64")
+    for mode in ("store", "rerun"):
+        Ey_f, Ey, G, g = run(pb, g0, C, "fp64", ckpt_mode=mode)
+        Eo, Go, go = orc.gradient(pb, g0, C)
+        say(f"  {mode}: errors Ey {ey_err(Ey, Eo):.2e} grad {g_err(g, go):.2e}")
+        assert ey_err(Ey, Eo) <= 1e-12
+        assert g_err(g, go) <= 1e-9
+
+
+def test_lv_checkpoint_spacings(lv_small):
+    pb, g0, gt, C, _ = lv_small
+    res = {}
+    for mode in ("store", "rerun"):
+        for k in (8, 16, 32):
+            res[(mode, k)] = run(pb, g0, C, "fp32", ckpt_every=k, ckpt_mode=mode)
+    base = res[("store", 16)]
+    for key, r in res.items():
+        np.testing.assert_array_equal(r[1], base[1])
+        assert g_err(r[3], base[3]) <= 1e-5, key
+    for k in (8, 16, 32):
+        np.testing.assert_array_equal(res[("store", k)][3], res[("rerun", k)][3])
+
+
+def test_autograd_backward_is_the_adjoint(lv_small):
+    """theta.grad of G = 1/2 |Ey - C|^2 through the autograd wrapper equals
+    calibrate_gradient's gradient (same streams, FP32)."""
+    pb, g0, gt, C, _ = lv_small
+    mc = AG.make(pb, "fp32")
+    th = torch.tensor(g0, dtype=torch.float64, device="cuda", requires_grad=True)
+    Ct = torch.as_tensor(C, device="cuda")
+    Ey = AG.mc_prices(th, mc)
+    G = 0.5 * torch.sum((Ey - Ct) ** 2)
+    G.backward()
+    _, G2, g2 = mc.gradient(g0, Ct)
+    assert abs(G.item() - G2.item()) <= 1e-12 * G2.item()
+    np.testing.assert_allclose(th.grad.cpu().numpy(), g2.cpu().numpy(), rtol=0, atol=1e-6 * g2.abs().max().item())
+    mc.close()
+
+
+def test_memory_budget_picks_spacing():
+    pb = W.lv_problem()[0]     # 2^22 paths x 256 steps, one state variable
+    assert AG.checkpoint_bytes(pb, "fp32", 16) == 16 * (1 << 22) * 4
+    assert AG.choose_ckpt_every(pb, "fp32", budget_bytes=300 << 20) == 16
+    assert AG.choose_ckpt_every(pb, "fp32", budget_bytes=600 << 20) == 8
+    with pytest.raises(MemoryError):
+        AG.choose_ckpt_every(pb, "fp32", budget_bytes=1 << 20)
+
+
+def test_lv_full_size_fd_and_oracle(orc):
+    """2^22 paths x 256 steps, checkpoints every 16 steps: the adjoint
+    gradient against the oracle, and against central differences (h = 1e-4,
+    common random numbers) on 10 random nodes."""
+    pb, g0, gt, eps, coords = W.lv_problem()
+    say("lv full size: oracle targets (2^22 paths, seed 2)")
+    C = W.noisy_targets(orc.forward(pb.with_(seed=2), gt), eps)
+    mc = AG.make(pb, "fp32", budget_bytes=300 << 20)
+    assert mc.geometry()["ckpt_every"] == 16
+    Ct = torch.as_tensor(C, device="cuda")
+    say("lv full size: device gradient")
+    Ey, G, g = mc.gradient(g0, Ct)
+    g = g.cpu().numpy()
+    say("lv full size: oracle gradient")
+    Eo, Go, go = orc.gradient(pb, g0, C)
+    say(f"  full size errors Ey {ey_err(Ey.cpu().numpy(), Eo):.2e} grad {g_err(g, go):.2e}")
+    assert ey_err(Ey.cpu().numpy(), Eo) <= 1e-5
+    assert g_err(g, go) <= 1e-4
+    h = 1e-4
+    worst = 0.0
+    for j in coords:
+        e = np.zeros(pb.n_params)
+        e[j] = h
+        Gp = 0.5 * torch.sum((mc.forward(g0 + e) - Ct) ** 2).item()
+        Gm = 0.5 * torch.sum((mc.forward(g0 - e) - Ct) ** 2).item()
+        fd = (Gp - Gm) / (2 * h)
+        worst = max(worst, abs(fd - g[j]) / np.max(np.abs(g)))
+        say(f"  node {j}: fd {fd:.6g} adjoint {g[j]:.6g}")
+    say(f"  worst |fd - adjoint| / max|g| = {worst:.2e}")
+    assert worst <= 1e-3
+    mc.close()
