@@ -129,6 +129,20 @@ def noisy_targets(prices: np.ndarray, eps: np.ndarray, rel: float = 1e-3) -> np.
 # --------------------------------------------------------------------------
 # Local volatility: 10 maturities x 20 strikes, bilinear grid, M = 200
 # --------------------------------------------------------------------------
+def lv_surface(rng, t_nodes, k_nodes, s0: float = 100.0) -> np.ndarray:
+    """A smooth random local-volatility surface on the nodes, inside
+    [0.1, 0.5]: level + skew m + smile m^2 + term T with m = K/S0 - 1 and
+    coefficients drawn uniformly (level 0.15..0.35, skew -0.3..0, smile
+    0..0.5, term -0.05..0.05).  Flattened time-major [a * nK + k]."""
+    level = rng.uniform(0.15, 0.35)
+    skew = rng.uniform(-0.3, 0.0)
+    smile = rng.uniform(0.0, 0.5)
+    term = rng.uniform(-0.05, 0.05)
+    T, K = np.meshgrid(np.asarray(t_nodes), np.asarray(k_nodes), indexing="ij")
+    m = K / s0 - 1.0
+    return np.clip(level + skew * m + smile * m * m + term * T, 0.1, 0.5).ravel()
+
+
 def lv_problem(n_paths: int = 1 << 22, seed: int = 1, n_steps: int = 256, t_max: float = 2.0,
                n_t: int = 10, n_k: int = 20):
     t_nodes = 0.2 * np.arange(1, n_t + 1) * (t_max / (0.2 * n_t))
@@ -141,8 +155,8 @@ def lv_problem(n_paths: int = 1 << 22, seed: int = 1, n_steps: int = 256, t_max:
                  instr_step=instr_step, instr_strike=instr_strike, s0=100.0, rate=0.02, seed=seed,
                  t_nodes=t_nodes, k_nodes=k_nodes)
     rng = np.random.default_rng(4)
-    grid0 = rng.uniform(0.1, 0.5, n_t * n_k)
-    grid_target = rng.uniform(0.1, 0.5, n_t * n_k)
+    grid0 = lv_surface(rng, t_nodes, k_nodes)
+    grid_target = lv_surface(rng, t_nodes, k_nodes)
     eps = np.random.default_rng(5).standard_normal(len(instr_step))
     fd_coords = np.sort(np.random.default_rng(5).choice(n_t * n_k, size=min(10, n_t * n_k), replace=False))
     return pb, grid0, grid_target, eps, fd_coords
