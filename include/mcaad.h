@@ -192,6 +192,51 @@ int cal_philox(const uint32_t *d_ctr, uint32_t key0, uint32_t key1, int64_t n, u
 int cal_normals(int32_t precision, uint64_t seed, uint32_t inst, uint32_t path0, int64_t n_paths,
                 uint32_t q0, int32_t nq, void *d_out, void *stream);
 
+/*
+ * Batches: many independent calibration problems of uneven size (m, P, N)
+ * computed by one gradient step (the paper's steps 1-3 for every instance).
+ * Persistent workgroups take (instance, 256-path block) items from a queue
+ * ordered longest instance first, so uneven instances share the GPU; each
+ * instance's results are bitwise those of its own cal_create context.
+ * All instances share model (BS or Heston) and precision; checkpoints are
+ * stored by pass 1.
+ *
+ * Device arrays of a batch: d_theta [n_inst * M]; d_C and d_Ey concatenated
+ * per instance (instance i at offsets[i] .. offsets[i+1], see calb_offsets,
+ * in the instance's own instrument order); d_G [n_inst]; d_grad
+ * [n_inst * M].
+ */
+typedef struct calb_ctx calb_ctx;
+
+/* Validate every problem, allocate all workspace (checkpoints sized for the
+ * densest spacing, 8 steps) and upload the tables. */
+int calb_create(const cal_problem *problems, int32_t n_inst, calb_ctx **out);
+int calb_destroy(calb_ctx *ctx);
+
+/* instr_offsets[n_inst + 1]: start of each instance in d_C / d_Ey. */
+int calb_offsets(const calb_ctx *ctx, int64_t *instr_offsets);
+
+/* Checkpoint spacing (8, 16, 32) and persistent workgroups per compute
+ * unit (0 = as many as fit).  Synchronises the device and drops a captured
+ * graph. */
+int calb_configure(calb_ctx *ctx, int32_t ckpt_every, int32_t workgroups_per_cu);
+int calb_geometry(const calb_ctx *ctx, int32_t *ckpt_every, int32_t *grid, int32_t *n_items);
+
+/* One gradient step for all instances, enqueued on `stream`. */
+int calibrate_gradient_batch(calb_ctx *ctx, const double *d_theta, const double *d_C, double *d_Ey, double *d_G,
+                             double *d_grad, void *stream);
+
+/* Capture one gradient step bound to these arrays into a HIP graph (stream
+ * must be a created stream, not the null stream); calb_replay launches it.
+ * The step contains no memset nodes: the queue heads are reset by a kernel. */
+int calb_capture(calb_ctx *ctx, const double *d_theta, const double *d_C, double *d_Ey, double *d_G,
+                 double *d_grad, void *stream);
+int calb_replay(calb_ctx *ctx, void *stream);
+
+/* Synchronise `stream`, return and clear the batch's device status bits. */
+int calb_status(calb_ctx *ctx, void *stream);
+const char *calb_last_error(const calb_ctx *ctx);
+
 #ifdef __cplusplus
 }
 #endif

@@ -538,3 +538,346 @@ extern "C" int cal_normals(int32_t precision, uint64_t seed, uint32_t inst, uint
                                   q0, nq, d_out, (hipStream_t)stream);
     return e == hipSuccess ? CAL_OK : hip_fail(nullptr, e, "normals launch");
 }
+
+// ---------------------------------------------------------------------------
+// Batched instances
+// ---------------------------------------------------------------------------
+struct calb_ctx {
+    int device = 0;
+    int model = 0;
+    bool fp64 = false;
+    int n_inst = 0;
+    int M = 0;
+    int K = 16;
+    int wpc = 0;                       // persistent workgroups per CU (0 = occupancy limit)
+    int cus = 256;
+    std::vector<BatchInst> host;       // descriptors (device pointers inside)
+    std::vector<int64_t> offsets;      // [n_inst + 1] instrument offsets
+    std::vector<int> nsteps;
+    BatchLaunch L{};
+    std::vector<void *> allocs;
+    int32_t *d_status = nullptr;
+    BatchInst *d_insts = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    std::string err;
+};
+
+static int bfail(calb_ctx *c, int code, const std::string &m)
+{
+    if (c) c->err = m;
+    g_err = m;
+    return code;
+}
+
+extern "C" int calb_destroy(calb_ctx *c)
+{
+    if (!c) return CAL_OK;
+    (void)hipDeviceSynchronize();
+    if (c->exec) (void)hipGraphExecDestroy(c->exec);
+    if (c->graph) (void)hipGraphDestroy(c->graph);
+    for (void *p : c->allocs) (void)hipFree(p);
+    delete c;
+    return CAL_OK;
+}
+
+// Descriptors for the current checkpoint spacing, uploaded synchronously.
+static int calb_upload(calb_ctx *c)
+{
+    for (int i = 0; i < c->n_inst; ++i) {
+        c->host[i].pb.K = c->K;
+        c->host[i].pb.nseg = (c->nsteps[i] + c->K - 1) / c->K;
+    }
+    hipError_t e = hipMemcpy(c->d_insts, c->host.data(), sizeof(BatchInst) * c->n_inst, hipMemcpyHostToDevice);
+    if (e != hipSuccess) return bfail(c, CAL_EHIP, std::string("descriptor upload: ") + hipGetErrorString(e));
+    const int bpc = batch_blocks_per_cu(c->model, c->fp64, c->K, c->L.max_m);
+    const int per = c->wpc > 0 ? std::min(c->wpc, bpc) : bpc;
+    c->L.grid = (unsigned)std::max(1, std::min(c->L.n_items, per * c->cus));
+    c->L.K = c->K;
+    if (c->exec) {
+        (void)hipGraphExecDestroy(c->exec);
+        c->exec = nullptr;
+    }
+    if (c->graph) {
+        (void)hipGraphDestroy(c->graph);
+        c->graph = nullptr;
+    }
+    return CAL_OK;
+}
+
+extern "C" int calb_create(const cal_problem *problems, int32_t n_inst, calb_ctx **out)
+{
+    if (!out || !problems) return bfail(nullptr, CAL_EINVAL, "null argument");
+    *out = nullptr;
+    if (n_inst < 1 || n_inst > 65535) return bfail(nullptr, CAL_EINVAL, "n_inst must be in 1..65535");
+    for (int i = 0; i < n_inst; ++i) {
+        int code;
+        std::string msg = validate(&problems[i], &code);
+        if (code != CAL_OK) return bfail(nullptr, code, "instance " + std::to_string(i) + ": " + msg);
+        if (problems[i].model == CAL_LV) return bfail(nullptr, CAL_EUNSUPPORTED, "batches take BS or Heston");
+        if (problems[i].model != problems[0].model || problems[i].precision != problems[0].precision)
+            return bfail(nullptr, CAL_EINVAL, "all instances of a batch share model and precision");
+    }
+    calb_ctx *c = new calb_ctx();
+    (void)hipGetDevice(&c->device);
+    (void)hipDeviceGetAttribute(&c->cus, hipDeviceAttributeMultiprocessorCount, c->device);
+    c->model = problems[0].model;
+    c->fp64 = problems[0].precision == CAL_FP64;
+    c->n_inst = n_inst;
+    c->M = problems[0].n_params;
+    c->K = problems[0].ckpt_every ? problems[0].ckpt_every : (c->fp64 ? 8 : 16);
+    const size_t real = c->fp64 ? 8 : 4;
+    const int nv = c->model == CAL_HESTON ? 2 : 1;
+
+    // host tables, concatenated
+    std::vector<int32_t> date_step, date_begin, ids;
+    std::vector<double> strike, disc;
+    std::vector<float> strike_f;
+    std::vector<size_t> ds_off(n_inst), db_off(n_inst), in_off(n_inst);
+    std::vector<size_t> py_off(n_inst), pg_off(n_inst), lam_off(n_inst), ck_off(n_inst);
+    std::vector<int64_t> nblocks(n_inst);
+    size_t py = 0, pg = 0, lam = 0, ck = 0;
+    int max_m = 0;
+    c->offsets.assign(n_inst + 1, 0);
+    c->nsteps.resize(n_inst);
+    for (int i = 0; i < n_inst; ++i) {
+        const cal_problem *pb = &problems[i];
+        const int m = pb->n_instr;
+        max_m = std::max(max_m, m);
+        c->offsets[i + 1] = c->offsets[i] + m;
+        c->nsteps[i] = pb->n_steps;
+        std::vector<int32_t> order(m);
+        std::iota(order.begin(), order.end(), 0);
+        std::stable_sort(order.begin(), order.end(),
+                         [&](int a, int b) { return pb->instr_step[a] < pb->instr_step[b]; });
+        ds_off[i] = date_step.size();
+        db_off[i] = date_begin.size();
+        in_off[i] = strike.size();
+        const double h = pb->t_max / pb->n_steps;
+        int nd = 0;
+        for (int k = 0; k < m; ++k) {
+            const int s = pb->instr_step[order[k]];
+            if (nd == 0 || date_step.back() != s) {
+                date_step.push_back(s);
+                date_begin.push_back(k);
+                ++nd;
+            }
+            strike.push_back(pb->instr_strike[order[k]]);
+            strike_f.push_back((float)pb->instr_strike[order[k]]);
+            disc.push_back(std::exp(-pb->rate * s * h));
+            ids.push_back(order[k]);
+        }
+        date_begin.push_back(m);
+        nblocks[i] = (pb->n_paths + kBlock - 1) / kBlock;
+        py_off[i] = py;
+        py += (size_t)nblocks[i] * m;
+        pg_off[i] = pg;
+        pg += (size_t)nblocks[i] * c->M;
+        lam_off[i] = lam;
+        lam += (size_t)m;
+        ck_off[i] = ck;
+        ck += (size_t)((pb->n_steps + 7) / 8) * nv * (size_t)pb->n_paths;   // sized for the densest spacing
+        BatchInst &I = c->host.emplace_back();
+        std::memset(&I, 0, sizeof(I));
+        DevProblem &d = I.pb;
+        d.N = pb->n_steps;
+        d.m = m;
+        d.M = c->M;
+        d.ndates = nd;
+        d.P = pb->n_paths;
+        d.k0 = (uint32_t)pb->seed;
+        d.k1 = (uint32_t)(pb->seed >> 32);
+        d.inst = pb->inst;
+        d.use_eps = pb->sqrt_eps > 0.0;
+        d.s0 = pb->s0;
+        d.rate = pb->rate;
+        d.h = h;
+        d.sq = std::sqrt(h);
+        d.sqrt_eps = pb->sqrt_eps;
+        I.nblocks = nblocks[i];
+        I.y_off = (int32_t)c->offsets[i];
+    }
+    hipError_t e = hipSuccess;
+    auto A = [&](void **p, size_t bytes) {
+        if (e != hipSuccess) return;
+        e = hipMalloc(p, bytes ? bytes : 16);
+        if (e == hipSuccess) c->allocs.push_back(*p);
+    };
+    int32_t *d_ds, *d_db, *d_id;
+    double *d_strike, *d_disc, *d_py, *d_pg;
+    float *d_strike_f;
+    void *d_lam, *d_ck;
+    int2 *d_items;
+    unsigned *d_counters;
+    A((void **)&d_ds, 4 * date_step.size());
+    A((void **)&d_db, 4 * date_begin.size());
+    A((void **)&d_id, 4 * ids.size());
+    A((void **)&d_strike, 8 * strike.size());
+    A((void **)&d_strike_f, 4 * strike_f.size());
+    A((void **)&d_disc, 8 * disc.size());
+    A((void **)&d_py, 8 * py);
+    A((void **)&d_pg, 8 * pg);
+    A(&d_lam, real * lam);
+    A(&d_ck, real * ck);
+    A((void **)&c->d_status, 4);
+    A((void **)&c->d_insts, sizeof(BatchInst) * n_inst);
+    // work items: instances with more steps first, then path blocks in order
+    std::vector<int> byN(n_inst);
+    std::iota(byN.begin(), byN.end(), 0);
+    std::stable_sort(byN.begin(), byN.end(), [&](int a, int b) { return c->nsteps[a] > c->nsteps[b]; });
+    std::vector<int2> items;
+    for (int i : byN)
+        for (int64_t b = 0; b < nblocks[i]; ++b) items.push_back(make_int2(i, (int)b));
+    A((void **)&d_items, sizeof(int2) * items.size());
+    A((void **)&d_counters, 2 * sizeof(unsigned));
+    if (e != hipSuccess) {
+        calb_destroy(c);
+        return bfail(nullptr, CAL_ENOMEM, std::string("batch workspace allocation failed: ") + hipGetErrorString(e));
+    }
+    auto H2D = [&](void *dst, const void *src, size_t bytes) {
+        if (e == hipSuccess && bytes) e = hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice);
+    };
+    H2D(d_ds, date_step.data(), 4 * date_step.size());
+    H2D(d_db, date_begin.data(), 4 * date_begin.size());
+    H2D(d_id, ids.data(), 4 * ids.size());
+    H2D(d_strike, strike.data(), 8 * strike.size());
+    H2D(d_strike_f, strike_f.data(), 4 * strike_f.size());
+    H2D(d_disc, disc.data(), 8 * disc.size());
+    H2D(d_items, items.data(), sizeof(int2) * items.size());
+    if (e == hipSuccess) e = hipMemset(c->d_status, 0, 4);
+    if (e != hipSuccess) {
+        calb_destroy(c);
+        return bfail(nullptr, CAL_EHIP, std::string("batch table upload failed: ") + hipGetErrorString(e));
+    }
+    for (int i = 0; i < n_inst; ++i) {
+        BatchInst &I = c->host[i];
+        DevProblem &d = I.pb;
+        d.date_step = d_ds + ds_off[i];
+        d.date_begin = d_db + db_off[i];
+        d.strike = d_strike + in_off[i];
+        d.strike_f = d_strike_f + in_off[i];
+        d.disc = d_disc + in_off[i];
+        d.id = d_id + in_off[i];
+        d.status = c->d_status;
+        I.part_y = d_py + py_off[i];
+        I.part_g = d_pg + pg_off[i];
+        I.lamD = (char *)d_lam + real * lam_off[i];
+        I.ckpt = (char *)d_ck + real * ck_off[i];
+    }
+    c->L.model = c->model;
+    c->L.fp64 = c->fp64;
+    c->L.n_inst = n_inst;
+    c->L.n_items = (int)items.size();
+    c->L.max_m = max_m;
+    c->L.insts = c->d_insts;
+    c->L.items = d_items;
+    c->L.counters = d_counters;
+    int rc = calb_upload(c);
+    if (rc) {
+        calb_destroy(c);
+        return rc;
+    }
+    *out = c;
+    return CAL_OK;
+}
+
+extern "C" int calb_offsets(const calb_ctx *c, int64_t *instr_offsets)
+{
+    if (!c || !instr_offsets) return CAL_EINVAL;
+    for (int i = 0; i <= c->n_inst; ++i) instr_offsets[i] = c->offsets[i];
+    return CAL_OK;
+}
+
+extern "C" int calb_configure(calb_ctx *c, int32_t ckpt_every, int32_t workgroups_per_cu)
+{
+    if (!c) return bfail(nullptr, CAL_EINVAL, "null context");
+    if (ckpt_every != 8 && ckpt_every != 16 && ckpt_every != 32) return bfail(c, CAL_EINVAL, "ckpt_every must be 8, 16 or 32");
+    if (workgroups_per_cu < 0 || workgroups_per_cu > 64) return bfail(c, CAL_EINVAL, "workgroups_per_cu in 0..64");
+    (void)hipDeviceSynchronize();
+    c->K = ckpt_every;
+    c->wpc = workgroups_per_cu;
+    return calb_upload(c);
+}
+
+extern "C" int calb_geometry(const calb_ctx *c, int32_t *ckpt_every, int32_t *grid, int32_t *n_items)
+{
+    if (!c) return CAL_EINVAL;
+    if (ckpt_every) *ckpt_every = c->K;
+    if (grid) *grid = (int32_t)c->L.grid;
+    if (n_items) *n_items = c->L.n_items;
+    return CAL_OK;
+}
+
+static int calb_bind(calb_ctx *c, const double *d_theta, const double *d_C, double *d_Ey, double *d_G, double *d_grad)
+{
+    if (!c) return bfail(nullptr, CAL_EINVAL, "null context");
+    if (!d_theta || !d_C || !d_Ey || !d_G || !d_grad) return bfail(c, CAL_EINVAL, "null device pointer");
+    int dev = -1;
+    (void)hipGetDevice(&dev);
+    if (dev != c->device) return bfail(c, CAL_EINVAL, "context belongs to another device");
+    c->L.theta = d_theta;
+    c->L.C = d_C;
+    c->L.Ey = d_Ey;
+    c->L.G = d_G;
+    c->L.grad = d_grad;
+    c->err.clear();
+    return CAL_OK;
+}
+
+extern "C" int calibrate_gradient_batch(calb_ctx *c, const double *d_theta, const double *d_C, double *d_Ey,
+                                        double *d_G, double *d_grad, void *stream)
+{
+    int rc = calb_bind(c, d_theta, d_C, d_Ey, d_G, d_grad);
+    if (rc) return rc;
+    hipError_t e = launch_batch_step(c->L, (hipStream_t)stream);
+    return e == hipSuccess ? CAL_OK : bfail(c, CAL_EHIP, std::string("batch launch: ") + hipGetErrorString(e));
+}
+
+extern "C" int calb_capture(calb_ctx *c, const double *d_theta, const double *d_C, double *d_Ey, double *d_G,
+                            double *d_grad, void *stream)
+{
+    int rc = calb_bind(c, d_theta, d_C, d_Ey, d_G, d_grad);
+    if (rc) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    if (!st) return bfail(c, CAL_EINVAL, "capture needs a created (non-null) stream");
+    if (c->exec) {
+        (void)hipGraphExecDestroy(c->exec);
+        c->exec = nullptr;
+    }
+    if (c->graph) {
+        (void)hipGraphDestroy(c->graph);
+        c->graph = nullptr;
+    }
+    hipError_t e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return bfail(c, CAL_EHIP, std::string("begin capture: ") + hipGetErrorString(e));
+    hipError_t el = launch_batch_step(c->L, st);
+    e = hipStreamEndCapture(st, &c->graph);
+    if (el != hipSuccess || e != hipSuccess)
+        return bfail(c, CAL_EHIP, std::string("capture: ") + hipGetErrorString(el != hipSuccess ? el : e));
+    e = hipGraphInstantiate(&c->exec, c->graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) return bfail(c, CAL_EHIP, std::string("instantiate: ") + hipGetErrorString(e));
+    return CAL_OK;
+}
+
+extern "C" int calb_replay(calb_ctx *c, void *stream)
+{
+    if (!c) return bfail(nullptr, CAL_EINVAL, "null context");
+    if (!c->exec) return bfail(c, CAL_EINVAL, "no captured step (call calb_capture first)");
+    hipError_t e = hipGraphLaunch(c->exec, (hipStream_t)stream);
+    return e == hipSuccess ? CAL_OK : bfail(c, CAL_EHIP, std::string("graph launch: ") + hipGetErrorString(e));
+}
+
+extern "C" int calb_status(calb_ctx *c, void *stream)
+{
+    if (!c) return bfail(nullptr, CAL_EINVAL, "null context");
+    hipStream_t st = (hipStream_t)stream;
+    int32_t flags = 0;
+    hipError_t e = hipMemcpyAsync(&flags, c->d_status, 4, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e == hipSuccess) e = hipMemsetAsync(c->d_status, 0, 4, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return bfail(c, CAL_EHIP, std::string("status read: ") + hipGetErrorString(e));
+    return flags;
+}
+
+extern "C" const char *calb_last_error(const calb_ctx *c) { return c ? c->err.c_str() : g_err.c_str(); }

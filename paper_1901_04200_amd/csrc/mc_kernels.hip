@@ -159,19 +159,21 @@ __device__ void check_theta(const DevProblem &pb, const double *th)
 // ---------------------------------------------------------------------------
 // Pass 1: forward sweep, payoffs, block partials of sum_p y_i(p)
 // ---------------------------------------------------------------------------
+// One workgroup's share: paths blk*256 .. blk*256+255; lds holds
+// [kWavesPerBlock][m] doubles.
 template <int MODEL, typename R, bool STORE>
-__global__ __launch_bounds__(kBlock) void k_pass1(DevProblem pb, const double *__restrict__ theta,
-                                                  double *__restrict__ partial, R *__restrict__ ckpt)
+__device__ __forceinline__ void pass1_block(const DevProblem &pb, const double *__restrict__ theta,
+                                            double *__restrict__ partial, R *__restrict__ ckpt, int64_t blk,
+                                            double *lds)
 {
     using T = Traits<MODEL>;
-    extern __shared__ double lds[];   // [kWavesPerBlock][m]
     const int tid = threadIdx.x;
     const int lane = tid & (kWave - 1);
     const int wave = tid / kWave;
-    const int64_t p = (int64_t)blockIdx.x * kBlock + tid;
+    const int64_t p = blk * kBlock + tid;
     const bool active = p < pb.P;
     const uint32_t path = (uint32_t)p;
-    if (blockIdx.x == 0 && tid == 0) check_theta<MODEL>(pb, theta);
+    if (blk == 0 && tid == 0) check_theta<MODEL>(pb, theta);
 
     Consts<R> c;
     load_consts<MODEL, R>(pb, theta, c);
@@ -217,28 +219,36 @@ __global__ __launch_bounds__(kBlock) void k_pass1(DevProblem pb, const double *_
         double s = lds[k];
 #pragma unroll
         for (int w = 1; w < kWavesPerBlock; ++w) s += lds[w * pb.m + k];
-        partial[(int64_t)blockIdx.x * pb.m + k] = s;
+        partial[blk * pb.m + k] = s;
     }
+}
+
+template <int MODEL, typename R, bool STORE>
+__global__ __launch_bounds__(kBlock) void k_pass1(DevProblem pb, const double *__restrict__ theta,
+                                                  double *__restrict__ partial, R *__restrict__ ckpt)
+{
+    extern __shared__ double lds[];
+    pass1_block<MODEL, R, STORE>(pb, theta, partial, ckpt, blockIdx.x, lds);
 }
 
 // ---------------------------------------------------------------------------
 // Pass 2: (re-run forward with checkpoints) + reverse sweep, block partials
 // of sum_p thetabar(p)
 // ---------------------------------------------------------------------------
+// One workgroup's share; lds holds [kWavesPerBlock][NP] doubles.
 template <int MODEL, typename R, bool FROM_CKPT, int K>
-__global__ __launch_bounds__(kBlock) void k_pass2(DevProblem pb, const double *__restrict__ theta,
-                                                  const R *__restrict__ lamD, double *__restrict__ partial,
-                                                  R *__restrict__ ckpt)
+__device__ __forceinline__ void pass2_block(const DevProblem &pb, const double *__restrict__ theta,
+                                            const R *__restrict__ lamD, double *__restrict__ partial,
+                                            R *__restrict__ ckpt, int64_t blk, double *lds)
 {
     using T = Traits<MODEL>;
     constexpr int NP = T::NP;
     constexpr int SPC = 4 / T::D;
     static_assert(K % SPC == 0, "segments must start on a Philox call");
-    extern __shared__ double lds[];   // [kWavesPerBlock][NP]
     const int tid = threadIdx.x;
     const int lane = tid & (kWave - 1);
     const int wave = tid / kWave;
-    const int64_t p = (int64_t)blockIdx.x * kBlock + tid;
+    const int64_t p = blk * kBlock + tid;
     const bool active = p < pb.P;
     const int64_t pc = active ? p : 0;   // inactive lanes read path 0's checkpoints
     const uint32_t path = (uint32_t)p;
@@ -367,8 +377,17 @@ __global__ __launch_bounds__(kBlock) void k_pass2(DevProblem pb, const double *_
         double s = lds[tid];
 #pragma unroll
         for (int w = 1; w < kWavesPerBlock; ++w) s += lds[w * NP + tid];
-        partial[(int64_t)blockIdx.x * NP + tid] = s;
+        partial[blk * NP + tid] = s;
     }
+}
+
+template <int MODEL, typename R, bool FROM_CKPT, int K>
+__global__ __launch_bounds__(kBlock) void k_pass2(DevProblem pb, const double *__restrict__ theta,
+                                                  const R *__restrict__ lamD, double *__restrict__ partial,
+                                                  R *__restrict__ ckpt)
+{
+    extern __shared__ double lds[];
+    pass2_block<MODEL, R, FROM_CKPT, K>(pb, theta, lamD, partial, ckpt, blockIdx.x, lds);
 }
 
 // ---------------------------------------------------------------------------
@@ -742,6 +761,178 @@ hipError_t launch_normals(bool fp64, uint32_t k0, uint32_t k1, uint32_t inst, ui
         hipLaunchKernelGGL(k_normals<float>, dim3((unsigned)nb), dim3(kBlock), 0, st, k0, k1, inst, path0, npaths,
                            q0, nq, (float *)out);
     return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Batched instances: persistent workgroups take (instance, path block) work
+// items from a queue (an atomic counter over a list ordered longest-first),
+// run the same per-block bodies as the single-instance kernels, and exit
+// when the queue is empty.  Per-instance finalizers sum the block partials
+// in the same fixed order as k_reduce_sorted, so every instance's result is
+// bitwise the one its own context would give.
+// ---------------------------------------------------------------------------
+__global__ void k_batch_reset(unsigned *counters)
+{
+    if (threadIdx.x < 2) counters[threadIdx.x] = 0u;
+}
+
+__device__ __forceinline__ int next_item(unsigned *counter)
+{
+    __shared__ int s_item;
+    __syncthreads();   // the previous item's LDS traffic is over
+    if (threadIdx.x == 0) s_item = (int)atomicAdd(counter, 1u);
+    __syncthreads();
+    return s_item;
+}
+
+template <int MODEL, typename R, bool STORE>
+__global__ __launch_bounds__(kBlock) void k_batch_pass1(const BatchInst *__restrict__ insts,
+                                                        const int2 *__restrict__ items, int n_items,
+                                                        unsigned *counter, const double *__restrict__ theta_all)
+{
+    extern __shared__ double lds[];
+    for (;;) {
+        const int it = next_item(counter);
+        if (it >= n_items) break;
+        const int2 w = items[it];
+        const DevProblem pb = insts[w.x].pb;
+        pass1_block<MODEL, R, STORE>(pb, theta_all + (int64_t)w.x * Traits<MODEL>::NP, insts[w.x].part_y,
+                                     (R *)insts[w.x].ckpt, w.y, lds);
+    }
+}
+
+template <int MODEL, typename R, bool FROM_CKPT, int K>
+__global__ __launch_bounds__(kBlock) void k_batch_pass2(const BatchInst *__restrict__ insts,
+                                                        const int2 *__restrict__ items, int n_items,
+                                                        unsigned *counter, const double *__restrict__ theta_all)
+{
+    extern __shared__ double lds[];
+    for (;;) {
+        const int it = next_item(counter);
+        if (it >= n_items) break;
+        const int2 w = items[it];
+        const DevProblem pb = insts[w.x].pb;
+        pass2_block<MODEL, R, FROM_CKPT, K>(pb, theta_all + (int64_t)w.x * Traits<MODEL>::NP,
+                                            (const R *)insts[w.x].lamD, insts[w.x].part_g, (R *)insts[w.x].ckpt,
+                                            w.y, lds);
+    }
+}
+
+// grid (max m, n_inst): Ey[y_off + id[k]] = sum_b part_y[b][k] / P
+__global__ __launch_bounds__(kBlock) void k_batch_reduce_y(const BatchInst *__restrict__ insts,
+                                                           double *__restrict__ Ey)
+{
+    __shared__ double sh[kBlock];
+    const BatchInst &I = insts[blockIdx.y];
+    const int k = blockIdx.x;
+    if (k >= I.pb.m) return;   // uniform per workgroup
+    double acc = 0.0;
+    for (int64_t b = threadIdx.x; b < I.nblocks; b += kBlock) acc += I.part_y[b * I.pb.m + k];
+    const double s = block_sum(acc, sh) * (1.0 / (double)I.pb.P);
+    if (threadIdx.x == 0) {
+        Ey[I.y_off + I.pb.id[k]] = s;
+        if (!isfinite(s)) atomicOr(I.pb.status, 2);
+    }
+}
+
+template <typename R>
+__global__ __launch_bounds__(kBlock) void k_batch_residual(const BatchInst *__restrict__ insts,
+                                                           const double *__restrict__ Ey_all,
+                                                           const double *__restrict__ C_all, double *__restrict__ G)
+{
+    __shared__ double sh[kBlock];
+    const BatchInst &I = insts[blockIdx.x];
+    const DevProblem &pb = I.pb;
+    const double *Ey = Ey_all + I.y_off;
+    const double *C = C_all + I.y_off;
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < pb.m; i += kBlock) {
+        const double r = Ey[i] - C[i];
+        acc += 0.5 * r * r;
+    }
+    const double g = block_sum(acc, sh);
+    if (threadIdx.x == 0) {
+        G[blockIdx.x] = g;
+        if (!isfinite(g)) atomicOr(pb.status, 2);
+    }
+    const double invP = 1.0 / (double)pb.P;
+    R *lamD = (R *)I.lamD;
+    for (int k = threadIdx.x; k < pb.m; k += kBlock) {
+        const int i = pb.id[k];
+        lamD[k] = (R)((Ey[i] - C[i]) * pb.disc[k] * invP);
+    }
+}
+
+// grid (NP, n_inst)
+__global__ __launch_bounds__(kBlock) void k_batch_reduce_g(const BatchInst *__restrict__ insts, int NP,
+                                                           double *__restrict__ grad)
+{
+    __shared__ double sh[kBlock];
+    const BatchInst &I = insts[blockIdx.y];
+    const int j = blockIdx.x;
+    double acc = 0.0;
+    for (int64_t b = threadIdx.x; b < I.nblocks; b += kBlock) acc += I.part_g[b * NP + j];
+    const double s = block_sum(acc, sh);
+    if (threadIdx.x == 0) {
+        grad[(int64_t)blockIdx.y * NP + j] = s;
+        if (!isfinite(s)) atomicOr(I.pb.status, 2);
+    }
+}
+
+template <int MODEL, typename R, int K>
+static hipError_t batch_step_t(const BatchLaunch &L, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(64), 0, st, L.counters);
+    const size_t lds1 = sizeof(double) * kWavesPerBlock * L.max_m;
+    const size_t lds2 = sizeof(double) * kWavesPerBlock * Traits<MODEL>::NP;
+    hipLaunchKernelGGL((k_batch_pass1<MODEL, R, true>), dim3(L.grid), dim3(kBlock), lds1, st, L.insts, L.items,
+                       L.n_items, L.counters, L.theta);
+    hipLaunchKernelGGL(k_batch_reduce_y, dim3(L.max_m, L.n_inst), dim3(kBlock), 0, st, L.insts, L.Ey);
+    hipLaunchKernelGGL(k_batch_residual<R>, dim3(L.n_inst), dim3(kBlock), 0, st, L.insts, L.Ey, L.C, L.G);
+    hipLaunchKernelGGL((k_batch_pass2<MODEL, R, true, K>), dim3(L.grid), dim3(kBlock), lds2, st, L.insts, L.items,
+                       L.n_items, L.counters + 1, L.theta);
+    hipLaunchKernelGGL(k_batch_reduce_g, dim3(Traits<MODEL>::NP, L.n_inst), dim3(kBlock), 0, st, L.insts,
+                       Traits<MODEL>::NP, L.grad);
+    return hipGetLastError();
+}
+
+template <int MODEL, typename R>
+static hipError_t batch_step_m(const BatchLaunch &L, hipStream_t st)
+{
+    switch (L.K) {
+    case 8: return batch_step_t<MODEL, R, 8>(L, st);
+    case 16: return batch_step_t<MODEL, R, 16>(L, st);
+    case 32: return batch_step_t<MODEL, R, 32>(L, st);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_batch_step(const BatchLaunch &L, hipStream_t st)
+{
+    if (L.model == kBS) return L.fp64 ? batch_step_m<kBS, double>(L, st) : batch_step_m<kBS, float>(L, st);
+    return L.fp64 ? batch_step_m<kHeston, double>(L, st) : batch_step_m<kHeston, float>(L, st);
+}
+
+int batch_blocks_per_cu(int model, bool fp64, int K, int max_m)
+{
+    int n1 = 0, n2 = 0;
+    const size_t lds1 = sizeof(double) * kWavesPerBlock * max_m;
+    const size_t lds2 = sizeof(double) * kWavesPerBlock * 5;
+#define MCAAD_OCC(M_, R_, K_)                                                                                  \
+    do {                                                                                                       \
+        (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&n1, k_batch_pass1<M_, R_, true>, kBlock, lds1);    \
+        (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&n2, k_batch_pass2<M_, R_, true, K_>, kBlock, lds2); \
+    } while (0)
+    if (model == kBS) {
+        if (fp64) { if (K == 8) MCAAD_OCC(kBS, double, 8); else if (K == 16) MCAAD_OCC(kBS, double, 16); else MCAAD_OCC(kBS, double, 32); }
+        else { if (K == 8) MCAAD_OCC(kBS, float, 8); else if (K == 16) MCAAD_OCC(kBS, float, 16); else MCAAD_OCC(kBS, float, 32); }
+    } else {
+        if (fp64) { if (K == 8) MCAAD_OCC(kHeston, double, 8); else if (K == 16) MCAAD_OCC(kHeston, double, 16); else MCAAD_OCC(kHeston, double, 32); }
+        else { if (K == 8) MCAAD_OCC(kHeston, float, 8); else if (K == 16) MCAAD_OCC(kHeston, float, 16); else MCAAD_OCC(kHeston, float, 32); }
+    }
+#undef MCAAD_OCC
+    const int n = n1 < n2 ? n1 : n2;
+    return n > 0 ? n : 1;
 }
 
 }  // namespace mcaad

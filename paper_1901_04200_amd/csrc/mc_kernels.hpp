@@ -36,6 +36,40 @@ struct DevProblem {
     const double *t_nodes;
 };
 
+// One instance of a batch: its problem plus its slices of the batch workspace.
+struct BatchInst {
+    DevProblem pb;
+    double *part_y;    // [nblocks][m]
+    double *part_g;    // [nblocks][M]
+    void *ckpt;        // [nseg][n_state][P] in the path precision
+    void *lamD;        // [m] in the path precision
+    int64_t nblocks;
+    int32_t y_off;     // first index of this instance in the concatenated C / Ey arrays
+    int32_t pad_;
+};
+
+// Everything one batched gradient step launches with.
+struct BatchLaunch {
+    int model;
+    bool fp64;
+    int K;
+    int n_inst;
+    int n_items;
+    int max_m;
+    unsigned grid;             // persistent workgroups
+    const BatchInst *insts;    // device [n_inst]
+    const int2 *items;         // device [n_items] (instance, block), longest instances first
+    unsigned *counters;        // device [2] work-queue heads of the two passes
+    const double *theta;       // device [n_inst][M]
+    const double *C;           // device, concatenated
+    double *Ey;                // device, concatenated
+    double *G;                 // device [n_inst]
+    double *grad;              // device [n_inst][M]
+};
+
+hipError_t launch_batch_step(const BatchLaunch &L, hipStream_t st);
+int batch_blocks_per_cu(int model, bool fp64, int K, int max_m);
+
 // Local-volatility passes (lv_kernels.hip).
 hipError_t launch_lv_pass1(const DevProblem &pb, bool fp64, bool store_ckpt, const double *theta, double *partial,
                            void *ckpt, int64_t nblocks, hipStream_t stream);

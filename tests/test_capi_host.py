@@ -33,9 +33,9 @@ def L():
 
 
 def test_header_declarations_are_exported(L):
-    from paper_1901_04200_amd import surrogate
+    from paper_1901_04200_amd import batch, surrogate
     names = _declared()
-    assert set(names) == set(capi.EXPORTED) | set(surrogate.EXPORTED), names
+    assert set(names) == set(capi.EXPORTED) | set(surrogate.EXPORTED) | set(batch.EXPORTED), names
     out = subprocess.run(["nm", "-D", "--defined-only", capi.LIB_PATH], capture_output=True, text=True,
                          check=True).stdout
     exported = {l.split()[-1] for l in out.splitlines() if l.strip()}
