@@ -25,19 +25,134 @@ if ROOT not in sys.path:
 METRIC = "paths·steps/s for ∇G (F_v+R_v), K_R/K_F, % FP32 VALU peak; surrogate vs MC step"
 
 
-def cpu_baseline(pb, theta, C, sample_paths):
-    """The oracle, as it stands, on the first `sample_paths` paths."""
+def cpu_baseline(pb, theta, C, sample_paths, min_seconds):
+    """The oracle, as it stands, on the first `sample_paths` paths, repeated
+    until at least `min_seconds` have passed."""
     from oracle import build as ob
     ob.build(force=False)
     from oracle import oracle as O
     sub = pb.with_(n_paths=sample_paths)
+    reps = 0
     t0 = time.perf_counter()
-    O.gradient(sub, theta, C)
-    dt = time.perf_counter() - t0
-    return {"value": sample_paths * pb.n_steps / dt, "unit": "paths*steps/s", "cores": O.get_threads(),
+    while True:
+        O.gradient(sub, theta, C)
+        reps += 1
+        dt = time.perf_counter() - t0
+        if dt >= min_seconds:
+            break
+    return {"value": reps * sample_paths * pb.n_steps / dt, "unit": "paths*steps/s", "cores": O.get_threads(),
             "kind": "oracle",
             "sample": f"full two-pass gradient (forward, reverse sweep, FP64 sums) on the first {sample_paths} "
-                      f"of the {pb.n_paths} paths, {dt:.1f} s"}
+                      f"of the {pb.n_paths} paths, {reps} time(s), {dt:.1f} s"}
+
+
+def time_ms(fn, reps):
+    import torch
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def e2_sweep(n_paths, reps=5):
+    """K_R/K_F over steps N x instruments m (128 steps per year): the paper
+    reports its coefficients nearly constant as both grow."""
+    import numpy as np
+    import torch
+    from paper_1901_04200_amd import capi, costmodel
+    from paper_1901_04200_amd import workloads as W
+    from paper_1901_04200_amd.mc import MonteCarloCalibration
+    th = W.heston_draws(2, 10)[9]
+    rows = []
+    for N in (32, 64, 128, 256, 512):
+        for ns, nm in ((8, 1), (8, 5), (24, 5), (40, 5)):
+            t_max = N / 128.0
+            st, kk = W.heston_instruments(ns, np.linspace(t_max / nm, t_max, nm), 128)
+            pb = W.Problem(model=W.MODEL_HESTON, n_params=5, n_steps=N, n_paths=n_paths, t_max=t_max,
+                           instr_step=st, instr_strike=kk)
+            mc = MonteCarloCalibration(pb)
+            C = torch.full((pb.n_instr,), 5.0, dtype=torch.float64, device="cuda")
+            thd = torch.tensor(th, device="cuda")
+            Ey = torch.empty(pb.n_instr, dtype=torch.float64, device="cuda")
+            G = torch.empty(1, dtype=torch.float64, device="cuda")
+            g = torch.empty(5, dtype=torch.float64, device="cuda")
+            capi.calibrate_gradient(mc.ctx, thd, C, Ey, G, g)
+            capi.cal_timing_enable(mc.ctx, True)
+            for _ in range(reps):
+                capi.calibrate_forward(mc.ctx, thd, Ey)
+            tf = capi.cal_timing_read(mc.ctx, 0)
+            capi.cal_timing_enable(mc.ctx, True)
+            for _ in range(reps):
+                capi.calibrate_gradient(mc.ctx, thd, C, Ey, G, g)
+            t2 = capi.cal_timing_read(mc.ctx, 1)
+            capi.cal_timing_enable(mc.ctx, False)
+            mc.close()
+            kr = costmodel.kr_over_kf(tf[0] / tf[1], t2[0] / t2[1])
+            rows.append({"N": N, "m": pb.n_instr, "kr_over_kf": round(kr, 4)})
+    return rows
+
+
+def batched_leg(n_inst, reps):
+    """The batched workload: n_inst Heston instances with m ~ U{8..120},
+    P in {2^14, 2^16, 2^18}, N in {64, 128, 256}; one captured step per
+    gradient, autotuned, against the same instances one context at a time."""
+    import numpy as np
+    import torch
+    from paper_1901_04200_amd import capi
+    from paper_1901_04200_amd import workloads as W
+    from paper_1901_04200_amd.batch import BatchCalibration
+    from paper_1901_04200_amd.mc import MonteCarloCalibration
+    insts = W.batched_instances(n_inst)
+    pbs = [pb for pb, *_ in insts]
+    th0 = torch.tensor(np.array([t for _, t, _, _ in insts]), device="cuda")
+    tht = torch.tensor(np.array([t for _, _, t, _ in insts]), device="cuda")
+    B = BatchCalibration(pbs)
+    zero = torch.zeros(int(B.offsets[-1]), dtype=torch.float64, device="cuda")
+    Ey_t, _, _ = B.gradient(tht, zero)         # prices at the target draws
+    eps = np.concatenate([e for _, _, _, e in insts])
+    C = Ey_t.clone() * torch.tensor(1.0 + 1e-3 * eps, device="cuda")
+    best, table = B.autotune(th0, C, reps=2)
+    ms_graph = time_ms(B.replay, reps)
+    flags = B.status()
+    path_steps = sum(pb.n_paths * pb.n_steps for pb in pbs)
+    Cs = B.split(C)
+    mcs = [MonteCarloCalibration(pb, ckpt_every=best[0]) for pb in pbs]
+    ths = [th0[i].contiguous() for i in range(n_inst)]
+    Cs = [c.contiguous() for c in Cs]
+    outs = [(torch.empty(pb.n_instr, dtype=torch.float64, device="cuda"),
+             torch.empty(1, dtype=torch.float64, device="cuda"),
+             torch.empty(5, dtype=torch.float64, device="cuda")) for pb in pbs]
+
+    def sequential():
+        for i, mc in enumerate(mcs):
+            capi.calibrate_gradient(mc.ctx, ths[i], Cs[i], *outs[i])
+
+    sequential()
+    ms_seq = time_ms(sequential, max(1, reps // 2))
+    for mc in mcs:
+        mc.close()
+    B.close()
+    return {"instances": n_inst, "path_steps": path_steps, "status": flags,
+            "autotuned": {"ckpt_every": best[0], "workgroups_per_cu": best[1],
+                          "candidates_ms": {f"k{c[0]}_w{c[1]}": round(t * 1e3, 3) for c, t in table}},
+            "ms_graph_step": ms_graph, "paths_steps_per_s": path_steps / (ms_graph * 1e-3),
+            "ms_one_context_at_a_time": ms_seq, "speedup": ms_seq / ms_graph}
+
+
+def copy_probe(nbytes):
+    """A plain device-to-device copy of nbytes (3 launches): what the HBM
+    counters read for it scales their readings on the calibration kernels."""
+    import torch
+    a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").uniform_()
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes": nbytes, "launches": 3}), flush=True)
 
 
 def main():
@@ -49,8 +164,20 @@ def main():
     ap.add_argument("--ckpt-mode", default="store", choices=["store", "rerun"])
     ap.add_argument("--ckpt-every", type=int, default=16)
     ap.add_argument("--cpu-sample-paths", type=int, default=1 << 20)
+    ap.add_argument("--cpu-min-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true", help="skip the sweep, batched and surrogate legs")
+    ap.add_argument("--sweep-paths", type=int, default=1 << 20)
+    ap.add_argument("--batch-instances", type=int, default=256)
+    ap.add_argument("--surrogate-draws", type=int, default=1 << 16)
+    ap.add_argument("--surrogate-paths", type=int, default=1 << 16)
+    ap.add_argument("--surrogate-epochs", type=int, default=150)
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
+                    help="only run a plain copy of BYTES (HBM counter scaling) and exit")
     args = ap.parse_args()
+    if args.copy_probe:
+        copy_probe(args.copy_probe)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU sharding of "
               f"paths is described in DESIGN.md, not run.", file=sys.stderr)
@@ -172,11 +299,34 @@ def main():
             "traffic": None,
         },
     }
+    mc.close()
+    if not args.no_extras:
+        legs = (("e2_sweep", lambda: e2_sweep(args.sweep_paths)),
+                ("batched", lambda: batched_leg(args.batch_instances, max(3, args.steps // 4))),
+                ("surrogate_vs_mc", lambda: surrogate_leg(args)))
+        for name, fn in legs:
+            print(f"bench: {name} ...", file=sys.stderr, flush=True)
+            try:
+                out[name] = fn()
+            except Exception as exc:   # a failing extra leg must not hide the headline numbers
+                out[name] = {"error": f"{type(exc).__name__}: {exc}"}
+            print(f"bench: {name} done", file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
         print("bench: oracle CPU baseline ...", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(pb, th0, C.cpu().numpy(), args.cpu_sample_paths)
-    mc.close()
+        out["cpu_baseline"] = cpu_baseline(pb, th0, C.cpu().numpy(), args.cpu_sample_paths,
+                                           args.cpu_min_seconds)
     print(json.dumps(out), flush=True)
+
+
+def surrogate_leg(args):
+    from paper_1901_04200_amd import surrogate_study
+    res = surrogate_study.run(n_train=args.surrogate_draws, train_paths=args.surrogate_paths,
+                              epochs=args.surrogate_epochs,
+                              log=lambda s: print("bench: " + s, file=sys.stderr, flush=True))
+    st = res["step_seconds"]
+    return {"grad_rel_err_surrogate": res["surrogate_grad_rel_err"]["median"], "p_star_paths": res["p_star"],
+            "us_surrogate_step": st["surrogate"] * 1e6, "us_mc_step_at_p_star": st["mc_at_p_star"] * 1e6,
+            "mc_over_surrogate": st["mc_over_surrogate"], "details": res}
 
 
 if __name__ == "__main__":
