@@ -46,6 +46,36 @@ def cpu_baseline(pb, theta, C, sample_paths, min_seconds):
                       f"of the {pb.n_paths} paths, {reps} time(s), {dt:.1f} s"}
 
 
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "mc_kernels_heston_2p20x256_hbm_counters.md")
+
+
+def code_hash(path):
+    """sha256 of a source with comments and whitespace removed."""
+    import hashlib
+    import re
+    text = open(path).read()
+    text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", " ", text)
+    return hashlib.sha256(" ".join(text.split()).encode()).hexdigest()
+
+
+def pass2_traffic():
+    """HBM bytes per pass-2 launch from the committed counter summary, or None
+    when any source of that kernel has changed since the counters were taken."""
+    try:
+        lines = open(TRAFFIC_PROFILE).read().splitlines()
+    except OSError:
+        return None
+    value, ok = None, True
+    for ln in lines:
+        f = ln.split()
+        if len(f) == 2 and f[0] == "k_pass2_bytes_per_launch":
+            value = float(f[1])
+        elif len(f) == 3 and f[0] == "code-sha256":
+            ok = ok and os.path.exists(os.path.join(ROOT, f[1])) and code_hash(os.path.join(ROOT, f[1])) == f[2]
+    return value if ok else None
+
+
 def time_ms(fn, reps):
     import torch
     torch.cuda.synchronize()
@@ -296,7 +326,10 @@ def main():
             "peak": roofline.PEAK_SLOTS / 1e12,
             "unit": "T VALU lane-slots/s",
             "frac": achieved / roofline.PEAK_SLOTS,
-            "traffic": None,
+            "traffic": pass2_traffic(),
+            "traffic_unit": "HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-scaled)",
+            "traffic_algorithmic": roofline.pass2_bytes(pb.n_paths, geo["ckpt_every"], geo["blocks"], pb.n_instr,
+                                                        pb.n_steps),
         },
     }
     mc.close()

@@ -26,15 +26,18 @@ def flags(extra=()):
 
 def build(verbose: bool = False, resource_usage: bool = False) -> str:
     os.makedirs(LIBDIR, exist_ok=True)
-    objs = []
+    objs, procs = [], []
     extra = ["-Rpass-analysis=kernel-resource-usage"] if resource_usage else []
-    for src in SOURCES:
+    for src in SOURCES:   # one hipcc per source, all at once
         obj = os.path.join(LIBDIR, os.path.splitext(src)[0] + ".o")
         cmd = [HIPCC, *flags(extra), "-c", os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
-        subprocess.run(cmd, check=True)
+        procs.append((src, subprocess.Popen(cmd)))
         objs.append(obj)
+    failed = [src for src, p in procs if p.wait() != 0]
+    if failed:
+        raise RuntimeError("hipcc failed on " + ", ".join(failed))
     tmp = LIB + ".tmp"
     subprocess.run([HIPCC, "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp, *objs], check=True)
     os.replace(tmp, LIB)

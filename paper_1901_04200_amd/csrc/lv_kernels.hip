@@ -144,11 +144,8 @@ __global__ __launch_bounds__(kBlock) void k_lv_pass1(DevProblem pb, const double
                 x = x + (rh - hh * c.sig * c.sig) + (sq * c.sig) * z[j];
                 if (n + 1 == next) {
                     const double Sd = (double)(s0 * exp_t(x));
-                    for (int k = pb.date_begin[d]; k < pb.date_begin[d + 1]; ++k) {
-                        double y = active ? pb.disc[k] * fmax(Sd - pb.strike[k], 0.0) : 0.0;
-                        y = wave_sum(y);
-                        if (lane == 0) L.dbl[wave * pb.m + k] = y;
-                    }
+                    payoff_sums(pb.strike, pb.disc, Sd, active, lane, pb.date_begin[d], pb.date_begin[d + 1],
+                                L.dbl + wave * pb.m);
                     ++d;
                     next = d < pb.ndates ? pb.date_step[d] : -1;
                 }

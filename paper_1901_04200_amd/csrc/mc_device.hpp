@@ -106,13 +106,118 @@ __device__ __forceinline__ void normals4(uint32_t call, uint32_t path, uint32_t 
     }
 }
 
-// Butterfly sum over the 64 lanes of a wavefront; every lane receives the
-// total.  The pairing order is fixed, so the FP64 result is deterministic.
+// ---------------------------------------------------------------------------
+// Wavefront sums of FP64 values, with no LDS traffic: the two halves of the
+// wave and the row pairs (rows = 16 lanes) are exchanged with gfx950's
+// v_permlane32_swap / v_permlane16_swap, the steps inside a row with DPP
+// moves.  A double moves as two 32-bit halves.
+//
+// Every sum follows one fixed tree: lane l with l+32, then rows 2r with
+// 2r+1, then lane i of a row with lane 15-i, then i with 7-i inside each
+// half row, then quad partners 2 apart, then 1 apart.  Each step adds two
+// operands that are exchanged between partner lanes, so partners compute the
+// same sum (FP64 addition commutes) and the result is deterministic and
+// identical in every lane that holds it.
+// ---------------------------------------------------------------------------
+namespace lanes {
+
+__device__ __forceinline__ uint32_t lo32(double v) { return (uint32_t)__builtin_bit_cast(uint64_t, v); }
+__device__ __forceinline__ uint32_t hi32(double v) { return (uint32_t)(__builtin_bit_cast(uint64_t, v) >> 32); }
+__device__ __forceinline__ double join(uint32_t lo, uint32_t hi)
+{
+    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
+constexpr int kQuadXor1 = 0xB1;        // quad_perm [1,0,3,2]
+constexpr int kQuadXor2 = 0x4E;        // quad_perm [2,3,0,1]
+constexpr int kRowHalfMirror = 0x141;  // lane i of each 8 reads lane 7-i
+constexpr int kRowMirror = 0x140;      // lane i of each 16 reads lane 15-i
+
+template <int CTRL>
+__device__ __forceinline__ double dpp(double v)
+{
+    return join(__builtin_amdgcn_update_dpp(0u, lo32(v), CTRL, 0xF, 0xF, false),
+                __builtin_amdgcn_update_dpp(0u, hi32(v), CTRL, 0xF, 0xF, false));
+}
+
+// v_permlane32_swap(a, b) exchanges lanes 32..63 of a with lanes 0..31 of b:
+// afterwards a = (a's lanes 0..31, b's lanes 0..31) and b = (a's lanes
+// 32..63, b's lanes 32..63), so a + b is, in lanes 0..31, the sum of a over
+// lanes l and l+32, and in lanes 32..63 the sum of b over lanes l-32 and l.
+__device__ __forceinline__ double fold32(double a, double b)
+{
+    const auto L = __builtin_amdgcn_permlane32_swap(lo32(a), lo32(b), false, false);
+    const auto H = __builtin_amdgcn_permlane32_swap(hi32(a), hi32(b), false, false);
+    return join(L[0], H[0]) + join(L[1], H[1]);
+}
+
+// v_permlane16_swap(a, b) exchanges the odd rows of a with the even rows of
+// b: afterwards each row pair of a holds a's even row then b's even row, and
+// of b a's odd row then b's odd row, so a + b is, in even rows, the sum of a
+// over the row pair, and in odd rows the sum of b over the row pair.
+__device__ __forceinline__ double fold16(double a, double b)
+{
+    const auto L = __builtin_amdgcn_permlane16_swap(lo32(a), lo32(b), false, false);
+    const auto H = __builtin_amdgcn_permlane16_swap(hi32(a), hi32(b), false, false);
+    return join(L[0], H[0]) + join(L[1], H[1]);
+}
+
+// the steps inside a row; the caller has already folded halves and row pairs
+__device__ __forceinline__ double row_tail(double v)
+{
+    v += dpp<kRowHalfMirror>(v);
+    v += dpp<kQuadXor2>(v);
+    v += dpp<kQuadXor1>(v);
+    return v;
+}
+
+}  // namespace lanes
+
+// Sum over the 64 lanes; every lane receives the total.  Must be called with
+// all 64 lanes active.
 __device__ __forceinline__ double wave_sum(double v)
 {
+    v = lanes::fold32(v, v);
+    v = lanes::fold16(v, v);
+    v += lanes::dpp<lanes::kRowMirror>(v);
+    return lanes::row_tail(v);
+}
+
+// Eight sums at once: a[j] summed over the 64 lanes for j = 0..7, at the
+// cost of about ten single-value steps instead of 48.  The total of a[j] is
+// returned in the eight lanes 8j..8j+7 (j = lane / 8); it is bitwise the
+// value wave_sum(a[j]) gives.  Must be called with all 64 lanes active.
+__device__ __forceinline__ double wave_sum8(const double a[8])
+{
+    const int lane = (int)(threadIdx.x & (kWave - 1));
+    double b[4], c[2];
 #pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, kWave);
-    return v;
+    for (int i = 0; i < 4; ++i) b[i] = lanes::fold32(a[i], a[i + 4]);        // lanes 0..31: a[i]; 32..63: a[i+4]
+#pragma unroll
+    for (int i = 0; i < 2; ++i) c[i] = lanes::fold16(b[i], b[i + 2]);        // even rows: b[i]; odd rows: b[i+2]
+    const bool up = lane & 8;                                                 // lanes 8..15 of a row keep c[1]
+    const double keep = up ? c[1] : c[0];
+    const double send = up ? c[0] : c[1];
+    return lanes::row_tail(keep + lanes::dpp<lanes::kRowMirror>(send));
+}
+
+// Wave totals of the discounted call payoffs disc[k] max(S - strike[k], 0),
+// k in [kb, ke) (the instruments maturing at one date), eight instruments per
+// wave_sum8; lanes with active == false add 0.  Total k goes to out[k].
+__device__ __forceinline__ void payoff_sums(const double *__restrict__ strike, const double *__restrict__ disc,
+                                            double S, bool active, int lane, int kb, int ke, double *out)
+{
+    for (int k0 = kb; k0 < ke; k0 += 8) {
+        double a[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const int k = k0 + i < ke ? k0 + i : ke - 1;   // stays inside the table
+            a[i] = active && k0 + i < ke ? disc[k] * fmax(S - strike[k], 0.0) : 0.0;
+        }
+        const double y = wave_sum8(a);
+        const int k = k0 + (lane >> 3);
+        if ((lane & 7) == 0 && k < ke) out[k] = y;
+    }
 }
 
 }  // namespace mcaad

@@ -2,8 +2,9 @@
 //
 // One path per lane, path state in VGPRs, normals regenerated from the
 // counter-based Philox stream whenever they are needed (never stored), FP64
-// sums over paths: wavefront butterfly -> LDS (one slot per wave) -> one
-// FP64 partial per workgroup -> fixed-order final sum in a separate kernel.
+// sums over paths: wavefront sum by cross-lane moves (eight values per
+// reduction where there are several) -> LDS (one slot per wave) -> one FP64
+// partial per workgroup -> fixed-order final sum in a separate kernel.
 //
 //  pass 1 (paper: algorithm step 1, cost eq. 1211A)
 //      Euler sweep F_v, payoffs at maturity dates, block partials of sum y_i;
@@ -203,11 +204,8 @@ __device__ __forceinline__ void pass1_block(const DevProblem &pb, const double *
                 euler_step<MODEL, R>(c, x, v, z + j * T::D);
                 if (n + 1 == next) {
                     const double S = (double)(c.s0 * exp_r(x));
-                    for (int k = pb.date_begin[d]; k < pb.date_begin[d + 1]; ++k) {
-                        double y = active ? pb.disc[k] * fmax(S - pb.strike[k], 0.0) : 0.0;
-                        y = wave_sum(y);
-                        if (lane == 0) lds[wave * pb.m + k] = y;
-                    }
+                    payoff_sums(pb.strike, pb.disc, S, active, lane, pb.date_begin[d], pb.date_begin[d + 1],
+                                lds + wave * pb.m);
                     ++d;
                     next = d < pb.ndates ? pb.date_step[d] : -1;
                 }
@@ -367,11 +365,12 @@ __device__ __forceinline__ void pass2_block(const DevProblem &pb, const double *
     }
     if constexpr (MODEL == kHeston) g[4] += (double)vb;   // v_0 is theta[4]
 
+    static_assert(NP <= 8, "one wave_sum8 per path's gradient");
+    double a[8];
 #pragma unroll
-    for (int j = 0; j < NP; ++j) {
-        const double t = wave_sum(active ? g[j] : 0.0);
-        if (lane == 0) lds[wave * NP + j] = t;
-    }
+    for (int j = 0; j < 8; ++j) a[j] = j < NP && active ? g[j] : 0.0;
+    const double t = wave_sum8(a);
+    if ((lane & 7) == 0 && (lane >> 3) < NP) lds[wave * NP + (lane >> 3)] = t;
     __syncthreads();
     if (tid < NP) {
         double s = lds[tid];
@@ -402,6 +401,7 @@ __global__ __launch_bounds__(kBlock) void k_tangent(DevProblem pb, const double 
     using T = Traits<MODEL>;
     constexpr int NP = T::NP;
     constexpr int W = NP + 1;
+    static_assert(W <= 8, "E y and its derivatives in one wave_sum8");
     extern __shared__ double lds[];   // [kWavesPerBlock][m * W]
     const int tid = threadIdx.x;
     const int lane = tid & (kWave - 1);
@@ -464,16 +464,15 @@ __global__ __launch_bounds__(kBlock) void k_tangent(DevProblem pb, const double 
                 if (n + 1 == next) {
                     const double S = (double)(c.s0 * exp_r(x));
                     for (int k = pb.date_begin[d]; k < pb.date_begin[d + 1]; ++k) {
+                        // y and its NP derivatives, one wave_sum8
                         const bool itm = active && S > pb.strike[k];
-                        double y = itm ? pb.disc[k] * (S - pb.strike[k]) : 0.0;
-                        y = wave_sum(y);
-                        if (lane == 0) lds[wave * pb.m * W + k * W] = y;
                         const double dS = itm ? pb.disc[k] * S : 0.0;
+                        double a[8];
+                        a[0] = itm ? pb.disc[k] * (S - pb.strike[k]) : 0.0;
 #pragma unroll
-                        for (int q = 0; q < NP; ++q) {
-                            const double t = wave_sum(dS * (double)xd[q]);
-                            if (lane == 0) lds[wave * pb.m * W + k * W + 1 + q] = t;
-                        }
+                        for (int q = 1; q < 8; ++q) a[q] = q <= NP ? dS * (double)xd[q <= NP ? q - 1 : 0] : 0.0;
+                        const double t = wave_sum8(a);
+                        if ((lane & 7) == 0 && (lane >> 3) < W) lds[wave * pb.m * W + k * W + (lane >> 3)] = t;
                     }
                     ++d;
                     next = d < pb.ndates ? pb.date_step[d] : -1;

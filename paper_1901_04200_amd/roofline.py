@@ -63,3 +63,13 @@ def per_path_step(model: str, kernel: str) -> dict:
     if kernel == "pass2_rerun":
         return add(add(F, F), R)
     raise ValueError(kernel)
+
+
+def pass2_bytes(n_paths: int, ckpt_every: int, n_blocks: int, n_instr: int, n_steps: int,
+                n_state: int = 2, n_params: int = 5, real_bytes: int = 4) -> int:
+    """Algorithmic HBM bytes of one pass-2 launch from stored checkpoints:
+    every path's state at the start of each K-step segment is read once, one
+    FP64 partial per workgroup and parameter is written, and the m seeds
+    lambda_i D_i / P are read."""
+    n_seg = -(-n_steps // ckpt_every)
+    return n_seg * n_state * n_paths * real_bytes + n_blocks * n_params * 8 + n_instr * real_bytes
