@@ -78,8 +78,8 @@ typedef struct cal_ctx cal_ctx;
  *   ckpt_every (k)    : 0 = auto, else 8, 16 or 32 steps between checkpoints
  *   ckpt_mode         : CAL_CKPT_*
  *   s0, rate, t_max   : spot, risk-free rate (drift and discounting), horizon
- *   sqrt_eps          : Heston only; 0 = plain full truncation (s = sqrt(v+));
- *                       > 0 replaces sqrt below eps by v(3 - v/eps)/(2 sqrt(eps))
+ *   sqrt_eps          : must be 0 (plain full truncation, s = sqrt(v+)); any
+ *                       other finite value >= 0 is refused with CAL_EUNSUPPORTED
  *   instr_step[m]     : maturity step of call i, 1..N (maturity = step * t_max / N)
  *   instr_strike[m]   : strike of call i (>= 0)
  * Random numbers: normal q of path p is Box-Muller of the uniforms

@@ -96,15 +96,17 @@ static std::string validate(const cal_problem *pb, int *code)
     if (!(pb->t_max > 0.0) || !std::isfinite(pb->t_max)) return "t_max must be positive";
     if (!std::isfinite(pb->rate)) return "rate must be finite";
     if (!(pb->sqrt_eps >= 0.0) || !std::isfinite(pb->sqrt_eps)) return "sqrt_eps must be finite and >= 0";
+    if (pb->sqrt_eps != 0.0) {
+        *code = CAL_EUNSUPPORTED;
+        return "sqrt_eps must be 0: the device path runs plain full truncation";
+    }
     if (pb->ckpt_every != 0 && pb->ckpt_every != 8 && pb->ckpt_every != 16 && pb->ckpt_every != 32)
         return "ckpt_every must be 0, 8, 16 or 32";
     if (pb->ckpt_mode < CAL_CKPT_AUTO || pb->ckpt_mode > CAL_CKPT_STORE) return "unknown ckpt_mode";
     if (pb->max_batch < 0 || pb->max_batch > 65535) return "max_batch must be in 0..65535";
     if (pb->model == CAL_BS && pb->n_params != 1) return "Black-Scholes takes n_params = 1";
     if (pb->model == CAL_HESTON && pb->n_params != 5) return "Heston takes n_params = 5";
-    if (pb->model == CAL_BS && pb->sqrt_eps != 0.0) return "sqrt_eps applies to Heston only";
     if (pb->model == CAL_LV) {
-        if (pb->sqrt_eps != 0.0) return "sqrt_eps applies to Heston only";
         const int nT = pb->n_t_nodes, nK = pb->n_k_nodes;
         if (nT < 2 || nK < 2 || nT > 64 || nK > 64) return "local vol needs 2..64 time and spot nodes";
         if (!pb->t_nodes || !pb->k_nodes) return "null node arrays";
@@ -276,12 +278,10 @@ extern "C" int cal_create(const cal_problem *pb, cal_ctx **out)
     d.k0 = (uint32_t)pb->seed;
     d.k1 = (uint32_t)(pb->seed >> 32);
     d.inst = pb->inst;
-    d.use_eps = pb->sqrt_eps > 0.0;
     d.s0 = pb->s0;
     d.rate = pb->rate;
     d.h = h;
     d.sq = std::sqrt(h);
-    d.sqrt_eps = pb->sqrt_eps;
     d.date_step = c->d_date_step;
     d.date_begin = c->d_date_begin;
     d.strike = c->d_strike;
@@ -688,13 +688,11 @@ extern "C" int calb_create(const cal_problem *problems, int32_t n_inst, calb_ctx
         d.k0 = (uint32_t)pb->seed;
         d.k1 = (uint32_t)(pb->seed >> 32);
         d.inst = pb->inst;
-        d.use_eps = pb->sqrt_eps > 0.0;
-        d.s0 = pb->s0;
+            d.s0 = pb->s0;
         d.rate = pb->rate;
         d.h = h;
         d.sq = std::sqrt(h);
-        d.sqrt_eps = pb->sqrt_eps;
-        I.nblocks = nblocks[i];
+            I.nblocks = nblocks[i];
         I.y_off = (int32_t)c->offsets[i];
     }
     hipError_t e = hipSuccess;

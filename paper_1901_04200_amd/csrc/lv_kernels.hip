@@ -131,7 +131,7 @@ __global__ __launch_bounds__(kBlock) void k_lv_pass1(DevProblem pb, const double
     const int ncalls = (pb.N + 3) / 4;
     for (int call = 0; call < ncalls; ++call) {
         R z[4];
-        normals4<R>((uint32_t)call, path, pb.inst, pb.k0, pb.k1, z);
+        normals4<R>((uint32_t)call, path, pb.inst, pb.k0, pb.k1, box_muller_scale<R>(1.0), z);
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             const int n = call * 4 + j;
@@ -212,7 +212,7 @@ __global__ __launch_bounds__(kBlock) void k_lv_pass2(DevProblem pb, const double
         const int ncalls = (pb.N + 3) / 4;
         for (int call = 0; call < ncalls; ++call) {
             R z[4];
-            normals4<R>((uint32_t)call, path, pb.inst, pb.k0, pb.k1, z);
+            normals4<R>((uint32_t)call, path, pb.inst, pb.k0, pb.k1, box_muller_scale<R>(1.0), z);
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
                 const int n = call * 4 + j;
@@ -246,7 +246,7 @@ __global__ __launch_bounds__(kBlock) void k_lv_pass2(DevProblem pb, const double
             s_z[j] = (R)0;
             s_S[j] = (R)0;
             if (n < pb.N) {
-                if (j % 4 == 0) normals4<R>((uint32_t)(n / 4), path, pb.inst, pb.k0, pb.k1, z);
+                if (j % 4 == 0) normals4<R>((uint32_t)(n / 4), path, pb.inst, pb.k0, pb.k1, box_muller_scale<R>(1.0), z);
                 const R S = s0 * exp_t(x);
                 const Cell<R> c = locate<R>(pb, L.rows + n * pb.nK, S, K0, invdK, Klast);
                 s_S[j] = S;

@@ -11,6 +11,16 @@ constexpr int kWave = 64;
 constexpr int kBlock = 256;          // 4 waves per workgroup
 constexpr int kWavesPerBlock = kBlock / kWave;
 
+// Read element i of a table that no kernel writes while the reading kernel
+// runs (instrument tables, seeds): through the constant address space, so a
+// uniform index becomes a scalar load even when the table's pointer was itself
+// loaded from memory (batched instances), where the compiler cannot prove it.
+template <typename T>
+__device__ __forceinline__ T ldc(const T *p, int i)
+{
+    return ((const __attribute__((address_space(4))) T *)p)[i];
+}
+
 // a ^ b ^ k in one VALU instruction (k uniform, in a scalar register):
 // gfx950's three-input bitwise op with truth table 0x96 (odd parity), which
 // is symmetric in its operands.  (gfx9 has no v_xor3_b32.)
@@ -59,9 +69,12 @@ __device__ __forceinline__ void philox4x32_10(uint32_t c0, uint32_t c1, uint32_t
 }
 
 // Uniform in (0,1): ((w >> 9) + 0.5) * 2^-23, exact in FP32 and FP64.
+// FP32: one v_alignbit_b32 builds the float 1 + (w >> 9) 2^-23 (exponent bits
+// 0x7F above the 23 high bits of w), and subtracting 1 - 2^-24 is exact
+// (Sterbenz), so the value is the same as the textbook formula's.
 __device__ __forceinline__ float uniform_f32(uint32_t w)
 {
-    return ((float)(w >> 9) + 0.5f) * 0x1p-23f;
+    return __uint_as_float(__builtin_amdgcn_alignbit(0x7Fu, w, 9u)) - 0x1.fffffep-1f;
 }
 
 __device__ __forceinline__ double uniform_f64(uint32_t w)
@@ -69,40 +82,49 @@ __device__ __forceinline__ double uniform_f64(uint32_t w)
     return ((double)(w >> 9) + 0.5) * 0x1p-23;
 }
 
-// Box-Muller on one pair: rho = sqrt(-2 ln u0), (rho cos 2pi u1, rho sin 2pi u1).
-// FP32 uses the hardware transcendentals: v_log_f32 (log2), v_sqrt_f32 and
+// Box-Muller on one pair, scaled by sqrt(h): rho = sqrt(-2 h ln u0),
+// (rho cos 2pi u1, rho sin 2pi u1).  bm is the constant under the root:
+// -2 ln(2) h in FP32, which multiplies v_log_f32 (log2), and -2 h in FP64.
+// FP32 uses the hardware transcendentals: v_log_f32, v_sqrt_f32 and
 // v_sin/v_cos_f32, whose argument is in revolutions, so 2 pi u1 needs no
 // multiply and no range reduction.
-__device__ __forceinline__ void box_muller(float u0, float u1, float &z0, float &z1)
+template <typename R>
+__device__ __forceinline__ R box_muller_scale(double h)
 {
-    const float m2ln2 = -1.3862943611198906f;   // -2 ln 2
-    const float rho = __builtin_amdgcn_sqrtf(m2ln2 * __builtin_amdgcn_logf(u0));
+    if constexpr (sizeof(R) == 4) return (float)(-2.0 * 0.69314718055994530942 * h);
+    else return -2.0 * h;
+}
+
+__device__ __forceinline__ void box_muller(float u0, float u1, float bm, float &z0, float &z1)
+{
+    const float rho = __builtin_amdgcn_sqrtf(bm * __builtin_amdgcn_logf(u0));
     z0 = rho * __builtin_amdgcn_cosf(u1);
     z1 = rho * __builtin_amdgcn_sinf(u1);
 }
 
-__device__ __forceinline__ void box_muller(double u0, double u1, double &z0, double &z1)
+__device__ __forceinline__ void box_muller(double u0, double u1, double bm, double &z0, double &z1)
 {
-    const double rho = sqrt(-2.0 * log(u0));
+    const double rho = sqrt(bm * log(u0));
     double s, c;
     sincospi(2.0 * u1, &s, &c);
     z0 = rho * c;
     z1 = rho * s;
 }
 
-// Four normals of one Philox call (counter (call, path, inst, 0)).
+// Four normals of one Philox call (counter (call, path, inst, 0)), each
+// scaled by sqrt(h) for bm = box_muller_scale(h).
 template <typename R>
-__device__ __forceinline__ void normals4(uint32_t call, uint32_t path, uint32_t inst, uint32_t k0, uint32_t k1,
+__device__ __forceinline__ void normals4(uint32_t call, uint32_t path, uint32_t inst, uint32_t k0, uint32_t k1, R bm,
                                          R z[4])
 {
     uint32_t w[4];
     philox4x32_10(call, path, inst, 0u, k0, k1, w);
     if constexpr (sizeof(R) == 4) {
-        box_muller(uniform_f32(w[0]), uniform_f32(w[1]), z[0], z[1]);
-        box_muller(uniform_f32(w[2]), uniform_f32(w[3]), z[2], z[3]);
+        box_muller(uniform_f32(w[0]), uniform_f32(w[1]), bm, z[0], z[1]);
+        box_muller(uniform_f32(w[2]), uniform_f32(w[3]), bm, z[2], z[3]);
     } else {
-        box_muller(uniform_f64(w[0]), uniform_f64(w[1]), z[0], z[1]);
-        box_muller(uniform_f64(w[2]), uniform_f64(w[3]), z[2], z[3]);
+        box_muller(uniform_f64(w[0]), uniform_f64(w[1]), bm, z[0], z[1]);
+        box_muller(uniform_f64(w[2]), uniform_f64(w[3]), bm, z[2], z[3]);
     }
 }
 
@@ -212,7 +234,7 @@ __device__ __forceinline__ void payoff_sums(const double *__restrict__ strike, c
 #pragma unroll
         for (int i = 0; i < 8; ++i) {
             const int k = k0 + i < ke ? k0 + i : ke - 1;   // stays inside the table
-            a[i] = active && k0 + i < ke ? disc[k] * fmax(S - strike[k], 0.0) : 0.0;
+            a[i] = active && k0 + i < ke ? ldc(disc, k) * fmax(S - ldc(strike, k), 0.0) : 0.0;
         }
         const double y = wave_sum8(a);
         const int k = k0 + (lane >> 3);

@@ -27,31 +27,27 @@ namespace mcaad {
 
 // ---------------------------------------------------------------------------
 // Model constants, computed per lane from theta (uniform values)
+//
+// Variables of the sweeps (same maps as the paper's F, rewritten to save
+// instructions; the oracle keeps the textbook form):
+//   z'  = sqrt(h) z: the normals come out of Box-Muller already scaled
+//         (h goes under its square root), so no step multiplies by sqrt(h);
+//   x~  = x - n r h: the log-price without its deterministic drift, which is
+//         added back only where a payoff needs S = s0 exp(x~ + n r h);
+//   w'  = rho z1' + rho' z2', the variance shock, rho' = sqrt(1 - rho^2).
+// Black-Scholes:  x~ <- x~ - sigma^2 h / 2 + sigma z'
+// Heston:         x~ <- x~ - (h/2) v+ + s z1'
+//                 v  <- v + (kappa theta_bar h - kappa h v+) + xi s w'
+//                 with v+ = max(v, 0), s = sqrt(v+) (full truncation).
 // ---------------------------------------------------------------------------
 template <typename R>
 struct Consts {
-    R s0, sq;
-    // Black-Scholes: x += (r - sigma^2/2) h + sigma sq z
-    R bs_drift, bs_vol, bs_gh;
-    // Heston (theta = kappa, theta_bar, xi, rho, v0)
-    R rh, hh, kh, khth, xsq, rho, rhop, rr, thbh, h, v0;
-    R eps, e_c1, e_c2;
-    int use_eps;
+    R s0, rh, bm;          // spot, r h, Box-Muller constant for normals scaled by sqrt(h)
+    R bs_drift, bs_vol, bs_gh;   // -sigma^2 h/2, sigma, -sigma h
+    R hh, kh, khth, xi, rho, rhop, thbh, h, v0;
+    // FP64 factors turning a segment's FP32 sums into gradient terms (Heston)
+    double g_kh, g_rho;   // kappa h, xi / (1 - rho^2)
 };
-
-template <typename R>
-__device__ __forceinline__ R sqrt_r(R v)
-{
-    if constexpr (sizeof(R) == 4) return __builtin_amdgcn_sqrtf(v);
-    else return sqrt(v);
-}
-
-template <typename R>
-__device__ __forceinline__ R half_rcp(R s)
-{
-    if constexpr (sizeof(R) == 4) return 0.5f * __builtin_amdgcn_rcpf(s);
-    else return 0.5 / s;
-}
 
 template <typename R>
 __device__ __forceinline__ R exp_r(R x)
@@ -64,67 +60,86 @@ template <int MODEL, typename R>
 __device__ __forceinline__ void load_consts(const DevProblem &pb, const double *th, Consts<R> &c)
 {
     c.s0 = (R)pb.s0;
-    c.sq = (R)pb.sq;
+    c.rh = (R)(pb.rate * pb.h);
+    c.bm = box_muller_scale<R>(pb.h);
     if constexpr (MODEL == kBS) {
         const double sig = th[0];
-        c.bs_drift = (R)((pb.rate - 0.5 * sig * sig) * pb.h);
-        c.bs_vol = (R)(sig * pb.sq);
+        c.bs_drift = (R)(-0.5 * sig * sig * pb.h);
+        c.bs_vol = (R)sig;
         c.bs_gh = (R)(-sig * pb.h);
     } else {
         const double kap = th[0], thb = th[1], xi = th[2], rho = th[3], v0 = th[4];
-        const double rhop = sqrt(1.0 - rho * rho);
-        c.rh = (R)(pb.rate * pb.h);
         c.hh = (R)(0.5 * pb.h);
         c.kh = (R)(kap * pb.h);
         c.khth = (R)(kap * thb * pb.h);
-        c.xsq = (R)(xi * pb.sq);
+        c.xi = (R)xi;
         c.rho = (R)rho;
-        c.rhop = (R)rhop;
-        c.rr = (R)(rho / rhop);
+        c.rhop = (R)sqrt(1.0 - rho * rho);
         c.thbh = (R)(thb * pb.h);
         c.h = (R)pb.h;
         c.v0 = (R)v0;
-        c.use_eps = pb.use_eps;
-        const double e = pb.sqrt_eps;
-        c.eps = (R)e;
-        c.e_c1 = e > 0.0 ? (R)(1.5 / sqrt(e)) : (R)0;
-        c.e_c2 = e > 0.0 ? (R)(0.5 / (e * sqrt(e))) : (R)0;
+        c.g_kh = kap * pb.h;
+        c.g_rho = xi / (1.0 - rho * rho);
     }
 }
 
-// Diffusion coefficient of the variance and its derivative (full truncation;
-// optionally a C1 quadratic below eps).
+// v+ = max(v, 0).  In FP32 one integer max on the bit pattern: a float with
+// the sign bit set is a negative int32 (so -0 and negatives give +0), with no
+// canonicalising instruction in front as the float max needs.
 template <typename R>
-__device__ __forceinline__ R heston_s(const Consts<R> &c, R vp)
+__device__ __forceinline__ R vplus(R v)
 {
-    R s = sqrt_r(vp);
-    if (c.use_eps && vp < c.eps) s = vp * (c.e_c1 - c.e_c2 * vp);
-    return s;
+    if constexpr (sizeof(R) == 4) return __int_as_float(max(__float_as_int(v), 0));
+    else return fmax(v, 0.0);
 }
 
 template <typename R>
-__device__ __forceinline__ R heston_ds(const Consts<R> &c, R vp, R s)
+__device__ __forceinline__ R sqrt_r(R v)
 {
-    R d = vp > (R)0 ? half_rcp(s) : (R)0;
-    if (c.use_eps && vp < c.eps) d = vp > (R)0 ? c.e_c1 - (R)2 * c.e_c2 * vp : (R)0;
-    return d;
+    if constexpr (sizeof(R) == 4) return __builtin_amdgcn_sqrtf(v);
+    else return sqrt(v);
 }
 
-// One Euler step of the forward algorithm F.  z points at the d normals of the step.
+template <typename R>
+__device__ __forceinline__ R rcp_r(R s)
+{
+    if constexpr (sizeof(R) == 4) return __builtin_amdgcn_rcpf(s);
+    else return 1.0 / s;
+}
+
+// S = s0 exp(x~ + n r h) after step n-1, i.e. at time n h
+template <typename R>
+__device__ __forceinline__ R spot(const Consts<R> &c, R xt, int n)
+{
+    return c.s0 * exp_r(xt + (R)n * c.rh);
+}
+
+// One Heston step on (x~, v) with scaled normals z0, z1; returns what the
+// reverse sweep needs (v+, s, w').  Every sweep steps through this function,
+// so all passes follow bitwise the same path.
+template <typename R>
+struct HestonStep {
+    R vp, s, w;
+};
+
+template <typename R>
+__device__ __forceinline__ HestonStep<R> heston_step(const Consts<R> &c, R &x, R &v, R z0, R z1)
+{
+    HestonStep<R> q;
+    q.vp = vplus(v);
+    q.s = sqrt_r(q.vp);
+    q.w = c.rhop * z1 + c.rho * z0;
+    x = q.s * z0 + (x - c.hh * q.vp);
+    v = q.s * (c.xi * q.w) + (v + (c.khth - c.kh * q.vp));
+    return q;
+}
+
+// One Euler step of the forward algorithm F on (x~, v); z = the step's scaled normals.
 template <int MODEL, typename R>
 __device__ __forceinline__ void euler_step(const Consts<R> &c, R &x, R &v, const R *z)
 {
-    if constexpr (MODEL == kBS) {
-        x = x + c.bs_drift + c.bs_vol * z[0];
-    } else {
-        const R vp = v > (R)0 ? v : (R)0;
-        const R s = heston_s(c, vp);
-        const R w = c.rho * z[0] + c.rhop * z[1];
-        const R xn = x + (c.rh - c.hh * vp) + (c.sq * s) * z[0];
-        const R vn = v + (c.khth - c.kh * vp) + (c.xsq * s) * w;
-        x = xn;
-        v = vn;
-    }
+    if constexpr (MODEL == kBS) x = x + c.bs_drift + c.bs_vol * z[0];
+    else (void)heston_step(c, x, v, z[0], z[1]);
 }
 
 template <int MODEL>
@@ -184,12 +199,12 @@ __device__ __forceinline__ void pass1_block(const DevProblem &pb, const double *
     constexpr int SPC = 4 / T::D;   // steps per Philox call
     const int ncalls = (pb.N * T::D + 3) / 4;
     int d = 0;
-    int next = pb.ndates > 0 ? pb.date_step[0] : -1;
+    int next = pb.ndates > 0 ? ldc(pb.date_step, 0) : -1;
     const int kmask = pb.K - 1;
     const int kshift = __builtin_ctz(pb.K);
     for (int call = 0; call < ncalls; ++call) {
         R z[4];
-        normals4<R>((uint32_t)call, path, pb.inst, pb.k0, pb.k1, z);
+        normals4<R>((uint32_t)call, path, pb.inst, pb.k0, pb.k1, c.bm, z);
 #pragma unroll
         for (int j = 0; j < SPC; ++j) {
             const int n = call * SPC + j;
@@ -203,11 +218,11 @@ __device__ __forceinline__ void pass1_block(const DevProblem &pb, const double *
                 }
                 euler_step<MODEL, R>(c, x, v, z + j * T::D);
                 if (n + 1 == next) {
-                    const double S = (double)(c.s0 * exp_r(x));
-                    payoff_sums(pb.strike, pb.disc, S, active, lane, pb.date_begin[d], pb.date_begin[d + 1],
+                    const double S = (double)spot(c, x, n + 1);
+                    payoff_sums(pb.strike, pb.disc, S, active, lane, ldc(pb.date_begin, d), ldc(pb.date_begin, d + 1),
                                 lds + wave * pb.m);
                     ++d;
-                    next = d < pb.ndates ? pb.date_step[d] : -1;
+                    next = d < pb.ndates ? ldc(pb.date_step, d) : -1;
                 }
             }
         }
@@ -233,7 +248,16 @@ __global__ __launch_bounds__(kBlock) void k_pass1(DevProblem pb, const double *_
 // Pass 2: (re-run forward with checkpoints) + reverse sweep, block partials
 // of sum_p thetabar(p)
 // ---------------------------------------------------------------------------
-// One workgroup's share; lds holds [kWavesPerBlock][NP] doubles.
+// LDS bytes of one pass-2 workgroup: [kWavesPerBlock][NP] doubles for the
+// gradient sums, then [K][kBlock] reals, one column per lane, for the payoff
+// adjoints of the maturity dates of the current segment.
+template <int MODEL, typename R, int K>
+constexpr size_t pass2_lds_bytes()
+{
+    return sizeof(double) * kWavesPerBlock * Traits<MODEL>::NP + sizeof(R) * K * kBlock;
+}
+
+// One workgroup's share; lds as pass2_lds_bytes describes.
 template <int MODEL, typename R, bool FROM_CKPT, int K>
 __device__ __forceinline__ void pass2_block(const DevProblem &pb, const double *__restrict__ theta,
                                             const R *__restrict__ lamD, double *__restrict__ partial,
@@ -256,6 +280,7 @@ __device__ __forceinline__ void pass2_block(const DevProblem &pb, const double *
     const R *strike_r;
     if constexpr (sizeof(R) == 4) strike_r = pb.strike_f;
     else strike_r = pb.strike;
+    R *inj_lds = reinterpret_cast<R *>(lds + kWavesPerBlock * NP);
 
     if constexpr (!FROM_CKPT) {
         // The forward re-run of the paper's step 2: sweep again, keep the state
@@ -265,7 +290,7 @@ __device__ __forceinline__ void pass2_block(const DevProblem &pb, const double *
         const int ncalls = (pb.N * T::D + 3) / 4;
         for (int call = 0; call < ncalls; ++call) {
             R z[4];
-            normals4<R>((uint32_t)call, path, pb.inst, pb.k0, pb.k1, z);
+            normals4<R>((uint32_t)call, path, pb.inst, pb.k0, pb.k1, c.bm, z);
 #pragma unroll
             for (int j = 0; j < SPC; ++j) {
                 const int n = call * SPC + j;
@@ -294,74 +319,94 @@ __device__ __forceinline__ void pass2_block(const DevProblem &pb, const double *
         R v = (R)0;
         if constexpr (T::NV == 2) v = ckpt[base + pb.P];
         int dlo = dhi;
-        while (dlo > 0 && pb.date_step[dlo - 1] > n0) --dlo;
+        while (dlo > 0 && ldc(pb.date_step, dlo - 1) > n0) --dlo;
         int d = dlo;
-        int next = d < dhi ? pb.date_step[d] : -1;
+        int next = d < dhi ? ldc(pb.date_step, d) : -1;
 
-        // recompute the segment, keeping what the reverse sweep needs
-        R s_z1[K], s_z2[K], s_vp[K], s_s[K], s_inj[K];
+        // recompute the segment, keeping what the reverse sweep needs in
+        // registers (Heston: z1', w', v+, s of every step; Black-Scholes: z'),
+        // and the payoff adjoint of a maturity date in this lane's LDS column
+        R s_z1[K], s_w[K], s_vp[K], s_s[K];
         R z[4];
 #pragma unroll
         for (int j = 0; j < K; ++j) {
             const int n = n0 + j;
-            s_inj[j] = (R)0;
-            s_z2[j] = (R)0;
+            s_z1[j] = (R)0;
+            s_w[j] = (R)0;
             s_vp[j] = (R)0;
             s_s[j] = (R)0;
             if (n < pb.N) {
-                if (j % SPC == 0) normals4<R>((uint32_t)(n / SPC), path, pb.inst, pb.k0, pb.k1, z);
+                if (j % SPC == 0) normals4<R>((uint32_t)(n / SPC), path, pb.inst, pb.k0, pb.k1, c.bm, z);
                 const R *zs = z + (j % SPC) * T::D;
                 s_z1[j] = zs[0];
                 if constexpr (MODEL == kHeston) {
-                    const R vp = v > (R)0 ? v : (R)0;
-                    s_z2[j] = zs[1];
-                    s_vp[j] = vp;
-                    s_s[j] = heston_s(c, vp);
+                    const HestonStep<R> q = heston_step(c, x, v, zs[0], zs[1]);
+                    s_w[j] = q.w;
+                    s_vp[j] = q.vp;
+                    s_s[j] = q.s;
+                } else {
+                    euler_step<MODEL, R>(c, x, v, zs);
                 }
-                euler_step<MODEL, R>(c, x, v, zs);
                 if (n + 1 == next) {
                     // payoff adjoints of this date: sum_i lambda_i D_i / P 1{S > K_i} S
-                    const R S = c.s0 * exp_r(x);
+                    const R S = spot(c, x, n + 1);
                     R inj = (R)0;
-                    for (int k = pb.date_begin[d]; k < pb.date_begin[d + 1]; ++k)
-                        inj += S > strike_r[k] ? lamD[k] * S : (R)0;
-                    s_inj[j] = inj;
+                    for (int k = ldc(pb.date_begin, d); k < ldc(pb.date_begin, d + 1); ++k)
+                        inj += S > ldc(strike_r, k) ? ldc(lamD, k) * S : (R)0;
+                    inj_lds[j * kBlock + tid] = inj;
                     ++d;
-                    next = d < dhi ? pb.date_step[d] : -1;
+                    next = d < dhi ? ldc(pb.date_step, d) : -1;
                 }
-            } else {
-                s_z1[j] = (R)0;
             }
         }
         dhi = dlo;
 
-        // reverse sweep over the segment
-        R gs[NP];
-#pragma unroll
-        for (int j = 0; j < NP; ++j) gs[j] = (R)0;
+        // reverse sweep over the segment; its dates are dlo .. d-1, met last
+        // first.  xb, the adjoint of x~, changes only at those dates.
+        // Heston: sums over the segment's steps (b = vb before the step)
+        //   tk = sum b (theta_bar h - h v+), sb = sum b, t2 = sum b s w',
+        //   t3 = sum b s (z1' - rho w'),
+        // from which d/d(kappa) = tk, d/d(theta_bar) = kappa h sb, d/d(xi) = t2,
+        // d/d(rho) = xi t3 / (1 - rho^2).  (tk is summed per step: its two
+        // parts nearly cancel when v+ stays near theta_bar.)
+        int dr = d - 1;
+        int rnext = dr >= dlo ? ldc(pb.date_step, dr) : -1;
+        R ca = -(c.hh * xb);
+        R sb = (R)0, tk = (R)0, t2 = (R)0, t3 = (R)0;
 #pragma unroll
         for (int j = K - 1; j >= 0; --j) {
             if (n0 + j < pb.N) {
-                xb += s_inj[j];
+                if (n0 + j + 1 == rnext) {
+                    xb += inj_lds[j * kBlock + tid];
+                    ca = -(c.hh * xb);
+                    --dr;
+                    rnext = dr >= dlo ? ldc(pb.date_step, dr) : -1;
+                }
                 if constexpr (MODEL == kBS) {
-                    // x' = x + (r - sigma^2/2) h + sigma sq z
-                    gs[0] += xb * (c.bs_gh + c.sq * s_z1[j]);
+                    // d x~' / d sigma = -sigma h + z'
+                    sb += xb * (c.bs_gh + s_z1[j]);
                 } else {
-                    const R vp = s_vp[j], s = s_s[j], z1 = s_z1[j], z2 = s_z2[j];
-                    const R w = c.rho * z1 + c.rhop * z2;
-                    const R a = xb, b = vb;
-                    const R sbar = a * c.sq * z1 + b * c.xsq * w;
-                    const R vpbar = -a * c.hh - b * c.kh + sbar * heston_ds(c, vp, s);
-                    gs[0] += b * (c.thbh - c.h * vp);
-                    gs[1] += b * c.kh;
-                    gs[2] += b * s * c.sq * w;
-                    gs[3] += b * c.xsq * s * (z1 - c.rr * z2);
-                    vb = b + (vp > (R)0 ? vpbar : (R)0);
+                    const R vp = s_vp[j], sv = s_s[j], z1 = s_z1[j], w = s_w[j];
+                    const R b = vb;
+                    const R sbar = (b * c.xi) * w + xb * z1;
+                    const R vpbar = sbar * ((R)0.5 * rcp_r(sv)) + (ca - c.kh * b);
+                    sb += b;
+                    tk += b * (c.thbh - c.h * vp);
+                    const R t = b * sv;
+                    t2 += t * w;
+                    t3 += t * (z1 - c.rho * w);
+                    vb = vp > (R)0 ? b + vpbar : b;
                 }
             }
         }
-#pragma unroll
-        for (int j = 0; j < NP; ++j) g[j] += (double)gs[j];
+        if constexpr (MODEL == kBS) {
+            g[0] += (double)sb;
+        } else {
+            g[0] += (double)tk;
+            g[1] += c.g_kh * (double)sb;
+            g[2] += (double)t2;
+            g[3] += c.g_rho * (double)t3;
+        }
     }
     if constexpr (MODEL == kHeston) g[4] += (double)vb;   // v_0 is theta[4]
 
@@ -432,37 +477,38 @@ __global__ __launch_bounds__(kBlock) void k_tangent(DevProblem pb, const double 
     int next = pb.ndates > 0 ? pb.date_step[0] : -1;
     for (int call = 0; call < ncalls; ++call) {
         R z[4];
-        normals4<R>((uint32_t)call, path, pb.inst, pb.k0, pb.k1, z);
+        normals4<R>((uint32_t)call, path, pb.inst, pb.k0, pb.k1, c.bm, z);
 #pragma unroll
         for (int j = 0; j < SPC; ++j) {
             const int n = call * SPC + j;
             if (n < pb.N) {
                 const R *zs = z + j * T::D;
                 if constexpr (MODEL == kBS) {
-                    xd[0] += c.bs_gh + c.sq * zs[0];
+                    xd[0] += c.bs_gh + zs[0];
+                    euler_step<MODEL, R>(c, x, v, zs);
                 } else {
-                    const R vp = v > (R)0 ? v : (R)0;
-                    const R s = heston_s(c, vp);
-                    const R ds = heston_ds(c, vp, s);
-                    const R z1 = zs[0], z2 = zs[1];
-                    const R w = c.rho * z1 + c.rhop * z2;
-                    const R sw = s * c.sq * w;
+                    // tangents of (x~, v) through one step, before the step moves v
+                    const bool pos = v > (R)0;
+                    const R z1 = zs[0];
+                    const HestonStep<R> q = heston_step(c, x, v, z1, zs[1]);
+                    const R ds = pos ? (R)0.5 * rcp_r(q.s) : (R)0;
+                    const R xw = c.xi * q.w;
+                    const R dw_drho = (z1 - c.rho * q.w) * ((R)1 / (c.rhop * c.rhop));
 #pragma unroll
-                    for (int q = 0; q < NP; ++q) {
-                        const R vpd = v > (R)0 ? vd[q] : (R)0;
+                    for (int k = 0; k < NP; ++k) {
+                        const R vpd = pos ? vd[k] : (R)0;
                         const R sd = ds * vpd;
                         R direct = (R)0;
-                        if (q == 0) direct = c.thbh - c.h * vp;
-                        if (q == 1) direct = c.kh;
-                        if (q == 2) direct = sw;
-                        if (q == 3) direct = c.xsq * s * (z1 - c.rr * z2);
-                        xd[q] = xd[q] - c.hh * vpd + c.sq * z1 * sd;
-                        vd[q] = vd[q] - c.kh * vpd + c.xsq * w * sd + direct;
+                        if (k == 0) direct = c.thbh - c.h * q.vp;
+                        if (k == 1) direct = c.kh;
+                        if (k == 2) direct = q.s * q.w;
+                        if (k == 3) direct = c.xi * q.s * dw_drho;
+                        xd[k] = xd[k] - c.hh * vpd + z1 * sd;
+                        vd[k] = vd[k] - c.kh * vpd + xw * sd + direct;
                     }
                 }
-                euler_step<MODEL, R>(c, x, v, zs);
                 if (n + 1 == next) {
-                    const double S = (double)(c.s0 * exp_r(x));
+                    const double S = (double)spot(c, x, n + 1);
                     for (int k = pb.date_begin[d]; k < pb.date_begin[d + 1]; ++k) {
                         // y and its NP derivatives, one wave_sum8
                         const bool itm = active && S > pb.strike[k];
@@ -614,7 +660,7 @@ __global__ __launch_bounds__(kBlock) void k_normals(uint32_t k0, uint32_t k1, ui
     const int64_t pp = i / nq;
     const uint32_t q = q0 + (uint32_t)(i % nq);
     R z[4];
-    normals4<R>(q >> 2, path0 + (uint32_t)pp, inst, k0, k1, z);
+    normals4<R>(q >> 2, path0 + (uint32_t)pp, inst, k0, k1, box_muller_scale<R>(1.0), z);
     out[i] = z[q & 3u];
 }
 
@@ -649,7 +695,7 @@ template <int MODEL, typename R, int K>
 static hipError_t pass2_k(const DevProblem &pb, bool from_ckpt, const double *theta, const void *lamD,
                           double *partial, void *ckpt, int64_t nblocks, hipStream_t st)
 {
-    const size_t lds = sizeof(double) * kWavesPerBlock * Traits<MODEL>::NP;
+    const size_t lds = pass2_lds_bytes<MODEL, R, K>();
     if (from_ckpt)
         hipLaunchKernelGGL((k_pass2<MODEL, R, true, K>), dim3((unsigned)nblocks), dim3(kBlock), lds, st, pb, theta,
                            (const R *)lamD, partial, (R *)ckpt);
@@ -781,7 +827,9 @@ __device__ __forceinline__ int next_item(unsigned *counter)
     __syncthreads();   // the previous item's LDS traffic is over
     if (threadIdx.x == 0) s_item = (int)atomicAdd(counter, 1u);
     __syncthreads();
-    return s_item;
+    // the same value in every lane; saying so keeps the item's tables and
+    // problem constants in scalar registers
+    return __builtin_amdgcn_readfirstlane(s_item);
 }
 
 template <int MODEL, typename R, bool STORE>
@@ -883,7 +931,7 @@ static hipError_t batch_step_t(const BatchLaunch &L, hipStream_t st)
 {
     hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(64), 0, st, L.counters);
     const size_t lds1 = sizeof(double) * kWavesPerBlock * L.max_m;
-    const size_t lds2 = sizeof(double) * kWavesPerBlock * Traits<MODEL>::NP;
+    const size_t lds2 = pass2_lds_bytes<MODEL, R, K>();
     hipLaunchKernelGGL((k_batch_pass1<MODEL, R, true>), dim3(L.grid), dim3(kBlock), lds1, st, L.insts, L.items,
                        L.n_items, L.counters, L.theta);
     hipLaunchKernelGGL(k_batch_reduce_y, dim3(L.max_m, L.n_inst), dim3(kBlock), 0, st, L.insts, L.Ey);
@@ -916,11 +964,11 @@ int batch_blocks_per_cu(int model, bool fp64, int K, int max_m)
 {
     int n1 = 0, n2 = 0;
     const size_t lds1 = sizeof(double) * kWavesPerBlock * max_m;
-    const size_t lds2 = sizeof(double) * kWavesPerBlock * 5;
 #define MCAAD_OCC(M_, R_, K_)                                                                                  \
     do {                                                                                                       \
         (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&n1, k_batch_pass1<M_, R_, true>, kBlock, lds1);    \
-        (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&n2, k_batch_pass2<M_, R_, true, K_>, kBlock, lds2); \
+        (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&n2, k_batch_pass2<M_, R_, true, K_>, kBlock,        \
+                                                           pass2_lds_bytes<M_, R_, K_>());                   \
     } while (0)
     if (model == kBS) {
         if (fp64) { if (K == 8) MCAAD_OCC(kBS, double, 8); else if (K == 16) MCAAD_OCC(kBS, double, 16); else MCAAD_OCC(kBS, double, 32); }

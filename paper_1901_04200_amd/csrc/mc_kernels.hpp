@@ -20,8 +20,7 @@ struct DevProblem {
     int64_t P;            // paths
     uint32_t k0, k1;      // Philox key
     uint32_t inst;        // Philox counter word 2
-    int32_t use_eps;      // Heston smoothed square root in effect
-    double s0, rate, h, sq, sqrt_eps;
+    double s0, rate, h, sq;
     const int32_t *date_step;   // [ndates] ascending maturity steps
     const int32_t *date_begin;  // [ndates + 1] ranges into the date-sorted tables
     const double *strike;       // [m] date-sorted strikes

@@ -14,34 +14,37 @@ FP32 fma 93, xor/shift 103, FP64 fma 52, v_mad_u64_u32 ~32, transcendentals
   32x32->64 integer multiply (v_mad_u64_u32):                           COST_MAD64 = 4
   transcendental (log2, sqrt, sin, cos, rcp, exp2):                     COST_TRANS = 4
 
-Per path-step, Heston (d = 2 normals per step), FP32 state:
-  Philox4x32-10, half a call: 10 rounds x (2 wide multiplies + 2 three-way xors) / 2
-                                          = 10 mad64 + 10 valu
-  two uniforms (shift, convert, fma)       = 6 valu
-  Box-Muller pair                          = 3 valu + 4 trans
-  Euler step (truncation, sqrt, w, x, v)   = 11 valu + 1 trans
-  forward step F                           = 10 mad64 + 30 valu + 5 trans  (90 slots)
-  reverse step R (adjoints of x, v; theta-bar accumulation)
-                                           = 24 valu + 1 trans             (28 slots)
+Per path-step, Heston (d = 2 normals per step), FP32 state, counting the
+work that differs per lane (the uniform parts of Philox's first rounds run on
+the scalar unit and are not counted):
+  Philox4x32-10, half a call: counter (call, path, inst, 0) has one varying
+    word, so 16 of the 20 wide multiplies and 18 of the 20 three-way xors of
+    a call vary per lane                   = 8 mad64 + 9 valu
+  two uniforms (align-bit, subtract)       = 4 valu
+  Box-Muller pair, scaled by sqrt(h)       = 3 valu + 4 trans
+  Euler step on (x~, v): v+, sqrt, w', xi w', x~ (2 fma), v (3)
+                                           = 9 valu + 1 trans
+  forward step F                           = 8 mad64 + 25 valu + 5 trans  (77 slots)
+  reverse step R: sbar (3), s' (rcp, 1), v+bar (2), the four segment sums
+    (6), adjoint of v (3)                  = 16 valu + 1 trans            (20 slots)
   pass 1 (F)                               = F
-  pass 2 from stored checkpoints (F + R)   = 10 mad64 + 54 valu + 6 trans  (118 slots)
-FP32 flops (FMA = 2) per path-step: F 22, R 31.
+  pass 2 from stored checkpoints (F + R)   = 8 mad64 + 41 valu + 6 trans  (97 slots)
+FP32 flops (FMA = 2) per path-step: F 18, R 22.
 """
 
 CUS = 256
 LANE_SLOTS_PER_CU_CLOCK = 128   # 157.3 TFLOP/s / (2 flops x 256 CU x 2.4 GHz)
 CLOCK_HZ = 2.4e9
 PEAK_SLOTS = CUS * LANE_SLOTS_PER_CU_CLOCK * CLOCK_HZ   # 7.86e13 lane-slots/s
-PEAK_FP32_TFLOPS = 157.3        # published packed-FP32 vector peak
-PEAK_FP32_NONPACKED_TFLOPS = 78.6
+PEAK_FP32_TFLOPS = 157.3        # published FP32 vector peak (FMA = 2 flops)
 
 COST_MAD64 = 4.0
 COST_TRANS = 4.0
 
-HESTON_F = {"mad64": 10, "valu": 30, "trans": 5, "flops": 22}
-HESTON_R = {"mad64": 0, "valu": 24, "trans": 1, "flops": 31}
-BS_F = {"mad64": 5, "valu": 11, "trans": 2, "flops": 6}     # quarter call + one normal per step
-BS_R = {"mad64": 0, "valu": 4, "trans": 0, "flops": 4}
+HESTON_F = {"mad64": 8, "valu": 25, "trans": 5, "flops": 18}
+HESTON_R = {"mad64": 0, "valu": 16, "trans": 1, "flops": 22}
+BS_F = {"mad64": 4, "valu": 10, "trans": 2, "flops": 5}     # quarter call + one normal per step
+BS_R = {"mad64": 0, "valu": 3, "trans": 0, "flops": 3}
 
 
 def slots(op: dict) -> float:

@@ -54,7 +54,10 @@ def test_validate_accepts_the_workloads(L):
     assert _ok(pb, precision=capi.CAL_FP64)[0] == capi.CAL_OK
     pb2, _, _, _ = W.heston_problem()
     assert _ok(pb2)[0] == capi.CAL_OK
-    assert _ok(pb2.with_(sqrt_eps=1e-4), ckpt_every=32, ckpt_mode=capi.CAL_CKPT_RERUN)[0] == capi.CAL_OK
+    assert _ok(pb2, ckpt_every=32, ckpt_mode=capi.CAL_CKPT_RERUN)[0] == capi.CAL_OK
+    # the smoothed square root exists in the oracle only
+    rc, msg = _ok(pb2.with_(sqrt_eps=1e-4))
+    assert rc == capi.CAL_EUNSUPPORTED and "sqrt_eps" in msg
 
 
 @pytest.mark.parametrize("change,expect", [
@@ -69,7 +72,7 @@ def test_validate_accepts_the_workloads(L):
     (dict(t_max=-1.0), "t_max"),
     (dict(n_params=2), "n_params"),
     (dict(model=7), "model"),
-    (dict(sqrt_eps=1e-3), "sqrt_eps"),
+    (dict(sqrt_eps=-1e-3), "sqrt_eps"),
 ])
 def test_validate_rejects_bad_problems(L, change, expect):
     pb, _, _ = W.bs_problem()
@@ -99,4 +102,4 @@ def test_local_vol_validation(L):
     t[2] = t[1]
     assert _ok(pb.with_(t_nodes=t))[0] == capi.CAL_EINVAL
     assert _ok(pb.with_(n_params=199))[0] == capi.CAL_EINVAL
-    assert _ok(pb.with_(sqrt_eps=1e-4))[0] == capi.CAL_EINVAL
+    assert _ok(pb.with_(sqrt_eps=1e-4))[0] == capi.CAL_EUNSUPPORTED
