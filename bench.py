@@ -59,9 +59,10 @@ def code_hash(path):
     return hashlib.sha256(" ".join(text.split()).encode()).hexdigest()
 
 
-def pass2_traffic():
-    """HBM bytes per pass-2 launch from the committed counter summary, or None
-    when any source of that kernel has changed since the counters were taken."""
+def pass2_traffic(ckpt_every):
+    """HBM bytes per pass-2 launch at this checkpoint spacing from the committed
+    counter summary, or None when no figure was taken for it or any source of
+    the kernel has changed since the counters were taken."""
     try:
         lines = open(TRAFFIC_PROFILE).read().splitlines()
     except OSError:
@@ -69,8 +70,8 @@ def pass2_traffic():
     value, ok = None, True
     for ln in lines:
         f = ln.split()
-        if len(f) == 2 and f[0] == "k_pass2_bytes_per_launch":
-            value = float(f[1])
+        if len(f) == 3 and f[0] == "k_pass2_bytes_per_launch" and f[1] == f"K={ckpt_every}":
+            value = float(f[2])
         elif len(f) == 3 and f[0] == "code-sha256":
             ok = ok and os.path.exists(os.path.join(ROOT, f[1])) and code_hash(os.path.join(ROOT, f[1])) == f[2]
     return value if ok else None
@@ -192,7 +193,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
     ap.add_argument("--ckpt-mode", default="store", choices=["store", "rerun"])
-    ap.add_argument("--ckpt-every", type=int, default=16)
+    ap.add_argument("--ckpt-every", type=int, default=0, help="8, 16 or 32; 0 = the fastest of 8 and 16")
     ap.add_argument("--cpu-sample-paths", type=int, default=1 << 20)
     ap.add_argument("--cpu-min-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -227,7 +228,12 @@ def main():
     gen = MonteCarloCalibration(pb.with_(seed=2), precision=args.precision)
     C = torch.tensor(W.noisy_targets(gen.forward(tht).cpu().numpy(), eps), dtype=torch.float64, device="cuda")
     gen.close()
-    mc = MonteCarloCalibration(pb, precision=args.precision, ckpt_every=args.ckpt_every, ckpt_mode=args.ckpt_mode)
+    ckpt_every, ckpt_table = args.ckpt_every, None
+    if ckpt_every == 0:
+        from paper_1901_04200_amd.mc import pick_ckpt_every
+        ckpt_every, ckpt_table = pick_ckpt_every(pb, th0, C, precision=args.precision, ks=(8, 16))
+        print(f"bench: checkpoint spacing {ckpt_every} ({ckpt_table})", file=sys.stderr, flush=True)
+    mc = MonteCarloCalibration(pb, precision=args.precision, ckpt_every=ckpt_every, ckpt_mode=args.ckpt_mode)
     theta = torch.tensor(th0, dtype=torch.float64, device="cuda")
     Ey = torch.empty(pb.n_instr, dtype=torch.float64, device="cuda")
     G = torch.empty(1, dtype=torch.float64, device="cuda")
@@ -308,6 +314,7 @@ def main():
                         "(8 strikes x 5 maturities), M=5, full truncation, FP32 state, FP64 sums",
             "n_paths": P, "n_steps": N, "n_instr": pb.n_instr, "n_params": 5,
             "ckpt_every": geo["ckpt_every"], "ckpt_mode": args.ckpt_mode,
+            "ckpt_every_ms": None if ckpt_table is None else {str(k): t * 1e3 for k, t in ckpt_table},
             "threads_per_block": geo["threads"], "blocks": geo["blocks"],
         },
         "forward_value": path_steps / (ms_fwd * 1e-3),
@@ -326,7 +333,7 @@ def main():
             "peak": roofline.PEAK_SLOTS / 1e12,
             "unit": "T VALU lane-slots/s",
             "frac": achieved / roofline.PEAK_SLOTS,
-            "traffic": pass2_traffic(),
+            "traffic": pass2_traffic(geo["ckpt_every"]),
             "traffic_unit": "HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-scaled)",
             "traffic_algorithmic": roofline.pass2_bytes(pb.n_paths, geo["ckpt_every"], geo["blocks"], pb.n_instr,
                                                         pb.n_steps),

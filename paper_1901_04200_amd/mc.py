@@ -77,3 +77,29 @@ class MonteCarloCalibration:
             self.close()
         except Exception:
             pass
+
+
+def pick_ckpt_every(problem, theta, targets, precision: str = "fp32", ks=(8, 16, 32), reps: int = 5):
+    """Time `reps` gradient calls (after one warm-up) at each checkpoint
+    spacing in `ks` and return (fastest spacing, [(k, seconds per call)]).
+    The spacing trades pass 1's checkpoint stores and pass 2's register
+    footprint (occupancy) against each other; which wins depends on the
+    model, the sizes and the device."""
+    table = []
+    for k in ks:
+        mc = MonteCarloCalibration(problem, precision=precision, ckpt_every=k, ckpt_mode="store")
+        th = mc._dev(theta, mc.M)
+        C = mc._dev(targets, mc.m)
+        Ey = torch.empty(mc.m, dtype=torch.float64, device=mc.device)
+        G = torch.empty(1, dtype=torch.float64, device=mc.device)
+        g = torch.empty(mc.M, dtype=torch.float64, device=mc.device)
+        capi.calibrate_gradient(mc.ctx, th, C, Ey, G, g)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            capi.calibrate_gradient(mc.ctx, th, C, Ey, G, g)
+        e1.record()
+        torch.cuda.synchronize()
+        table.append((k, e0.elapsed_time(e1) * 1e-3 / reps))
+        mc.close()
+    return min(table, key=lambda r: r[1])[0], table
