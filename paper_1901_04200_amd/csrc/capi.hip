@@ -423,7 +423,7 @@ extern "C" int calibrate_forward(cal_ctx *ctx, const double *d_theta, double *d_
     hipStream_t st = (hipStream_t)stream;
     rc = run_pass1(ctx, d_theta, false, st);
     if (rc) return rc;
-    hipError_t e = launch_reduce_sorted(ctx->d_part_y, ctx->nblocks, ctx->m, ctx->m, ctx->d_id, 1.0 / (double)ctx->P,
+    hipError_t e = launch_reduce_sorted(ctx->d_part_y, ctx->nblocks, ctx->m, ctx->d_id, 1.0 / (double)ctx->P,
                                         d_Ey, ctx->d_status, st);
     if (e != hipSuccess) return hip_fail(ctx, e, "reduce launch");
     return CAL_OK;
@@ -441,7 +441,7 @@ extern "C" int calibrate_vjp(cal_ctx *ctx, const double *d_theta, const double *
     if (e != hipSuccess) return hip_fail(ctx, e, "lambda launch");
     rc = run_pass2(ctx, d_theta, false, st);
     if (rc) return rc;
-    e = launch_reduce_sorted(ctx->d_part_g, ctx->nblocks, ctx->M, ctx->M, nullptr, 1.0, d_grad, ctx->d_status, st);
+    e = launch_reduce_sorted(ctx->d_part_g, ctx->nblocks, ctx->M, nullptr, 1.0, d_grad, ctx->d_status, st);
     if (e != hipSuccess) return hip_fail(ctx, e, "reduce launch");
     return CAL_OK;
 }
@@ -456,13 +456,13 @@ extern "C" int calibrate_gradient(cal_ctx *ctx, const double *d_theta, const dou
     const bool store = ctx->mode == CAL_CKPT_STORE;
     rc = run_pass1(ctx, d_theta, store, st);
     if (rc) return rc;
-    hipError_t e = launch_reduce_sorted(ctx->d_part_y, ctx->nblocks, ctx->m, ctx->m, ctx->d_id, 1.0 / (double)ctx->P,
+    hipError_t e = launch_reduce_sorted(ctx->d_part_y, ctx->nblocks, ctx->m, ctx->d_id, 1.0 / (double)ctx->P,
                                         d_Ey, ctx->d_status, st);
     if (e == hipSuccess) e = launch_residual(ctx->dp, ctx->fp64, d_Ey, d_C, d_G, ctx->d_lamD, d_theta, st);
     if (e != hipSuccess) return hip_fail(ctx, e, "residual launch");
     rc = run_pass2(ctx, d_theta, store, st);
     if (rc) return rc;
-    e = launch_reduce_sorted(ctx->d_part_g, ctx->nblocks, ctx->M, ctx->M, nullptr, 1.0, d_grad, ctx->d_status, st);
+    e = launch_reduce_sorted(ctx->d_part_g, ctx->nblocks, ctx->M, nullptr, 1.0, d_grad, ctx->d_status, st);
     if (e != hipSuccess) return hip_fail(ctx, e, "reduce launch");
     return CAL_OK;
 }

@@ -157,7 +157,7 @@ __global__ __launch_bounds__(kBlock) void k_lv_pass1(DevProblem pb, const double
         double s = L.dbl[k];
 #pragma unroll
         for (int w = 1; w < kWavesPerBlock; ++w) s += L.dbl[w * pb.m + k];
-        partial[(int64_t)blockIdx.x * pb.m + k] = s;
+        partial[(int64_t)k * gridDim.x + blockIdx.x] = s;
     }
 }
 
@@ -290,7 +290,7 @@ __global__ __launch_bounds__(kBlock) void k_lv_pass2(DevProblem pb, const double
     }
     flush_cell<R>(pb, L, cur_a);
     const int M = pb.nT * pb.nK;
-    for (int i = tid; i < M; i += kBlock) partial[(int64_t)blockIdx.x * M + i] = L.dbl[i];
+    for (int i = tid; i < M; i += kBlock) partial[(int64_t)i * gridDim.x + blockIdx.x] = L.dbl[i];
 }
 
 template <typename R>

@@ -142,6 +142,13 @@ __device__ __forceinline__ void euler_step(const Consts<R> &c, R &x, R &v, const
     else (void)heston_step(c, x, v, z[0], z[1]);
 }
 
+// Workgroups covering the problem's paths; block partials are stored
+// [column][workgroup], so each column's fixed-order sum reads contiguous memory.
+__device__ __forceinline__ int64_t nblocks_of(const DevProblem &pb)
+{
+    return (pb.P + kBlock - 1) / kBlock;
+}
+
 template <int MODEL>
 struct Traits;
 template <>
@@ -232,7 +239,7 @@ __device__ __forceinline__ void pass1_block(const DevProblem &pb, const double *
         double s = lds[k];
 #pragma unroll
         for (int w = 1; w < kWavesPerBlock; ++w) s += lds[w * pb.m + k];
-        partial[blk * pb.m + k] = s;
+        partial[(int64_t)k * nblocks_of(pb) + blk] = s;
     }
 }
 
@@ -421,7 +428,7 @@ __device__ __forceinline__ void pass2_block(const DevProblem &pb, const double *
         double s = lds[tid];
 #pragma unroll
         for (int w = 1; w < kWavesPerBlock; ++w) s += lds[w * NP + tid];
-        partial[blk * NP + tid] = s;
+        partial[(int64_t)tid * nblocks_of(pb) + blk] = s;
     }
 }
 
@@ -532,7 +539,7 @@ __global__ __launch_bounds__(kBlock) void k_tangent(DevProblem pb, const double 
         double s = lds[k];
 #pragma unroll
         for (int w = 1; w < kWavesPerBlock; ++w) s += lds[w * width + k];
-        partial[(int64_t)blockIdx.x * width + k] = s;
+        partial[(int64_t)k * gridDim.x + blockIdx.x] = s;
     }
 }
 
@@ -556,14 +563,15 @@ __device__ __forceinline__ double block_sum(double v, double *sh)
 // One workgroup per output column k: thread t sums blocks t, t+256, ... in
 // order, then a fixed tree.
 __global__ __launch_bounds__(kBlock) void k_reduce_sorted(const double *__restrict__ partial, int64_t nblocks,
-                                                          int32_t width, const int32_t *__restrict__ id,
+                                                          const int32_t *__restrict__ id,
                                                           double scale, double *__restrict__ out,
                                                           int32_t *status)
 {
     __shared__ double sh[kBlock];
     const int k = blockIdx.x;
     double acc = 0.0;
-    for (int64_t b = threadIdx.x; b < nblocks; b += kBlock) acc += partial[b * width + k];
+    const double *col = partial + (int64_t)k * nblocks;
+    for (int64_t b = threadIdx.x; b < nblocks; b += kBlock) acc += col[b];
     const double s = block_sum(acc, sh) * scale;
     if (threadIdx.x == 0) {
         out[id ? id[k] : k] = s;
@@ -586,7 +594,8 @@ __global__ __launch_bounds__(kBlock) void k_reduce_jac(const double *__restrict_
     double *Ey = Ey_all + (int64_t)blockIdx.y * m;
     double *J = J_all + (int64_t)blockIdx.y * m * M;
     double acc = 0.0;
-    for (int64_t b = threadIdx.x; b < nblocks; b += kBlock) acc += partial[b * width + col];
+    const double *cp = partial + (int64_t)col * nblocks;
+    for (int64_t b = threadIdx.x; b < nblocks; b += kBlock) acc += cp[b];
     const double s = block_sum(acc, sh) * scale;
     if (threadIdx.x == 0) {
         const int k = col / W, t = col % W;
@@ -747,11 +756,11 @@ hipError_t launch_tangent(const DevProblem &pb, int model, bool fp64, const doub
                 : tangent_t<kHeston, float>(pb, theta, partial, nblocks, ninst, st);
 }
 
-hipError_t launch_reduce_sorted(const double *partial, int64_t nblocks, int32_t width, int32_t count,
-                                const int32_t *id, double scale, double *out, int32_t *status, hipStream_t st)
+hipError_t launch_reduce_sorted(const double *partial, int64_t nblocks, int32_t count, const int32_t *id,
+                                double scale, double *out, int32_t *status, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_reduce_sorted, dim3((unsigned)count), dim3(kBlock), 0, st, partial, nblocks, width, id,
-                       scale, out, status);
+    hipLaunchKernelGGL(k_reduce_sorted, dim3((unsigned)count), dim3(kBlock), 0, st, partial, nblocks, id, scale, out,
+                       status);
     return hipGetLastError();
 }
 
@@ -874,7 +883,8 @@ __global__ __launch_bounds__(kBlock) void k_batch_reduce_y(const BatchInst *__re
     const int k = blockIdx.x;
     if (k >= I.pb.m) return;   // uniform per workgroup
     double acc = 0.0;
-    for (int64_t b = threadIdx.x; b < I.nblocks; b += kBlock) acc += I.part_y[b * I.pb.m + k];
+    const double *col = I.part_y + (int64_t)k * I.nblocks;
+    for (int64_t b = threadIdx.x; b < I.nblocks; b += kBlock) acc += col[b];
     const double s = block_sum(acc, sh) * (1.0 / (double)I.pb.P);
     if (threadIdx.x == 0) {
         Ey[I.y_off + I.pb.id[k]] = s;
@@ -918,7 +928,8 @@ __global__ __launch_bounds__(kBlock) void k_batch_reduce_g(const BatchInst *__re
     const BatchInst &I = insts[blockIdx.y];
     const int j = blockIdx.x;
     double acc = 0.0;
-    for (int64_t b = threadIdx.x; b < I.nblocks; b += kBlock) acc += I.part_g[b * NP + j];
+    const double *col = I.part_g + (int64_t)j * I.nblocks;
+    for (int64_t b = threadIdx.x; b < I.nblocks; b += kBlock) acc += col[b];
     const double s = block_sum(acc, sh);
     if (threadIdx.x == 0) {
         grad[(int64_t)blockIdx.y * NP + j] = s;

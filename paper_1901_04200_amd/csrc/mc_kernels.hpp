@@ -38,8 +38,8 @@ struct DevProblem {
 // One instance of a batch: its problem plus its slices of the batch workspace.
 struct BatchInst {
     DevProblem pb;
-    double *part_y;    // [nblocks][m]
-    double *part_g;    // [nblocks][M]
+    double *part_y;    // [m][nblocks]
+    double *part_g;    // [M][nblocks]
     void *ckpt;        // [nseg][n_state][P] in the path precision
     void *lamD;        // [m] in the path precision
     int64_t nblocks;
@@ -87,10 +87,10 @@ hipError_t launch_tangent(const DevProblem &pb, int model, bool fp64, const doub
 hipError_t launch_reduce_jac(const double *partial, int64_t nblocks, int32_t M, int32_t m, const int32_t *id,
                              double scale, double *Ey, double *J, int32_t *status, int ninst, hipStream_t st);
 hipError_t launch_check_theta(const DevProblem &pb, const double *theta, int model, hipStream_t st);
-// out[id[k]] = scale * sum_b partial[b*width + k] for k < count (fixed order)
-hipError_t launch_reduce_sorted(const double *partial, int64_t nblocks, int32_t width, int32_t count,
-                                const int32_t *id, double scale, double *out, int32_t *status,
-                                hipStream_t stream);
+// out[id[k]] = scale * sum_b partial[k*nblocks + b] for k < count (fixed order;
+// block partials are stored column by column)
+hipError_t launch_reduce_sorted(const double *partial, int64_t nblocks, int32_t count, const int32_t *id,
+                                double scale, double *out, int32_t *status, hipStream_t stream);
 // r = Ey - C, G = 1/2 sum r^2, lamD[k] = r[id[k]] * disc[k] / P (in FP32 or FP64)
 hipError_t launch_residual(const DevProblem &pb, bool fp64, const double *Ey, const double *C, double *G,
                            void *lamD, const double *theta, hipStream_t stream);
