@@ -264,16 +264,19 @@ class StepRecord:
     grad_rel_err: float
     seconds_surrogate: float
     seconds_mc: float
+    mc_calls: int = 1
 
 
 def surrogate_calibration(net: MLP, mc, targets, theta0, lo, hi, *, iters: int = 20, alpha: float = 0.5,
-                          feller: bool = True, max_backtracks: int = 12):
+                          feller: bool = True, max_backtracks: int = 12, g_stop: float = 0.0):
     """Each iteration proposes a step from the surrogate's gradient
     (projected, Armijo on the surrogate's G), then judges it with the Monte
     Carlo gradient at the proposal: accepted if the Monte Carlo G decreases,
     otherwise a Monte Carlo gradient step (with backtracking on the Monte
     Carlo G) is taken instead.  Every iteration logs the surrogate gradient's
-    relative error against the Monte Carlo gradient."""
+    relative error against the Monte Carlo gradient and its Monte Carlo
+    calls; the loop ends after `iters` iterations or once the Monte Carlo G
+    is at most g_stop."""
     import torch
     from .calibrate import project
     lo, hi = np.asarray(lo, np.float64), np.asarray(hi, np.float64)
@@ -290,6 +293,8 @@ def surrogate_calibration(net: MLP, mc, targets, theta0, lo, hi, *, iters: int =
     Ey, G_mc, g_mc = mc.gradient(th, C)
     G_mc, g_mc = float(G_mc.item()), g_mc.cpu().numpy()
     for it in range(iters):
+        if G_mc <= g_stop:
+            break
         t0 = time.perf_counter()
         Gs, gs = sur(th)
         a = alpha
@@ -306,6 +311,7 @@ def surrogate_calibration(net: MLP, mc, targets, theta0, lo, hi, *, iters: int =
         tm = time.perf_counter() - t1
         err = float(np.linalg.norm(gs - g_mc) / max(np.linalg.norm(g_mc), 1e-300))
         accepted = G_c < G_mc
+        calls = 1
         if accepted:
             th, G_mc, g_mc = cand, G_c, g_c.cpu().numpy()
         else:
@@ -314,9 +320,10 @@ def surrogate_calibration(net: MLP, mc, targets, theta0, lo, hi, *, iters: int =
             for _ in range(max_backtracks):
                 cand = project(th - a * D * g_mc / max(np.max(np.abs(D * g_mc)), 1e-300) * 0.05, lo, hi, feller)
                 Ey_c, G_c, g_c = mc.gradient(cand, C)
+                calls += 1
                 if float(G_c.item()) < G_mc:
                     th, G_mc, g_mc = cand, float(G_c.item()), g_c.cpu().numpy()
                     break
                 a *= 0.5
-        recs.append(StepRecord(it, G_mc, accepted, err, ts, tm))
+        recs.append(StepRecord(it, G_mc, accepted, err, ts, tm, calls))
     return th, recs

@@ -6,10 +6,16 @@
   3. accuracy: on held-out draws, the surrogate's gradient of
      G = 1/2 |y - C|^2 against a Monte Carlo reference gradient at
      ref_paths paths gives eps_s (median relative error);
-  4. the Monte Carlo gradient's own error at P paths (independent seeds)
-     falls like P^-1/2; P* is where it equals eps_s;
+  4. the Monte Carlo gradient's own error at P paths (independent seeds,
+     the same held-out draws, the same reference) falls like P^-1/2; P* is
+     where it equals eps_s;
   5. cost of one gradient step: surrogate (network forward, batch 1) vs the
-     Monte Carlo adjoint (calibrate_gradient) at P* paths.
+     Monte Carlo adjoint (calibrate_gradient) at P* paths;
+  6. gain test: on n_gain calibration instances (start and target draws),
+     wall time and Monte Carlo evaluations to bring G below g_frac G(theta0)
+     by Monte Carlo gradient descent alone and by the surrogate-assisted
+     iteration (surrogate proposes, Monte Carlo judges), both at the
+     benchmark's 2^20 paths.
 Everything is on the Feller-satisfying part of the Heston box, where the
 pathwise gradient is well conditioned.
 """
@@ -36,8 +42,8 @@ def _time_call(fn, reps):
     return (time.perf_counter() - t0) / reps
 
 
-def run(n_train=1 << 14, train_paths=1 << 14, n_heldout=32, ref_paths=1 << 20, epochs=200, batch=4096,
-        lr=2e-3, lr_final=5e-5, w=1.0, seeds_mc=8, log=print):
+def run(n_train=1 << 14, train_paths=1 << 14, n_heldout=32, ref_paths=1 << 24, epochs=200, batch=4096,
+        lr=2e-3, lr_final=5e-5, w=1.0, seeds_mc=4, n_gain=16, g_frac=1e-3, max_iter=200, log=print):
     import torch
     out = {}
     pb, th0, tht, eps = W.heston_problem()
@@ -90,23 +96,28 @@ def run(n_train=1 << 14, train_paths=1 << 14, n_heldout=32, ref_paths=1 << 20, e
     log(f"surrogate: held-out gradient error median {eps_s:.3g} (vs MC at {ref_paths} paths)")
 
     # ---- 4. Monte Carlo gradient error vs paths -----------------------------
+    # every held-out draw, seeds 1000.., against the same reference
     curve = []
     for lp in range(10, 19, 2):
         P = 1 << lp
         errs = []
-        for s in range(seeds_mc):
-            mc = MonteCarloCalibration(pb.with_(n_paths=P, seed=1000 + s))
-            for k in range(min(8, n_heldout)):
+        for s_ in range(seeds_mc):
+            mc = MonteCarloCalibration(pb.with_(n_paths=P, seed=1000 + s_))
+            for k in range(n_heldout):
                 _, _, g = mc.gradient(ho[k], C)
                 errs.append(np.linalg.norm(g.cpu().numpy() - g_ref[k]) / np.linalg.norm(g_ref[k]))
             mc.close()
         curve.append((P, float(np.median(errs))))
     out["mc_grad_rel_err_vs_paths"] = curve
-    # fit err = a P^-1/2 on the curve, solve for eps_s
-    a = float(np.median([e * math.sqrt(P) for P, e in curve]))
+    # err = a P^-1/2 fitted on the points with P >= 2^14 (below that the
+    # relative error is no longer small), then solved for eps_s
+    a = float(np.median([e * math.sqrt(P) for P, e in curve if P >= 1 << 14]))
     p_star = max(1, int(round((a / eps_s) ** 2)))
+    out["mc_err_coefficient"] = a
+    out["reference_rel_err_estimate"] = a / math.sqrt(ref_paths)
     out["p_star"] = p_star
-    log(f"surrogate: MC gradient error ~ {a:.3g}/sqrt(P); equal to eps_s at P* = {p_star}")
+    log(f"surrogate: MC gradient error ~ {a:.3g}/sqrt(P) (reference ~{a / math.sqrt(ref_paths):.2g}); "
+        f"equal to eps_s at P* = {p_star}")
 
     # ---- 5. step costs ------------------------------------------------------
     th1 = torch.as_tensor(ho[:1], dtype=torch.float32, device="cuda")
@@ -122,5 +133,59 @@ def run(n_train=1 << 14, train_paths=1 << 14, n_heldout=32, ref_paths=1 << 20, e
     out["step_seconds"] = {"surrogate": t_sur, "mc_at_p_star": t_mc, "p_star_paths_timed": P_time,
                            "mc_over_surrogate": t_mc / t_sur}
     log(f"surrogate: step {t_sur * 1e6:.1f} us vs MC adjoint at {P_time} paths {t_mc * 1e6:.1f} us")
+
+    # ---- 6. gain test ---------------------------------------------------------
+    if n_gain > 0:
+        out["gain"] = gain_test(net, pb, n_gain, g_frac, max_iter, log)
     net.close()
     return out
+
+
+def gain_test(net, pb, n_inst, g_frac, max_iter, log=print):
+    """Calibrate n_inst instances (theta0, theta_target: Feller draws of
+    rng(11); targets = prices at theta_target, Philox seed 2, times 1 + 1e-3
+    eps) to G <= g_frac G(theta0), by Monte Carlo gradient descent and by the
+    surrogate-assisted iteration; wall time and Monte Carlo calls each."""
+    import torch
+    from .calibrate import MonteCarloObjective, calibrate
+    lo, hi = W.HESTON_LO, W.HESTON_HI
+    draws = W.heston_feller_draws(11, 2 * n_inst)
+    eps = np.random.default_rng(12).standard_normal((n_inst, pb.n_instr))
+    gen = MonteCarloCalibration(pb.with_(seed=2))
+    mc = MonteCarloCalibration(pb)
+    rows = []
+    for i in range(n_inst):
+        th0, tht = draws[2 * i], draws[2 * i + 1]
+        C = W.noisy_targets(gen.forward(tht).cpu().numpy(), eps[i])
+        obj = MonteCarloObjective(mc, C)
+        G0, _ = obj.value_and_grad(th0)
+        g_tol = g_frac * G0
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        obj.n_grad = obj.n_value = 0
+        r = calibrate(obj.value_and_grad, obj.value, th0, lo, hi, max_iter=max_iter, g_tol=g_tol, feller=True)
+        t_mc = time.perf_counter() - t0
+        mc_calls = obj.n_grad + obj.n_value
+        t0 = time.perf_counter()
+        th_s, recs = S.surrogate_calibration(net, mc, C, th0, lo, hi, iters=max_iter, feller=True, g_stop=g_tol)
+        t_s = time.perf_counter() - t0
+        G_s = recs[-1].G_mc if recs else G0
+        rows.append({"G0": G0, "mc": {"reached": r.G <= g_tol, "G": r.G, "seconds": t_mc, "mc_calls": mc_calls,
+                                      "iters": len(r.history)},
+                     "surrogate": {"reached": G_s <= g_tol, "G": G_s, "seconds": t_s,
+                                   "mc_calls": sum(x.mc_calls for x in recs), "iters": len(recs),
+                                   "accepted": sum(1 for x in recs if x.accepted_surrogate)}})
+    gen.close()
+    mc.close()
+    both = [r_ for r_ in rows if r_["mc"]["reached"] and r_["surrogate"]["reached"]]
+    summ = {"instances": n_inst, "g_frac": g_frac, "paths": pb.n_paths,
+            "reached_mc": sum(r_["mc"]["reached"] for r_ in rows),
+            "reached_surrogate": sum(r_["surrogate"]["reached"] for r_ in rows),
+            "median_seconds_mc": float(np.median([r_["mc"]["seconds"] for r_ in both])) if both else None,
+            "median_seconds_surrogate": float(np.median([r_["surrogate"]["seconds"] for r_ in both])) if both else None,
+            "median_mc_calls_mc": float(np.median([r_["mc"]["mc_calls"] for r_ in both])) if both else None,
+            "median_mc_calls_surrogate": float(np.median([r_["surrogate"]["mc_calls"] for r_ in both])) if both else None,
+            "per_instance": rows}
+    log(f"surrogate: gain test reached {summ['reached_mc']}/{n_inst} (MC) and {summ['reached_surrogate']}/{n_inst} "
+        f"(surrogate-assisted); median seconds {summ['median_seconds_mc']} vs {summ['median_seconds_surrogate']}")
+    return summ

@@ -195,3 +195,33 @@ def test_training_reduces_loss():
     say(f"  loss {hist[0].loss:.4g} -> {hist[-1].loss:.4g}")
     assert hist[-1].loss < 0.1 * hist[0].loss
     net.close()
+
+
+def test_surrogate_assisted_calibration():
+    """The surrogate-assisted iteration only accepts Monte Carlo improvements
+    (G never rises), counts its Monte Carlo calls, and stops at g_stop."""
+    from paper_1901_04200_amd.mc import MonteCarloCalibration
+    pb, _, _, _ = W.heston_problem(n_paths=1 << 14)
+    draws = W.heston_feller_draws(12, 1024)
+    Ey, J = S.generate_labels(pb, draws, n_paths=1 << 12, seed=4, chunk=256)
+    net = S.MLP(5, 256, 40, max_batch=512)
+    net.init_params(0)
+    sh, sc, mu, sd = S.standard_scaling(W.HESTON_LO, W.HESTON_HI, Ey.cpu().numpy())
+    net.set_scaling(sh, sc, mu, sd)
+    S.fit(net, torch.as_tensor(draws, dtype=torch.float32, device="cuda"), Ey.float(), J.float(), epochs=30,
+          batch=512, lr=2e-3, w=0.1)
+    th0, tht = W.heston_feller_draws(13, 2)
+    mc = MonteCarloCalibration(pb)
+    C = mc.forward(tht).cpu().numpy()
+    G0 = float(mc.gradient(th0, C)[1].item())
+    th, recs = S.surrogate_calibration(net, mc, C, th0, W.HESTON_LO, W.HESTON_HI, iters=12)
+    Gs = [G0] + [r.G_mc for r in recs]
+    say("  G:", " ".join(f"{g:.3g}" for g in Gs), "accepted", sum(r.accepted_surrogate for r in recs))
+    assert all(b <= a for a, b in zip(Gs, Gs[1:]))
+    assert Gs[-1] < G0
+    assert all(r.mc_calls >= 1 for r in recs)
+    stop = 0.5 * (G0 + Gs[-1])
+    _, recs2 = S.surrogate_calibration(net, mc, C, th0, W.HESTON_LO, W.HESTON_HI, iters=12, g_stop=stop)
+    assert len(recs2) <= len(recs) and recs2[-1].G_mc <= stop
+    mc.close()
+    net.close()
