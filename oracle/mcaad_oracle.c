@@ -36,6 +36,10 @@
  *   1  Heston with full truncation, theta = (kappa, theta_bar, xi, rho, v0);
  *      the paper's test model with the leverage function set to one
  *   2  local volatility, theta = node values of a bilinear grid in (t, S)
+ *   3  Heston stochastic local volatility (the paper's test model):
+ *      dS/S = r dt + L(t,S) sqrt(v) dW1 with Heston's v, theta = (kappa,
+ *      theta_bar, xi, rho, v0, leverage node values L[a][k]); L piecewise
+ *      constant in t, linear across the spot nodes
  *
  * Sums over paths are taken in path order with Neumaier compensation.
  * Per-path work runs in parallel (OpenMP) into per-path buffers; only the
@@ -55,7 +59,7 @@
 #define ORC_EINVAL (-1)
 #define ORC_ENOMEM (-2)
 
-enum { ORC_BS = 0, ORC_HESTON = 1, ORC_LV = 2 };
+enum { ORC_BS = 0, ORC_HESTON = 1, ORC_LV = 2, ORC_SLV = 3 };
 
 typedef struct {
     int32_t model;
@@ -175,14 +179,18 @@ static int consts_make(const orc_problem *pb, orc_consts *c)
         if (pb->n_t_nodes < 2 || pb->n_k_nodes < 2 || !pb->t_nodes || !pb->k_nodes) return ORC_EINVAL;
         if (pb->n_params != pb->n_t_nodes * pb->n_k_nodes) return ORC_EINVAL;
     }
-    if (pb->model < 0 || pb->model > 2) return ORC_EINVAL;
+    if (pb->model == ORC_SLV) {
+        if (pb->n_t_nodes < 1 || pb->n_k_nodes < 2 || !pb->t_nodes || !pb->k_nodes) return ORC_EINVAL;
+        if (pb->n_params != 5 + pb->n_t_nodes * pb->n_k_nodes) return ORC_EINVAL;
+    }
+    if (pb->model < 0 || pb->model > 3) return ORC_EINVAL;
     if (!(pb->sqrt_eps >= 0.0)) return ORC_EINVAL;
     c->h = pb->t_max / N;
     c->sq = sqrt(c->h);
     c->r = pb->rate;
     c->s0 = pb->s0;
     c->N = N; c->m = m; c->M = pb->n_params;
-    c->d = pb->model == ORC_HESTON ? 2 : 1;
+    c->d = (pb->model == ORC_HESTON || pb->model == ORC_SLV) ? 2 : 1;
     c->date_begin = (int *)calloc((size_t)N + 2, sizeof(int));
     c->ids = (int *)malloc(sizeof(int) * (size_t)m);
     c->disc = (double *)malloc(sizeof(double) * (size_t)m);
@@ -286,6 +294,47 @@ static double lv_dsigma_dS(const orc_problem *pb, const double *grid, lv_cell c)
 }
 
 /* ------------------------------------------------------------------ */
+/* Heston stochastic local volatility: dS/S = r dt + L(t,S) sqrt(v) dW1, */
+/* v as in Heston.  theta = (kappa, theta_bar, xi, rho, v0, L[a][k]).    */
+/* L is piecewise constant in t: the row a of time t is the number of    */
+/* nodes t_i <= t (capped at the last row), so row a governs the time    */
+/* up to node a; across the spot nodes it is linear, flat outside.       */
+/* ------------------------------------------------------------------ */
+typedef struct {
+    int a, b;
+    double be;
+    int s_inside;
+} slv_cell;
+
+static slv_cell slv_locate(const orc_problem *pb, double t, double S)
+{
+    slv_cell c;
+    int nT = pb->n_t_nodes, nK = pb->n_k_nodes;
+    int a = 0;
+    while (a < nT && pb->t_nodes[a] <= t) ++a;
+    c.a = a < nT - 1 ? a : nT - 1;
+    c.b = lv_find(pb->k_nodes, nK, S);
+    double be = (S - pb->k_nodes[c.b]) / (pb->k_nodes[c.b + 1] - pb->k_nodes[c.b]);
+    c.be = be < 0.0 ? 0.0 : (be > 1.0 ? 1.0 : be);
+    c.s_inside = (S >= pb->k_nodes[0] && S <= pb->k_nodes[nK - 1]);
+    return c;
+}
+
+/* L at the cell and dL/dS; lev = theta + 5 */
+static double slv_lev(const orc_problem *pb, const double *lev, slv_cell c)
+{
+    int nK = pb->n_k_nodes;
+    return (1.0 - c.be) * lev[c.a * nK + c.b] + c.be * lev[c.a * nK + c.b + 1];
+}
+
+static double slv_dlev_dS(const orc_problem *pb, const double *lev, slv_cell c)
+{
+    if (!c.s_inside) return 0.0;
+    int nK = pb->n_k_nodes;
+    return (lev[c.a * nK + c.b + 1] - lev[c.a * nK + c.b]) / (pb->k_nodes[c.b + 1] - pb->k_nodes[c.b]);
+}
+
+/* ------------------------------------------------------------------ */
 /* One path: forward algorithm F (payoffs only)                        */
 /* ------------------------------------------------------------------ */
 static void path_forward(const orc_problem *pb, const orc_consts *c, const double *th, uint32_t p, double *y)
@@ -293,8 +342,9 @@ static void path_forward(const orc_problem *pb, const orc_consts *c, const doubl
     orc_rng g; rng_init(&g, pb, p);
     const double h = c->h, sq = c->sq, r = c->r;
     double x = 0.0;
-    double v = pb->model == ORC_HESTON ? th[4] : 0.0;
-    const double rhop = pb->model == ORC_HESTON ? sqrt(1.0 - th[3] * th[3]) : 0.0;
+    const int hv = pb->model == ORC_HESTON || pb->model == ORC_SLV;   /* has a variance process */
+    double v = hv ? th[4] : 0.0;
+    const double rhop = hv ? sqrt(1.0 - th[3] * th[3]) : 0.0;
     for (int n = 0; n < c->N; ++n) {
         if (pb->model == ORC_BS) {
             double sig = th[0];
@@ -308,6 +358,17 @@ static void path_forward(const orc_problem *pb, const orc_consts *c, const doubl
             double s = heston_s(vp, pb->sqrt_eps);
             double w = rho * z1 + rhop * z2;
             double xn = x + (r - 0.5 * vp) * h + s * sq * z1;
+            double vn = v + kap * (thb - vp) * h + xi * s * sq * w;
+            x = xn; v = vn;
+        } else if (pb->model == ORC_SLV) {
+            double kap = th[0], thb = th[1], xi = th[2], rho = th[3];
+            double z1 = rng_normal(&g, (uint32_t)(2 * n));
+            double z2 = rng_normal(&g, (uint32_t)(2 * n + 1));
+            double vp = v > 0.0 ? v : 0.0;
+            double s = heston_s(vp, pb->sqrt_eps);
+            double w = rho * z1 + rhop * z2;
+            double L = slv_lev(pb, th + 5, slv_locate(pb, n * h, c->s0 * exp(x)));
+            double xn = x + (r - 0.5 * L * L * vp) * h + L * s * sq * z1;
             double vn = v + kap * (thb - vp) * h + xi * s * sq * w;
             x = xn; v = vn;
         } else {
@@ -340,11 +401,12 @@ static void path_reverse(const orc_problem *pb, const orc_consts *c, const doubl
     double *z1s = vs + (N + 1);     /* z1_0..z1_{N-1} */
     double *z2s = z1s + N;          /* z2_0..z2_{N-1} */
     orc_rng g; rng_init(&g, pb, p);
-    const double rhop = pb->model == ORC_HESTON ? sqrt(1.0 - th[3] * th[3]) : 0.0;
+    const int hv = pb->model == ORC_HESTON || pb->model == ORC_SLV;
+    const double rhop = hv ? sqrt(1.0 - th[3] * th[3]) : 0.0;
 
     /* forward, recording the states and normals of every step */
     xs[0] = 0.0;
-    vs[0] = pb->model == ORC_HESTON ? th[4] : 0.0;
+    vs[0] = hv ? th[4] : 0.0;
     for (int n = 0; n < N; ++n) {
         double x = xs[n];
         if (pb->model == ORC_BS) {
@@ -362,6 +424,18 @@ static void path_reverse(const orc_problem *pb, const orc_consts *c, const doubl
             double w = rho * z1 + rhop * z2;
             z1s[n] = z1; z2s[n] = z2;
             xs[n + 1] = x + (r - 0.5 * vp) * h + s * sq * z1;
+            vs[n + 1] = v + kap * (thb - vp) * h + xi * s * sq * w;
+        } else if (pb->model == ORC_SLV) {
+            double kap = th[0], thb = th[1], xi = th[2], rho = th[3];
+            double z1 = rng_normal(&g, (uint32_t)(2 * n));
+            double z2 = rng_normal(&g, (uint32_t)(2 * n + 1));
+            double v = vs[n];
+            double vp = v > 0.0 ? v : 0.0;
+            double s = heston_s(vp, pb->sqrt_eps);
+            double w = rho * z1 + rhop * z2;
+            double L = slv_lev(pb, th + 5, slv_locate(pb, n * h, c->s0 * exp(x)));
+            z1s[n] = z1; z2s[n] = z2;
+            xs[n + 1] = x + (r - 0.5 * L * L * vp) * h + L * s * sq * z1;
             vs[n + 1] = v + kap * (thb - vp) * h + xi * s * sq * w;
         } else {
             double z = rng_normal(&g, (uint32_t)n);
@@ -404,6 +478,30 @@ static void path_reverse(const orc_problem *pb, const orc_consts *c, const doubl
             thbar[3] += b * xi * s * sq * (z1 - rho * z2 / rhop);
             xb = a;
             vb = b + (v > 0.0 ? vpbar : 0.0);
+        } else if (pb->model == ORC_SLV) {
+            /* x_{n+1} = x + (r - L^2 v+/2) h + L s sq z1, v_{n+1} as Heston, L = L(t_n, S_n) */
+            double kap = th[0], thb = th[1], xi = th[2], rho = th[3];
+            double v = vs[n];
+            double vp = v > 0.0 ? v : 0.0;
+            double s = heston_s(vp, pb->sqrt_eps);
+            double z1 = z1s[n], z2 = z2s[n];
+            double w = rho * z1 + rhop * z2;
+            double S = c->s0 * exp(xs[n]);
+            slv_cell cell = slv_locate(pb, n * h, S);
+            double L = slv_lev(pb, th + 5, cell);
+            double a = xb, b = vb;
+            double Lbar = a * (-L * vp * h + s * sq * z1);
+            double sbar = a * L * sq * z1 + b * xi * sq * w;
+            double vpbar = -0.5 * a * L * L * h - b * kap * h + sbar * heston_ds(vp, pb->sqrt_eps);
+            thbar[0] += b * (thb - vp) * h;
+            thbar[1] += b * kap * h;
+            thbar[2] += b * s * sq * w;
+            thbar[3] += b * xi * s * sq * (z1 - rho * z2 / rhop);
+            int nK = pb->n_k_nodes;
+            thbar[5 + cell.a * nK + cell.b] += Lbar * (1.0 - cell.be);
+            thbar[5 + cell.a * nK + cell.b + 1] += Lbar * cell.be;
+            xb = a + Lbar * slv_dlev_dS(pb, th + 5, cell) * S;
+            vb = b + (v > 0.0 ? vpbar : 0.0);
         } else {
             double x = xs[n];
             double S = c->s0 * exp(x);
@@ -418,7 +516,7 @@ static void path_reverse(const orc_problem *pb, const orc_consts *c, const doubl
             xb = xb + sigbar * lv_dsigma_dS(pb, th, cell) * S;
         }
     }
-    if (pb->model == ORC_HESTON) thbar[4] += vb;  /* v_0 = theta[4] */
+    if (hv) thbar[4] += vb;  /* v_0 = theta[4] */
 }
 
 /* ------------------------------------------------------------------ */
@@ -431,12 +529,12 @@ static void path_tangent(const orc_problem *pb, const orc_consts *c, const doubl
     const double h = c->h, sq = c->sq, r = c->r;
     double *xd = work;        /* dx/dtheta_j */
     double *vd = work + M;    /* dv/dtheta_j */
-    double *sd = work + 2 * M;/* dsigma/dtheta_j (LV) */
+    double *sd = work + 2 * M;/* dsigma/dtheta_j (LV), dL/dtheta_j (SLV) */
     orc_rng g; rng_init(&g, pb, p);
     double x = 0.0, v = 0.0;
     for (int j = 0; j < M; ++j) { xd[j] = 0.0; vd[j] = 0.0; }
     double rhop = 0.0;
-    if (pb->model == ORC_HESTON) { v = th[4]; vd[4] = 1.0; rhop = sqrt(1.0 - th[3] * th[3]); }
+    if (pb->model == ORC_HESTON || pb->model == ORC_SLV) { v = th[4]; vd[4] = 1.0; rhop = sqrt(1.0 - th[3] * th[3]); }
     for (int n = 0; n < N; ++n) {
         if (pb->model == ORC_BS) {
             double sig = th[0];
@@ -463,6 +561,37 @@ static void path_tangent(const orc_problem *pb, const orc_consts *c, const doubl
                 xd[j] = xnd; vd[j] = vnd;
             }
             double xn = x + (r - 0.5 * vp) * h + s * sq * z1;
+            double vn = v + kap * (thb - vp) * h + xi * s * sq * w;
+            x = xn; v = vn;
+        } else if (pb->model == ORC_SLV) {
+            double kap = th[0], thb = th[1], xi = th[2], rho = th[3];
+            double z1 = rng_normal(&g, (uint32_t)(2 * n));
+            double z2 = rng_normal(&g, (uint32_t)(2 * n + 1));
+            double vp = v > 0.0 ? v : 0.0;
+            double s = heston_s(vp, pb->sqrt_eps);
+            double dsdv = heston_ds(vp, pb->sqrt_eps);
+            double w = rho * z1 + rhop * z2;
+            double dw_drho = z1 - rho * z2 / rhop;
+            double S = c->s0 * exp(x);
+            slv_cell cell = slv_locate(pb, n * h, S);
+            double L = slv_lev(pb, th + 5, cell);
+            double dLdS = slv_dlev_dS(pb, th + 5, cell);
+            int nK = pb->n_k_nodes;
+            double *Ld = sd;   /* dL/dtheta_j */
+            for (int j = 0; j < M; ++j) Ld[j] = dLdS * S * xd[j];
+            Ld[5 + cell.a * nK + cell.b] += 1.0 - cell.be;
+            Ld[5 + cell.a * nK + cell.b + 1] += cell.be;
+            for (int j = 0; j < M; ++j) {
+                double vpd = v > 0.0 ? vd[j] : 0.0;
+                double sdj = dsdv * vpd;
+                double wd = j == 3 ? dw_drho : 0.0;
+                double kapd = j == 0 ? 1.0 : 0.0, thbd = j == 1 ? 1.0 : 0.0, xid = j == 2 ? 1.0 : 0.0;
+                double xnd = xd[j] - 0.5 * (2.0 * L * Ld[j] * vp + L * L * vpd) * h + (Ld[j] * s + L * sdj) * sq * z1;
+                double vnd = vd[j] + kapd * (thb - vp) * h + kap * (thbd - vpd) * h
+                           + xid * s * sq * w + xi * sdj * sq * w + xi * s * sq * wd;
+                xd[j] = xnd; vd[j] = vnd;
+            }
+            double xn = x + (r - 0.5 * L * L * vp) * h + L * s * sq * z1;
             double vn = v + kap * (thb - vp) * h + xi * s * sq * w;
             x = xn; v = vn;
         } else {
@@ -504,8 +633,9 @@ static void path_forward_cstep(const orc_problem *pb, const orc_consts *c, const
     orc_rng g; rng_init(&g, pb, p);
     const double h = c->h, sq = c->sq, r = c->r;
     double complex x = 0.0;
-    double complex v = pb->model == ORC_HESTON ? thc[4] : 0.0;
-    double complex rhop = pb->model == ORC_HESTON ? csqrt(1.0 - thc[3] * thc[3]) : 0.0;
+    const int hv = pb->model == ORC_HESTON || pb->model == ORC_SLV;
+    double complex v = hv ? thc[4] : 0.0;
+    double complex rhop = hv ? csqrt(1.0 - thc[3] * thc[3]) : 0.0;
     for (int n = 0; n < c->N; ++n) {
         if (pb->model == ORC_BS) {
             double complex sig = thc[0];
@@ -519,6 +649,23 @@ static void path_forward_cstep(const orc_problem *pb, const orc_consts *c, const
             double complex s = heston_s_c(vp, pb->sqrt_eps);
             double complex w = rho * z1 + rhop * z2;
             double complex xn = x + (r - 0.5 * vp) * h + s * sq * z1;
+            double complex vn = v + kap * (thb - vp) * h + xi * s * sq * w;
+            x = xn; v = vn;
+        } else if (pb->model == ORC_SLV) {
+            double complex kap = thc[0], thb = thc[1], xi = thc[2], rho = thc[3];
+            double z1 = rng_normal(&g, (uint32_t)(2 * n));
+            double z2 = rng_normal(&g, (uint32_t)(2 * n + 1));
+            double complex vp = creal(v) > 0.0 ? v : 0.0;
+            double complex s = heston_s_c(vp, pb->sqrt_eps);
+            double complex w = rho * z1 + rhop * z2;
+            double complex S = c->s0 * cexp(x);
+            slv_cell cell = slv_locate(pb, n * h, creal(S));
+            double complex be = cell.be;
+            if (cell.be > 0.0 && cell.be < 1.0)
+                be = (S - pb->k_nodes[cell.b]) / (pb->k_nodes[cell.b + 1] - pb->k_nodes[cell.b]);
+            int nK = pb->n_k_nodes;
+            double complex L = (1.0 - be) * thc[5 + cell.a * nK + cell.b] + be * thc[5 + cell.a * nK + cell.b + 1];
+            double complex xn = x + (r - 0.5 * L * L * vp) * h + L * s * sq * z1;
             double complex vn = v + kap * (thb - vp) * h + xi * s * sq * w;
             x = xn; v = vn;
         } else {

@@ -21,8 +21,9 @@ import numpy as np
 MODEL_BS = 0
 MODEL_HESTON = 1
 MODEL_LV = 2
+MODEL_SLV = 3
 
-MODEL_NAMES = {MODEL_BS: "bs", MODEL_HESTON: "heston", MODEL_LV: "lv"}
+MODEL_NAMES = {MODEL_BS: "bs", MODEL_HESTON: "heston", MODEL_LV: "lv", MODEL_SLV: "slv"}
 
 # Heston parameter box: kappa, theta_bar, xi, rho, v0
 HESTON_LO = np.array([0.5, 0.01, 0.1, -0.9, 0.01])
@@ -160,6 +161,45 @@ def lv_problem(n_paths: int = 1 << 22, seed: int = 1, n_steps: int = 256, t_max:
     eps = np.random.default_rng(5).standard_normal(len(instr_step))
     fd_coords = np.sort(np.random.default_rng(5).choice(n_t * n_k, size=min(10, n_t * n_k), replace=False))
     return pb, grid0, grid_target, eps, fd_coords
+
+
+# --------------------------------------------------------------------------
+# Heston stochastic local volatility (the paper's own test model)
+# --------------------------------------------------------------------------
+def leverage_surface(rng, t_nodes, k_nodes, s0: float = 100.0) -> np.ndarray:
+    """A smooth random leverage surface around 1, inside [0.5, 1.5]:
+    level U(0.8, 1.2) + skew U(-0.5, 0) m + smile U(0, 1) m^2 + term
+    U(-0.1, 0.1) T with m = K/S0 - 1.  Flattened time-major [a * nK + k]."""
+    level = rng.uniform(0.8, 1.2)
+    skew = rng.uniform(-0.5, 0.0)
+    smile = rng.uniform(0.0, 1.0)
+    term = rng.uniform(-0.1, 0.1)
+    T, K = np.meshgrid(np.asarray(t_nodes), np.asarray(k_nodes), indexing="ij")
+    m = K / s0 - 1.0
+    return np.clip(level + skew * m + smile * m * m + term * T, 0.5, 1.5).ravel()
+
+
+def slv_problem(n_paths: int = 1 << 20, seed: int = 1, n_steps: int = 256, t_max: float = 2.0,
+                n_t: int = 10, n_k: int = 20):
+    """Heston SLV: leverage rows at the maturities 0.2..2.0 (row a governs
+    the time up to maturity a), spot nodes 55..150, calls at every node
+    (m = n_t n_k), Heston parameters from the Feller part of the box
+    (draws of rng(21)), leverage surfaces from rng(22); targets priced at
+    the second draw.  theta = (kappa, theta_bar, xi, rho, v0, L[a][k])."""
+    t_nodes = 0.2 * np.arange(1, n_t + 1) * (t_max / (0.2 * n_t))
+    k_nodes = 55.0 + 5.0 * np.arange(n_k) * (19.0 / max(n_k - 1, 1))
+    spy = n_steps / t_max
+    steps = np.array([int(round(t * spy)) for t in t_nodes], dtype=np.int32)
+    pb = Problem(model=MODEL_SLV, n_params=5 + n_t * n_k, n_steps=n_steps, n_paths=n_paths, t_max=t_max,
+                 instr_step=np.repeat(steps, n_k), instr_strike=np.tile(k_nodes, n_t), s0=100.0, rate=0.02,
+                 seed=seed, t_nodes=t_nodes, k_nodes=k_nodes)
+    hd = heston_feller_draws(21, 2)
+    rng = np.random.default_rng(22)
+    th0 = np.concatenate([hd[0], leverage_surface(rng, t_nodes, k_nodes)])
+    tht = np.concatenate([hd[1], leverage_surface(rng, t_nodes, k_nodes)])
+    eps = np.random.default_rng(23).standard_normal(pb.n_instr)
+    fd_coords = np.sort(np.random.default_rng(24).choice(pb.n_params, size=10, replace=False))
+    return pb, th0, tht, eps, fd_coords
 
 
 # --------------------------------------------------------------------------
