@@ -41,7 +41,10 @@ extern "C" {
 /* model */
 #define CAL_BS 0      /* Black-Scholes GBM, theta = (sigma), log-Euler */
 #define CAL_HESTON 1  /* Heston, theta = (kappa, theta_bar, xi, rho, v0), full-truncation log-Euler */
-#define CAL_LV 2      /* local volatility, theta = bilinear node values (reserved) */
+#define CAL_LV 2      /* local volatility, theta = node values of sigma(t, S), bilinear on the nodes */
+#define CAL_SLV 3     /* Heston stochastic local volatility (the paper's test model): dS/S = r dt +
+                         L(t, S) sqrt(v) dW1, v as Heston; theta = (kappa, theta_bar, xi, rho, v0,
+                         L[a][k]); L piecewise constant in t, linear across the spot nodes */
 
 /* precision of the path state */
 #define CAL_FP32 0
@@ -69,7 +72,7 @@ typedef struct cal_ctx cal_ctx;
  * Problem description (all pointers are host pointers, read during
  * cal_validate / cal_create only).
  *   model, precision  : see above
- *   n_params (M)      : 1 (BS), 5 (Heston)
+ *   n_params (M)      : 1 (BS), 5 (Heston), nT*nK (LV), 5 + nT*nK (SLV)
  *   n_instr  (m)      : number of calls, 1..2048
  *   n_steps  (N)      : Euler steps over [0, t_max], 1..65536
  *   n_paths  (P)      : 1..2^32; path p uses Philox counter word 1 = p
@@ -82,10 +85,16 @@ typedef struct cal_ctx cal_ctx;
  *                       other finite value >= 0 is refused with CAL_EUNSUPPORTED
  *   instr_step[m]     : maturity step of call i, 1..N (maturity = step * t_max / N)
  *   instr_strike[m]   : strike of call i (>= 0)
+ *   n_t_nodes (nT), t_nodes[nT] : LV and SLV time nodes, finite and increasing
+ *                       (LV: 2..64, bilinear in t, flat outside; SLV: 1..64,
+ *                       step n uses row a = #{t_nodes <= n h}, capped at nT-1)
+ *   n_k_nodes (nK), k_nodes[nK] : LV and SLV spot nodes, 2..64, uniformly spaced
+ *                       (within 1e-9 relative), linear in S, flat outside;
+ *                       theta[(5 +) a*nK + k] is the value at (t_a, K_k)
  * Random numbers: normal q of path p is Box-Muller of the uniforms
  * ((w >> 9) + 0.5) 2^-23 of Philox4x32-10 counter (q/4, p, inst, 0), key
- * (seed lo, seed hi); q = n*d + j for normal j of step n (d = 2 for Heston,
- * 1 otherwise).
+ * (seed lo, seed hi); q = n*d + j for normal j of step n (d = 2 for Heston
+ * and SLV, 1 otherwise).
  */
 typedef struct {
     int32_t model;
@@ -106,7 +115,7 @@ typedef struct {
     double sqrt_eps;
     const int32_t *instr_step;
     const double *instr_strike;
-    int32_t n_t_nodes;           /* LV (reserved) */
+    int32_t n_t_nodes;           /* LV, SLV */
     int32_t n_k_nodes;
     const double *t_nodes;
     const double *k_nodes;
@@ -148,7 +157,8 @@ int calibrate_gradient(cal_ctx *ctx, const double *d_theta, const double *d_C, d
                        double *d_G, double *d_grad, void *stream);
 
 /* Forward tangent mode over the same paths: d_Ey[m] and the Jacobian
- * d_J[m*M] (row-major, J[i*M + j] = dE y_i/dtheta_j).  Heston and BS.  By
+ * d_J[m*M] (row-major, J[i*M + j] = dE y_i/dtheta_j).  Heston and BS (the
+ * grid models return CAL_EUNSUPPORTED).  By
  * the paper's eq. 0711A the same numbers follow from m reverse sweeps; with
  * M < m the tangent sweep is the cheaper route to the whole matrix. */
 int calibrate_jacobian(cal_ctx *ctx, const double *d_theta, double *d_Ey, double *d_J, void *stream);

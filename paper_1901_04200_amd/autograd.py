@@ -34,7 +34,7 @@ def mc_prices(theta, mc: MonteCarloCalibration):
 
 
 def checkpoint_bytes(problem, precision: str, ckpt_every: int) -> int:
-    nv = 2 if problem.model == 1 else 1
+    nv = 2 if problem.model in (1, 3) else 1   # Heston and SLV checkpoint (x, v)
     real = 8 if precision == "fp64" else 4
     nseg = -(-problem.n_steps // ckpt_every)
     return nseg * nv * problem.n_paths * real

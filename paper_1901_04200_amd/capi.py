@@ -14,7 +14,7 @@ import os
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "lib", "libmcaad.so")
 
-CAL_BS, CAL_HESTON, CAL_LV = 0, 1, 2
+CAL_BS, CAL_HESTON, CAL_LV, CAL_SLV = 0, 1, 2, 3
 CAL_FP32, CAL_FP64 = 0, 1
 CAL_CKPT_AUTO, CAL_CKPT_RERUN, CAL_CKPT_STORE = 0, 1, 2
 CAL_OK, CAL_EINVAL, CAL_ENOMEM, CAL_EHIP, CAL_EUNSUPPORTED = 0, -1, -2, -3, -4

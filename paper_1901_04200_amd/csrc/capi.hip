@@ -59,6 +59,7 @@ struct cal_ctx {
     void *d_lamD = nullptr;
     void *d_ckpt = nullptr;
     double *d_t_nodes = nullptr;
+    int32_t *d_step_row = nullptr;
     // timing
     bool timing = false;
     std::vector<TimedPair> timed;
@@ -82,7 +83,8 @@ static std::string validate(const cal_problem *pb, int *code)
 {
     *code = CAL_EINVAL;
     if (!pb) return "null problem";
-    if (pb->model != CAL_BS && pb->model != CAL_HESTON && pb->model != CAL_LV) return "unknown model";
+    if (pb->model != CAL_BS && pb->model != CAL_HESTON && pb->model != CAL_LV && pb->model != CAL_SLV)
+        return "unknown model";
     if (pb->precision != CAL_FP32 && pb->precision != CAL_FP64) return "unknown precision";
     if (pb->n_instr < 1 || pb->n_instr > kMaxInstr) return "n_instr must be in 1..2048";
     if (pb->n_steps < 1 || pb->n_steps > kMaxSteps) return "n_steps must be in 1..65536";
@@ -106,11 +108,16 @@ static std::string validate(const cal_problem *pb, int *code)
     if (pb->max_batch < 0 || pb->max_batch > 65535) return "max_batch must be in 0..65535";
     if (pb->model == CAL_BS && pb->n_params != 1) return "Black-Scholes takes n_params = 1";
     if (pb->model == CAL_HESTON && pb->n_params != 5) return "Heston takes n_params = 5";
-    if (pb->model == CAL_LV) {
+    if (pb->model == CAL_LV || pb->model == CAL_SLV) {
+        const bool lv = pb->model == CAL_LV;
         const int nT = pb->n_t_nodes, nK = pb->n_k_nodes;
-        if (nT < 2 || nK < 2 || nT > 64 || nK > 64) return "local vol needs 2..64 time and spot nodes";
+        if (lv && (nT < 2 || nK < 2 || nT > 64 || nK > 64)) return "local vol needs 2..64 time and spot nodes";
+        if (!lv && (nT < 1 || nK < 2 || nT > 64 || nK > 64))
+            return "stochastic local vol needs 1..64 time and 2..64 spot nodes";
         if (!pb->t_nodes || !pb->k_nodes) return "null node arrays";
-        if (pb->n_params != nT * nK) return "local vol takes n_params = n_t_nodes * n_k_nodes";
+        if (lv && pb->n_params != nT * nK) return "local vol takes n_params = n_t_nodes * n_k_nodes";
+        if (!lv && pb->n_params != 5 + nT * nK)
+            return "stochastic local vol takes n_params = 5 + n_t_nodes * n_k_nodes";
         for (int a = 0; a < nT; ++a)
             if (!std::isfinite(pb->t_nodes[a]) || (a > 0 && !(pb->t_nodes[a] > pb->t_nodes[a - 1])))
                 return "t_nodes must be finite and increasing";
@@ -146,7 +153,7 @@ extern "C" int cal_destroy(cal_ctx *ctx)
     (void)hipDeviceSynchronize();
     void *bufs[] = {ctx->d_date_step, ctx->d_date_begin, ctx->d_strike, ctx->d_strike_f, ctx->d_disc, ctx->d_id,
                     ctx->d_status, ctx->d_part_y, ctx->d_part_g, ctx->d_part_j, ctx->d_lamD, ctx->d_ckpt,
-                    ctx->d_t_nodes};
+                    ctx->d_t_nodes, ctx->d_step_row};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
     for (auto &t : ctx->timed) {
@@ -177,8 +184,8 @@ extern "C" int cal_create(const cal_problem *pb, cal_ctx **out)
     c->P = pb->n_paths;
     c->nblocks = (c->P + kBlock - 1) / kBlock;
     c->max_batch = pb->max_batch > 0 ? pb->max_batch : 1;
-    c->K = pb->ckpt_every ? pb->ckpt_every : (c->fp64 ? 8 : 16);
-    const int nv = c->model == CAL_HESTON ? 2 : 1;
+    c->K = pb->ckpt_every ? pb->ckpt_every : (c->fp64 || c->model == CAL_SLV ? 8 : 16);
+    const int nv = c->model == CAL_HESTON || c->model == CAL_SLV ? 2 : 1;
     const int nseg = (c->N + c->K - 1) / c->K;
     const size_t ckpt_bytes = (size_t)nseg * nv * (size_t)c->P * c->real;
     c->mode = pb->ckpt_mode == CAL_CKPT_AUTO ? CAL_CKPT_STORE : pb->ckpt_mode;
@@ -207,21 +214,25 @@ extern "C" int cal_create(const cal_problem *pb, cal_ctx **out)
     date_begin.push_back(m);
     const int nd = (int)date_step.size();
 
-    // tangent mode serves Black-Scholes and Heston (labels); not the local-vol grid
-    const size_t tan_w = c->model == CAL_LV ? 0 : (size_t)m * (c->M + 1);
-    if (c->model == CAL_LV) {
+    // tangent mode serves Black-Scholes and Heston (labels); not the grid models
+    const bool grid = c->model == CAL_LV || c->model == CAL_SLV;
+    const size_t tan_w = grid ? 0 : (size_t)m * (c->M + 1);
+    if (grid) {
         DevProblem probe{};
         probe.N = c->N;
         probe.m = m;
+        probe.K = c->K;
         probe.nT = pb->n_t_nodes;
         probe.nK = pb->n_k_nodes;
         int max_lds = 0;
         (void)hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, c->device);
-        const size_t need = std::max(lv_lds_bytes(probe, c->fp64, 1), lv_lds_bytes(probe, c->fp64, 2));
+        const size_t need = c->model == CAL_LV
+                                ? std::max(lv_lds_bytes(probe, c->fp64, 1), lv_lds_bytes(probe, c->fp64, 2))
+                                : std::max(slv_lds_bytes(probe, c->fp64, 1), slv_lds_bytes(probe, c->fp64, 2));
         if (need > (size_t)max_lds) {
             delete c;
             return fail(nullptr, CAL_EUNSUPPORTED,
-                        "local vol grid x steps too large for one workgroup's LDS (" + std::to_string(need) + " > " +
+                        "grid, steps and spacing too large for one workgroup's LDS (" + std::to_string(need) + " > " +
                             std::to_string(max_lds) + " bytes)");
         }
     }
@@ -241,6 +252,7 @@ extern "C" int cal_create(const cal_problem *pb, cal_ctx **out)
     A((void **)&c->d_part_j, sizeof(double) * (size_t)c->nblocks * tan_w * c->max_batch);
     A(&c->d_lamD, c->real * m);
     if (c->model == CAL_LV) A((void **)&c->d_t_nodes, sizeof(double) * pb->n_t_nodes);
+    if (c->model == CAL_SLV) A((void **)&c->d_step_row, sizeof(int32_t) * c->N);
     if (e != hipSuccess) {
         cal_destroy(c);
         return fail(nullptr, CAL_ENOMEM, std::string("workspace allocation failed: ") + hipGetErrorString(e));
@@ -260,6 +272,16 @@ extern "C" int cal_create(const cal_problem *pb, cal_ctx **out)
     H2D(c->d_disc, disc.data(), sizeof(double) * m);
     H2D(c->d_id, order.data(), sizeof(int32_t) * m);
     if (c->model == CAL_LV) H2D(c->d_t_nodes, pb->t_nodes, sizeof(double) * pb->n_t_nodes);
+    if (c->model == CAL_SLV) {
+        // leverage row of step n: the number of time nodes <= n h, capped at the last row
+        std::vector<int32_t> row(c->N);
+        for (int n = 0; n < c->N; ++n) {
+            int a = 0;
+            while (a < pb->n_t_nodes && pb->t_nodes[a] <= n * h) ++a;
+            row[n] = a < pb->n_t_nodes - 1 ? a : pb->n_t_nodes - 1;
+        }
+        H2D(c->d_step_row, row.data(), sizeof(int32_t) * c->N);
+    }
     if (e == hipSuccess) e = hipMemset(c->d_status, 0, sizeof(int32_t));
     if (e == hipSuccess) e = hipDeviceSynchronize();
     if (e != hipSuccess) {
@@ -289,12 +311,13 @@ extern "C" int cal_create(const cal_problem *pb, cal_ctx **out)
     d.disc = c->d_disc;
     d.id = c->d_id;
     d.status = c->d_status;
-    if (c->model == CAL_LV) {
+    if (grid) {
         d.nT = pb->n_t_nodes;
         d.nK = pb->n_k_nodes;
         d.K0 = pb->k_nodes[0];
         d.dK = (pb->k_nodes[d.nK - 1] - pb->k_nodes[0]) / (d.nK - 1);
         d.t_nodes = c->d_t_nodes;
+        d.step_row = c->d_step_row;
     }
     *out = c;
     return CAL_OK;
@@ -389,14 +412,16 @@ static int check_ctx(cal_ctx *ctx)
 
 static int run_pass1(cal_ctx *c, const double *theta, bool store, hipStream_t st)
 {
-    if (c->model == CAL_LV) {
+    if (c->model == CAL_LV || c->model == CAL_SLV) {
         hipError_t ec = launch_check_theta(c->dp, theta, c->model, st);
         if (ec != hipSuccess) return hip_fail(c, ec, "theta check launch");
     }
     Timed t(c, st, 0);
-    hipError_t e = c->model == CAL_LV
-                       ? launch_lv_pass1(c->dp, c->fp64, store, theta, c->d_part_y, c->d_ckpt, c->nblocks, st)
-                       : launch_pass1(c->dp, c->model, c->fp64, store, theta, c->d_part_y, c->d_ckpt, c->nblocks, st);
+    hipError_t e =
+        c->model == CAL_LV    ? launch_lv_pass1(c->dp, c->fp64, store, theta, c->d_part_y, c->d_ckpt, c->nblocks, st)
+        : c->model == CAL_SLV ? launch_slv_pass1(c->dp, c->fp64, store, theta, c->d_part_y, c->d_ckpt, c->nblocks, st)
+                              : launch_pass1(c->dp, c->model, c->fp64, store, theta, c->d_part_y, c->d_ckpt,
+                                             c->nblocks, st);
     t.done();
     if (e != hipSuccess) return hip_fail(c, e, "pass-1 launch");
     return CAL_OK;
@@ -408,6 +433,9 @@ static int run_pass2(cal_ctx *c, const double *theta, bool from_ckpt, hipStream_
     hipError_t e = c->model == CAL_LV
                        ? launch_lv_pass2(c->dp, c->fp64, from_ckpt, theta, c->d_lamD, c->d_part_g, c->d_ckpt,
                                          c->nblocks, st)
+                   : c->model == CAL_SLV
+                       ? launch_slv_pass2(c->dp, c->fp64, from_ckpt, theta, c->d_lamD, c->d_part_g, c->d_ckpt,
+                                          c->nblocks, st)
                        : launch_pass2(c->dp, c->model, c->fp64, from_ckpt, theta, c->d_lamD, c->d_part_g, c->d_ckpt,
                                       c->nblocks, st);
     t.done();
@@ -473,7 +501,8 @@ extern "C" int calibrate_jacobian_batch(cal_ctx *ctx, const double *d_theta, int
     int rc = check_ctx(ctx);
     if (rc) return rc;
     if (!d_theta || !d_Ey || !d_J) return fail(ctx, CAL_EINVAL, "null device pointer");
-    if (ctx->model == CAL_LV) return fail(ctx, CAL_EUNSUPPORTED, "tangent mode serves Black-Scholes and Heston");
+    if (ctx->model == CAL_LV || ctx->model == CAL_SLV)
+        return fail(ctx, CAL_EUNSUPPORTED, "tangent mode serves Black-Scholes and Heston");
     if (n_inst < 1 || n_inst > ctx->max_batch) return fail(ctx, CAL_EINVAL, "n_inst outside 1..max_batch");
     if ((size_t)ctx->m * (ctx->M + 1) * kWavesPerBlock * sizeof(double) > 64 * 1024)
         return fail(ctx, CAL_EUNSUPPORTED, "m * (M + 1) too large for the tangent kernel's LDS");
@@ -614,7 +643,8 @@ extern "C" int calb_create(const cal_problem *problems, int32_t n_inst, calb_ctx
         int code;
         std::string msg = validate(&problems[i], &code);
         if (code != CAL_OK) return bfail(nullptr, code, "instance " + std::to_string(i) + ": " + msg);
-        if (problems[i].model == CAL_LV) return bfail(nullptr, CAL_EUNSUPPORTED, "batches take BS or Heston");
+        if (problems[i].model == CAL_LV || problems[i].model == CAL_SLV)
+            return bfail(nullptr, CAL_EUNSUPPORTED, "batches take BS or Heston");
         if (problems[i].model != problems[0].model || problems[i].precision != problems[0].precision)
             return bfail(nullptr, CAL_EINVAL, "all instances of a batch share model and precision");
     }

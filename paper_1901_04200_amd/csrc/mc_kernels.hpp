@@ -7,7 +7,7 @@
 
 namespace mcaad {
 
-enum Model { kBS = 0, kHeston = 1 };
+enum Model { kBS = 0, kHeston = 1, kLV = 2, kSLV = 3 };
 
 // Everything a kernel needs besides theta, passed by value.
 struct DevProblem {
@@ -29,10 +29,13 @@ struct DevProblem {
     const int32_t *id;          // [m] original index of date-sorted instrument k
     int32_t *status;            // device status bits
     // local volatility: bilinear grid on time nodes t_nodes[nT] and uniformly
-    // spaced spot nodes K0 + k dK, k < nK; theta[a*nK + k] is the node value
+    // spaced spot nodes K0 + k dK, k < nK; theta[a*nK + k] is the node value.
+    // Stochastic local volatility: the same spot nodes, theta[5 + a*nK + k] is
+    // the leverage of time row a, and step n uses row step_row[n].
     int32_t nT, nK;
     double K0, dK;
     const double *t_nodes;
+    const int32_t *step_row;    // [N] (SLV)
 };
 
 // One instance of a batch: its problem plus its slices of the batch workspace.
@@ -75,6 +78,13 @@ hipError_t launch_lv_pass1(const DevProblem &pb, bool fp64, bool store_ckpt, con
 hipError_t launch_lv_pass2(const DevProblem &pb, bool fp64, bool from_ckpt, const double *theta, const void *lamD,
                            double *partial, void *ckpt, int64_t nblocks, hipStream_t stream);
 size_t lv_lds_bytes(const DevProblem &pb, bool fp64, int pass);
+
+// Heston stochastic local volatility passes (slv_kernels.hip).
+hipError_t launch_slv_pass1(const DevProblem &pb, bool fp64, bool store_ckpt, const double *theta,
+                            double *partial, void *ckpt, int64_t nblocks, hipStream_t stream);
+hipError_t launch_slv_pass2(const DevProblem &pb, bool fp64, bool from_ckpt, const double *theta, const void *lamD,
+                            double *partial, void *ckpt, int64_t nblocks, hipStream_t stream);
+size_t slv_lds_bytes(const DevProblem &pb, bool fp64, int pass);
 
 // All launchers enqueue on `stream` and return hipGetLastError().
 hipError_t launch_pass1(const DevProblem &pb, int model, bool fp64, bool store_ckpt, const double *theta,

@@ -198,7 +198,7 @@ def slv_problem(n_paths: int = 1 << 20, seed: int = 1, n_steps: int = 256, t_max
     th0 = np.concatenate([hd[0], leverage_surface(rng, t_nodes, k_nodes)])
     tht = np.concatenate([hd[1], leverage_surface(rng, t_nodes, k_nodes)])
     eps = np.random.default_rng(23).standard_normal(pb.n_instr)
-    fd_coords = np.sort(np.random.default_rng(24).choice(pb.n_params, size=10, replace=False))
+    fd_coords = np.sort(np.random.default_rng(24).choice(pb.n_params, size=min(10, pb.n_params), replace=False))
     return pb, th0, tht, eps, fd_coords
 
 
