@@ -127,6 +127,46 @@ def e2_sweep(n_paths, reps=5):
     return rows
 
 
+def slv_leg(reps):
+    """Heston stochastic local volatility (the paper's test model): 2^20
+    paths x 256 steps, 5 Heston parameters + a 10 x 20 leverage grid, 200
+    calls at the grid nodes; gradient and forward throughput, K_R/K_F."""
+    import torch
+    from paper_1901_04200_amd import capi, costmodel
+    from paper_1901_04200_amd import workloads as W
+    from paper_1901_04200_amd.mc import MonteCarloCalibration, pick_ckpt_every
+    pb, th0, tht, eps, _ = W.slv_problem()
+    gen = MonteCarloCalibration(pb.with_(seed=2))
+    C = torch.tensor(W.noisy_targets(gen.forward(tht).cpu().numpy(), eps), device="cuda")
+    gen.close()
+    k, table = pick_ckpt_every(pb, th0, C, ks=(8, 16))
+    mc = MonteCarloCalibration(pb, ckpt_every=k, ckpt_mode="store")
+    th = torch.tensor(th0, device="cuda")
+    Ey = torch.empty(pb.n_instr, dtype=torch.float64, device="cuda")
+    G = torch.empty(1, dtype=torch.float64, device="cuda")
+    g = torch.empty(pb.n_params, dtype=torch.float64, device="cuda")
+    capi.calibrate_gradient(mc.ctx, th, C, Ey, G, g)
+    capi.cal_timing_enable(mc.ctx, True)
+    ms_grad = time_ms(lambda: capi.calibrate_gradient(mc.ctx, th, C, Ey, G, g), reps)
+    p1 = capi.cal_timing_read(mc.ctx, 0)
+    p2 = capi.cal_timing_read(mc.ctx, 1)
+    capi.cal_timing_enable(mc.ctx, True)
+    ms_fwd = time_ms(lambda: capi.calibrate_forward(mc.ctx, th, Ey), reps)
+    f = capi.cal_timing_read(mc.ctx, 0)
+    capi.cal_timing_enable(mc.ctx, False)
+    status = mc.status()
+    mc.close()
+    ps = pb.n_paths * pb.n_steps
+    t_f, t_2 = f[0] / f[1], p2[0] / p2[1]
+    return {"workload": "Heston SLV: 2^20 paths x 256 steps, 5 Heston parameters + 10 x 20 leverage grid "
+                        "(piecewise constant in t, linear in S), m = 200 calls, FP32 state, FP64 sums",
+            "ckpt_every": k, "ckpt_every_ms": {str(kk): t * 1e3 for kk, t in table}, "status": status,
+            "paths_steps_per_s": ps / (ms_grad * 1e-3), "ms_per_step": ms_grad,
+            "forward_paths_steps_per_s": ps / (ms_fwd * 1e-3), "ms_forward": ms_fwd,
+            "ms_pass1_kernel": p1[0] / p1[1], "ms_pass2_kernel": t_2,
+            "kr_over_kf": costmodel.kr_over_kf(t_f, t_2)}
+
+
 def batched_leg(n_inst, reps):
     """The batched workload: n_inst Heston instances with m ~ U{8..120},
     P in {2^14, 2^16, 2^18}, N in {64, 128, 256}; one captured step per
@@ -197,7 +237,9 @@ def main():
     ap.add_argument("--cpu-sample-paths", type=int, default=1 << 20)
     ap.add_argument("--cpu-min-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-extras", action="store_true", help="skip the sweep, batched and surrogate legs")
+    ap.add_argument("--no-extras", action="store_true", help="skip the extra legs")
+    ap.add_argument("--extras", default="slv,e2_sweep,batched,surrogate_vs_mc",
+                    help="comma-separated extra legs to run")
     ap.add_argument("--sweep-paths", type=int, default=1 << 20)
     ap.add_argument("--batch-instances", type=int, default=256)
     ap.add_argument("--surrogate-draws", type=int, default=1 << 16)
@@ -341,10 +383,14 @@ def main():
     }
     mc.close()
     if not args.no_extras:
-        legs = (("e2_sweep", lambda: e2_sweep(args.sweep_paths)),
+        legs = (("slv", lambda: slv_leg(max(5, args.steps // 2))),
+                ("e2_sweep", lambda: e2_sweep(args.sweep_paths)),
                 ("batched", lambda: batched_leg(args.batch_instances, max(3, args.steps // 4))),
                 ("surrogate_vs_mc", lambda: surrogate_leg(args)))
+        chosen = set(args.extras.split(","))
         for name, fn in legs:
+            if name not in chosen:
+                continue
             print(f"bench: {name} ...", file=sys.stderr, flush=True)
             try:
                 out[name] = fn()
