@@ -134,13 +134,13 @@ def slv_leg(reps):
     import torch
     from paper_1901_04200_amd import capi, costmodel
     from paper_1901_04200_amd import workloads as W
-    from paper_1901_04200_amd.mc import MonteCarloCalibration, pick_ckpt_every
+    from paper_1901_04200_amd.mc import MonteCarloCalibration, pick_config
     pb, th0, tht, eps, _ = W.slv_problem()
     gen = MonteCarloCalibration(pb.with_(seed=2))
     C = torch.tensor(W.noisy_targets(gen.forward(tht).cpu().numpy(), eps), device="cuda")
     gen.close()
-    k, table = pick_ckpt_every(pb, th0, C, ks=(8, 16))
-    mc = MonteCarloCalibration(pb, ckpt_every=k, ckpt_mode="store")
+    (k, ppl), table = pick_config(pb, th0, C, ks=(8, 16), ppls=(1, 2))
+    mc = MonteCarloCalibration(pb, ckpt_every=k, ckpt_mode="store", paths_per_lane=ppl)
     th = torch.tensor(th0, device="cuda")
     Ey = torch.empty(pb.n_instr, dtype=torch.float64, device="cuda")
     G = torch.empty(1, dtype=torch.float64, device="cuda")
@@ -160,7 +160,8 @@ def slv_leg(reps):
     t_f, t_2 = f[0] / f[1], p2[0] / p2[1]
     return {"workload": "Heston SLV: 2^20 paths x 256 steps, 5 Heston parameters + 10 x 20 leverage grid "
                         "(piecewise constant in t, linear in S), m = 200 calls, FP32 state, FP64 sums",
-            "ckpt_every": k, "ckpt_every_ms": {str(kk): t * 1e3 for kk, t in table}, "status": status,
+            "ckpt_every": k, "paths_per_lane": ppl,
+            "tuning_ms": {f"k{kk}_ppl{pp}": t * 1e3 for (kk, pp), t in table}, "status": status,
             "paths_steps_per_s": ps / (ms_grad * 1e-3), "ms_per_step": ms_grad,
             "forward_paths_steps_per_s": ps / (ms_fwd * 1e-3), "ms_forward": ms_fwd,
             "ms_pass1_kernel": p1[0] / p1[1], "ms_pass2_kernel": t_2,
@@ -191,7 +192,7 @@ def batched_leg(n_inst, reps):
     flags = B.status()
     path_steps = sum(pb.n_paths * pb.n_steps for pb in pbs)
     Cs = B.split(C)
-    mcs = [MonteCarloCalibration(pb, ckpt_every=best[0]) for pb in pbs]
+    mcs = [MonteCarloCalibration(pb, ckpt_every=best[0], paths_per_lane=best[2]) for pb in pbs]
     ths = [th0[i].contiguous() for i in range(n_inst)]
     Cs = [c.contiguous() for c in Cs]
     outs = [(torch.empty(pb.n_instr, dtype=torch.float64, device="cuda"),
@@ -208,8 +209,8 @@ def batched_leg(n_inst, reps):
         mc.close()
     B.close()
     return {"instances": n_inst, "path_steps": path_steps, "status": flags,
-            "autotuned": {"ckpt_every": best[0], "workgroups_per_cu": best[1],
-                          "candidates_ms": {f"k{c[0]}_w{c[1]}": round(t * 1e3, 3) for c, t in table}},
+            "autotuned": {"ckpt_every": best[0], "workgroups_per_cu": best[1], "paths_per_lane": best[2],
+                          "candidates_ms": {f"k{c[0]}_w{c[1]}_ppl{c[2]}": round(t * 1e3, 3) for c, t in table}},
             "ms_graph_step": ms_graph, "paths_steps_per_s": path_steps / (ms_graph * 1e-3),
             "ms_one_context_at_a_time": ms_seq, "speedup": ms_seq / ms_graph}
 
@@ -233,7 +234,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
     ap.add_argument("--ckpt-mode", default="store", choices=["store", "rerun"])
-    ap.add_argument("--ckpt-every", type=int, default=0, help="8, 16 or 32; 0 = the fastest of 8 and 16")
+    ap.add_argument("--ckpt-every", type=int, default=0, help="8, 16 or 32; 0 = tuned (8 or 16)")
+    ap.add_argument("--paths-per-lane", type=int, default=0, help="1, 2 or 4; 0 = tuned (1 or 2)")
     ap.add_argument("--cpu-sample-paths", type=int, default=1 << 20)
     ap.add_argument("--cpu-min-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -270,12 +272,16 @@ def main():
     gen = MonteCarloCalibration(pb.with_(seed=2), precision=args.precision)
     C = torch.tensor(W.noisy_targets(gen.forward(tht).cpu().numpy(), eps), dtype=torch.float64, device="cuda")
     gen.close()
-    ckpt_every, ckpt_table = args.ckpt_every, None
-    if ckpt_every == 0:
-        from paper_1901_04200_amd.mc import pick_ckpt_every
-        ckpt_every, ckpt_table = pick_ckpt_every(pb, th0, C, precision=args.precision, ks=(8, 16))
-        print(f"bench: checkpoint spacing {ckpt_every} ({ckpt_table})", file=sys.stderr, flush=True)
-    mc = MonteCarloCalibration(pb, precision=args.precision, ckpt_every=ckpt_every, ckpt_mode=args.ckpt_mode)
+    ckpt_every, ppl, tune_table = args.ckpt_every, args.paths_per_lane, None
+    if ckpt_every == 0 or ppl == 0:
+        from paper_1901_04200_amd.mc import pick_config
+        (ckpt_every, ppl), tune_table = pick_config(pb, th0, C, precision=args.precision,
+                                                    ks=(8, 16) if ckpt_every == 0 else (ckpt_every,),
+                                                    ppls=(1, 2) if ppl == 0 else (ppl,))
+        print(f"bench: checkpoint spacing {ckpt_every}, {ppl} path(s) per lane ({tune_table})", file=sys.stderr,
+              flush=True)
+    mc = MonteCarloCalibration(pb, precision=args.precision, ckpt_every=ckpt_every, ckpt_mode=args.ckpt_mode,
+                               paths_per_lane=ppl)
     theta = torch.tensor(th0, dtype=torch.float64, device="cuda")
     Ey = torch.empty(pb.n_instr, dtype=torch.float64, device="cuda")
     G = torch.empty(1, dtype=torch.float64, device="cuda")
@@ -356,7 +362,8 @@ def main():
                         "(8 strikes x 5 maturities), M=5, full truncation, FP32 state, FP64 sums",
             "n_paths": P, "n_steps": N, "n_instr": pb.n_instr, "n_params": 5,
             "ckpt_every": geo["ckpt_every"], "ckpt_mode": args.ckpt_mode,
-            "ckpt_every_ms": None if ckpt_table is None else {str(k): t * 1e3 for k, t in ckpt_table},
+            "paths_per_lane": ppl,
+            "tuning_ms": None if tune_table is None else {f"k{k}_ppl{q}": t * 1e3 for (k, q), t in tune_table},
             "threads_per_block": geo["threads"], "blocks": geo["blocks"],
         },
         "forward_value": path_steps / (ms_fwd * 1e-3),

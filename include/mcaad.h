@@ -79,6 +79,9 @@ typedef struct cal_ctx cal_ctx;
  *   seed              : Philox key (lo, hi words)
  *   inst              : Philox counter word 2 (instance / draw index)
  *   ckpt_every (k)    : 0 = auto, else 8, 16 or 32 steps between checkpoints
+ *   paths_per_lane    : 0 = 1, else 1, 2 or 4 paths each lane runs one after
+ *                       another (a workgroup then covers 256 x that many
+ *                       paths); local volatility takes 1 only
  *   ckpt_mode         : CAL_CKPT_*
  *   s0, rate, t_max   : spot, risk-free rate (drift and discounting), horizon
  *   sqrt_eps          : must be 0 (plain full truncation, s = sqrt(v+)); any
@@ -108,7 +111,7 @@ typedef struct {
     uint32_t inst;
     int32_t ckpt_mode;
     int32_t max_batch;           /* instances per calibrate_jacobian_batch call (0 = 1) */
-    int32_t reserved0;
+    int32_t paths_per_lane;      /* 0 or 1, 2, 4 */
     double s0;
     double rate;
     double t_max;
@@ -226,11 +229,12 @@ int calb_destroy(calb_ctx *ctx);
 /* instr_offsets[n_inst + 1]: start of each instance in d_C / d_Ey. */
 int calb_offsets(const calb_ctx *ctx, int64_t *instr_offsets);
 
-/* Checkpoint spacing (8, 16, 32) and persistent workgroups per compute
- * unit (0 = as many as fit).  Synchronises the device and drops a captured
- * graph. */
-int calb_configure(calb_ctx *ctx, int32_t ckpt_every, int32_t workgroups_per_cu);
-int calb_geometry(const calb_ctx *ctx, int32_t *ckpt_every, int32_t *grid, int32_t *n_items);
+/* Checkpoint spacing (8, 16, 32), persistent workgroups per compute unit
+ * (0 = as many as fit) and paths per lane (1, 2, 4) for every instance.
+ * Synchronises the device and drops a captured graph. */
+int calb_configure(calb_ctx *ctx, int32_t ckpt_every, int32_t workgroups_per_cu, int32_t paths_per_lane);
+int calb_geometry(const calb_ctx *ctx, int32_t *ckpt_every, int32_t *grid, int32_t *n_items,
+                  int32_t *paths_per_lane);
 
 /* One gradient step for all instances, enqueued on `stream`. */
 int calibrate_gradient_batch(calb_ctx *ctx, const double *d_theta, const double *d_C, double *d_Ey, double *d_G,

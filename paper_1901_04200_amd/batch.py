@@ -26,8 +26,8 @@ def lib():
             "calb_create": ([vp, i32, C.POINTER(vp)], C.c_int),
             "calb_destroy": ([vp], C.c_int),
             "calb_offsets": ([vp, C.POINTER(C.c_int64)], C.c_int),
-            "calb_configure": ([vp, i32, i32], C.c_int),
-            "calb_geometry": ([vp, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32)], C.c_int),
+            "calb_configure": ([vp, i32, i32, i32], C.c_int),
+            "calb_geometry": ([vp, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32), C.POINTER(i32)], C.c_int),
             "calibrate_gradient_batch": ([vp, vp, vp, vp, vp, vp, vp], C.c_int),
             "calb_capture": ([vp, vp, vp, vp, vp, vp, vp], C.c_int),
             "calb_replay": ([vp, vp], C.c_int),
@@ -79,14 +79,14 @@ class BatchCalibration:
             raise capi.CalError(rc, lib().calb_last_error(self.ctx).decode())
         return rc
 
-    def configure(self, ckpt_every: int, workgroups_per_cu: int = 0):
-        self._check(lib().calb_configure(self.ctx, int(ckpt_every), int(workgroups_per_cu)))
+    def configure(self, ckpt_every: int, workgroups_per_cu: int = 0, paths_per_lane: int = 1):
+        self._check(lib().calb_configure(self.ctx, int(ckpt_every), int(workgroups_per_cu), int(paths_per_lane)))
         self._bound = None
 
     def geometry(self):
-        k, g, n = C.c_int32(), C.c_int32(), C.c_int32()
-        lib().calb_geometry(self.ctx, C.byref(k), C.byref(g), C.byref(n))
-        return {"ckpt_every": k.value, "grid": g.value, "n_items": n.value}
+        k, g, n, ppl = C.c_int32(), C.c_int32(), C.c_int32(), C.c_int32()
+        lib().calb_geometry(self.ctx, C.byref(k), C.byref(g), C.byref(n), C.byref(ppl))
+        return {"ckpt_every": k.value, "grid": g.value, "n_items": n.value, "paths_per_lane": ppl.value}
 
     def split(self, flat):
         return [flat[self.offsets[i]:self.offsets[i + 1]] for i in range(self.n)]
@@ -115,21 +115,23 @@ class BatchCalibration:
     def status(self):
         return self._check(lib().calb_status(self.ctx, C.c_void_p(self.torch.cuda.current_stream().cuda_stream)))
 
-    def autotune(self, theta, C_flat, ks=(8, 16, 32), wpcs=(0, 1, 2, 4), reps: int = 5):
+    def autotune(self, theta, C_flat, ks=(8, 16, 32), wpcs=(0, 1, 2, 4), ppls=(1, 2), reps: int = 5):
         """Time the captured step for every (checkpoint spacing, persistent
-        workgroups per CU) and keep the fastest.  Returns (choice, table)."""
+        workgroups per CU, paths per lane) and keep the fastest.  Returns
+        (choice, table)."""
         table = []
         for k in ks:
             for w in wpcs:
-                self.configure(k, w)
-                self.capture(theta, C_flat)
-                self.replay()
-                self.torch.cuda.synchronize()
-                t0 = time.perf_counter()
-                for _ in range(reps):
+                for ppl in ppls:
+                    self.configure(k, w, ppl)
+                    self.capture(theta, C_flat)
                     self.replay()
-                self.torch.cuda.synchronize()
-                table.append(((k, w), (time.perf_counter() - t0) / reps))
+                    self.torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    for _ in range(reps):
+                        self.replay()
+                    self.torch.cuda.synchronize()
+                    table.append(((k, w, ppl), (time.perf_counter() - t0) / reps))
         best = min(table, key=lambda r: r[1])[0]
         self.configure(*best)
         self.capture(theta, C_flat)

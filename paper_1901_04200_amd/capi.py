@@ -31,7 +31,7 @@ class cal_problem(C.Structure):
     _fields_ = [
         ("model", C.c_int32), ("precision", C.c_int32), ("n_params", C.c_int32), ("n_instr", C.c_int32),
         ("n_steps", C.c_int32), ("ckpt_every", C.c_int32), ("n_paths", C.c_int64), ("seed", C.c_uint64),
-        ("inst", C.c_uint32), ("ckpt_mode", C.c_int32), ("max_batch", C.c_int32), ("reserved0", C.c_int32),
+        ("inst", C.c_uint32), ("ckpt_mode", C.c_int32), ("max_batch", C.c_int32), ("paths_per_lane", C.c_int32),
         ("s0", C.c_double), ("rate", C.c_double), ("t_max", C.c_double), ("sqrt_eps", C.c_double),
         ("instr_step", C.POINTER(C.c_int32)), ("instr_strike", C.POINTER(C.c_double)),
         ("n_t_nodes", C.c_int32), ("n_k_nodes", C.c_int32),
@@ -103,7 +103,7 @@ def _check(rc, ctx=None):
 class Packed:
     """A cal_problem plus the host arrays it points at."""
 
-    def __init__(self, pb, precision=CAL_FP32, ckpt_every=0, ckpt_mode=CAL_CKPT_AUTO, max_batch=0):
+    def __init__(self, pb, precision=CAL_FP32, ckpt_every=0, ckpt_mode=CAL_CKPT_AUTO, max_batch=0, paths_per_lane=0):
         import numpy as np
         self.step = np.ascontiguousarray(pb.instr_step, dtype=np.int32)
         self.strike = np.ascontiguousarray(pb.instr_strike, dtype=np.float64)
@@ -121,6 +121,7 @@ class Packed:
         s.inst = int(pb.inst)
         s.ckpt_mode = int(ckpt_mode)
         s.max_batch = int(max_batch)
+        s.paths_per_lane = int(paths_per_lane)
         s.s0 = float(pb.s0)
         s.rate = float(pb.rate)
         s.t_max = float(pb.t_max)
@@ -134,16 +135,16 @@ class Packed:
         self.s = s
 
 
-def cal_validate(pb, precision=CAL_FP32, ckpt_every=0, ckpt_mode=CAL_CKPT_AUTO):
+def cal_validate(pb, precision=CAL_FP32, ckpt_every=0, ckpt_mode=CAL_CKPT_AUTO, paths_per_lane=0):
     """(code, message) of the host-side problem check."""
-    pk = Packed(pb, precision, ckpt_every, ckpt_mode)
+    pk = Packed(pb, precision, ckpt_every, ckpt_mode, 0, paths_per_lane)
     buf = C.create_string_buffer(256)
     rc = lib().cal_validate(C.byref(pk.s), buf, 256)
     return rc, buf.value.decode()
 
 
-def cal_create(pb, precision=CAL_FP32, ckpt_every=0, ckpt_mode=CAL_CKPT_AUTO, max_batch=0):
-    pk = Packed(pb, precision, ckpt_every, ckpt_mode, max_batch)
+def cal_create(pb, precision=CAL_FP32, ckpt_every=0, ckpt_mode=CAL_CKPT_AUTO, max_batch=0, paths_per_lane=0):
+    pk = Packed(pb, precision, ckpt_every, ckpt_mode, max_batch, paths_per_lane)
     h = C.c_void_p()
     _check(lib().cal_create(C.byref(pk.s), C.byref(h)))
     return h

@@ -42,6 +42,8 @@ struct cal_ctx {
     int64_t nblocks = 0;
     int max_batch = 1;
     int K = 16;
+    int ppl = 1;                 // paths per lane
+    int64_t nblocks_tan = 0;     // tangent mode runs one path per lane
     int mode = CAL_CKPT_STORE;
     size_t real = 4;
     DevProblem dp{};
@@ -105,6 +107,12 @@ static std::string validate(const cal_problem *pb, int *code)
     if (pb->ckpt_every != 0 && pb->ckpt_every != 8 && pb->ckpt_every != 16 && pb->ckpt_every != 32)
         return "ckpt_every must be 0, 8, 16 or 32";
     if (pb->ckpt_mode < CAL_CKPT_AUTO || pb->ckpt_mode > CAL_CKPT_STORE) return "unknown ckpt_mode";
+    if (pb->paths_per_lane != 0 && pb->paths_per_lane != 1 && pb->paths_per_lane != 2 && pb->paths_per_lane != 4)
+        return "paths_per_lane must be 0, 1, 2 or 4";
+    if (pb->model == CAL_LV && pb->paths_per_lane > 1) {
+        *code = CAL_EUNSUPPORTED;
+        return "local volatility runs one path per lane";
+    }
     if (pb->max_batch < 0 || pb->max_batch > 65535) return "max_batch must be in 0..65535";
     if (pb->model == CAL_BS && pb->n_params != 1) return "Black-Scholes takes n_params = 1";
     if (pb->model == CAL_HESTON && pb->n_params != 5) return "Heston takes n_params = 5";
@@ -182,7 +190,9 @@ extern "C" int cal_create(const cal_problem *pb, cal_ctx **out)
     c->m = pb->n_instr;
     c->N = pb->n_steps;
     c->P = pb->n_paths;
-    c->nblocks = (c->P + kBlock - 1) / kBlock;
+    c->ppl = pb->paths_per_lane > 0 ? pb->paths_per_lane : 1;
+    c->nblocks = (c->P + (int64_t)kBlock * c->ppl - 1) / ((int64_t)kBlock * c->ppl);
+    c->nblocks_tan = (c->P + kBlock - 1) / kBlock;
     c->max_batch = pb->max_batch > 0 ? pb->max_batch : 1;
     c->K = pb->ckpt_every ? pb->ckpt_every : (c->fp64 || c->model == CAL_SLV ? 8 : 16);
     const int nv = c->model == CAL_HESTON || c->model == CAL_SLV ? 2 : 1;
@@ -249,7 +259,7 @@ extern "C" int cal_create(const cal_problem *pb, cal_ctx **out)
     A((void **)&c->d_status, sizeof(int32_t));
     A((void **)&c->d_part_y, sizeof(double) * (size_t)c->nblocks * m);
     A((void **)&c->d_part_g, sizeof(double) * (size_t)c->nblocks * c->M);
-    A((void **)&c->d_part_j, sizeof(double) * (size_t)c->nblocks * tan_w * c->max_batch);
+    A((void **)&c->d_part_j, sizeof(double) * (size_t)c->nblocks_tan * tan_w * c->max_batch);
     A(&c->d_lamD, c->real * m);
     if (c->model == CAL_LV) A((void **)&c->d_t_nodes, sizeof(double) * pb->n_t_nodes);
     if (c->model == CAL_SLV) A((void **)&c->d_step_row, sizeof(int32_t) * c->N);
@@ -296,6 +306,7 @@ extern "C" int cal_create(const cal_problem *pb, cal_ctx **out)
     d.ndates = nd;
     d.nseg = nseg;
     d.K = c->K;
+    d.ppl = c->ppl;
     d.P = c->P;
     d.k0 = (uint32_t)pb->seed;
     d.k1 = (uint32_t)(pb->seed >> 32);
@@ -512,11 +523,11 @@ extern "C" int calibrate_jacobian_batch(cal_ctx *ctx, const double *d_theta, int
     hipError_t e;
     {
         Timed t(ctx, st, 2);
-        e = launch_tangent(dp, ctx->model, ctx->fp64, d_theta, ctx->d_part_j, ctx->nblocks, n_inst, st);
+        e = launch_tangent(dp, ctx->model, ctx->fp64, d_theta, ctx->d_part_j, ctx->nblocks_tan, n_inst, st);
         t.done();
     }
     if (e != hipSuccess) return hip_fail(ctx, e, "tangent launch");
-    e = launch_reduce_jac(ctx->d_part_j, ctx->nblocks, ctx->M, ctx->m, ctx->d_id, 1.0 / (double)ctx->P, d_Ey, d_J,
+    e = launch_reduce_jac(ctx->d_part_j, ctx->nblocks_tan, ctx->M, ctx->m, ctx->d_id, 1.0 / (double)ctx->P, d_Ey, d_J,
                           ctx->d_status, n_inst, st);
     if (e != hipSuccess) return hip_fail(ctx, e, "reduce launch");
     return CAL_OK;
@@ -579,10 +590,14 @@ struct calb_ctx {
     int M = 0;
     int K = 16;
     int wpc = 0;                       // persistent workgroups per CU (0 = occupancy limit)
+    int ppl = 1;                       // paths per lane
     int cus = 256;
     std::vector<BatchInst> host;       // descriptors (device pointers inside)
     std::vector<int64_t> offsets;      // [n_inst + 1] instrument offsets
     std::vector<int> nsteps;
+    std::vector<int64_t> npaths;
+    std::vector<int> order;            // instances, more steps first
+    int2 *d_items = nullptr;
     BatchLaunch L{};
     std::vector<void *> allocs;
     int32_t *d_status = nullptr;
@@ -610,15 +625,25 @@ extern "C" int calb_destroy(calb_ctx *c)
     return CAL_OK;
 }
 
-// Descriptors for the current checkpoint spacing, uploaded synchronously.
+// Descriptors and work items for the current checkpoint spacing and paths
+// per lane, uploaded synchronously.  Items: (instance, workgroup) pairs,
+// instances with more steps first, workgroups in order.
 static int calb_upload(calb_ctx *c)
 {
+    std::vector<int2> items;
     for (int i = 0; i < c->n_inst; ++i) {
-        c->host[i].pb.K = c->K;
-        c->host[i].pb.nseg = (c->nsteps[i] + c->K - 1) / c->K;
+        BatchInst &I = c->host[i];
+        I.pb.K = c->K;
+        I.pb.nseg = (c->nsteps[i] + c->K - 1) / c->K;
+        I.pb.ppl = c->ppl;
+        I.nblocks = (c->npaths[i] + (int64_t)kBlock * c->ppl - 1) / ((int64_t)kBlock * c->ppl);
     }
+    for (int i : c->order)
+        for (int64_t b = 0; b < c->host[i].nblocks; ++b) items.push_back(make_int2(i, (int)b));
     hipError_t e = hipMemcpy(c->d_insts, c->host.data(), sizeof(BatchInst) * c->n_inst, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(c->d_items, items.data(), sizeof(int2) * items.size(), hipMemcpyHostToDevice);
     if (e != hipSuccess) return bfail(c, CAL_EHIP, std::string("descriptor upload: ") + hipGetErrorString(e));
+    c->L.n_items = (int)items.size();
     const int bpc = batch_blocks_per_cu(c->model, c->fp64, c->K, c->L.max_m);
     const int per = c->wpc > 0 ? std::min(c->wpc, bpc) : bpc;
     c->L.grid = (unsigned)std::max(1, std::min(c->L.n_items, per * c->cus));
@@ -670,12 +695,14 @@ extern "C" int calb_create(const cal_problem *problems, int32_t n_inst, calb_ctx
     int max_m = 0;
     c->offsets.assign(n_inst + 1, 0);
     c->nsteps.resize(n_inst);
+    c->npaths.resize(n_inst);
     for (int i = 0; i < n_inst; ++i) {
         const cal_problem *pb = &problems[i];
         const int m = pb->n_instr;
         max_m = std::max(max_m, m);
         c->offsets[i + 1] = c->offsets[i] + m;
         c->nsteps[i] = pb->n_steps;
+        c->npaths[i] = pb->n_paths;
         std::vector<int32_t> order(m);
         std::iota(order.begin(), order.end(), 0);
         std::stable_sort(order.begin(), order.end(),
@@ -749,14 +776,13 @@ extern "C" int calb_create(const cal_problem *problems, int32_t n_inst, calb_ctx
     A(&d_ck, real * ck);
     A((void **)&c->d_status, 4);
     A((void **)&c->d_insts, sizeof(BatchInst) * n_inst);
-    // work items: instances with more steps first, then path blocks in order
-    std::vector<int> byN(n_inst);
-    std::iota(byN.begin(), byN.end(), 0);
-    std::stable_sort(byN.begin(), byN.end(), [&](int a, int b) { return c->nsteps[a] > c->nsteps[b]; });
-    std::vector<int2> items;
-    for (int i : byN)
-        for (int64_t b = 0; b < nblocks[i]; ++b) items.push_back(make_int2(i, (int)b));
-    A((void **)&d_items, sizeof(int2) * items.size());
+    // work items (one path per lane is the most there can be); calb_upload fills them
+    c->order.resize(n_inst);
+    std::iota(c->order.begin(), c->order.end(), 0);
+    std::stable_sort(c->order.begin(), c->order.end(), [&](int a, int b) { return c->nsteps[a] > c->nsteps[b]; });
+    size_t max_items = 0;
+    for (int i = 0; i < n_inst; ++i) max_items += (size_t)nblocks[i];
+    A((void **)&d_items, sizeof(int2) * max_items);
     A((void **)&d_counters, 2 * sizeof(unsigned));
     if (e != hipSuccess) {
         calb_destroy(c);
@@ -771,7 +797,6 @@ extern "C" int calb_create(const cal_problem *problems, int32_t n_inst, calb_ctx
     H2D(d_strike, strike.data(), 8 * strike.size());
     H2D(d_strike_f, strike_f.data(), 4 * strike_f.size());
     H2D(d_disc, disc.data(), 8 * disc.size());
-    H2D(d_items, items.data(), sizeof(int2) * items.size());
     if (e == hipSuccess) e = hipMemset(c->d_status, 0, 4);
     if (e != hipSuccess) {
         calb_destroy(c);
@@ -787,6 +812,7 @@ extern "C" int calb_create(const cal_problem *problems, int32_t n_inst, calb_ctx
         d.disc = d_disc + in_off[i];
         d.id = d_id + in_off[i];
         d.status = c->d_status;
+        d.ppl = 1;
         I.part_y = d_py + py_off[i];
         I.part_g = d_pg + pg_off[i];
         I.lamD = (char *)d_lam + real * lam_off[i];
@@ -795,10 +821,10 @@ extern "C" int calb_create(const cal_problem *problems, int32_t n_inst, calb_ctx
     c->L.model = c->model;
     c->L.fp64 = c->fp64;
     c->L.n_inst = n_inst;
-    c->L.n_items = (int)items.size();
     c->L.max_m = max_m;
     c->L.insts = c->d_insts;
     c->L.items = d_items;
+    c->d_items = d_items;
     c->L.counters = d_counters;
     int rc = calb_upload(c);
     if (rc) {
@@ -816,23 +842,28 @@ extern "C" int calb_offsets(const calb_ctx *c, int64_t *instr_offsets)
     return CAL_OK;
 }
 
-extern "C" int calb_configure(calb_ctx *c, int32_t ckpt_every, int32_t workgroups_per_cu)
+extern "C" int calb_configure(calb_ctx *c, int32_t ckpt_every, int32_t workgroups_per_cu, int32_t paths_per_lane)
 {
     if (!c) return bfail(nullptr, CAL_EINVAL, "null context");
     if (ckpt_every != 8 && ckpt_every != 16 && ckpt_every != 32) return bfail(c, CAL_EINVAL, "ckpt_every must be 8, 16 or 32");
     if (workgroups_per_cu < 0 || workgroups_per_cu > 64) return bfail(c, CAL_EINVAL, "workgroups_per_cu in 0..64");
+    if (paths_per_lane != 1 && paths_per_lane != 2 && paths_per_lane != 4)
+        return bfail(c, CAL_EINVAL, "paths_per_lane must be 1, 2 or 4");
     (void)hipDeviceSynchronize();
     c->K = ckpt_every;
     c->wpc = workgroups_per_cu;
+    c->ppl = paths_per_lane;
     return calb_upload(c);
 }
 
-extern "C" int calb_geometry(const calb_ctx *c, int32_t *ckpt_every, int32_t *grid, int32_t *n_items)
+extern "C" int calb_geometry(const calb_ctx *c, int32_t *ckpt_every, int32_t *grid, int32_t *n_items,
+                             int32_t *paths_per_lane)
 {
     if (!c) return CAL_EINVAL;
     if (ckpt_every) *ckpt_every = c->K;
     if (grid) *grid = (int32_t)c->L.grid;
     if (n_items) *n_items = c->L.n_items;
+    if (paths_per_lane) *paths_per_lane = c->ppl;
     return CAL_OK;
 }
 

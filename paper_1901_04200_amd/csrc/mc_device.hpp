@@ -225,9 +225,11 @@ __device__ __forceinline__ double wave_sum8(const double a[8])
 
 // Wave totals of the discounted call payoffs disc[k] max(S - strike[k], 0),
 // k in [kb, ke) (the instruments maturing at one date), eight instruments per
-// wave_sum8; lanes with active == false add 0.  Total k goes to out[k].
+// wave_sum8; lanes with active == false add 0.  Total k goes to out[k], or is
+// added to it when `add` (a lane's later paths).
 __device__ __forceinline__ void payoff_sums(const double *__restrict__ strike, const double *__restrict__ disc,
-                                            double S, bool active, int lane, int kb, int ke, double *out)
+                                            double S, bool active, int lane, int kb, int ke, double *out,
+                                            bool add = false)
 {
     for (int k0 = kb; k0 < ke; k0 += 8) {
         double a[8];
@@ -238,7 +240,7 @@ __device__ __forceinline__ void payoff_sums(const double *__restrict__ strike, c
         }
         const double y = wave_sum8(a);
         const int k = k0 + (lane >> 3);
-        if ((lane & 7) == 0 && k < ke) out[k] = y;
+        if ((lane & 7) == 0 && k < ke) out[k] = add ? out[k] + y : y;
     }
 }
 

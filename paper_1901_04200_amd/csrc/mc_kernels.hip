@@ -40,43 +40,45 @@ __device__ __forceinline__ void pass1_block(const DevProblem &pb, const double *
     const int tid = threadIdx.x;
     const int lane = tid & (kWave - 1);
     const int wave = tid / kWave;
-    const int64_t p = blk * kBlock + tid;
-    const bool active = p < pb.P;
-    const uint32_t path = (uint32_t)p;
     if (blk == 0 && tid == 0) check_theta<MODEL>(pb, theta);
 
     Consts<R> c;
     load_consts<MODEL, R>(pb, theta, c);
-    R x = (R)0;
-    R v = MODEL == kHeston ? c.v0 : (R)0;
-
     constexpr int SPC = 4 / T::D;   // steps per Philox call
     const int ncalls = (pb.N * T::D + 3) / 4;
-    int d = 0;
-    int next = pb.ndates > 0 ? ldc(pb.date_step, 0) : -1;
     const int kmask = pb.K - 1;
     const int kshift = __builtin_ctz(pb.K);
-    for (int call = 0; call < ncalls; ++call) {
-        R z[4];
-        normals4<R>((uint32_t)call, path, pb.inst, pb.k0, pb.k1, c.bm, z);
+    // the workgroup's paths: ppl runs of kBlock consecutive paths, one after another
+    for (int sp = 0; sp < pb.ppl; ++sp) {
+        const int64_t p = (blk * pb.ppl + sp) * kBlock + tid;
+        const bool active = p < pb.P;
+        const uint32_t path = (uint32_t)p;
+        R x = (R)0;
+        R v = MODEL == kHeston ? c.v0 : (R)0;
+        int d = 0;
+        int next = pb.ndates > 0 ? ldc(pb.date_step, 0) : -1;
+        for (int call = 0; call < ncalls; ++call) {
+            R z[4];
+            normals4<R>((uint32_t)call, path, pb.inst, pb.k0, pb.k1, c.bm, z);
 #pragma unroll
-        for (int j = 0; j < SPC; ++j) {
-            const int n = call * SPC + j;
-            if (n < pb.N) {
-                if constexpr (STORE) {
-                    if ((n & kmask) == 0 && active) {
-                        const int64_t base = (int64_t)((n >> kshift) * T::NV) * pb.P + p;
-                        ckpt[base] = x;
-                        if constexpr (T::NV == 2) ckpt[base + pb.P] = v;
+            for (int j = 0; j < SPC; ++j) {
+                const int n = call * SPC + j;
+                if (n < pb.N) {
+                    if constexpr (STORE) {
+                        if ((n & kmask) == 0 && active) {
+                            const int64_t base = (int64_t)((n >> kshift) * T::NV) * pb.P + p;
+                            ckpt[base] = x;
+                            if constexpr (T::NV == 2) ckpt[base + pb.P] = v;
+                        }
                     }
-                }
-                euler_step<MODEL, R>(c, x, v, z + j * T::D);
-                if (n + 1 == next) {
-                    const double S = (double)spot(c, x, n + 1);
-                    payoff_sums(pb.strike, pb.disc, S, active, lane, ldc(pb.date_begin, d), ldc(pb.date_begin, d + 1),
-                                lds + wave * pb.m);
-                    ++d;
-                    next = d < pb.ndates ? ldc(pb.date_step, d) : -1;
+                    euler_step<MODEL, R>(c, x, v, z + j * T::D);
+                    if (n + 1 == next) {
+                        const double S = (double)spot(c, x, n + 1);
+                        payoff_sums(pb.strike, pb.disc, S, active, lane, ldc(pb.date_begin, d),
+                                    ldc(pb.date_begin, d + 1), lds + wave * pb.m, sp > 0);
+                        ++d;
+                        next = d < pb.ndates ? ldc(pb.date_step, d) : -1;
+                    }
                 }
             }
         }
@@ -124,10 +126,6 @@ __device__ __forceinline__ void pass2_block(const DevProblem &pb, const double *
     const int tid = threadIdx.x;
     const int lane = tid & (kWave - 1);
     const int wave = tid / kWave;
-    const int64_t p = blk * kBlock + tid;
-    const bool active = p < pb.P;
-    const int64_t pc = active ? p : 0;   // inactive lanes read path 0's checkpoints
-    const uint32_t path = (uint32_t)p;
 
     Consts<R> c;
     load_consts<MODEL, R>(pb, theta, c);
@@ -136,138 +134,147 @@ __device__ __forceinline__ void pass2_block(const DevProblem &pb, const double *
     else strike_r = pb.strike;
     R *inj_lds = reinterpret_cast<R *>(lds + kWavesPerBlock * NP);
 
-    if constexpr (!FROM_CKPT) {
-        // The forward re-run of the paper's step 2: sweep again, keep the state
-        // at the start of every segment.
-        R x = (R)0;
-        R v = MODEL == kHeston ? c.v0 : (R)0;
-        const int ncalls = (pb.N * T::D + 3) / 4;
-        for (int call = 0; call < ncalls; ++call) {
-            R z[4];
-            normals4<R>((uint32_t)call, path, pb.inst, pb.k0, pb.k1, c.bm, z);
-#pragma unroll
-            for (int j = 0; j < SPC; ++j) {
-                const int n = call * SPC + j;
-                if (n < pb.N) {
-                    if ((n % K) == 0 && active) {
-                        const int64_t base = (int64_t)((n / K) * T::NV) * pb.P + p;
-                        ckpt[base] = x;
-                        if constexpr (T::NV == 2) ckpt[base + pb.P] = v;
-                    }
-                    euler_step<MODEL, R>(c, x, v, z + j * T::D);
-                }
-            }
-        }
-    }
-
-    R xb = (R)0, vb = (R)0;     // adjoints of the state after the current step
     double g[NP];
 #pragma unroll
     for (int j = 0; j < NP; ++j) g[j] = 0.0;
-    int dhi = pb.ndates;        // dates with index < dhi mature at or before this segment's end
+    // the workgroup's paths: ppl runs of kBlock consecutive paths, one after another
+    for (int sp = 0; sp < pb.ppl; ++sp) {
+        const int64_t p = (blk * pb.ppl + sp) * kBlock + tid;
+        const bool active = p < pb.P;
+        const int64_t pc = active ? p : 0;   // inactive lanes read path 0's checkpoints
+        const uint32_t path = (uint32_t)p;
 
-    for (int seg = pb.nseg - 1; seg >= 0; --seg) {
-        const int n0 = seg * K;
-        const int64_t base = (int64_t)(seg * T::NV) * pb.P + pc;
-        R x = ckpt[base];
-        R v = (R)0;
-        if constexpr (T::NV == 2) v = ckpt[base + pb.P];
-        int dlo = dhi;
-        while (dlo > 0 && ldc(pb.date_step, dlo - 1) > n0) --dlo;
-        int d = dlo;
-        int next = d < dhi ? ldc(pb.date_step, d) : -1;
-
-        // recompute the segment, keeping what the reverse sweep needs in
-        // registers (Heston: z1', w', v+, s of every step; Black-Scholes: z'),
-        // and the payoff adjoint of a maturity date in this lane's LDS column
-        R s_z1[K], s_w[K], s_vp[K], s_s[K];
-        R z[4];
+        if constexpr (!FROM_CKPT) {
+            // The forward re-run of the paper's step 2: sweep again, keep the state
+            // at the start of every segment.
+            R x = (R)0;
+            R v = MODEL == kHeston ? c.v0 : (R)0;
+            const int ncalls = (pb.N * T::D + 3) / 4;
+            for (int call = 0; call < ncalls; ++call) {
+                R z[4];
+                normals4<R>((uint32_t)call, path, pb.inst, pb.k0, pb.k1, c.bm, z);
 #pragma unroll
-        for (int j = 0; j < K; ++j) {
-            const int n = n0 + j;
-            s_z1[j] = (R)0;
-            s_w[j] = (R)0;
-            s_vp[j] = (R)0;
-            s_s[j] = (R)0;
-            if (n < pb.N) {
-                if (j % SPC == 0) normals4<R>((uint32_t)(n / SPC), path, pb.inst, pb.k0, pb.k1, c.bm, z);
-                const R *zs = z + (j % SPC) * T::D;
-                s_z1[j] = zs[0];
-                if constexpr (MODEL == kHeston) {
-                    const HestonStep<R> q = heston_step(c, x, v, zs[0], zs[1]);
-                    s_w[j] = q.w;
-                    s_vp[j] = q.vp;
-                    s_s[j] = q.s;
-                } else {
-                    euler_step<MODEL, R>(c, x, v, zs);
-                }
-                if (n + 1 == next) {
-                    // payoff adjoints of this date: sum_i lambda_i D_i / P 1{S > K_i} S
-                    const R S = spot(c, x, n + 1);
-                    R inj = (R)0;
-                    for (int k = ldc(pb.date_begin, d); k < ldc(pb.date_begin, d + 1); ++k)
-                        inj += S > ldc(strike_r, k) ? ldc(lamD, k) * S : (R)0;
-                    inj_lds[j * kBlock + tid] = inj;
-                    ++d;
-                    next = d < dhi ? ldc(pb.date_step, d) : -1;
+                for (int j = 0; j < SPC; ++j) {
+                    const int n = call * SPC + j;
+                    if (n < pb.N) {
+                        if ((n % K) == 0 && active) {
+                            const int64_t base = (int64_t)((n / K) * T::NV) * pb.P + p;
+                            ckpt[base] = x;
+                            if constexpr (T::NV == 2) ckpt[base + pb.P] = v;
+                        }
+                        euler_step<MODEL, R>(c, x, v, z + j * T::D);
+                    }
                 }
             }
         }
-        dhi = dlo;
 
-        // reverse sweep over the segment; its dates are dlo .. d-1, met last
-        // first.  xb, the adjoint of x~, changes only at those dates.
-        // Heston: sums over the segment's steps (b = vb before the step)
-        //   tk = sum b (theta_bar h - h v+), sb = sum b, t2 = sum b s w',
-        //   t3 = sum b s (z1' - rho w'),
-        // from which d/d(kappa) = tk, d/d(theta_bar) = kappa h sb, d/d(xi) = t2,
-        // d/d(rho) = xi t3 / (1 - rho^2).  (tk is summed per step: its two
-        // parts nearly cancel when v+ stays near theta_bar.)
-        int dr = d - 1;
-        int rnext = dr >= dlo ? ldc(pb.date_step, dr) : -1;
-        R ca = -(c.hh * xb);
-        R sb = (R)0, tk = (R)0, t2 = (R)0, t3 = (R)0;
+        R xb = (R)0, vb = (R)0;     // adjoints of the state after the current step
+        const double on = active ? 1.0 : 0.0;   // inactive lanes add nothing
+        int dhi = pb.ndates;        // dates with index < dhi mature at or before this segment's end
+
+        for (int seg = pb.nseg - 1; seg >= 0; --seg) {
+            const int n0 = seg * K;
+            const int64_t base = (int64_t)(seg * T::NV) * pb.P + pc;
+            R x = ckpt[base];
+            R v = (R)0;
+            if constexpr (T::NV == 2) v = ckpt[base + pb.P];
+            int dlo = dhi;
+            while (dlo > 0 && ldc(pb.date_step, dlo - 1) > n0) --dlo;
+            int d = dlo;
+            int next = d < dhi ? ldc(pb.date_step, d) : -1;
+
+            // recompute the segment, keeping what the reverse sweep needs in
+            // registers (Heston: z1', w', v+, s of every step; Black-Scholes: z'),
+            // and the payoff adjoint of a maturity date in this lane's LDS column
+            R s_z1[K], s_w[K], s_vp[K], s_s[K];
+            R z[4];
 #pragma unroll
-        for (int j = K - 1; j >= 0; --j) {
-            if (n0 + j < pb.N) {
-                if (n0 + j + 1 == rnext) {
-                    xb += inj_lds[j * kBlock + tid];
-                    ca = -(c.hh * xb);
-                    --dr;
-                    rnext = dr >= dlo ? ldc(pb.date_step, dr) : -1;
-                }
-                if constexpr (MODEL == kBS) {
-                    // d x~' / d sigma = -sigma h + z'
-                    sb += xb * (c.bs_gh + s_z1[j]);
-                } else {
-                    const R vp = s_vp[j], sv = s_s[j], z1 = s_z1[j], w = s_w[j];
-                    const R b = vb;
-                    const R sbar = (b * c.xi) * w + xb * z1;
-                    const R vpbar = sbar * ((R)0.5 * rcp_r(sv)) + (ca - c.kh * b);
-                    sb += b;
-                    tk += b * (c.thbh - c.h * vp);
-                    const R t = b * sv;
-                    t2 += t * w;
-                    t3 += t * (z1 - c.rho * w);
-                    vb = vp > (R)0 ? b + vpbar : b;
+            for (int j = 0; j < K; ++j) {
+                const int n = n0 + j;
+                s_z1[j] = (R)0;
+                s_w[j] = (R)0;
+                s_vp[j] = (R)0;
+                s_s[j] = (R)0;
+                if (n < pb.N) {
+                    if (j % SPC == 0) normals4<R>((uint32_t)(n / SPC), path, pb.inst, pb.k0, pb.k1, c.bm, z);
+                    const R *zs = z + (j % SPC) * T::D;
+                    s_z1[j] = zs[0];
+                    if constexpr (MODEL == kHeston) {
+                        const HestonStep<R> q = heston_step(c, x, v, zs[0], zs[1]);
+                        s_w[j] = q.w;
+                        s_vp[j] = q.vp;
+                        s_s[j] = q.s;
+                    } else {
+                        euler_step<MODEL, R>(c, x, v, zs);
+                    }
+                    if (n + 1 == next) {
+                        // payoff adjoints of this date: sum_i lambda_i D_i / P 1{S > K_i} S
+                        const R S = spot(c, x, n + 1);
+                        R inj = (R)0;
+                        for (int k = ldc(pb.date_begin, d); k < ldc(pb.date_begin, d + 1); ++k)
+                            inj += S > ldc(strike_r, k) ? ldc(lamD, k) * S : (R)0;
+                        inj_lds[j * kBlock + tid] = inj;
+                        ++d;
+                        next = d < dhi ? ldc(pb.date_step, d) : -1;
+                    }
                 }
             }
+            dhi = dlo;
+
+            // reverse sweep over the segment; its dates are dlo .. d-1, met last
+            // first.  xb, the adjoint of x~, changes only at those dates.
+            // Heston: sums over the segment's steps (b = vb before the step)
+            //   tk = sum b (theta_bar h - h v+), sb = sum b, t2 = sum b s w',
+            //   t3 = sum b s (z1' - rho w'),
+            // from which d/d(kappa) = tk, d/d(theta_bar) = kappa h sb, d/d(xi) = t2,
+            // d/d(rho) = xi t3 / (1 - rho^2).  (tk is summed per step: its two
+            // parts nearly cancel when v+ stays near theta_bar.)
+            int dr = d - 1;
+            int rnext = dr >= dlo ? ldc(pb.date_step, dr) : -1;
+            R ca = -(c.hh * xb);
+            R sb = (R)0, tk = (R)0, t2 = (R)0, t3 = (R)0;
+#pragma unroll
+            for (int j = K - 1; j >= 0; --j) {
+                if (n0 + j < pb.N) {
+                    if (n0 + j + 1 == rnext) {
+                        xb += inj_lds[j * kBlock + tid];
+                        ca = -(c.hh * xb);
+                        --dr;
+                        rnext = dr >= dlo ? ldc(pb.date_step, dr) : -1;
+                    }
+                    if constexpr (MODEL == kBS) {
+                        // d x~' / d sigma = -sigma h + z'
+                        sb += xb * (c.bs_gh + s_z1[j]);
+                    } else {
+                        const R vp = s_vp[j], sv = s_s[j], z1 = s_z1[j], w = s_w[j];
+                        const R b = vb;
+                        const R sbar = (b * c.xi) * w + xb * z1;
+                        const R vpbar = sbar * ((R)0.5 * rcp_r(sv)) + (ca - c.kh * b);
+                        sb += b;
+                        tk += b * (c.thbh - c.h * vp);
+                        const R t = b * sv;
+                        t2 += t * w;
+                        t3 += t * (z1 - c.rho * w);
+                        vb = vp > (R)0 ? b + vpbar : b;
+                    }
+                }
+            }
+            if constexpr (MODEL == kBS) {
+                g[0] += on * (double)sb;
+            } else {
+                g[0] += on * (double)tk;
+                g[1] += on * (c.g_kh * (double)sb);
+                g[2] += on * (double)t2;
+                g[3] += on * (c.g_rho * (double)t3);
+            }
         }
-        if constexpr (MODEL == kBS) {
-            g[0] += (double)sb;
-        } else {
-            g[0] += (double)tk;
-            g[1] += c.g_kh * (double)sb;
-            g[2] += (double)t2;
-            g[3] += c.g_rho * (double)t3;
-        }
+        if constexpr (MODEL == kHeston) g[4] += on * (double)vb;   // v_0 is theta[4]
     }
-    if constexpr (MODEL == kHeston) g[4] += (double)vb;   // v_0 is theta[4]
 
     static_assert(NP <= 8, "one wave_sum8 per path's gradient");
     double a[8];
 #pragma unroll
-    for (int j = 0; j < 8; ++j) a[j] = j < NP && active ? g[j] : 0.0;
+    for (int j = 0; j < 8; ++j) a[j] = j < NP ? g[j] : 0.0;
     const double t = wave_sum8(a);
     if ((lane & 7) == 0 && (lane >> 3) < NP) lds[wave * NP + (lane >> 3)] = t;
     __syncthreads();

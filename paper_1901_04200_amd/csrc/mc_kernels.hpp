@@ -17,6 +17,7 @@ struct DevProblem {
     int32_t ndates;       // distinct maturity steps
     int32_t nseg;         // checkpoint segments = ceil(N / K)
     int32_t K;            // checkpoint spacing (8, 16, 32)
+    int32_t ppl;          // paths per lane, run one after another (1, 2, 4)
     int64_t P;            // paths
     uint32_t k0, k1;      // Philox key
     uint32_t inst;        // Philox counter word 2

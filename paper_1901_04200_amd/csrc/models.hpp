@@ -127,11 +127,13 @@ __device__ __forceinline__ void euler_step(const Consts<R> &c, R &x, R &v, const
     else (void)heston_step(c, x, v, z[0], z[1]);
 }
 
-// Workgroups covering the problem's paths; block partials are stored
-// [column][workgroup], so each column's fixed-order sum reads contiguous memory.
+// Workgroups covering the problem's paths (kBlock lanes x ppl paths each);
+// block partials are stored [column][workgroup], so each column's
+// fixed-order sum reads contiguous memory.
 __device__ __forceinline__ int64_t nblocks_of(const DevProblem &pb)
 {
-    return (pb.P + kBlock - 1) / kBlock;
+    const int64_t per = (int64_t)kBlock * pb.ppl;
+    return (pb.P + per - 1) / per;
 }
 
 template <int MODEL>

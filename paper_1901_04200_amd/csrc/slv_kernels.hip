@@ -123,44 +123,47 @@ __global__ __launch_bounds__(kBlock) void k_slv_pass1(DevProblem pb, const doubl
     const int tid = threadIdx.x;
     const int lane = tid & (kWave - 1);
     const int wave = tid / kWave;
-    const int64_t p = (int64_t)blockIdx.x * kBlock + tid;
-    const bool active = p < pb.P;
-    const uint32_t path = (uint32_t)p;
     load_grid<R>(pb, theta, L.lev);
     __syncthreads();
 
     Consts<R> c;
     load_consts<kHeston, R>(pb, theta, c);
     const R K0 = (R)pb.K0, invdK = (R)(1.0 / pb.dK), Klast = (R)(pb.K0 + (pb.nK - 1) * pb.dK);
-    R x = (R)0;
-    R v = c.v0;
-    int d = 0;
-    int next = pb.ndates > 0 ? ldc(pb.date_step, 0) : -1;
     const int kmask = pb.K - 1;
     const int kshift = __builtin_ctz(pb.K);
     const int ncalls = (pb.N * 2 + 3) / 4;
-    for (int call = 0; call < ncalls; ++call) {
-        R z[4];
-        normals4<R>((uint32_t)call, path, pb.inst, pb.k0, pb.k1, c.bm, z);
+    // the workgroup's paths: ppl runs of kBlock consecutive paths, one after another
+    for (int sp = 0; sp < pb.ppl; ++sp) {
+        const int64_t p = ((int64_t)blockIdx.x * pb.ppl + sp) * kBlock + tid;
+        const bool active = p < pb.P;
+        const uint32_t path = (uint32_t)p;
+        R x = (R)0;
+        R v = c.v0;
+        int d = 0;
+        int next = pb.ndates > 0 ? ldc(pb.date_step, 0) : -1;
+        for (int call = 0; call < ncalls; ++call) {
+            R z[4];
+            normals4<R>((uint32_t)call, path, pb.inst, pb.k0, pb.k1, c.bm, z);
 #pragma unroll
-        for (int j = 0; j < 2; ++j) {
-            const int n = call * 2 + j;
-            if (n < pb.N) {
-                if constexpr (STORE) {
-                    if ((n & kmask) == 0 && active) {
-                        const int64_t base = (int64_t)((n >> kshift) * 2) * pb.P + p;
-                        ckpt[base] = x;
-                        ckpt[base + pb.P] = v;
+            for (int j = 0; j < 2; ++j) {
+                const int n = call * 2 + j;
+                if (n < pb.N) {
+                    if constexpr (STORE) {
+                        if ((n & kmask) == 0 && active) {
+                            const int64_t base = (int64_t)((n >> kshift) * 2) * pb.P + p;
+                            ckpt[base] = x;
+                            ckpt[base + pb.P] = v;
+                        }
                     }
-                }
-                const R *row = L.lev + ldc(pb.step_row, n) * pb.nK;
-                (void)slv_step(c, x, v, z[2 * j], z[2 * j + 1], row, n, K0, invdK, Klast, pb.nK);
-                if (n + 1 == next) {
-                    const double S = (double)spot(c, x, n + 1);
-                    payoff_sums(pb.strike, pb.disc, S, active, lane, ldc(pb.date_begin, d),
-                                ldc(pb.date_begin, d + 1), L.sums + wave * pb.m);
-                    ++d;
-                    next = d < pb.ndates ? ldc(pb.date_step, d) : -1;
+                    const R *row = L.lev + ldc(pb.step_row, n) * pb.nK;
+                    (void)slv_step(c, x, v, z[2 * j], z[2 * j + 1], row, n, K0, invdK, Klast, pb.nK);
+                    if (n + 1 == next) {
+                        const double S = (double)spot(c, x, n + 1);
+                        payoff_sums(pb.strike, pb.disc, S, active, lane, ldc(pb.date_begin, d),
+                                    ldc(pb.date_begin, d + 1), L.sums + wave * pb.m, sp > 0);
+                        ++d;
+                        next = d < pb.ndates ? ldc(pb.date_step, d) : -1;
+                    }
                 }
             }
         }
@@ -203,10 +206,6 @@ __global__ __launch_bounds__(kBlock) void k_slv_pass2(DevProblem pb, const doubl
     const int tid = threadIdx.x;
     const int lane = tid & (kWave - 1);
     const int wave = tid / kWave;
-    const int64_t p = (int64_t)blockIdx.x * kBlock + tid;
-    const bool active = p < pb.P;
-    const int64_t pc = active ? p : 0;   // inactive lanes run path 0 with zero adjoints
-    const uint32_t path = (uint32_t)p;
     load_grid<R>(pb, theta, L.lev);
     for (int i = tid; i < pb.nT * pb.nK; i += kBlock) L.sums[i] = 0.0;
     for (int i = tid; i < pb.nK * kBlock; i += kBlock) L.slices[i] = 0.f;
@@ -220,128 +219,136 @@ __global__ __launch_bounds__(kBlock) void k_slv_pass2(DevProblem pb, const doubl
     if constexpr (sizeof(R) == 4) strike_r = pb.strike_f;
     else strike_r = pb.strike;
 
-    if constexpr (!FROM_CKPT) {
-        R x = (R)0;
-        R v = c.v0;
-        const int ncalls = (pb.N * 2 + 3) / 4;
-        for (int call = 0; call < ncalls; ++call) {
-            R z[4];
-            normals4<R>((uint32_t)call, path, pb.inst, pb.k0, pb.k1, c.bm, z);
-#pragma unroll
-            for (int j = 0; j < 2; ++j) {
-                const int n = call * 2 + j;
-                if (n < pb.N) {
-                    if ((n % K) == 0 && active) {
-                        const int64_t base = (int64_t)((n / K) * 2) * pb.P + p;
-                        ckpt[base] = x;
-                        ckpt[base + pb.P] = v;
-                    }
-                    const R *row = L.lev + ldc(pb.step_row, n) * nK;
-                    (void)slv_step(c, x, v, z[2 * j], z[2 * j + 1], row, n, K0, invdK, Klast, nK);
-                }
-            }
-        }
-    }
-
-    R xb = (R)0, vb = (R)0;
     double g[kHes];
 #pragma unroll
     for (int j = 0; j < kHes; ++j) g[j] = 0.0;
     float *my = L.slices + tid;   // this lane's column of the slices
     int cur_a = ldc(pb.step_row, pb.N - 1);
-    int dhi = pb.ndates;
-    for (int seg = pb.nseg - 1; seg >= 0; --seg) {
-        const int n0 = seg * K;
-        const int64_t base = (int64_t)(seg * 2) * pb.P + pc;
-        R x = ckpt[base];
-        R v = ckpt[base + pb.P];
-        int dlo = dhi;
-        while (dlo > 0 && ldc(pb.date_step, dlo - 1) > n0) --dlo;
-        int d = dlo;
-        int next = d < dhi ? ldc(pb.date_step, d) : -1;
-
-        // recompute the segment, keeping (S, z1', w', v+, s) of every step
-        R s_S[K], s_z1[K], s_w[K], s_vp[K], s_s[K];
-        R z[4];
+    // the workgroup's paths: ppl runs of kBlock consecutive paths, one after another
+    for (int sp = 0; sp < pb.ppl; ++sp) {
+        const int64_t p = ((int64_t)blockIdx.x * pb.ppl + sp) * kBlock + tid;
+        const bool active = p < pb.P;
+        const int64_t pc = active ? p : 0;   // inactive lanes run path 0 with zero adjoints
+        const uint32_t path = (uint32_t)p;
+        const double on = active ? 1.0 : 0.0;
+        if constexpr (!FROM_CKPT) {
+            R x = (R)0;
+            R v = c.v0;
+            const int ncalls = (pb.N * 2 + 3) / 4;
+            for (int call = 0; call < ncalls; ++call) {
+                R z[4];
+                normals4<R>((uint32_t)call, path, pb.inst, pb.k0, pb.k1, c.bm, z);
 #pragma unroll
-        for (int j = 0; j < K; ++j) {
-            const int n = n0 + j;
-            s_S[j] = (R)0;
-            s_z1[j] = (R)0;
-            s_w[j] = (R)0;
-            s_vp[j] = (R)0;
-            s_s[j] = (R)0;
-            if (n < pb.N) {
-                if (j % 2 == 0) normals4<R>((uint32_t)(n / 2), path, pb.inst, pb.k0, pb.k1, c.bm, z);
-                const R *zs = z + (j % 2) * 2;
-                const R *row = L.lev + ldc(pb.step_row, n) * nK;
-                const SlvStep<R> q = slv_step(c, x, v, zs[0], zs[1], row, n, K0, invdK, Klast, nK);
-                s_S[j] = q.S;
-                s_z1[j] = zs[0];
-                s_w[j] = q.w;
-                s_vp[j] = q.vp;
-                s_s[j] = q.s;
-                if (n + 1 == next) {
-                    // payoff adjoints of this date: sum_i lambda_i D_i / P 1{S > K_i} S
-                    const R S = spot(c, x, n + 1);
-                    R inj = (R)0;
-                    for (int k = ldc(pb.date_begin, d); k < ldc(pb.date_begin, d + 1); ++k)
-                        inj += S > ldc(strike_r, k) ? ldc(lamD, k) * S : (R)0;
-                    L.inj[j * kBlock + tid] = active ? inj : (R)0;
-                    ++d;
-                    next = d < dhi ? ldc(pb.date_step, d) : -1;
+                for (int j = 0; j < 2; ++j) {
+                    const int n = call * 2 + j;
+                    if (n < pb.N) {
+                        if ((n % K) == 0 && active) {
+                            const int64_t base = (int64_t)((n / K) * 2) * pb.P + p;
+                            ckpt[base] = x;
+                            ckpt[base + pb.P] = v;
+                        }
+                        const R *row = L.lev + ldc(pb.step_row, n) * nK;
+                        (void)slv_step(c, x, v, z[2 * j], z[2 * j + 1], row, n, K0, invdK, Klast, nK);
+                    }
                 }
             }
         }
-        dhi = dlo;
 
-        // reverse sweep over the segment; its dates are dlo .. d-1, met last first
-        int dr = d - 1;
-        int rnext = dr >= dlo ? ldc(pb.date_step, dr) : -1;
-        R sb = (R)0, tk = (R)0, t2 = (R)0, t3 = (R)0;
+        R xb = (R)0, vb = (R)0;
+        int dhi = pb.ndates;
+        for (int seg = pb.nseg - 1; seg >= 0; --seg) {
+            const int n0 = seg * K;
+            const int64_t base = (int64_t)(seg * 2) * pb.P + pc;
+            R x = ckpt[base];
+            R v = ckpt[base + pb.P];
+            int dlo = dhi;
+            while (dlo > 0 && ldc(pb.date_step, dlo - 1) > n0) --dlo;
+            int d = dlo;
+            int next = d < dhi ? ldc(pb.date_step, d) : -1;
+
+            // recompute the segment, keeping (S, z1', w', v+, s) of every step
+            R s_S[K], s_z1[K], s_w[K], s_vp[K], s_s[K];
+            R z[4];
 #pragma unroll
-        for (int j = K - 1; j >= 0; --j) {
-            const int n = n0 + j;
-            if (n < pb.N) {
-                if (n + 1 == rnext) {
-                    xb += L.inj[j * kBlock + tid];
-                    --dr;
-                    rnext = dr >= dlo ? ldc(pb.date_step, dr) : -1;
+            for (int j = 0; j < K; ++j) {
+                const int n = n0 + j;
+                s_S[j] = (R)0;
+                s_z1[j] = (R)0;
+                s_w[j] = (R)0;
+                s_vp[j] = (R)0;
+                s_s[j] = (R)0;
+                if (n < pb.N) {
+                    if (j % 2 == 0) normals4<R>((uint32_t)(n / 2), path, pb.inst, pb.k0, pb.k1, c.bm, z);
+                    const R *zs = z + (j % 2) * 2;
+                    const R *row = L.lev + ldc(pb.step_row, n) * nK;
+                    const SlvStep<R> q = slv_step(c, x, v, zs[0], zs[1], row, n, K0, invdK, Klast, nK);
+                    s_S[j] = q.S;
+                    s_z1[j] = zs[0];
+                    s_w[j] = q.w;
+                    s_vp[j] = q.vp;
+                    s_s[j] = q.s;
+                    if (n + 1 == next) {
+                        // payoff adjoints of this date: sum_i lambda_i D_i / P 1{S > K_i} S
+                        const R S = spot(c, x, n + 1);
+                        R inj = (R)0;
+                        for (int k = ldc(pb.date_begin, d); k < ldc(pb.date_begin, d + 1); ++k)
+                            inj += S > ldc(strike_r, k) ? ldc(lamD, k) * S : (R)0;
+                        L.inj[j * kBlock + tid] = active ? inj : (R)0;
+                        ++d;
+                        next = d < dhi ? ldc(pb.date_step, d) : -1;
+                    }
                 }
-                const int a_n = ldc(pb.step_row, n);
-                if (a_n != cur_a) {
-                    flush_row<R>(pb, L, cur_a);
-                    cur_a = a_n;
-                }
-                const R S = s_S[j], vp = s_vp[j], sv = s_s[j], z1 = s_z1[j], w = s_w[j];
-                const SpotCell<R> q = spot_cell(L.lev + a_n * nK, S, K0, invdK, Klast, nK);
-                const R b = vb;
-                const R Lbar = xb * (sv * z1 - c.h * q.L * vp);
-                const R sbar = (b * c.xi) * w + (xb * q.L) * z1;
-                const R vpbar = sbar * ((R)0.5 * rcp_r(sv)) - c.hh * (q.L * q.L) * xb - c.kh * b;
-                sb += b;
-                tk += b * (c.thbh - c.h * vp);
-                const R t = b * sv;
-                t2 += t * w;
-                t3 += t * (z1 - c.rho * w);
-                const R w1 = Lbar * q.be;
-                my[q.b * kBlock] += (float)(Lbar - w1);
-                my[(q.b + 1) * kBlock] += (float)w1;
-                xb = xb + Lbar * (q.inside ? (q.r1 - q.r0) * invdK : (R)0) * S;
-                vb = vp > (R)0 ? b + vpbar : b;
             }
+            dhi = dlo;
+
+            // reverse sweep over the segment; its dates are dlo .. d-1, met last first
+            int dr = d - 1;
+            int rnext = dr >= dlo ? ldc(pb.date_step, dr) : -1;
+            R sb = (R)0, tk = (R)0, t2 = (R)0, t3 = (R)0;
+#pragma unroll
+            for (int j = K - 1; j >= 0; --j) {
+                const int n = n0 + j;
+                if (n < pb.N) {
+                    if (n + 1 == rnext) {
+                        xb += L.inj[j * kBlock + tid];
+                        --dr;
+                        rnext = dr >= dlo ? ldc(pb.date_step, dr) : -1;
+                    }
+                    const int a_n = ldc(pb.step_row, n);
+                    if (a_n != cur_a) {
+                        flush_row<R>(pb, L, cur_a);
+                        cur_a = a_n;
+                    }
+                    const R S = s_S[j], vp = s_vp[j], sv = s_s[j], z1 = s_z1[j], w = s_w[j];
+                    const SpotCell<R> q = spot_cell(L.lev + a_n * nK, S, K0, invdK, Klast, nK);
+                    const R b = vb;
+                    const R Lbar = xb * (sv * z1 - c.h * q.L * vp);
+                    const R sbar = (b * c.xi) * w + (xb * q.L) * z1;
+                    const R vpbar = sbar * ((R)0.5 * rcp_r(sv)) - c.hh * (q.L * q.L) * xb - c.kh * b;
+                    sb += b;
+                    tk += b * (c.thbh - c.h * vp);
+                    const R t = b * sv;
+                    t2 += t * w;
+                    t3 += t * (z1 - c.rho * w);
+                    const R w1 = Lbar * q.be;
+                    my[q.b * kBlock] += (float)(Lbar - w1);
+                    my[(q.b + 1) * kBlock] += (float)w1;
+                    xb = xb + Lbar * (q.inside ? (q.r1 - q.r0) * invdK : (R)0) * S;
+                    vb = vp > (R)0 ? b + vpbar : b;
+                }
+            }
+            g[0] += on * (double)tk;
+            g[1] += on * (c.g_kh * (double)sb);
+            g[2] += on * (double)t2;
+            g[3] += on * (c.g_rho * (double)t3);
         }
-        g[0] += (double)tk;
-        g[1] += c.g_kh * (double)sb;
-        g[2] += (double)t2;
-        g[3] += c.g_rho * (double)t3;
+        g[4] += on * (double)vb;   // v_0 is theta[4]
     }
-    g[4] += (double)vb;   // v_0 is theta[4]
     flush_row<R>(pb, L, cur_a);
 
     double a8[8];
 #pragma unroll
-    for (int j = 0; j < 8; ++j) a8[j] = j < kHes && active ? g[j] : 0.0;
+    for (int j = 0; j < 8; ++j) a8[j] = j < kHes ? g[j] : 0.0;
     const double t = wave_sum8(a8);
     if ((lane & 7) == 0 && (lane >> 3) < kHes) L.hes[wave * kHes + (lane >> 3)] = t;
     __syncthreads();

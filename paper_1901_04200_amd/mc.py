@@ -16,13 +16,14 @@ class MonteCarloCalibration:
     current device (host arrays are copied there)."""
 
     def __init__(self, problem, precision: str = "fp32", ckpt_every: int = 0, ckpt_mode: str = "auto",
-                 max_batch: int = 0):
+                 max_batch: int = 0, paths_per_lane: int = 0):
         if not torch.cuda.is_available():
             raise RuntimeError("the Monte Carlo calibration path needs a HIP device")
         self.problem = problem
         self.precision = precision
         self.device = torch.device("cuda", torch.cuda.current_device())
-        self.ctx = capi.cal_create(problem, _PREC[precision], ckpt_every, _MODE[ckpt_mode], max_batch)
+        self.ctx = capi.cal_create(problem, _PREC[precision], ckpt_every, _MODE[ckpt_mode], max_batch,
+                                   paths_per_lane)
         self.m = int(len(problem.instr_step))
         self.M = int(problem.n_params)
 
@@ -79,27 +80,30 @@ class MonteCarloCalibration:
             pass
 
 
-def pick_ckpt_every(problem, theta, targets, precision: str = "fp32", ks=(8, 16, 32), reps: int = 5):
-    """Time `reps` gradient calls (after one warm-up) at each checkpoint
-    spacing in `ks` and return (fastest spacing, [(k, seconds per call)]).
-    The spacing trades pass 1's checkpoint stores and pass 2's register
-    footprint (occupancy) against each other; which wins depends on the
-    model, the sizes and the device."""
+def pick_config(problem, theta, targets, precision: str = "fp32", ks=(8, 16, 32), ppls=(1,), reps: int = 5):
+    """Time `reps` gradient calls (after one warm-up) for every checkpoint
+    spacing in `ks` and paths per lane in `ppls`; return (fastest (k, ppl),
+    [((k, ppl), seconds per call)]).  The spacing trades pass 1's checkpoint
+    stores and pass 2's register footprint (occupancy) against each other;
+    more paths per lane mean fewer workgroups and fewer partial sums; which
+    wins depends on the model, the sizes and the device."""
     table = []
     for k in ks:
-        mc = MonteCarloCalibration(problem, precision=precision, ckpt_every=k, ckpt_mode="store")
-        th = mc._dev(theta, mc.M)
-        C = mc._dev(targets, mc.m)
-        Ey = torch.empty(mc.m, dtype=torch.float64, device=mc.device)
-        G = torch.empty(1, dtype=torch.float64, device=mc.device)
-        g = torch.empty(mc.M, dtype=torch.float64, device=mc.device)
-        capi.calibrate_gradient(mc.ctx, th, C, Ey, G, g)
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        for _ in range(reps):
+        for ppl in ppls:
+            mc = MonteCarloCalibration(problem, precision=precision, ckpt_every=k, ckpt_mode="store",
+                                       paths_per_lane=ppl)
+            th = mc._dev(theta, mc.M)
+            C = mc._dev(targets, mc.m)
+            Ey = torch.empty(mc.m, dtype=torch.float64, device=mc.device)
+            G = torch.empty(1, dtype=torch.float64, device=mc.device)
+            g = torch.empty(mc.M, dtype=torch.float64, device=mc.device)
             capi.calibrate_gradient(mc.ctx, th, C, Ey, G, g)
-        e1.record()
-        torch.cuda.synchronize()
-        table.append((k, e0.elapsed_time(e1) * 1e-3 / reps))
-        mc.close()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(reps):
+                capi.calibrate_gradient(mc.ctx, th, C, Ey, G, g)
+            e1.record()
+            torch.cuda.synchronize()
+            table.append(((k, ppl), e0.elapsed_time(e1) * 1e-3 / reps))
+            mc.close()
     return min(table, key=lambda r: r[1])[0], table

@@ -103,3 +103,18 @@ def test_local_vol_validation(L):
     assert _ok(pb.with_(t_nodes=t))[0] == capi.CAL_EINVAL
     assert _ok(pb.with_(n_params=199))[0] == capi.CAL_EINVAL
     assert _ok(pb.with_(sqrt_eps=1e-4))[0] == capi.CAL_EUNSUPPORTED
+
+
+def test_paths_per_lane_validation(L):
+    pb, _, _, _ = W.heston_problem()
+    for ppl in (0, 1, 2, 4):
+        assert capi.cal_validate(pb, paths_per_lane=ppl)[0] == capi.CAL_OK
+    for ppl in (3, 8, -1):
+        rc, msg = capi.cal_validate(pb, paths_per_lane=ppl)
+        assert rc == capi.CAL_EINVAL and "paths_per_lane" in msg
+    lv = W.lv_problem(n_paths=1024)[0]
+    assert capi.cal_validate(lv, paths_per_lane=1)[0] == capi.CAL_OK
+    assert capi.cal_validate(lv, paths_per_lane=2)[0] == capi.CAL_EUNSUPPORTED
+    slv = W.slv_problem(n_paths=1024)[0]
+    assert capi.cal_validate(slv, paths_per_lane=4)[0] == capi.CAL_OK
+    assert capi.cal_validate(slv.with_(n_params=204))[0] == capi.CAL_EINVAL

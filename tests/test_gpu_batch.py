@@ -41,8 +41,8 @@ def batch12():
     return insts, Cs, th
 
 
-def single(pb, th, C, precision="fp32", k=16):
-    mc = MonteCarloCalibration(pb, precision=precision, ckpt_every=k, ckpt_mode="store")
+def single(pb, th, C, precision="fp32", k=16, ppl=1):
+    mc = MonteCarloCalibration(pb, precision=precision, ckpt_every=k, ckpt_mode="store", paths_per_lane=ppl)
     Ey, G, g = mc.gradient(th, C)
     out = Ey.cpu().numpy(), float(G.item()), g.cpu().numpy()
     mc.close()
@@ -98,20 +98,21 @@ def test_batch_configure_and_autotune(batch12):
     B = BatchCalibration([pb for pb, *_ in sub])
     thd = torch.tensor(th[:5], device="cuda")
     Cd = torch.tensor(np.concatenate(Cs[:5]), device="cuda")
-    for k, w in ((8, 1), (32, 2)):
-        B.configure(k, w)
+    for k, w, ppl in ((8, 1, 1), (32, 2, 2), (16, 0, 4)):
+        B.configure(k, w, ppl)
+        assert B.geometry()["paths_per_lane"] == ppl
         Ey, G, g = B.gradient(thd, Cd)
         Ey = B.split(Ey.cpu().numpy())
         for i in (0, 4):
-            e1, G1, g1 = single(sub[i][0], sub[i][1], Cs[i], k=k)
+            e1, G1, g1 = single(sub[i][0], sub[i][1], Cs[i], k=k, ppl=ppl)
             np.testing.assert_array_equal(Ey[i], e1)
             np.testing.assert_array_equal(g.cpu().numpy()[i], g1)
-    best, table = B.autotune(thd, Cd, ks=(8, 16), wpcs=(0, 2), reps=2)
+    best, table = B.autotune(thd, Cd, ks=(8, 16), wpcs=(0, 2), ppls=(1, 2), reps=2)
     say("autotune:", best, [(c, round(t * 1e3, 3)) for c, t in table])
     assert best in [c for c, _ in table]
     B.replay()
     torch.cuda.synchronize()
-    e1, G1, g1 = single(sub[1][0], sub[1][1], Cs[1], k=best[0])
+    e1, G1, g1 = single(sub[1][0], sub[1][1], Cs[1], k=best[0], ppl=best[2])
     np.testing.assert_array_equal(B.split(B.Ey.cpu().numpy())[1], e1)
     B.close()
 

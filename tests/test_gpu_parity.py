@@ -338,3 +338,26 @@ def test_heston_full_size(orc):
     say("full-size fp32 first-draw Ey error %.3g" % ey_err(Ey0_g, Ey0))
     # ill-conditioned point (see test_heston_fp32_first_draw_stated): stated, guarded loosely
     assert ey_err(Ey0_g, Ey0) <= 5e-4
+
+
+@pytest.mark.parametrize("model", ["bs", "heston"])
+def test_paths_per_lane(orc, model):
+    """A lane running 2 or 4 paths one after another (fewer workgroups) gives
+    the oracle's result; ragged path counts leave the last lanes idle."""
+    if model == "bs":
+        pb, th, C = W.bs_problem(n_paths=3 * 256 + 77)
+    else:
+        pb, _, _, _ = W.heston_problem(n_paths=3 * 256 + 77, n_steps=64, t_max=0.5)
+        th = W.heston_feller_draws(17, 1)[0]
+        C = np.linspace(2.0, 12.0, pb.n_instr)
+    Eo, Go, go = orc.gradient(pb, th, C)
+    for ppl in (1, 2, 4):
+        for mode in ("store", "rerun"):
+            mc = MonteCarloCalibration(pb, precision="fp64", ckpt_every=8, ckpt_mode=mode, paths_per_lane=ppl)
+            Ey, G, g = mc.gradient(th, C)
+            assert mc.status() == 0
+            assert mc.geometry()["blocks"] == -(-pb.n_paths // (256 * ppl))
+            mc.close()
+            ey, eg = ey_err(Ey.cpu().numpy(), Eo), g_err(g.cpu().numpy(), go)
+            say(f"  {model} ppl={ppl} {mode}: Ey {ey:.2e} grad {eg:.2e}")
+            assert ey <= 1e-12 and eg <= 1e-9

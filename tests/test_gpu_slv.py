@@ -163,3 +163,14 @@ def test_slv_full_size_oracle_and_fd(orc):
     say(f"  worst |fd - adjoint| / max|g| = {worst:.2e}")
     assert worst <= 1e-5
     mc.close()
+
+
+def test_slv_paths_per_lane(orc):
+    pb, th0, tht, eps, _ = W.slv_problem(n_paths=2 * 256 + 5, n_steps=48)
+    C = np.linspace(2.0, 9.0, pb.n_instr)
+    Eo, Go, go = orc.gradient(pb, th0, C)
+    for ppl in (2, 4):
+        Ey_f, Ey, G, g = run(pb, th0, C, "fp64", paths_per_lane=ppl)
+        say(f"  ppl={ppl}: Ey {ey_err(Ey, Eo):.2e} grad {g_err(g, go):.2e}")
+        assert ey_err(Ey, Eo) <= 1e-12
+        assert g_err(g, go) <= 1e-6
