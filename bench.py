@@ -59,10 +59,10 @@ def code_hash(path):
     return hashlib.sha256(" ".join(text.split()).encode()).hexdigest()
 
 
-def pass2_traffic(ckpt_every):
-    """HBM bytes per pass-2 launch at this checkpoint spacing from the committed
-    counter summary, or None when no figure was taken for it or any source of
-    the kernel has changed since the counters were taken."""
+def pass2_traffic(ckpt_every, ppl):
+    """HBM bytes per pass-2 launch at this checkpoint spacing and paths per
+    lane from the committed counter summary, or None when no figure was taken
+    for them or any source of the kernel has changed since."""
     try:
         lines = open(TRAFFIC_PROFILE).read().splitlines()
     except OSError:
@@ -70,8 +70,8 @@ def pass2_traffic(ckpt_every):
     value, ok = None, True
     for ln in lines:
         f = ln.split()
-        if len(f) == 3 and f[0] == "k_pass2_bytes_per_launch" and f[1] == f"K={ckpt_every}":
-            value = float(f[2])
+        if len(f) == 4 and f[0] == "k_pass2_bytes_per_launch" and f[1:3] == [f"K={ckpt_every}", f"ppl={ppl}"]:
+            value = float(f[3])
         elif len(f) == 3 and f[0] == "code-sha256":
             ok = ok and os.path.exists(os.path.join(ROOT, f[1])) and code_hash(os.path.join(ROOT, f[1])) == f[2]
     return value if ok else None
@@ -382,7 +382,7 @@ def main():
             "peak": roofline.PEAK_SLOTS / 1e12,
             "unit": "T VALU lane-slots/s",
             "frac": achieved / roofline.PEAK_SLOTS,
-            "traffic": pass2_traffic(geo["ckpt_every"]),
+            "traffic": pass2_traffic(geo["ckpt_every"], ppl),
             "traffic_unit": "HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-scaled)",
             "traffic_algorithmic": roofline.pass2_bytes(pb.n_paths, geo["ckpt_every"], geo["blocks"], pb.n_instr,
                                                         pb.n_steps),
