@@ -9,7 +9,8 @@
  * or constant generator with the HIP library.
  *
  * What it computes, in the paper's order:
- *   - the forward algorithm F (paper: "Calculation of ... F : R^{M+N} -> R^m")
+ *   - the forward algorithm F : R^{M+N} -> R^m (paper, section on the
+ *     calculation of the gradient of G)
  *     for one path: an Euler-discretised SDE driven by N independent normals,
  *     producing the m payoffs y_i of that path;
  *   - the Monte Carlo expectation E y ~ (1/P) sum_k y(w_k) (paper, remarks on
@@ -30,8 +31,8 @@
  * so both precisions see the same uniforms) and pairs of uniforms to normals by
  * Box-Muller: rho = sqrt(-2 ln u0), z0 = rho cos(2 pi u1), z1 = rho sin(2 pi u1).
  *
- * Models (all step the log-price x = ln(S/S0), "standard Euler" read as
- * log-Euler; payoffs are discounted calls):
+ * Models (all step the log-price x = ln(S/S0): the paper's Euler scheme read
+ * as log-Euler; payoffs are discounted calls):
  *   0  Black-Scholes GBM, theta = (sigma)
  *   1  Heston with full truncation, theta = (kappa, theta_bar, xi, rho, v0);
  *      the paper's test model with the leverage function set to one

@@ -8,8 +8,8 @@
 //
 //  pass 1 (paper: algorithm step 1, cost eq. 1211A)
 //      Euler sweep F_v, payoffs at maturity dates, block partials of sum y_i;
-//      optionally stores the state every K steps (the paper's "execution
-//      results of the first step ... stored in the memory", step 2).
+//      optionally stores the state every K steps (in the paper's step 2 the
+//      results of step 1 are kept in memory).
 //  pass 2 (paper: algorithm step 2, eq. 0711A; step 3 is the final sum)
 //      per path: forward sweep again (or the stored checkpoints), then for
 //      every K-step segment from the last to the first: reload the segment's
