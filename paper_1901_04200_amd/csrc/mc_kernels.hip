@@ -46,8 +46,9 @@ __device__ __forceinline__ void pass1_block(const DevProblem &pb, const double *
     load_consts<MODEL, R>(pb, theta, c);
     constexpr int SPC = 4 / T::D;   // steps per Philox call
     const int ncalls = (pb.N * T::D + 3) / 4;
-    const int kmask = pb.K - 1;
-    const int kshift = __builtin_ctz(pb.K);
+    // Philox calls per checkpoint segment (K is a multiple of SPC; at least one
+    // call per segment whatever K holds, so the loop below always advances)
+    const int cps = max(pb.K / SPC, 1);
     // the workgroup's paths: ppl runs of kBlock consecutive paths, one after another
     for (int sp = 0; sp < pb.ppl; ++sp) {
         const int64_t p = (blk * pb.ppl + sp) * kBlock + tid;
@@ -57,27 +58,31 @@ __device__ __forceinline__ void pass1_block(const DevProblem &pb, const double *
         R v = MODEL == kHeston ? c.v0 : (R)0;
         int d = 0;
         int next = pb.ndates > 0 ? ldc(pb.date_step, 0) : -1;
-        for (int call = 0; call < ncalls; ++call) {
-            R z[4];
-            normals4<R>((uint32_t)call, path, pb.inst, pb.k0, pb.k1, c.bm, z);
+        // segments of K steps; the state at a segment's start is its checkpoint
+        R *cp = ckpt + p;
+        for (int call = 0; call < ncalls; cp += (int64_t)T::NV * pb.P) {
+            if constexpr (STORE) {
+                if (active) {
+                    cp[0] = x;
+                    if constexpr (T::NV == 2) cp[pb.P] = v;
+                }
+            }
+            const int cend = min(call + cps, ncalls);
+            for (; call < cend; ++call) {
+                R z[4];
+                normals4<R>((uint32_t)call, path, pb.inst, pb.k0, pb.k1, c.bm, z);
 #pragma unroll
-            for (int j = 0; j < SPC; ++j) {
-                const int n = call * SPC + j;
-                if (n < pb.N) {
-                    if constexpr (STORE) {
-                        if ((n & kmask) == 0 && active) {
-                            const int64_t base = (int64_t)((n >> kshift) * T::NV) * pb.P + p;
-                            ckpt[base] = x;
-                            if constexpr (T::NV == 2) ckpt[base + pb.P] = v;
+                for (int j = 0; j < SPC; ++j) {
+                    const int n = call * SPC + j;
+                    if (n < pb.N) {
+                        euler_step<MODEL, R>(c, x, v, z + j * T::D);
+                        if (n + 1 == next) {
+                            const double S = (double)spot(c, x, n + 1);
+                            payoff_sums(pb.strike, pb.disc, S, active, lane, ldc(pb.date_begin, d),
+                                        ldc(pb.date_begin, d + 1), lds + wave * pb.m, sp > 0);
+                            ++d;
+                            next = d < pb.ndates ? ldc(pb.date_step, d) : -1;
                         }
-                    }
-                    euler_step<MODEL, R>(c, x, v, z + j * T::D);
-                    if (n + 1 == next) {
-                        const double S = (double)spot(c, x, n + 1);
-                        payoff_sums(pb.strike, pb.disc, S, active, lane, ldc(pb.date_begin, d),
-                                    ldc(pb.date_begin, d + 1), lds + wave * pb.m, sp > 0);
-                        ++d;
-                        next = d < pb.ndates ? ldc(pb.date_step, d) : -1;
                     }
                 }
             }
@@ -184,16 +189,16 @@ __device__ __forceinline__ void pass2_block(const DevProblem &pb, const double *
             int next = d < dhi ? ldc(pb.date_step, d) : -1;
 
             // recompute the segment, keeping what the reverse sweep needs in
-            // registers (Heston: z1', w', v+, s of every step; Black-Scholes: z'),
-            // and the payoff adjoint of a maturity date in this lane's LDS column
-            R s_z1[K], s_w[K], s_vp[K], s_s[K];
+            // registers (Heston: z1', w', s = sqrt(v+) of every step, v+ is taken
+            // back as s^2; Black-Scholes: z'), and the payoff adjoint of a
+            // maturity date in this lane's LDS column
+            R s_z1[K], s_w[K], s_s[K];
             R z[4];
 #pragma unroll
             for (int j = 0; j < K; ++j) {
                 const int n = n0 + j;
                 s_z1[j] = (R)0;
                 s_w[j] = (R)0;
-                s_vp[j] = (R)0;
                 s_s[j] = (R)0;
                 if (n < pb.N) {
                     if (j % SPC == 0) normals4<R>((uint32_t)(n / SPC), path, pb.inst, pb.k0, pb.k1, c.bm, z);
@@ -202,7 +207,6 @@ __device__ __forceinline__ void pass2_block(const DevProblem &pb, const double *
                     if constexpr (MODEL == kHeston) {
                         const HestonStep<R> q = heston_step(c, x, v, zs[0], zs[1]);
                         s_w[j] = q.w;
-                        s_vp[j] = q.vp;
                         s_s[j] = q.s;
                     } else {
                         euler_step<MODEL, R>(c, x, v, zs);
@@ -246,7 +250,8 @@ __device__ __forceinline__ void pass2_block(const DevProblem &pb, const double *
                         // d x~' / d sigma = -sigma h + z'
                         sb += xb * (c.bs_gh + s_z1[j]);
                     } else {
-                        const R vp = s_vp[j], sv = s_s[j], z1 = s_z1[j], w = s_w[j];
+                        const R sv = s_s[j], z1 = s_z1[j], w = s_w[j];
+                        const R vp = sv * sv;
                         const R b = vb;
                         const R sbar = (b * c.xi) * w + xb * z1;
                         const R vpbar = sbar * ((R)0.5 * rcp_r(sv)) + (ca - c.kh * b);
@@ -255,7 +260,7 @@ __device__ __forceinline__ void pass2_block(const DevProblem &pb, const double *
                         const R t = b * sv;
                         t2 += t * w;
                         t3 += t * (z1 - c.rho * w);
-                        vb = vp > (R)0 ? b + vpbar : b;
+                        vb = sv > (R)0 ? b + vpbar : b;
                     }
                 }
             }

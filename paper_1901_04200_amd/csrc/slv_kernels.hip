@@ -266,8 +266,9 @@ __global__ __launch_bounds__(kBlock) void k_slv_pass2(DevProblem pb, const doubl
             int d = dlo;
             int next = d < dhi ? ldc(pb.date_step, d) : -1;
 
-            // recompute the segment, keeping (S, z1', w', v+, s) of every step
-            R s_S[K], s_z1[K], s_w[K], s_vp[K], s_s[K];
+            // recompute the segment, keeping (S, z1', w', s = sqrt(v+)) of every
+            // step; v+ is taken back as s^2
+            R s_S[K], s_z1[K], s_w[K], s_s[K];
             R z[4];
 #pragma unroll
             for (int j = 0; j < K; ++j) {
@@ -275,7 +276,6 @@ __global__ __launch_bounds__(kBlock) void k_slv_pass2(DevProblem pb, const doubl
                 s_S[j] = (R)0;
                 s_z1[j] = (R)0;
                 s_w[j] = (R)0;
-                s_vp[j] = (R)0;
                 s_s[j] = (R)0;
                 if (n < pb.N) {
                     if (j % 2 == 0) normals4<R>((uint32_t)(n / 2), path, pb.inst, pb.k0, pb.k1, c.bm, z);
@@ -285,7 +285,6 @@ __global__ __launch_bounds__(kBlock) void k_slv_pass2(DevProblem pb, const doubl
                     s_S[j] = q.S;
                     s_z1[j] = zs[0];
                     s_w[j] = q.w;
-                    s_vp[j] = q.vp;
                     s_s[j] = q.s;
                     if (n + 1 == next) {
                         // payoff adjoints of this date: sum_i lambda_i D_i / P 1{S > K_i} S
@@ -319,7 +318,8 @@ __global__ __launch_bounds__(kBlock) void k_slv_pass2(DevProblem pb, const doubl
                         flush_row<R>(pb, L, cur_a);
                         cur_a = a_n;
                     }
-                    const R S = s_S[j], vp = s_vp[j], sv = s_s[j], z1 = s_z1[j], w = s_w[j];
+                    const R S = s_S[j], sv = s_s[j], z1 = s_z1[j], w = s_w[j];
+                    const R vp = sv * sv;
                     const SpotCell<R> q = spot_cell(L.lev + a_n * nK, S, K0, invdK, Klast, nK);
                     const R b = vb;
                     const R Lbar = xb * (sv * z1 - c.h * q.L * vp);
@@ -334,7 +334,7 @@ __global__ __launch_bounds__(kBlock) void k_slv_pass2(DevProblem pb, const doubl
                     my[q.b * kBlock] += (float)(Lbar - w1);
                     my[(q.b + 1) * kBlock] += (float)w1;
                     xb = xb + Lbar * (q.inside ? (q.r1 - q.r0) * invdK : (R)0) * S;
-                    vb = vp > (R)0 ? b + vpbar : b;
+                    vb = sv > (R)0 ? b + vpbar : b;
                 }
             }
             g[0] += on * (double)tk;

@@ -25,11 +25,12 @@ the scalar unit and are not counted):
   Euler step on (x~, v): v+, sqrt, w', xi w', x~ (2 fma), v (3)
                                            = 9 valu + 1 trans
   forward step F                           = 8 mad64 + 25 valu + 5 trans  (77 slots)
-  reverse step R: sbar (3), s' (rcp, 1), v+bar (2), the four segment sums
-    (6), adjoint of v (3)                  = 16 valu + 1 trans            (20 slots)
+  reverse step R: v+ = s^2 (1: pass 2 keeps s, not v+, per step of a
+    segment), sbar (3), s' (rcp, 1), v+bar (2), the four segment sums (6),
+    adjoint of v (3)                       = 17 valu + 1 trans            (21 slots)
   pass 1 (F)                               = F
-  pass 2 from stored checkpoints (F + R)   = 8 mad64 + 41 valu + 6 trans  (97 slots)
-FP32 flops (FMA = 2) per path-step: F 18, R 22.
+  pass 2 from stored checkpoints (F + R)   = 8 mad64 + 42 valu + 6 trans  (98 slots)
+FP32 flops (FMA = 2) per path-step: F 18, R 23.
 """
 
 CUS = 256
@@ -42,7 +43,7 @@ COST_MAD64 = 4.0
 COST_TRANS = 4.0
 
 HESTON_F = {"mad64": 8, "valu": 25, "trans": 5, "flops": 18}
-HESTON_R = {"mad64": 0, "valu": 16, "trans": 1, "flops": 22}
+HESTON_R = {"mad64": 0, "valu": 17, "trans": 1, "flops": 23}
 BS_F = {"mad64": 4, "valu": 10, "trans": 2, "flops": 5}     # quarter call + one normal per step
 BS_R = {"mad64": 0, "valu": 3, "trans": 0, "flops": 3}
 
