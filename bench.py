@@ -168,6 +168,60 @@ def slv_leg(reps):
             "kr_over_kf": costmodel.kr_over_kf(t_f, t_2)}
 
 
+def lv_leg(reps):
+    """Local volatility (bilinear 10 x 20 grid, M = 200, 200 calls at the grid
+    nodes): 2^22 paths x 256 steps over 2 years, FP32 state, checkpoints every
+    16 steps.  Times calibrate_gradient, the forward pass, and one step through
+    the torch.autograd wrapper (forward keeping checkpoints, G in torch,
+    backward = pass 2 from those checkpoints)."""
+    import torch
+    from paper_1901_04200_amd import autograd as AG
+    from paper_1901_04200_amd import capi, costmodel
+    from paper_1901_04200_amd import workloads as W
+    from paper_1901_04200_amd.mc import MonteCarloCalibration
+    pb, g0, gt, eps, _ = W.lv_problem()
+    gen = MonteCarloCalibration(pb.with_(seed=2))
+    C = torch.tensor(W.noisy_targets(gen.forward(gt).cpu().numpy(), eps), device="cuda")
+    gen.close()
+    k = 16
+    mc = MonteCarloCalibration(pb, ckpt_every=k, ckpt_mode="store")
+    th = torch.tensor(g0, device="cuda")
+    Ey = torch.empty(pb.n_instr, dtype=torch.float64, device="cuda")
+    G = torch.empty(1, dtype=torch.float64, device="cuda")
+    g = torch.empty(pb.n_params, dtype=torch.float64, device="cuda")
+    capi.calibrate_gradient(mc.ctx, th, C, Ey, G, g)
+    capi.cal_timing_enable(mc.ctx, True)
+    ms_grad = time_ms(lambda: capi.calibrate_gradient(mc.ctx, th, C, Ey, G, g), reps)
+    p1 = capi.cal_timing_read(mc.ctx, 0)
+    p2 = capi.cal_timing_read(mc.ctx, 1)
+    capi.cal_timing_enable(mc.ctx, True)
+    ms_fwd = time_ms(lambda: capi.calibrate_forward(mc.ctx, th, Ey), reps)
+    f = capi.cal_timing_read(mc.ctx, 0)
+    capi.cal_timing_enable(mc.ctx, False)
+    thg = torch.tensor(g0, device="cuda", requires_grad=True)
+
+    def autograd_step():
+        thg.grad = None
+        Gt = 0.5 * torch.sum((AG.mc_prices(thg, mc) - C) ** 2)
+        Gt.backward()
+
+    autograd_step()
+    ms_ag = time_ms(autograd_step, reps)
+    agree = float(torch.max(torch.abs(thg.grad - g)) / torch.max(torch.abs(g)))
+    status = mc.status()
+    mc.close()
+    ps = pb.n_paths * pb.n_steps
+    t_f, t_2 = f[0] / f[1], p2[0] / p2[1]
+    return {"workload": "local volatility: 2^22 paths x 256 steps over 2 years, bilinear 10 x 20 grid (M = 200), "
+                        "m = 200 calls at the grid nodes, FP32 state, FP64 sums",
+            "ckpt_every": k, "status": status,
+            "paths_steps_per_s": ps / (ms_grad * 1e-3), "ms_per_step": ms_grad,
+            "forward_paths_steps_per_s": ps / (ms_fwd * 1e-3), "ms_forward": ms_fwd,
+            "ms_pass1_kernel": p1[0] / p1[1], "ms_pass2_kernel": t_2,
+            "kr_over_kf": costmodel.kr_over_kf(t_f, t_2),
+            "ms_autograd_step": ms_ag, "autograd_vs_gradient_rel_diff": agree}
+
+
 def batched_leg(n_inst, reps):
     """The batched workload: n_inst Heston instances with m ~ U{8..120},
     P in {2^14, 2^16, 2^18}, N in {64, 128, 256}; one captured step per
@@ -240,7 +294,7 @@ def main():
     ap.add_argument("--cpu-min-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the extra legs")
-    ap.add_argument("--extras", default="slv,e2_sweep,batched,surrogate_vs_mc",
+    ap.add_argument("--extras", default="slv,lv,e2_sweep,batched,surrogate_vs_mc",
                     help="comma-separated extra legs to run")
     ap.add_argument("--sweep-paths", type=int, default=1 << 20)
     ap.add_argument("--batch-instances", type=int, default=256)
@@ -391,6 +445,7 @@ def main():
     mc.close()
     if not args.no_extras:
         legs = (("slv", lambda: slv_leg(max(5, args.steps // 2))),
+                ("lv", lambda: lv_leg(max(5, args.steps // 2))),
                 ("e2_sweep", lambda: e2_sweep(args.sweep_paths)),
                 ("batched", lambda: batched_leg(args.batch_instances, max(3, args.steps // 4))),
                 ("surrogate_vs_mc", lambda: surrogate_leg(args)))

@@ -65,6 +65,8 @@ extern "C" {
 /* device status bits reported by cal_status */
 #define CAL_FLAG_THETA 1       /* theta outside the model's domain */
 #define CAL_FLAG_NONFINITE 2   /* a non-finite E y, G or gradient was produced */
+#define CAL_FLAG_CKPT 4        /* calibrate_vjp_stored got a theta other than the one the
+                                  checkpoints were written with (its gradient is invalid) */
 
 typedef struct cal_ctx cal_ctx;
 
@@ -150,6 +152,24 @@ int calibrate_forward(cal_ctx *ctx, const double *d_theta, double *d_Ey, void *s
  *   d_grad[M]   : out (FP64, device) */
 int calibrate_vjp(cal_ctx *ctx, const double *d_theta, const double *d_lambda, double *d_grad,
                   void *stream);
+
+/* Pass 1 that also keeps the path state at the start of every K-step segment
+ * (K = the context's ckpt_every) in the context's checkpoint buffer, the
+ * paper's step 2 keeping the results of step 1 in memory; outputs as
+ * calibrate_forward.  Afterwards calibrate_vjp_stored can run pass 2 from
+ * those checkpoints instead of re-running the forward sweep (a torch.autograd
+ * forward/backward pair costs 2 F + R instead of 3 F + R).  Works in either
+ * checkpoint mode (the buffer always exists). */
+int calibrate_forward_store(cal_ctx *ctx, const double *d_theta, double *d_Ey, void *stream);
+
+/* calibrate_vjp from the checkpoints of the last call on this context whose
+ * sweep wrote them: calibrate_forward_store, calibrate_gradient or
+ * calibrate_vjp (pass 2 re-running the forward sweep writes them too).
+ * d_theta must hold the same values as in that call: the device compares them
+ * bit for bit and sets CAL_FLAG_CKPT (see cal_status) if they differ.  Returns
+ * CAL_EINVAL when no such call has completed on the context yet. */
+int calibrate_vjp_stored(cal_ctx *ctx, const double *d_theta, const double *d_lambda, double *d_grad,
+                         void *stream);
 
 /* The paper's full algorithm (its steps 1-3, cost eq. 0711C): pass 1, then
  * r_i = E y_i - C_i and G = 1/2 sum r_i^2 in FP64 on the device, then pass 2

@@ -1,10 +1,13 @@
 """torch.autograd view of the Monte Carlo prices.
 
-forward(theta) = calibrate_forward (the paper's step 1); backward(dL/dEy) =
-calibrate_vjp (its step 2 summed over paths, eq. 0711A) seeded with the
-incoming adjoint.  For L = G = 1/2 sum (Ey - C)^2 the incoming adjoint is
-exactly lambda = Ey - C, so autograd reproduces the paper's two-pass
-gradient; any other differentiable function of the prices works the same way.
+forward(theta) = calibrate_forward_store (the paper's step 1, keeping the path
+state every K steps); backward(dL/dEy) = calibrate_vjp_stored (its step 2
+summed over paths, eq. 0711A) seeded with the incoming adjoint, from those
+checkpoints.  If another checkpoint-writing call ran on the same context in
+between, backward re-runs the forward sweep instead (calibrate_vjp).  For
+L = G = 1/2 sum (Ey - C)^2 the incoming adjoint is exactly lambda = Ey - C,
+so autograd reproduces the paper's two-pass gradient; any other
+differentiable function of the prices works the same way.
 """
 from __future__ import annotations
 
@@ -20,12 +23,18 @@ class MonteCarloPrices(torch.autograd.Function):
         ctx.mc = mc
         th = theta.detach().to(torch.float64).contiguous()
         ctx.save_for_backward(th)
-        return mc.forward(th)
+        Ey = mc.forward_store(th)
+        ctx.ckpt_id = mc.ckpt_writes
+        return Ey
 
     @staticmethod
     def backward(ctx, grad_out):
         (th,) = ctx.saved_tensors
-        g = ctx.mc.vjp(th, grad_out.detach().to(torch.float64).contiguous())
+        lam = grad_out.detach().to(torch.float64).contiguous()
+        if ctx.mc.ckpt_writes == ctx.ckpt_id:
+            g = ctx.mc.vjp_stored(th, lam)
+        else:
+            g = ctx.mc.vjp(th, lam)
         return g, None
 
 

@@ -18,11 +18,11 @@ CAL_BS, CAL_HESTON, CAL_LV, CAL_SLV = 0, 1, 2, 3
 CAL_FP32, CAL_FP64 = 0, 1
 CAL_CKPT_AUTO, CAL_CKPT_RERUN, CAL_CKPT_STORE = 0, 1, 2
 CAL_OK, CAL_EINVAL, CAL_ENOMEM, CAL_EHIP, CAL_EUNSUPPORTED = 0, -1, -2, -3, -4
-CAL_FLAG_THETA, CAL_FLAG_NONFINITE = 1, 2
+CAL_FLAG_THETA, CAL_FLAG_NONFINITE, CAL_FLAG_CKPT = 1, 2, 4
 
 EXPORTED = (
     "cal_validate", "cal_create", "cal_destroy", "calibrate_forward", "calibrate_vjp",
-    "calibrate_gradient", "calibrate_jacobian", "calibrate_jacobian_batch", "cal_status", "cal_last_error",
+    "calibrate_forward_store", "calibrate_vjp_stored", "calibrate_gradient", "calibrate_jacobian", "calibrate_jacobian_batch", "cal_status", "cal_last_error",
     "cal_timing_enable", "cal_timing_read", "cal_geometry", "cal_philox", "cal_normals",
 )
 
@@ -63,6 +63,8 @@ def lib():
             "cal_destroy": ([vp], C.c_int),
             "calibrate_forward": ([vp, dp, dp, vp], C.c_int),
             "calibrate_vjp": ([vp, dp, dp, dp, vp], C.c_int),
+            "calibrate_forward_store": ([vp, dp, dp, vp], C.c_int),
+            "calibrate_vjp_stored": ([vp, dp, dp, dp, vp], C.c_int),
             "calibrate_gradient": ([vp, dp, dp, dp, dp, dp, vp], C.c_int),
             "calibrate_jacobian": ([vp, dp, dp, dp, vp], C.c_int),
             "calibrate_jacobian_batch": ([vp, dp, i32, C.c_uint32, dp, dp, vp], C.c_int),
@@ -160,6 +162,14 @@ def calibrate_forward(ctx, theta, Ey, stream=None):
 
 def calibrate_vjp(ctx, theta, lam, grad, stream=None):
     return _check(lib().calibrate_vjp(ctx, _ptr(theta), _ptr(lam), _ptr(grad), _stream(stream)), ctx)
+
+
+def calibrate_forward_store(ctx, theta, Ey, stream=None):
+    return _check(lib().calibrate_forward_store(ctx, _ptr(theta), _ptr(Ey), _stream(stream)), ctx)
+
+
+def calibrate_vjp_stored(ctx, theta, lam, grad, stream=None):
+    return _check(lib().calibrate_vjp_stored(ctx, _ptr(theta), _ptr(lam), _ptr(grad), _stream(stream)), ctx)
 
 
 def calibrate_gradient(ctx, theta, C_, Ey, G, grad, stream=None):

@@ -60,6 +60,8 @@ struct cal_ctx {
     double *d_part_j = nullptr;
     void *d_lamD = nullptr;
     void *d_ckpt = nullptr;
+    double *d_theta_ckpt = nullptr;   // the parameters d_ckpt was last written with
+    bool ckpt_valid = false;          // d_ckpt holds every segment of a completed sweep
     double *d_t_nodes = nullptr;
     int32_t *d_step_row = nullptr;
     // timing
@@ -161,7 +163,7 @@ extern "C" int cal_destroy(cal_ctx *ctx)
     (void)hipDeviceSynchronize();
     void *bufs[] = {ctx->d_date_step, ctx->d_date_begin, ctx->d_strike, ctx->d_strike_f, ctx->d_disc, ctx->d_id,
                     ctx->d_status, ctx->d_part_y, ctx->d_part_g, ctx->d_part_j, ctx->d_lamD, ctx->d_ckpt,
-                    ctx->d_t_nodes, ctx->d_step_row};
+                    ctx->d_theta_ckpt, ctx->d_t_nodes, ctx->d_step_row};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
     for (auto &t : ctx->timed) {
@@ -261,6 +263,7 @@ extern "C" int cal_create(const cal_problem *pb, cal_ctx **out)
     A((void **)&c->d_part_g, sizeof(double) * (size_t)c->nblocks * c->M);
     A((void **)&c->d_part_j, sizeof(double) * (size_t)c->nblocks_tan * tan_w * c->max_batch);
     A(&c->d_lamD, c->real * m);
+    A((void **)&c->d_theta_ckpt, sizeof(double) * c->M);
     if (c->model == CAL_LV) A((void **)&c->d_t_nodes, sizeof(double) * pb->n_t_nodes);
     if (c->model == CAL_SLV) A((void **)&c->d_step_row, sizeof(int32_t) * c->N);
     if (e != hipSuccess) {
@@ -300,6 +303,7 @@ extern "C" int cal_create(const cal_problem *pb, cal_ctx **out)
     }
 
     DevProblem &d = c->dp;
+    d.theta_save = c->d_theta_ckpt;
     d.N = c->N;
     d.m = m;
     d.M = c->M;
@@ -468,21 +472,71 @@ extern "C" int calibrate_forward(cal_ctx *ctx, const double *d_theta, double *d_
     return CAL_OK;
 }
 
+// A sweep that writes every segment of the checkpoint buffer (pass 1 storing,
+// or pass 2 re-running the forward sweep) has been launched; its workgroup 0
+// copies theta to d_theta_ckpt (DevProblem::theta_save).
+static int ckpt_written(cal_ctx *c)
+{
+    c->ckpt_valid = true;
+    return CAL_OK;
+}
+
+extern "C" int calibrate_forward_store(cal_ctx *ctx, const double *d_theta, double *d_Ey, void *stream)
+{
+    int rc = check_ctx(ctx);
+    if (rc) return rc;
+    if (!d_theta || !d_Ey) return fail(ctx, CAL_EINVAL, "null device pointer");
+    hipStream_t st = (hipStream_t)stream;
+    ctx->ckpt_valid = false;
+    rc = run_pass1(ctx, d_theta, true, st);
+    if (rc) return rc;
+    rc = ckpt_written(ctx);
+    if (rc) return rc;
+    hipError_t e = launch_reduce_sorted(ctx->d_part_y, ctx->nblocks, ctx->m, ctx->d_id, 1.0 / (double)ctx->P,
+                                        d_Ey, ctx->d_status, st);
+    if (e != hipSuccess) return hip_fail(ctx, e, "reduce launch");
+    return CAL_OK;
+}
+
+// Pass 2 with a caller-given output adjoint; from_ckpt: from the buffer's
+// checkpoints (which must be there), else re-running the forward sweep.
+static int vjp(cal_ctx *ctx, const double *d_theta, const double *d_lambda, double *d_grad, bool from_ckpt,
+               hipStream_t st)
+{
+    if (!d_theta || !d_lambda || !d_grad) return fail(ctx, CAL_EINVAL, "null device pointer");
+    if (from_ckpt && !ctx->ckpt_valid)
+        return fail(ctx, CAL_EINVAL, "no stored checkpoints on this context (no completed storing sweep yet)");
+    hipError_t e = launch_check_theta(ctx->dp, d_theta, ctx->model, st);
+    if (e == hipSuccess)
+        e = launch_lambda(ctx->dp, ctx->fp64, d_lambda, ctx->d_lamD, from_ckpt ? ctx->d_theta_ckpt : nullptr, d_theta,
+                          st);
+    if (e != hipSuccess) return hip_fail(ctx, e, "lambda launch");
+    if (!from_ckpt) ctx->ckpt_valid = false;
+    int rc = run_pass2(ctx, d_theta, from_ckpt, st);
+    if (rc) return rc;
+    if (!from_ckpt) {
+        rc = ckpt_written(ctx);
+        if (rc) return rc;
+    }
+    e = launch_reduce_sorted(ctx->d_part_g, ctx->nblocks, ctx->M, nullptr, 1.0, d_grad, ctx->d_status, st);
+    if (e != hipSuccess) return hip_fail(ctx, e, "reduce launch");
+    return CAL_OK;
+}
+
 extern "C" int calibrate_vjp(cal_ctx *ctx, const double *d_theta, const double *d_lambda, double *d_grad,
                              void *stream)
 {
     int rc = check_ctx(ctx);
     if (rc) return rc;
-    if (!d_theta || !d_lambda || !d_grad) return fail(ctx, CAL_EINVAL, "null device pointer");
-    hipStream_t st = (hipStream_t)stream;
-    hipError_t e = launch_check_theta(ctx->dp, d_theta, ctx->model, st);
-    if (e == hipSuccess) e = launch_lambda(ctx->dp, ctx->fp64, d_lambda, ctx->d_lamD, d_theta, st);
-    if (e != hipSuccess) return hip_fail(ctx, e, "lambda launch");
-    rc = run_pass2(ctx, d_theta, false, st);
+    return vjp(ctx, d_theta, d_lambda, d_grad, false, (hipStream_t)stream);
+}
+
+extern "C" int calibrate_vjp_stored(cal_ctx *ctx, const double *d_theta, const double *d_lambda, double *d_grad,
+                                    void *stream)
+{
+    int rc = check_ctx(ctx);
     if (rc) return rc;
-    e = launch_reduce_sorted(ctx->d_part_g, ctx->nblocks, ctx->M, nullptr, 1.0, d_grad, ctx->d_status, st);
-    if (e != hipSuccess) return hip_fail(ctx, e, "reduce launch");
-    return CAL_OK;
+    return vjp(ctx, d_theta, d_lambda, d_grad, true, (hipStream_t)stream);
 }
 
 extern "C" int calibrate_gradient(cal_ctx *ctx, const double *d_theta, const double *d_C, double *d_Ey,
@@ -493,6 +547,7 @@ extern "C" int calibrate_gradient(cal_ctx *ctx, const double *d_theta, const dou
     if (!d_theta || !d_C || !d_Ey || !d_G || !d_grad) return fail(ctx, CAL_EINVAL, "null device pointer");
     hipStream_t st = (hipStream_t)stream;
     const bool store = ctx->mode == CAL_CKPT_STORE;
+    ctx->ckpt_valid = false;
     rc = run_pass1(ctx, d_theta, store, st);
     if (rc) return rc;
     hipError_t e = launch_reduce_sorted(ctx->d_part_y, ctx->nblocks, ctx->m, ctx->d_id, 1.0 / (double)ctx->P,
@@ -500,6 +555,8 @@ extern "C" int calibrate_gradient(cal_ctx *ctx, const double *d_theta, const dou
     if (e == hipSuccess) e = launch_residual(ctx->dp, ctx->fp64, d_Ey, d_C, d_G, ctx->d_lamD, d_theta, st);
     if (e != hipSuccess) return hip_fail(ctx, e, "residual launch");
     rc = run_pass2(ctx, d_theta, store, st);
+    if (rc) return rc;
+    rc = ckpt_written(ctx);   // either pass wrote every segment
     if (rc) return rc;
     e = launch_reduce_sorted(ctx->d_part_g, ctx->nblocks, ctx->M, nullptr, 1.0, d_grad, ctx->d_status, st);
     if (e != hipSuccess) return hip_fail(ctx, e, "reduce launch");

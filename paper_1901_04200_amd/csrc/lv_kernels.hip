@@ -3,7 +3,9 @@
 // outside the grid; log-Euler x' = x + (r - sigma^2/2) h + sigma sqrt(h) z.
 //
 // The time weights of step n are the same for every path, so each
-// workgroup first interpolates the grid in time once per step into LDS:
+// workgroup interpolates the grid in time into LDS, for the K steps of the
+// current checkpoint segment at a time (a window of K rows keeps the LDS
+// footprint small):
 // row_n[k] = (1 - al_n) theta[a_n][k] + al_n theta[a_n + 1][k].  A path-step
 // then needs its spot cell b, the weight be and two LDS reads.
 //
@@ -28,7 +30,7 @@ __device__ __forceinline__ R exp_t(R x)
     else return exp(x);
 }
 
-// LDS carve-up shared by both passes: [dbl area][al_n: R N][rows: R N*nK][a_n: int N][slices]
+// LDS carve-up shared by both passes: [dbl area][al_n: R N][rows: R K*nK][a_n: int N][slices]
 template <typename R>
 struct LvLds {
     double *dbl;   // pass 1: [waves][m] payoff sums; pass 2: [nT*nK] node sums
@@ -48,7 +50,7 @@ __device__ LvLds<R> carve(const DevProblem &pb, unsigned char *base, int ndbl)
     L.al = (R *)(base + o);
     o += sizeof(R) * pb.N;
     L.rows = (R *)(base + o);
-    o += sizeof(R) * pb.N * pb.nK;
+    o += sizeof(R) * pb.K * pb.nK;
     o = (o + 15) & ~(size_t)15;
     L.an = (int *)(base + o);
     o += sizeof(int) * pb.N;
@@ -57,9 +59,9 @@ __device__ LvLds<R> carve(const DevProblem &pb, unsigned char *base, int ndbl)
     return L;
 }
 
-// time cell and weight of every step, then the time-interpolated rows
+// time cell and weight of every step
 template <typename R>
-__device__ void build_rows(const DevProblem &pb, const double *theta, LvLds<R> &L)
+__device__ void build_times(const DevProblem &pb, LvLds<R> &L)
 {
     const int tid = threadIdx.x;
     for (int n = tid; n < pb.N; n += kBlock) {
@@ -72,12 +74,23 @@ __device__ void build_rows(const DevProblem &pb, const double *theta, LvLds<R> &
         L.al[n] = (R)al;
     }
     __syncthreads();
-    const int total = pb.N * pb.nK;
+}
+
+// the time-interpolated rows of steps n0 .. n0 + K - 1 (those < N) into the
+// window, row n at L.rows + (n - n0) * nK; every thread calls it (uniform)
+template <typename R>
+__device__ void build_window(const DevProblem &pb, const double *theta, LvLds<R> &L, int n0)
+{
+    const int tid = threadIdx.x;
+    __syncthreads();   // the previous window is no longer read
+    const int total = pb.K * pb.nK;
     for (int i = tid; i < total; i += kBlock) {
-        const int n = i / pb.nK, k = i % pb.nK;
-        const int a = L.an[n];
-        const double al = (double)L.al[n];
-        L.rows[i] = (R)((1.0 - al) * theta[a * pb.nK + k] + al * theta[(a + 1) * pb.nK + k]);
+        const int n = n0 + i / pb.nK, k = i % pb.nK;
+        if (n < pb.N) {
+            const int a = L.an[n];
+            const double al = (double)L.al[n];
+            L.rows[i] = (R)((1.0 - al) * theta[a * pb.nK + k] + al * theta[(a + 1) * pb.nK + k]);
+        }
     }
     __syncthreads();
 }
@@ -119,28 +132,33 @@ __global__ __launch_bounds__(kBlock) void k_lv_pass1(DevProblem pb, const double
     const int64_t p = (int64_t)blockIdx.x * kBlock + tid;
     const bool active = p < pb.P;
     const uint32_t path = (uint32_t)p;
-    build_rows<R>(pb, theta, L);
+    build_times<R>(pb, L);
+    if constexpr (STORE) save_theta(pb, theta, blockIdx.x);
 
     const R s0 = (R)pb.s0, rh = (R)(pb.rate * pb.h), hh = (R)(0.5 * pb.h), sq = (R)pb.sq;
     const R K0 = (R)pb.K0, invdK = (R)(1.0 / pb.dK), Klast = (R)(pb.K0 + (pb.nK - 1) * pb.dK);
     R x = (R)0;
     int d = 0;
     int next = pb.ndates > 0 ? pb.date_step[0] : -1;
-    const int kmask = pb.K - 1;
-    const int kshift = __builtin_ctz(pb.K);
+    const int cps = max(pb.K / 4, 1);   // Philox calls per segment (K is a multiple of 4)
     const int ncalls = (pb.N + 3) / 4;
+    int n0 = 0;                         // first step of the current segment and window
     for (int call = 0; call < ncalls; ++call) {
+        if (call % cps == 0) {
+            n0 = call * 4;
+            build_window<R>(pb, theta, L, n0);
+            if constexpr (STORE) {
+                if (active) ckpt[(int64_t)(call / cps) * pb.P + p] = x;
+            }
+        }
         R z[4];
         normals4<R>((uint32_t)call, path, pb.inst, pb.k0, pb.k1, box_muller_scale<R>(1.0), z);
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             const int n = call * 4 + j;
             if (n < pb.N) {
-                if constexpr (STORE) {
-                    if ((n & kmask) == 0 && active) ckpt[(int64_t)(n >> kshift) * pb.P + p] = x;
-                }
                 const R S = s0 * exp_t(x);
-                const Cell<R> c = locate<R>(pb, L.rows + n * pb.nK, S, K0, invdK, Klast);
+                const Cell<R> c = locate<R>(pb, L.rows + (n - n0) * pb.nK, S, K0, invdK, Klast);
                 x = x + (rh - hh * c.sig * c.sig) + (sq * c.sig) * z[j];
                 if (n + 1 == next) {
                     const double Sd = (double)(s0 * exp_t(x));
@@ -161,26 +179,13 @@ __global__ __launch_bounds__(kBlock) void k_lv_pass1(DevProblem pb, const double
     }
 }
 
-// Sum the lane slices of time cell `a` over the workgroup (fixed tree) into
-// the FP64 node sums, then clear them.  Called by every thread (uniform).
+// Sum the lane slices of time cell `a` (rows: cell a's nodes, then cell
+// a + 1's) over the workgroup into the FP64 node sums, then clear them.
+// Called by every thread (uniform).
 template <typename R>
 __device__ void flush_cell(const DevProblem &pb, LvLds<R> &L, int a)
 {
-    const int tid = threadIdx.x;
-    const int rows2 = 2 * pb.nK;
-    __syncthreads();
-    for (int stride = kBlock / 2; stride > 0; stride >>= 1) {
-        if (tid < stride)
-            for (int q = 0; q < rows2; ++q) L.slices[q * kBlock + tid] += L.slices[q * kBlock + tid + stride];
-        __syncthreads();
-    }
-    if (tid < rows2) {
-        const int half = tid / pb.nK, k = tid % pb.nK;   // half 0: cell a, half 1: cell a + 1
-        L.dbl[(a + half) * pb.nK + k] += (double)L.slices[tid * kBlock];
-    }
-    __syncthreads();
-    for (int i = tid; i < rows2 * kBlock; i += kBlock) L.slices[i] = 0.f;
-    __syncthreads();
+    flush_slices(L.slices, 2 * pb.nK, L.dbl + a * pb.nK);
 }
 
 template <typename R, bool FROM_CKPT, int K>
@@ -196,7 +201,8 @@ __global__ __launch_bounds__(kBlock) void k_lv_pass2(DevProblem pb, const double
     const bool active = p < pb.P;
     const int64_t pc = active ? p : 0;
     const uint32_t path = (uint32_t)p;
-    build_rows<R>(pb, theta, L);
+    build_times<R>(pb, L);
+    if constexpr (!FROM_CKPT) save_theta(pb, theta, blockIdx.x);
     for (int i = tid; i < pb.nT * pb.nK; i += kBlock) L.dbl[i] = 0.0;
     for (int i = tid; i < 2 * pb.nK * kBlock; i += kBlock) L.slices[i] = 0.f;
     __syncthreads();
@@ -208,18 +214,24 @@ __global__ __launch_bounds__(kBlock) void k_lv_pass2(DevProblem pb, const double
     else strike_r = pb.strike;
 
     if constexpr (!FROM_CKPT) {
+        // the forward re-run of the paper's step 2, storing every segment's start
         R x = (R)0;
         const int ncalls = (pb.N + 3) / 4;
+        int n0 = 0;
         for (int call = 0; call < ncalls; ++call) {
+            if ((call * 4) % K == 0) {
+                n0 = call * 4;
+                build_window<R>(pb, theta, L, n0);
+                if (active) ckpt[(int64_t)(n0 / K) * pb.P + p] = x;
+            }
             R z[4];
             normals4<R>((uint32_t)call, path, pb.inst, pb.k0, pb.k1, box_muller_scale<R>(1.0), z);
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
                 const int n = call * 4 + j;
                 if (n < pb.N) {
-                    if ((n % K) == 0 && active) ckpt[(int64_t)(n / K) * pb.P + p] = x;
                     const R S = s0 * exp_t(x);
-                    const Cell<R> c = locate<R>(pb, L.rows + n * pb.nK, S, K0, invdK, Klast);
+                    const Cell<R> c = locate<R>(pb, L.rows + (n - n0) * pb.nK, S, K0, invdK, Klast);
                     x = x + (rh - hh * c.sig * c.sig) + (sq * c.sig) * z[j];
                 }
             }
@@ -232,6 +244,7 @@ __global__ __launch_bounds__(kBlock) void k_lv_pass2(DevProblem pb, const double
     float *my0 = L.slices + tid;   // this lane's column of the slices
     for (int seg = pb.nseg - 1; seg >= 0; --seg) {
         const int n0 = seg * K;
+        build_window<R>(pb, theta, L, n0);
         R x = active ? ckpt[(int64_t)seg * pb.P + pc] : (R)0;   // inactive lanes run a harmless path
         int dlo = dhi;
         while (dlo > 0 && pb.date_step[dlo - 1] > n0) --dlo;
@@ -248,7 +261,7 @@ __global__ __launch_bounds__(kBlock) void k_lv_pass2(DevProblem pb, const double
             if (n < pb.N) {
                 if (j % 4 == 0) normals4<R>((uint32_t)(n / 4), path, pb.inst, pb.k0, pb.k1, box_muller_scale<R>(1.0), z);
                 const R S = s0 * exp_t(x);
-                const Cell<R> c = locate<R>(pb, L.rows + n * pb.nK, S, K0, invdK, Klast);
+                const Cell<R> c = locate<R>(pb, L.rows + j * pb.nK, S, K0, invdK, Klast);
                 s_S[j] = S;
                 s_z[j] = z[j % 4];
                 x = x + (rh - hh * c.sig * c.sig) + (sq * c.sig) * z[j % 4];
@@ -275,7 +288,7 @@ __global__ __launch_bounds__(kBlock) void k_lv_pass2(DevProblem pb, const double
                     cur_a = a;
                 }
                 const R S = s_S[j];
-                const Cell<R> c = locate<R>(pb, L.rows + n * pb.nK, S, K0, invdK, Klast);
+                const Cell<R> c = locate<R>(pb, L.rows + j * pb.nK, S, K0, invdK, Klast);
                 const R sbar = xb * (-c.sig * h + sq * s_z[j]);
                 const R dsdS = c.inside ? (c.r1 - c.r0) * invdK : (R)0;
                 xb = xb + sbar * dsdS * S;
@@ -340,7 +353,7 @@ size_t lv_lds_bytes(const DevProblem &pb, bool fp64, int pass)
     const size_t real = fp64 ? 8 : 4;
     size_t o = sizeof(double) * (pass == 1 ? (size_t)kWavesPerBlock * pb.m : (size_t)pb.nT * pb.nK);
     o += real * (size_t)pb.N;
-    o += real * (size_t)pb.N * pb.nK;
+    o += real * (size_t)pb.K * pb.nK;
     o = (o + 15) & ~(size_t)15;
     o += sizeof(int) * (size_t)pb.N;
     o = (o + 15) & ~(size_t)15;

@@ -223,6 +223,32 @@ __device__ __forceinline__ double wave_sum8(const double a[8])
     return lanes::row_tail(keep + lanes::dpp<lanes::kRowMirror>(send));
 }
 
+// Node-adjoint slices: `rows` rows of kBlock FP32 values in LDS, one column
+// per lane (slices[q * kBlock + tid]).  Adds the sum over the workgroup's
+// lanes of row q to dst[q] (FP64) and clears the slices.  Wave w takes rows
+// w, w + 4, ...: each lane loads four neighbouring columns of the row (one
+// 16-byte read, the wave covering the whole row), adds them in FP32, and the
+// wave sums the 64 lane values in FP64 along wave_sum's fixed tree, so the
+// sums are deterministic.  A rolled loop keeps the register footprint small
+// where this is inlined into a register-heavy sweep.  Called by all threads of
+// the workgroup (uniform control flow); slices must be 16-byte aligned.
+__device__ __forceinline__ void flush_slices(float *slices, int rows, double *dst)
+{
+    const int tid = threadIdx.x;
+    const int lane = tid & (kWave - 1);
+    const int wave = tid / kWave;
+    __syncthreads();
+#pragma unroll 1
+    for (int q = wave; q < rows; q += kWavesPerBlock) {
+        float4 *cell = reinterpret_cast<float4 *>(slices + q * kBlock) + lane;
+        const float4 v = *cell;
+        *cell = make_float4(0.f, 0.f, 0.f, 0.f);
+        const double t = wave_sum((double)((v.x + v.y) + (v.z + v.w)));
+        if (lane == 0) dst[q] += t;
+    }
+    __syncthreads();
+}
+
 // Wave totals of the discounted call payoffs disc[k] max(S - strike[k], 0),
 // k in [kb, ke) (the instruments maturing at one date), eight instruments per
 // wave_sum8; lanes with active == false add 0.  Total k goes to out[k], or is

@@ -41,6 +41,7 @@ __device__ __forceinline__ void pass1_block(const DevProblem &pb, const double *
     const int lane = tid & (kWave - 1);
     const int wave = tid / kWave;
     if (blk == 0 && tid == 0) check_theta<MODEL>(pb, theta);
+    if constexpr (STORE) save_theta(pb, theta, blk);
 
     Consts<R> c;
     load_consts<MODEL, R>(pb, theta, c);
@@ -138,6 +139,8 @@ __device__ __forceinline__ void pass2_block(const DevProblem &pb, const double *
     if constexpr (sizeof(R) == 4) strike_r = pb.strike_f;
     else strike_r = pb.strike;
     R *inj_lds = reinterpret_cast<R *>(lds + kWavesPerBlock * NP);
+
+    if constexpr (!FROM_CKPT) save_theta(pb, theta, blk);
 
     double g[NP];
 #pragma unroll
@@ -489,10 +492,18 @@ __global__ __launch_bounds__(kBlock) void k_residual(DevProblem pb, const double
 
 template <typename R>
 __global__ __launch_bounds__(kBlock) void k_lambda(DevProblem pb, const double *__restrict__ lambda,
-                                                   R *__restrict__ lamD)
+                                                   R *__restrict__ lamD, const double *__restrict__ saved,
+                                                   const double *__restrict__ theta)
 {
     const double invP = 1.0 / (double)pb.P;
     for (int k = threadIdx.x; k < pb.m; k += kBlock) lamD[k] = (R)(lambda[pb.id[k]] * pb.disc[k] * invP);
+    if (saved) {
+        // pass 2 is about to read checkpoints written with `saved`: same bits?
+        bool same = true;
+        for (int i = threadIdx.x; i < pb.M; i += kBlock)
+            same = same && __double_as_longlong(theta[i]) == __double_as_longlong(saved[i]);
+        if (!same) atomicOr(pb.status, 4);
+    }
 }
 
 __global__ void k_check_theta(DevProblem pb, const double *theta, int model)
@@ -646,12 +657,12 @@ hipError_t launch_residual(const DevProblem &pb, bool fp64, const double *Ey, co
     return hipGetLastError();
 }
 
-hipError_t launch_lambda(const DevProblem &pb, bool fp64, const double *lambda, void *lamD, const double *theta,
-                         hipStream_t st)
+hipError_t launch_lambda(const DevProblem &pb, bool fp64, const double *lambda, void *lamD, const double *saved,
+                         const double *theta, hipStream_t st)
 {
-    if (fp64) hipLaunchKernelGGL(k_lambda<double>, dim3(1), dim3(kBlock), 0, st, pb, lambda, (double *)lamD);
-    else hipLaunchKernelGGL(k_lambda<float>, dim3(1), dim3(kBlock), 0, st, pb, lambda, (float *)lamD);
-    (void)theta;
+    if (fp64)
+        hipLaunchKernelGGL(k_lambda<double>, dim3(1), dim3(kBlock), 0, st, pb, lambda, (double *)lamD, saved, theta);
+    else hipLaunchKernelGGL(k_lambda<float>, dim3(1), dim3(kBlock), 0, st, pb, lambda, (float *)lamD, saved, theta);
     return hipGetLastError();
 }
 

@@ -37,7 +37,18 @@ struct DevProblem {
     double K0, dK;
     const double *t_nodes;
     const int32_t *step_row;    // [N] (SLV)
+    // where a sweep that writes every checkpoint segment (pass 1 storing, pass
+    // 2 re-running the forward sweep) leaves a copy of theta (workgroup 0
+    // writes it; M doubles); null: no copy
+    double *theta_save;
 };
+
+// Workgroup 0 of a checkpoint-writing sweep keeps theta beside the buffer.
+__device__ __forceinline__ void save_theta(const DevProblem &pb, const double *theta, int64_t blk)
+{
+    if (blk == 0 && pb.theta_save)
+        for (int i = threadIdx.x; i < pb.M; i += blockDim.x) pb.theta_save[i] = theta[i];
+}
 
 // One instance of a batch: its problem plus its slices of the batch workspace.
 struct BatchInst {
@@ -106,7 +117,9 @@ hipError_t launch_reduce_sorted(const double *partial, int64_t nblocks, int32_t 
 hipError_t launch_residual(const DevProblem &pb, bool fp64, const double *Ey, const double *C, double *G,
                            void *lamD, const double *theta, hipStream_t stream);
 // lamD[k] = lambda[id[k]] * disc[k] / P
-hipError_t launch_lambda(const DevProblem &pb, bool fp64, const double *lambda, void *lamD,
+// saved (may be null): the theta the checkpoints were written with; status
+// bit 4 is set when theta differs from it in any bit.
+hipError_t launch_lambda(const DevProblem &pb, bool fp64, const double *lambda, void *lamD, const double *saved,
                          const double *theta, hipStream_t stream);
 hipError_t launch_philox(const uint32_t *ctr, uint32_t k0, uint32_t k1, int64_t n, uint32_t *out,
                          hipStream_t stream);

@@ -124,6 +124,7 @@ __global__ __launch_bounds__(kBlock) void k_slv_pass1(DevProblem pb, const doubl
     const int lane = tid & (kWave - 1);
     const int wave = tid / kWave;
     load_grid<R>(pb, theta, L.lev);
+    if constexpr (STORE) save_theta(pb, theta, blockIdx.x);
     __syncthreads();
 
     Consts<R> c;
@@ -177,22 +178,12 @@ __global__ __launch_bounds__(kBlock) void k_slv_pass1(DevProblem pb, const doubl
     }
 }
 
-// Sum the lane slices of time row `a` over the workgroup (fixed tree) into
-// the FP64 node sums, then clear them.  Called by every thread (uniform).
+// Sum the lane slices of time row `a` over the workgroup into the FP64 node
+// sums, then clear them.  Called by every thread (uniform).
 template <typename R>
 __device__ void flush_row(const DevProblem &pb, SlvLds<R> &L, int a)
 {
-    const int tid = threadIdx.x;
-    __syncthreads();
-    for (int stride = kBlock / 2; stride > 0; stride >>= 1) {
-        if (tid < stride)
-            for (int q = 0; q < pb.nK; ++q) L.slices[q * kBlock + tid] += L.slices[q * kBlock + tid + stride];
-        __syncthreads();
-    }
-    if (tid < pb.nK) L.sums[a * pb.nK + tid] += (double)L.slices[tid * kBlock];
-    __syncthreads();
-    for (int i = tid; i < pb.nK * kBlock; i += kBlock) L.slices[i] = 0.f;
-    __syncthreads();
+    flush_slices(L.slices, pb.nK, L.sums + a * pb.nK);
 }
 
 template <typename R, bool FROM_CKPT, int K>
@@ -207,6 +198,7 @@ __global__ __launch_bounds__(kBlock) void k_slv_pass2(DevProblem pb, const doubl
     const int lane = tid & (kWave - 1);
     const int wave = tid / kWave;
     load_grid<R>(pb, theta, L.lev);
+    if constexpr (!FROM_CKPT) save_theta(pb, theta, blockIdx.x);
     for (int i = tid; i < pb.nT * pb.nK; i += kBlock) L.sums[i] = 0.0;
     for (int i = tid; i < pb.nK * kBlock; i += kBlock) L.slices[i] = 0.f;
     __syncthreads();

@@ -26,6 +26,9 @@ class MonteCarloCalibration:
                                    paths_per_lane)
         self.m = int(len(problem.instr_step))
         self.M = int(problem.n_params)
+        # counts the calls whose sweep wrote the context's checkpoint buffer
+        # (forward_store, vjp, gradient); vjp_stored reads what the last wrote
+        self.ckpt_writes = 0
 
     def _dev(self, a, n):
         t = torch.as_tensor(a, dtype=torch.float64, device=self.device).contiguous()
@@ -39,11 +42,29 @@ class MonteCarloCalibration:
         capi.calibrate_forward(self.ctx, th, Ey)
         return Ey
 
+    def forward_store(self, theta):
+        """forward() that also keeps the checkpoints for vjp_stored."""
+        th = self._dev(theta, self.M)
+        Ey = torch.empty(self.m, dtype=torch.float64, device=self.device)
+        capi.calibrate_forward_store(self.ctx, th, Ey)
+        self.ckpt_writes += 1
+        return Ey
+
     def vjp(self, theta, lam):
         th = self._dev(theta, self.M)
         la = self._dev(lam, self.m)
         g = torch.empty(self.M, dtype=torch.float64, device=self.device)
         capi.calibrate_vjp(self.ctx, th, la, g)
+        self.ckpt_writes += 1
+        return g
+
+    def vjp_stored(self, theta, lam):
+        """vjp() from the checkpoints the last checkpoint-writing call left
+        (same theta required; the device flags CAL_FLAG_CKPT otherwise)."""
+        th = self._dev(theta, self.M)
+        la = self._dev(lam, self.m)
+        g = torch.empty(self.M, dtype=torch.float64, device=self.device)
+        capi.calibrate_vjp_stored(self.ctx, th, la, g)
         return g
 
     def gradient(self, theta, targets):
@@ -53,6 +74,7 @@ class MonteCarloCalibration:
         G = torch.empty(1, dtype=torch.float64, device=self.device)
         g = torch.empty(self.M, dtype=torch.float64, device=self.device)
         capi.calibrate_gradient(self.ctx, th, C, Ey, G, g)
+        self.ckpt_writes += 1
         return Ey, G, g
 
     def jacobian(self, theta):

@@ -112,6 +112,26 @@ def test_autograd_backward_is_the_adjoint(lv_small):
     mc.close()
 
 
+def test_autograd_two_forwards_then_backward(lv_small):
+    """Two forwards on one context before either backward: the second
+    overwrote the first's checkpoints, so the first's backward re-runs the
+    forward sweep; both gradients still equal calibrate_gradient's."""
+    pb, g0, gt, C, _ = lv_small
+    mc = AG.make(pb, "fp32")
+    Ct = torch.as_tensor(C, device="cuda")
+    th1 = torch.tensor(g0, dtype=torch.float64, device="cuda", requires_grad=True)
+    th2 = torch.tensor(gt, dtype=torch.float64, device="cuda", requires_grad=True)
+    G1 = 0.5 * torch.sum((AG.mc_prices(th1, mc) - Ct) ** 2)
+    G2 = 0.5 * torch.sum((AG.mc_prices(th2, mc) - Ct) ** 2)
+    (G1 + G2).backward()
+    assert mc.status() == 0
+    for th, vals in ((th1, g0), (th2, gt)):
+        _, _, gref = mc.gradient(vals, Ct)
+        np.testing.assert_allclose(th.grad.cpu().numpy(), gref.cpu().numpy(), rtol=0,
+                                   atol=1e-12 * gref.abs().max().item())
+    mc.close()
+
+
 def test_memory_budget_picks_spacing():
     pb = W.lv_problem()[0]     # 2^22 paths x 256 steps, one state variable
     assert AG.checkpoint_bytes(pb, "fp32", 16) == 16 * (1 << 22) * 4

@@ -233,6 +233,64 @@ def test_heston_fp64_jacobian(orc, heston_small):
 
 
 # ---------------------------------------------------------------------------
+# forward with stored checkpoints, then pass 2 from them (the autograd pair)
+# ---------------------------------------------------------------------------
+def _model_problem(model):
+    if model == "heston":
+        pb, th0, tht, eps = W.heston_problem(n_paths=3 * 256 + 11, n_steps=72)
+        return pb, W.heston_draws(2, 10)[9]
+    if model == "lv":
+        pb, g0, gt, eps, _ = W.lv_problem(n_paths=3 * 256 + 11, n_steps=72, n_t=4, n_k=6)
+        return pb, g0
+    pb, th0, tht, eps, _ = W.slv_problem(n_paths=3 * 256 + 11, n_steps=72, n_t=3, n_k=5)
+    return pb, th0
+
+
+@pytest.mark.parametrize("model", ["heston", "lv", "slv"])
+@pytest.mark.parametrize("k", [8, 16])
+def test_forward_store_and_vjp_stored(orc, model, k):
+    """calibrate_forward_store returns calibrate_forward's E y and
+    calibrate_vjp_stored calibrate_vjp's gradient, bit for bit (pass 2 reads
+    the very states pass 1 stored); after calibrate_gradient, with
+    lambda = E y - C, it returns that call's gradient bit for bit; and it
+    matches the oracle's vector-Jacobian product within the FP32 bound."""
+    pb, th = _model_problem(model)
+    lam = np.linspace(-1.0, 1.0, pb.n_instr)
+    C = np.linspace(3.0, 8.0, pb.n_instr)
+    say(f"{model} fp32 K={k}: forward_store / vjp_stored, P={pb.n_paths} N={pb.n_steps}")
+    mc = MonteCarloCalibration(pb, precision="fp32", ckpt_every=k)
+    Ey_f = mc.forward(th)
+    Ey_s = mc.forward_store(th)
+    assert torch.equal(Ey_f, Ey_s)
+    g_s = mc.vjp_stored(th, lam)
+    g_r = mc.vjp(th, lam)
+    assert torch.equal(g_s, g_r)
+    Ey, G, g = mc.gradient(th, C)
+    g_s2 = mc.vjp_stored(th, Ey - torch.as_tensor(C, device=Ey.device))
+    assert torch.equal(g, g_s2)
+    assert mc.status() == 0
+    mc.close()
+    assert g_err(g_s.cpu().numpy(), orc.vjp(pb, th, lam)) <= 1e-4
+
+
+def test_vjp_stored_needs_checkpoints_of_this_theta(heston_small):
+    pb, th0, tht, C = heston_small
+    mc = MonteCarloCalibration(pb.with_(n_paths=3 * 256 + 1), precision="fp32")
+    lam = np.ones(pb.n_instr)
+    with pytest.raises(capi.CalError) as err:
+        mc.vjp_stored(tht, lam)          # nothing stored on this context yet
+    assert err.value.code == capi.CAL_EINVAL
+    mc.forward_store(tht)
+    mc.vjp_stored(tht, lam)
+    assert mc.status() == 0
+    other = tht.copy()
+    other[0] = np.nextafter(other[0], 10.0)   # one bit away
+    mc.vjp_stored(other, lam)
+    assert mc.status() & capi.CAL_FLAG_CKPT
+    mc.close()
+
+
+# ---------------------------------------------------------------------------
 # invariants and edge cases
 # ---------------------------------------------------------------------------
 def test_checkpoint_modes_and_spacing(orc, heston_small):
