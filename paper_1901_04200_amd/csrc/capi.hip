@@ -64,6 +64,8 @@ struct cal_ctx {
     bool ckpt_valid = false;          // d_ckpt holds every segment of a completed sweep
     double *d_t_nodes = nullptr;
     int32_t *d_step_row = nullptr;
+    double *d_step_al = nullptr;      // local volatility: time weight of every step
+    float *d_step_al_f = nullptr;
     // timing
     bool timing = false;
     std::vector<TimedPair> timed;
@@ -163,7 +165,7 @@ extern "C" int cal_destroy(cal_ctx *ctx)
     (void)hipDeviceSynchronize();
     void *bufs[] = {ctx->d_date_step, ctx->d_date_begin, ctx->d_strike, ctx->d_strike_f, ctx->d_disc, ctx->d_id,
                     ctx->d_status, ctx->d_part_y, ctx->d_part_g, ctx->d_part_j, ctx->d_lamD, ctx->d_ckpt,
-                    ctx->d_theta_ckpt, ctx->d_t_nodes, ctx->d_step_row};
+                    ctx->d_theta_ckpt, ctx->d_t_nodes, ctx->d_step_row, ctx->d_step_al, ctx->d_step_al_f};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
     for (auto &t : ctx->timed) {
@@ -264,8 +266,12 @@ extern "C" int cal_create(const cal_problem *pb, cal_ctx **out)
     A((void **)&c->d_part_j, sizeof(double) * (size_t)c->nblocks_tan * tan_w * c->max_batch);
     A(&c->d_lamD, c->real * m);
     A((void **)&c->d_theta_ckpt, sizeof(double) * c->M);
-    if (c->model == CAL_LV) A((void **)&c->d_t_nodes, sizeof(double) * pb->n_t_nodes);
-    if (c->model == CAL_SLV) A((void **)&c->d_step_row, sizeof(int32_t) * c->N);
+    if (c->model == CAL_LV) {
+        A((void **)&c->d_t_nodes, sizeof(double) * pb->n_t_nodes);
+        A((void **)&c->d_step_al, sizeof(double) * c->N);
+        A((void **)&c->d_step_al_f, sizeof(float) * c->N);
+    }
+    if (c->model == CAL_LV || c->model == CAL_SLV) A((void **)&c->d_step_row, sizeof(int32_t) * c->N);
     if (e != hipSuccess) {
         cal_destroy(c);
         return fail(nullptr, CAL_ENOMEM, std::string("workspace allocation failed: ") + hipGetErrorString(e));
@@ -284,7 +290,28 @@ extern "C" int cal_create(const cal_problem *pb, cal_ctx **out)
     H2D(c->d_strike_f, strike_f.data(), sizeof(float) * m);
     H2D(c->d_disc, disc.data(), sizeof(double) * m);
     H2D(c->d_id, order.data(), sizeof(int32_t) * m);
-    if (c->model == CAL_LV) H2D(c->d_t_nodes, pb->t_nodes, sizeof(double) * pb->n_t_nodes);
+    if (c->model == CAL_LV) {
+        H2D(c->d_t_nodes, pb->t_nodes, sizeof(double) * pb->n_t_nodes);
+        // time cell a of step n (the last node row a + 1 <= nT - 1 with
+        // t_nodes[a] <= n h, or 0) and its weight on row a + 1, clamped to [0, 1]
+        std::vector<int32_t> cell(c->N);
+        std::vector<double> al(c->N);
+        std::vector<float> al_f(c->N);
+        const int nT = pb->n_t_nodes;
+        for (int n = 0; n < c->N; ++n) {
+            const double t = n * h;
+            int a = 0;
+            while (a + 1 < nT - 1 && pb->t_nodes[a + 1] <= t) ++a;
+            double w = (t - pb->t_nodes[a]) / (pb->t_nodes[a + 1] - pb->t_nodes[a]);
+            w = w < 0.0 ? 0.0 : (w > 1.0 ? 1.0 : w);
+            cell[n] = a;
+            al[n] = w;
+            al_f[n] = (float)w;
+        }
+        H2D(c->d_step_row, cell.data(), sizeof(int32_t) * c->N);
+        H2D(c->d_step_al, al.data(), sizeof(double) * c->N);
+        H2D(c->d_step_al_f, al_f.data(), sizeof(float) * c->N);
+    }
     if (c->model == CAL_SLV) {
         // leverage row of step n: the number of time nodes <= n h, capped at the last row
         std::vector<int32_t> row(c->N);
@@ -333,6 +360,8 @@ extern "C" int cal_create(const cal_problem *pb, cal_ctx **out)
         d.dK = (pb->k_nodes[d.nK - 1] - pb->k_nodes[0]) / (d.nK - 1);
         d.t_nodes = c->d_t_nodes;
         d.step_row = c->d_step_row;
+        d.step_al = c->d_step_al;
+        d.step_al_f = c->d_step_al_f;
     }
     *out = c;
     return CAL_OK;

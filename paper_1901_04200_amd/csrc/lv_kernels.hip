@@ -30,13 +30,11 @@ __device__ __forceinline__ R exp_t(R x)
     else return exp(x);
 }
 
-// LDS carve-up shared by both passes: [dbl area][al_n: R N][rows: R K*nK][a_n: int N][slices]
+// LDS carve-up shared by both passes: [dbl area][rows: R K*nK][slices]
 template <typename R>
 struct LvLds {
     double *dbl;   // pass 1: [waves][m] payoff sums; pass 2: [nT*nK] node sums
-    R *al;
     R *rows;
-    int *an;
     float *slices;   // pass 2: [2*nK][kBlock]
 };
 
@@ -47,33 +45,19 @@ __device__ LvLds<R> carve(const DevProblem &pb, unsigned char *base, int ndbl)
     size_t o = 0;
     L.dbl = (double *)(base + o);
     o += sizeof(double) * ndbl;
-    L.al = (R *)(base + o);
-    o += sizeof(R) * pb.N;
     L.rows = (R *)(base + o);
     o += sizeof(R) * pb.K * pb.nK;
-    o = (o + 15) & ~(size_t)15;
-    L.an = (int *)(base + o);
-    o += sizeof(int) * pb.N;
     o = (o + 15) & ~(size_t)15;
     L.slices = (float *)(base + o);
     return L;
 }
 
-// time cell and weight of every step
+// time weight al_n of step n in the path precision (host table, uniform)
 template <typename R>
-__device__ void build_times(const DevProblem &pb, LvLds<R> &L)
+__device__ __forceinline__ R step_al(const DevProblem &pb, int n)
 {
-    const int tid = threadIdx.x;
-    for (int n = tid; n < pb.N; n += kBlock) {
-        const double t = n * pb.h;
-        int a = 0;
-        while (a + 1 < pb.nT - 1 && pb.t_nodes[a + 1] <= t) ++a;
-        double al = (t - pb.t_nodes[a]) / (pb.t_nodes[a + 1] - pb.t_nodes[a]);
-        al = al < 0.0 ? 0.0 : (al > 1.0 ? 1.0 : al);
-        L.an[n] = a;
-        L.al[n] = (R)al;
-    }
-    __syncthreads();
+    if constexpr (sizeof(R) == 4) return ldc(pb.step_al_f, n);
+    else return ldc(pb.step_al, n);
 }
 
 // the time-interpolated rows of steps n0 .. n0 + K - 1 (those < N) into the
@@ -87,8 +71,8 @@ __device__ void build_window(const DevProblem &pb, const double *theta, LvLds<R>
     for (int i = tid; i < total; i += kBlock) {
         const int n = n0 + i / pb.nK, k = i % pb.nK;
         if (n < pb.N) {
-            const int a = L.an[n];
-            const double al = (double)L.al[n];
+            const int a = pb.step_row[n];
+            const double al = (double)step_al<R>(pb, n);
             L.rows[i] = (R)((1.0 - al) * theta[a * pb.nK + k] + al * theta[(a + 1) * pb.nK + k]);
         }
     }
@@ -132,7 +116,6 @@ __global__ __launch_bounds__(kBlock) void k_lv_pass1(DevProblem pb, const double
     const int64_t p = (int64_t)blockIdx.x * kBlock + tid;
     const bool active = p < pb.P;
     const uint32_t path = (uint32_t)p;
-    build_times<R>(pb, L);
     if constexpr (STORE) save_theta(pb, theta, blockIdx.x);
 
     const R s0 = (R)pb.s0, rh = (R)(pb.rate * pb.h), hh = (R)(0.5 * pb.h), sq = (R)pb.sq;
@@ -201,7 +184,6 @@ __global__ __launch_bounds__(kBlock) void k_lv_pass2(DevProblem pb, const double
     const bool active = p < pb.P;
     const int64_t pc = active ? p : 0;
     const uint32_t path = (uint32_t)p;
-    build_times<R>(pb, L);
     if constexpr (!FROM_CKPT) save_theta(pb, theta, blockIdx.x);
     for (int i = tid; i < pb.nT * pb.nK; i += kBlock) L.dbl[i] = 0.0;
     for (int i = tid; i < 2 * pb.nK * kBlock; i += kBlock) L.slices[i] = 0.f;
@@ -239,7 +221,7 @@ __global__ __launch_bounds__(kBlock) void k_lv_pass2(DevProblem pb, const double
     }
 
     R xb = (R)0;
-    int cur_a = L.an[pb.N - 1];
+    int cur_a = ldc(pb.step_row, pb.N - 1);
     int dhi = pb.ndates;
     float *my0 = L.slices + tid;   // this lane's column of the slices
     for (int seg = pb.nseg - 1; seg >= 0; --seg) {
@@ -250,20 +232,25 @@ __global__ __launch_bounds__(kBlock) void k_lv_pass2(DevProblem pb, const double
         while (dlo > 0 && pb.date_step[dlo - 1] > n0) --dlo;
         int d = dlo;
         int next = d < dhi ? pb.date_step[d] : -1;
-        R s_S[K], s_z[K], s_inj[K];
+        // recompute the segment, keeping per step what the reverse sweep needs,
+        // so that it reads no LDS but the slices it adds to:
+        //   s_c = d x'/d sigma = -sigma h + sqrt(h) z,  s_d = d sigma/dS * S,
+        //   the spot cell b and its weight be, the payoff adjoint injected
+        R s_c[K], s_d[K], s_be[K], s_inj[K];
+        int s_b[K];
         R z[4];
 #pragma unroll
         for (int j = 0; j < K; ++j) {
             const int n = n0 + j;
             s_inj[j] = (R)0;
-            s_z[j] = (R)0;
-            s_S[j] = (R)0;
             if (n < pb.N) {
                 if (j % 4 == 0) normals4<R>((uint32_t)(n / 4), path, pb.inst, pb.k0, pb.k1, box_muller_scale<R>(1.0), z);
                 const R S = s0 * exp_t(x);
                 const Cell<R> c = locate<R>(pb, L.rows + j * pb.nK, S, K0, invdK, Klast);
-                s_S[j] = S;
-                s_z[j] = z[j % 4];
+                s_c[j] = -c.sig * h + sq * z[j % 4];
+                s_d[j] = (c.inside ? (c.r1 - c.r0) * invdK : (R)0) * S;
+                s_b[j] = c.b;
+                s_be[j] = c.be;
                 x = x + (rh - hh * c.sig * c.sig) + (sq * c.sig) * z[j % 4];
                 if (n + 1 == next) {
                     const R Sn = s0 * exp_t(x);
@@ -282,22 +269,20 @@ __global__ __launch_bounds__(kBlock) void k_lv_pass2(DevProblem pb, const double
             const int n = n0 + j;
             if (n < pb.N) {
                 xb += s_inj[j];
-                const int a = L.an[n];
+                const int a = ldc(pb.step_row, n);
                 if (a != cur_a) {
                     flush_cell<R>(pb, L, cur_a);
                     cur_a = a;
                 }
-                const R S = s_S[j];
-                const Cell<R> c = locate<R>(pb, L.rows + j * pb.nK, S, K0, invdK, Klast);
-                const R sbar = xb * (-c.sig * h + sq * s_z[j]);
-                const R dsdS = c.inside ? (c.r1 - c.r0) * invdK : (R)0;
-                xb = xb + sbar * dsdS * S;
-                const R al = (R)L.al[n];
-                const R w1 = sbar * c.be, w0 = sbar - w1;
-                my0[c.b * kBlock] += (float)((1 - al) * w0);
-                my0[(c.b + 1) * kBlock] += (float)((1 - al) * w1);
-                my0[(pb.nK + c.b) * kBlock] += (float)(al * w0);
-                my0[(pb.nK + c.b + 1) * kBlock] += (float)(al * w1);
+                const R sbar = xb * s_c[j];
+                xb = xb + sbar * s_d[j];
+                const R al = step_al<R>(pb, n);
+                const R w1 = sbar * s_be[j], w0 = sbar - w1;
+                float *col = my0 + s_b[j] * kBlock;
+                col[0] += (float)((1 - al) * w0);
+                col[kBlock] += (float)((1 - al) * w1);
+                col[pb.nK * kBlock] += (float)(al * w0);
+                col[(pb.nK + 1) * kBlock] += (float)(al * w1);
             }
         }
     }
@@ -352,10 +337,7 @@ size_t lv_lds_bytes(const DevProblem &pb, bool fp64, int pass)
 {
     const size_t real = fp64 ? 8 : 4;
     size_t o = sizeof(double) * (pass == 1 ? (size_t)kWavesPerBlock * pb.m : (size_t)pb.nT * pb.nK);
-    o += real * (size_t)pb.N;
     o += real * (size_t)pb.K * pb.nK;
-    o = (o + 15) & ~(size_t)15;
-    o += sizeof(int) * (size_t)pb.N;
     o = (o + 15) & ~(size_t)15;
     if (pass == 2) o += sizeof(float) * 2 * (size_t)pb.nK * kBlock;
     return o;

@@ -30,13 +30,17 @@ struct DevProblem {
     const int32_t *id;          // [m] original index of date-sorted instrument k
     int32_t *status;            // device status bits
     // local volatility: bilinear grid on time nodes t_nodes[nT] and uniformly
-    // spaced spot nodes K0 + k dK, k < nK; theta[a*nK + k] is the node value.
+    // spaced spot nodes K0 + k dK, k < nK; theta[a*nK + k] is the node value;
+    // step n lies in time cell step_row[n] = a (a <= nT - 2) with weight
+    // step_al[n] on node row a + 1 (host tables).
     // Stochastic local volatility: the same spot nodes, theta[5 + a*nK + k] is
     // the leverage of time row a, and step n uses row step_row[n].
     int32_t nT, nK;
     double K0, dK;
     const double *t_nodes;
-    const int32_t *step_row;    // [N] (SLV)
+    const int32_t *step_row;    // [N]
+    const double *step_al;      // [N] (local volatility)
+    const float *step_al_f;     // [N] the same in FP32
     // where a sweep that writes every checkpoint segment (pass 1 storing, pass
     // 2 re-running the forward sweep) leaves a copy of theta (workgroup 0
     // writes it; M doubles); null: no copy
