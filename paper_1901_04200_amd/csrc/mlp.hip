@@ -242,13 +242,21 @@ __global__ __launch_bounds__(kThreads) void k_loss(const float *__restrict__ Z4,
     if (threadIdx.x == 0) partial[blockIdx.x] = sh[0];
 }
 
-__global__ void k_sum_partials(const double *__restrict__ p, int n, double *__restrict__ out)
+// out[0] = sum of the n block partials: thread t adds p[t], p[t + 256], ... in
+// order, then a fixed tree over the threads (one workgroup of kThreads).
+__global__ __launch_bounds__(kThreads) void k_sum_partials(const double *__restrict__ p, int n,
+                                                           double *__restrict__ out)
 {
-    if (threadIdx.x == 0 && blockIdx.x == 0) {
-        double s = 0.0;
-        for (int i = 0; i < n; ++i) s += p[i];
-        out[0] = s;
+    __shared__ double sh[kThreads];
+    double s = 0.0;
+    for (int i = threadIdx.x; i < n; i += kThreads) s += p[i];
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    for (int h = kThreads / 2; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) sh[threadIdx.x] += sh[threadIdx.x + h];
+        __syncthreads();
     }
+    if (threadIdx.x == 0) out[0] = sh[0];
 }
 
 // Adjoint through a hidden layer's activation (double backprop):
@@ -275,25 +283,36 @@ __global__ void k_act_bwd(const float *__restrict__ Hbar, const float *__restric
     ZbarP[(int64_t)b * H + j] = zb;
 }
 
-// out[j] = sum_b X[b*ld + j], b in order.
-__global__ void k_colsum(const float *__restrict__ X, int B, int ld, int ncols, float *__restrict__ out)
+// Column sums over the rows of a batch, in two deterministic stages: block
+// x sums rows x*kChunk .. x*kChunk + kChunk - 1 of column j in order into
+// part[x][j], then k_split_reduce adds the chunks in order.
+constexpr int kChunk = 32;   // rows per chunk; batches are multiples of 128
+
+__global__ void k_colsum_part(const float *__restrict__ X, int ld, int ncols, float *__restrict__ part)
 {
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y * blockDim.x + threadIdx.x;
     if (j >= ncols) return;
+    const int64_t b0 = (int64_t)blockIdx.x * kChunk;
     float s = 0.f;
-    for (int b = 0; b < B; ++b) s += X[(int64_t)b * ld + j];
-    out[j] = s;
+#pragma unroll 8
+    for (int b = 0; b < kChunk; ++b) s += X[(b0 + b) * ld + j];
+    part[(int64_t)blockIdx.x * ncols + j] = s;
 }
 
-// Layer-1 gradients: W1bar[t][j] = sum_b x_bt zbar_bj + sum_b ubar_t,bj, b1bar[j] = sum_b zbar_bj.
-__global__ void k_l1_bwd(const float *__restrict__ Hbar, const float *__restrict__ Z, const float *__restrict__ X,
-                         int B, int nin, int H, float *__restrict__ gW1, float *__restrict__ gb1)
+// Layer-1 gradients: W1bar[t][j] = sum_b x_bt zbar_bj + sum_b ubar_t,bj, b1bar[j] = sum_b zbar_bj,
+// chunk by chunk as k_colsum_part: part[x][t][j] for t <= nin (row nin: b1bar).
+constexpr int kMaxIn = 16;
+
+__global__ void k_l1_bwd_part(const float *__restrict__ Hbar, const float *__restrict__ Z,
+                              const float *__restrict__ X, int B, int nin, int H, float *__restrict__ part)
 {
-    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= (nin + 1) * H) return;
-    const int t = idx / H, j = idx % H;
-    float acc = 0.f;
-    for (int b = 0; b < B; ++b) {
+    const int j = blockIdx.y * blockDim.x + threadIdx.x;
+    if (j >= H) return;
+    const int b0 = blockIdx.x * kChunk;
+    float acc[kMaxIn + 1];
+#pragma unroll
+    for (int t = 0; t <= kMaxIn; ++t) acc[t] = 0.f;
+    for (int b = b0; b < b0 + kChunk; ++b) {
         const float z = Z[(int64_t)b * H + j];
         const float s = sigm(z);
         const float d1 = s * (1.f + z * (1.f - s));
@@ -303,11 +322,16 @@ __global__ void k_l1_bwd(const float *__restrict__ Hbar, const float *__restrict
             const int64_t r = (int64_t)(q + 1) * B + b;
             zb += Hbar[r * H + j] * Z[r * H + j] * d2;
         }
-        if (t < nin) acc += X[b * nin + t] * zb + Hbar[((int64_t)(t + 1) * B + b) * H + j] * d1;
-        else acc += zb;
+#pragma unroll
+        for (int t = 0; t < kMaxIn; ++t)
+            if (t < nin) acc[t] += X[b * nin + t] * zb + Hbar[((int64_t)(t + 1) * B + b) * H + j] * d1;
+        acc[kMaxIn] += zb;
     }
-    if (t < nin) gW1[t * H + j] = acc;
-    else gb1[j] = acc;
+    float *pz = part + (int64_t)blockIdx.x * (nin + 1) * H;
+#pragma unroll
+    for (int t = 0; t < kMaxIn; ++t)
+        if (t < nin) pz[(int64_t)t * H + j] = acc[t];
+    pz[(int64_t)nin * H + j] = acc[kMaxIn];
 }
 
 __global__ void k_adam(float *__restrict__ p, const float *__restrict__ g, float *__restrict__ m,
@@ -386,7 +410,7 @@ struct mlp_ctx {
     uint16_t *Zbar = nullptr;     // R x H
     float *ZbarP = nullptr;       // Bmax x H
     float *Xn = nullptr;          // Bmax x nin
-    float *split = nullptr;       // kMaxSplits x H x H
+    float *split = nullptr;       // kMaxSplits x H x H, or row-chunk partials of the column sums
     double *lossp = nullptr;
     std::vector<void *> allocs;
     std::string err;
@@ -415,6 +439,17 @@ static hipError_t launch_gemm(bool akc, bool bkc, const uint16_t *A, int lda, co
     else
         hipLaunchKernelGGL((k_gemm<false, true>), grid, dim3(kThreads), 0, st, A, lda, B, ldb, C, ldc, ss, K, ks);
     return hipGetLastError();
+}
+
+// out[j] = sum over the B rows of X (leading dimension ld) of column j < ncols,
+// through c->split (nchunk x ncols partials), deterministic order.
+static void colsum(mlp_ctx *c, const float *X, int B, int ld, int ncols, float *out, hipStream_t st)
+{
+    const int nchunk = B / kChunk;
+    hipLaunchKernelGGL(k_colsum_part, dim3(nchunk, (ncols + kThreads - 1) / kThreads), dim3(kThreads), 0, st, X, ld,
+                       ncols, c->split);
+    hipLaunchKernelGGL(k_split_reduce, dim3((ncols + kThreads - 1) / kThreads), dim3(kThreads), 0, st, c->split, nchunk,
+                       1, ncols, out, ncols, ncols);
 }
 
 extern "C" int mlp_destroy(mlp_ctx *c)
@@ -477,7 +512,9 @@ extern "C" int mlp_create(int32_t n_in, int32_t n_hidden, int32_t n_out, int32_t
     A((void **)&c->Zbar, 2 * R * H);
     A((void **)&c->ZbarP, 4 * (int64_t)c->Bmax * H);
     A((void **)&c->Xn, 4 * (int64_t)c->Bmax * n_in);
-    A((void **)&c->split, 4 * (int64_t)kMaxSplits * H * H);
+    // split-K GEMM partials, or the row-chunk partials of the column sums (at most
+    // (Bmax / kChunk) x (n_in + 1) x H floats)
+    A((void **)&c->split, 4 * std::max((int64_t)kMaxSplits * H * H, (int64_t)(c->Bmax / kChunk) * (n_in + 1) * H));
     A((void **)&c->lossp, 8 * (int64_t)((c->Bmax * kOutPad + kThreads - 1) / kThreads));
     if (e != hipSuccess) {
         mlp_destroy(c);
@@ -605,8 +642,8 @@ extern "C" int mlp_loss_grad(mlp_ctx *c, const float *d_theta, const float *d_Yl
     const unsigned nlb = nb((int64_t)B * kOutPad);
     hipLaunchKernelGGL(k_loss, dim3(nlb), dim3(kThreads), 0, st, c->Z[4], c->p + c->off[7], d_Ylab, d_Jlab, B, nin,
                        c->nout, w, c->in_scale, c->out_shift, c->out_scale, c->G4, c->ZbarP, c->lossp);
-    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(64), 0, st, c->lossp, (int)nlb, d_loss);
-    hipLaunchKernelGGL(k_colsum, dim3(1), dim3(kThreads), 0, st, c->ZbarP, B, kOutPad, c->nout, g + c->off[7]);
+    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(kThreads), 0, st, c->lossp, (int)nlb, d_loss);
+    colsum(c, c->ZbarP, B, kOutPad, c->nout, g + c->off[7], st);
     // output layer: W4bar = A3^T G4 (split over rows), H3bar = G4 W4^T
     const int S = std::min(kMaxSplits, std::max(1, R / 512));
     e = launch_gemm(false, false, c->A[3], H, c->G4, kOutPad, c->split, kOutPad, H, kOutPad, R, S, st);
@@ -619,7 +656,7 @@ extern "C" int mlp_loss_grad(mlp_ctx *c, const float *d_theta, const float *d_Yl
     for (int l = 3; l >= 2 && e == hipSuccess; --l) {
         hipLaunchKernelGGL(k_act_bwd, dim3(nb((int64_t)B * H)), dim3(kThreads), 0, st, c->Hbar, c->Z[l], B, nin, H,
                            c->Zbar, c->ZbarP);
-        hipLaunchKernelGGL(k_colsum, dim3(nb(H)), dim3(kThreads), 0, st, c->ZbarP, B, H, H, g + c->off[2 * l - 1]);
+        colsum(c, c->ZbarP, B, H, H, g + c->off[2 * l - 1], st);
         e = launch_gemm(false, false, c->A[l - 1], H, c->Zbar, H, c->split, H, H, H, R, S, st);
         if (e != hipSuccess) break;
         hipLaunchKernelGGL(k_split_reduce, dim3(nb((int64_t)H * H)), dim3(kThreads), 0, st, c->split, S, H, H,
@@ -627,8 +664,12 @@ extern "C" int mlp_loss_grad(mlp_ctx *c, const float *d_theta, const float *d_Yl
         e = launch_gemm(true, true, c->Zbar, H, c->Wb[l - 1], H, c->Hbar, H, R, H, H, 1, st);
     }
     if (e == hipSuccess) {
-        hipLaunchKernelGGL(k_l1_bwd, dim3(nb((int64_t)(nin + 1) * H)), dim3(kThreads), 0, st, c->Hbar, c->Z[1], c->Xn,
-                           B, nin, H, g + c->off[0], g + c->off[1]);
+        // W1bar (nin rows) and b1bar are contiguous in the gradient: one (nin + 1) x H reduction
+        const int nchunk = B / kChunk;
+        hipLaunchKernelGGL(k_l1_bwd_part, dim3(nchunk, (H + kThreads - 1) / kThreads), dim3(kThreads), 0, st, c->Hbar,
+                           c->Z[1], c->Xn, B, nin, H, c->split);
+        hipLaunchKernelGGL(k_split_reduce, dim3(nb((int64_t)(nin + 1) * H)), dim3(kThreads), 0, st, c->split, nchunk,
+                           nin + 1, H, g + c->off[0], H, H);
         e = hipGetLastError();
     }
     return e == hipSuccess ? 0 : mfail(c, -3, hipGetErrorString(e));

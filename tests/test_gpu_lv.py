@@ -143,8 +143,10 @@ def test_memory_budget_picks_spacing():
 
 def test_lv_full_size_fd_and_oracle(orc):
     """2^22 paths x 256 steps, checkpoints every 16 steps: the adjoint
-    gradient against the oracle, and against central differences (h = 1e-4,
-    common random numbers) on 10 random nodes."""
+    gradient against the oracle; the gradient through the torch.autograd
+    wrapper (forward keeping the checkpoints, backward from them) bit for bit
+    equal to calibrate_gradient's; and against central differences
+    (h = 1e-4, common random numbers) on 10 random nodes."""
     pb, g0, gt, eps, coords = W.lv_problem()
     say("lv full size: oracle targets (2^22 paths, seed 2)")
     C = W.noisy_targets(orc.forward(pb.with_(seed=2), gt), eps)
@@ -159,6 +161,12 @@ def test_lv_full_size_fd_and_oracle(orc):
     say(f"  full size errors Ey {ey_err(Ey.cpu().numpy(), Eo):.2e} grad {g_err(g, go):.2e}")
     assert ey_err(Ey.cpu().numpy(), Eo) <= 1e-5
     assert g_err(g, go) <= 1e-4
+    say("lv full size: autograd step")
+    th = torch.tensor(g0, dtype=torch.float64, device="cuda", requires_grad=True)
+    G_ag = 0.5 * torch.sum((AG.mc_prices(th, mc) - Ct) ** 2)
+    G_ag.backward()
+    assert mc.status() == 0
+    np.testing.assert_array_equal(th.grad.cpu().numpy(), g)
     h = 1e-4
     worst = 0.0
     for j in coords:
