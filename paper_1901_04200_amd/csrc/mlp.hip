@@ -47,18 +47,87 @@ __device__ __forceinline__ float sigm(float z) { return 1.0f / (1.0f + __expf(-z
 // Tiles 128 x 64 x 32; wave w owns rows 32w..32w+31 and both 32-column
 // blocks.  Operands are staged in LDS with k contiguous, so every MFMA
 // operand is one 16-byte LDS read (8 bf16 along k for one row / column).
+// Two LDS buffers: the global loads of the next k-tile are issued into
+// registers before the current tile's MFMAs and written to the other buffer
+// after them, one barrier per k-tile.  The k order of the accumulation is
+// the plain one, so results do not depend on the pipelining.
 // Requires M % 128 == 0, N % 64 == 0, K % 32 == 0, k_split % 32 == 0.
 // ---------------------------------------------------------------------------
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));   // 16 bytes
+constexpr int kAChunks = BM * BK / 8 / kThreads;   // 16-byte A pieces per thread and k-tile (2)
+static_assert(BN * BK / 8 == kThreads, "one 16-byte B piece per thread and k-tile");
+
+template <bool A_KC>
+__device__ __forceinline__ void gemm_load_a(const uint16_t *__restrict__ A, int lda, int m0, int k0, u32x4 *ra)
+{
+#pragma unroll
+    for (int i = 0; i < kAChunks; ++i) {
+        const int c = threadIdx.x + i * kThreads;
+        if constexpr (A_KC) {
+            const int r = c / (BK / 8), kc = c % (BK / 8);
+            ra[i] = *(const u32x4 *)(A + (int64_t)(m0 + r) * lda + k0 + kc * 8);
+        } else {
+            const int kr = c / (BM / 8), mc = c % (BM / 8);
+            ra[i] = *(const u32x4 *)(A + (int64_t)(k0 + kr) * lda + m0 + mc * 8);
+        }
+    }
+}
+
+template <bool A_KC>
+__device__ __forceinline__ void gemm_store_a(uint16_t *sA, const u32x4 *ra)
+{
+#pragma unroll
+    for (int i = 0; i < kAChunks; ++i) {
+        const int c = threadIdx.x + i * kThreads;
+        if constexpr (A_KC) {
+            const int r = c / (BK / 8), kc = c % (BK / 8);
+            *(u32x4 *)(sA + r * LDK + kc * 8) = ra[i];
+        } else {
+            const int kr = c / (BM / 8), mc = c % (BM / 8);
+            const uint16_t *e = (const uint16_t *)&ra[i];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) sA[(mc * 8 + q) * LDK + kr] = e[q];
+        }
+    }
+}
+
+template <bool B_KC>
+__device__ __forceinline__ u32x4 gemm_load_b(const uint16_t *__restrict__ B, int ldb, int n0, int k0)
+{
+    const int c = threadIdx.x;
+    if constexpr (B_KC) {
+        const int r = c / (BK / 8), kc = c % (BK / 8);
+        return *(const u32x4 *)(B + (int64_t)(n0 + r) * ldb + k0 + kc * 8);
+    } else {
+        const int kr = c / (BN / 8), nc = c % (BN / 8);
+        return *(const u32x4 *)(B + (int64_t)(k0 + kr) * ldb + n0 + nc * 8);
+    }
+}
+
+template <bool B_KC>
+__device__ __forceinline__ void gemm_store_b(uint16_t *sB, u32x4 rb)
+{
+    const int c = threadIdx.x;
+    if constexpr (B_KC) {
+        const int r = c / (BK / 8), kc = c % (BK / 8);
+        *(u32x4 *)(sB + r * LDK + kc * 8) = rb;
+    } else {
+        const int kr = c / (BN / 8), nc = c % (BN / 8);
+        const uint16_t *e = (const uint16_t *)&rb;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) sB[(nc * 8 + q) * LDK + kr] = e[q];
+    }
+}
+
 template <bool A_KC, bool B_KC>
 __global__ __launch_bounds__(kThreads) void k_gemm(const uint16_t *__restrict__ A, int lda,
                                                    const uint16_t *__restrict__ B, int ldb, float *__restrict__ C,
                                                    int ldc, int64_t split_stride, int K, int k_split)
 {
-    __shared__ __attribute__((aligned(16))) uint16_t sA[BM * LDK];
-    __shared__ __attribute__((aligned(16))) uint16_t sB[BN * LDK];
-    const int tid = threadIdx.x;
-    const int lane = tid & 63;
-    const int wave = tid >> 6;
+    __shared__ __attribute__((aligned(16))) uint16_t sA[2][BM * LDK];
+    __shared__ __attribute__((aligned(16))) uint16_t sB[2][BN * LDK];
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
     const int m0 = blockIdx.x * BM;
     const int n0 = blockIdx.y * BN;
     const int kbeg = blockIdx.z * k_split;
@@ -69,46 +138,37 @@ __global__ __launch_bounds__(kThreads) void k_gemm(const uint16_t *__restrict__ 
         acc0[i] = 0.f;
         acc1[i] = 0.f;
     }
+    u32x4 ra[kAChunks], rb;
+    if (kbeg < kend) {
+        gemm_load_a<A_KC>(A, lda, m0, kbeg, ra);
+        rb = gemm_load_b<B_KC>(B, ldb, n0, kbeg);
+        gemm_store_a<A_KC>(sA[0], ra);
+        gemm_store_b<B_KC>(sB[0], rb);
+    }
+    __syncthreads();
+    int cur = 0;
     for (int k0 = kbeg; k0 < kend; k0 += BK) {
-#pragma unroll
-        for (int c = tid; c < BM * BK / 8; c += kThreads) {
-            if constexpr (A_KC) {
-                const int r = c / (BK / 8), kc = c % (BK / 8);
-                const uint4 v = *(const uint4 *)(A + (int64_t)(m0 + r) * lda + k0 + kc * 8);
-                *(uint4 *)(sA + r * LDK + kc * 8) = v;
-            } else {
-                const int kr = c / (BM / 8), mc = c % (BM / 8);
-                const uint4 v = *(const uint4 *)(A + (int64_t)(k0 + kr) * lda + m0 + mc * 8);
-                const uint16_t *e = (const uint16_t *)&v;
-#pragma unroll
-                for (int i = 0; i < 8; ++i) sA[(mc * 8 + i) * LDK + kr] = e[i];
-            }
+        const bool more = k0 + BK < kend;
+        if (more) {   // next k-tile into registers while this one is multiplied
+            gemm_load_a<A_KC>(A, lda, m0, k0 + BK, ra);
+            rb = gemm_load_b<B_KC>(B, ldb, n0, k0 + BK);
         }
-        {
-            const int c = tid;   // BN * BK / 8 == kThreads
-            if constexpr (B_KC) {
-                const int r = c / (BK / 8), kc = c % (BK / 8);
-                const uint4 v = *(const uint4 *)(B + (int64_t)(n0 + r) * ldb + k0 + kc * 8);
-                *(uint4 *)(sB + r * LDK + kc * 8) = v;
-            } else {
-                const int kr = c / (BN / 8), nc = c % (BN / 8);
-                const uint4 v = *(const uint4 *)(B + (int64_t)(k0 + kr) * ldb + n0 + nc * 8);
-                const uint16_t *e = (const uint16_t *)&v;
-#pragma unroll
-                for (int i = 0; i < 8; ++i) sB[(nc * 8 + i) * LDK + kr] = e[i];
-            }
-        }
-        __syncthreads();
+        const uint16_t *a_s = sA[cur], *b_s = sB[cur];
 #pragma unroll
         for (int kk = 0; kk < BK; kk += 16) {
             const int ko = kk + 8 * (lane >> 5);
-            const bf16x8 a = *(const bf16x8 *)(sA + (wave * 32 + (lane & 31)) * LDK + ko);
-            const bf16x8 b0 = *(const bf16x8 *)(sB + (lane & 31) * LDK + ko);
-            const bf16x8 b1 = *(const bf16x8 *)(sB + (32 + (lane & 31)) * LDK + ko);
+            const bf16x8 a = *(const bf16x8 *)(a_s + (wave * 32 + (lane & 31)) * LDK + ko);
+            const bf16x8 b0 = *(const bf16x8 *)(b_s + (lane & 31) * LDK + ko);
+            const bf16x8 b1 = *(const bf16x8 *)(b_s + (32 + (lane & 31)) * LDK + ko);
             acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b0, acc0, 0, 0, 0);
             acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b1, acc1, 0, 0, 0);
         }
+        if (more) {   // the other buffer was last read before the previous barrier
+            gemm_store_a<A_KC>(sA[cur ^ 1], ra);
+            gemm_store_b<B_KC>(sB[cur ^ 1], rb);
+        }
         __syncthreads();
+        cur ^= 1;
     }
     float *Cz = C + (int64_t)blockIdx.z * split_stride;
     const int col = n0 + (lane & 31);
@@ -285,7 +345,7 @@ __global__ void k_act_bwd(const float *__restrict__ Hbar, const float *__restric
 
 // Column sums over the rows of a batch, in two deterministic stages: block
 // x sums rows x*kChunk .. x*kChunk + kChunk - 1 of column j in order into
-// part[x][j], then k_split_reduce adds the chunks in order.
+// part[x][j], then k_chunk_reduce adds the chunks in a fixed order.
 constexpr int kChunk = 32;   // rows per chunk; batches are multiples of 128
 
 __global__ void k_colsum_part(const float *__restrict__ X, int ld, int ncols, float *__restrict__ part)
@@ -299,20 +359,42 @@ __global__ void k_colsum_part(const float *__restrict__ X, int ld, int ncols, fl
     part[(int64_t)blockIdx.x * ncols + j] = s;
 }
 
+// out[o] = sum over z < S of part[z * n + o], o < n: eight threads per output,
+// thread q adding chunks q, q + 8, q + 16, ... in order, then the eight sums
+// in a fixed tree; 32 outputs per workgroup.
+__global__ __launch_bounds__(kThreads) void k_chunk_reduce(const float *__restrict__ part, int S, int n,
+                                                           float *__restrict__ out)
+{
+    __shared__ float sh[kThreads];
+    const int q = threadIdx.x & 7;
+    const int o = blockIdx.x * (kThreads / 8) + (threadIdx.x >> 3);
+    float s = 0.f;
+    if (o < n)
+        for (int z = q; z < S; z += 8) s += part[(int64_t)z * n + o];
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    if (q == 0 && o < n) {
+        const float *v = sh + threadIdx.x;
+        out[o] = ((v[0] + v[1]) + (v[2] + v[3])) + ((v[4] + v[5]) + (v[6] + v[7]));
+    }
+}
+
 // Layer-1 gradients: W1bar[t][j] = sum_b x_bt zbar_bj + sum_b ubar_t,bj, b1bar[j] = sum_b zbar_bj,
-// chunk by chunk as k_colsum_part: part[x][t][j] for t <= nin (row nin: b1bar).
+// chunk by chunk (kChunkL1 rows; the per-row work is heavier, so more, smaller
+// chunks) as k_colsum_part: part[x][t][j] for t <= nin (row nin: b1bar).
 constexpr int kMaxIn = 16;
+constexpr int kChunkL1 = 8;
 
 __global__ void k_l1_bwd_part(const float *__restrict__ Hbar, const float *__restrict__ Z,
                               const float *__restrict__ X, int B, int nin, int H, float *__restrict__ part)
 {
     const int j = blockIdx.y * blockDim.x + threadIdx.x;
     if (j >= H) return;
-    const int b0 = blockIdx.x * kChunk;
+    const int b0 = blockIdx.x * kChunkL1;
     float acc[kMaxIn + 1];
 #pragma unroll
     for (int t = 0; t <= kMaxIn; ++t) acc[t] = 0.f;
-    for (int b = b0; b < b0 + kChunk; ++b) {
+    for (int b = b0; b < b0 + kChunkL1; ++b) {
         const float z = Z[(int64_t)b * H + j];
         const float s = sigm(z);
         const float d1 = s * (1.f + z * (1.f - s));
@@ -448,8 +530,8 @@ static void colsum(mlp_ctx *c, const float *X, int B, int ld, int ncols, float *
     const int nchunk = B / kChunk;
     hipLaunchKernelGGL(k_colsum_part, dim3(nchunk, (ncols + kThreads - 1) / kThreads), dim3(kThreads), 0, st, X, ld,
                        ncols, c->split);
-    hipLaunchKernelGGL(k_split_reduce, dim3((ncols + kThreads - 1) / kThreads), dim3(kThreads), 0, st, c->split, nchunk,
-                       1, ncols, out, ncols, ncols);
+    hipLaunchKernelGGL(k_chunk_reduce, dim3((ncols + kThreads / 8 - 1) / (kThreads / 8)), dim3(kThreads), 0, st,
+                       c->split, nchunk, ncols, out);
 }
 
 extern "C" int mlp_destroy(mlp_ctx *c)
@@ -513,8 +595,8 @@ extern "C" int mlp_create(int32_t n_in, int32_t n_hidden, int32_t n_out, int32_t
     A((void **)&c->ZbarP, 4 * (int64_t)c->Bmax * H);
     A((void **)&c->Xn, 4 * (int64_t)c->Bmax * n_in);
     // split-K GEMM partials, or the row-chunk partials of the column sums (at most
-    // (Bmax / kChunk) x (n_in + 1) x H floats)
-    A((void **)&c->split, 4 * std::max((int64_t)kMaxSplits * H * H, (int64_t)(c->Bmax / kChunk) * (n_in + 1) * H));
+    // (Bmax / kChunkL1) x (n_in + 1) x H floats)
+    A((void **)&c->split, 4 * std::max((int64_t)kMaxSplits * H * H, (int64_t)(c->Bmax / kChunkL1) * (n_in + 1) * H));
     A((void **)&c->lossp, 8 * (int64_t)((c->Bmax * kOutPad + kThreads - 1) / kThreads));
     if (e != hipSuccess) {
         mlp_destroy(c);
@@ -665,11 +747,12 @@ extern "C" int mlp_loss_grad(mlp_ctx *c, const float *d_theta, const float *d_Yl
     }
     if (e == hipSuccess) {
         // W1bar (nin rows) and b1bar are contiguous in the gradient: one (nin + 1) x H reduction
-        const int nchunk = B / kChunk;
+        const int nchunk = B / kChunkL1;
         hipLaunchKernelGGL(k_l1_bwd_part, dim3(nchunk, (H + kThreads - 1) / kThreads), dim3(kThreads), 0, st, c->Hbar,
                            c->Z[1], c->Xn, B, nin, H, c->split);
-        hipLaunchKernelGGL(k_split_reduce, dim3(nb((int64_t)(nin + 1) * H)), dim3(kThreads), 0, st, c->split, nchunk,
-                           nin + 1, H, g + c->off[0], H, H);
+        const int nout1 = (nin + 1) * H;
+        hipLaunchKernelGGL(k_chunk_reduce, dim3((nout1 + kThreads / 8 - 1) / (kThreads / 8)), dim3(kThreads), 0, st,
+                           c->split, nchunk, nout1, g + c->off[0]);
         e = hipGetLastError();
     }
     return e == hipSuccess ? 0 : mfail(c, -3, hipGetErrorString(e));
