@@ -70,8 +70,16 @@ def run(n_train=1 << 14, train_paths=1 << 14, n_heldout=32, ref_paths=1 << 24, e
     hist = S.fit(net, thd, Ey.float(), J.float(), epochs=epochs, batch=min(batch, n_train), lr=lr,
                  lr_final=lr_final, w=w, log_every=max(1, epochs // 10))
     t_fit = time.perf_counter() - t0
+    steps = epochs * (n_train // min(batch, n_train))
+    # useful GEMM work of one step: forward, input gradient and weight gradient
+    # of the layers 256x256, 256x256 and 256xm over the primal and 5 tangent row
+    # blocks (the 5x256 first layer is elementwise)
+    rows = 6 * min(batch, n_train)
+    flops = 3 * 2 * rows * (2 * 256 * 256 + 256 * pb.n_instr)
     out["training"] = {"epochs": epochs, "seconds": t_fit, "loss_first": hist[0].loss, "loss_last": hist[-1].loss,
-                       "steps": epochs * (n_train // min(batch, n_train))}
+                       "steps": steps, "gemm_flop_per_step": flops,
+                       "gemm_tflops": flops * steps / t_fit * 1e-12,
+                       "bf16_peak_frac": flops * steps / t_fit / 2.5e15}
     log(f"surrogate: {epochs} epochs in {t_fit:.2f} s, loss {hist[0].loss:.4g} -> {hist[-1].loss:.4g}")
 
     # ---- 3. accuracy on held-out draws -------------------------------------
