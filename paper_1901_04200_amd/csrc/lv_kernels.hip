@@ -264,25 +264,44 @@ __global__ __launch_bounds__(kBlock) void k_lv_pass2(DevProblem pb, const double
             }
         }
         dhi = dlo;
+        // one reverse step: the adjoint of x~ through step n0 + j, and the node
+        // adjoints of the step's spot cell into this lane's slices
+        auto reverse_step = [&](int j) {
+            xb += s_inj[j];
+            const R sbar = xb * s_c[j];
+            xb = xb + sbar * s_d[j];
+            const R al = step_al<R>(pb, n0 + j);
+            const R w1 = sbar * s_be[j], w0 = sbar - w1;
+            float *col = my0 + s_b[j] * kBlock;
+            col[0] += (float)((1 - al) * w0);
+            col[kBlock] += (float)((1 - al) * w1);
+            col[pb.nK * kBlock] += (float)(al * w0);
+            col[(pb.nK + 1) * kBlock] += (float)(al * w1);
+        };
+        // the time cell of the segment's last step (cells do not decrease with n)
+        const int a_last = ldc(pb.step_row, min(n0 + K, pb.N) - 1);
+        if (a_last != cur_a) {
+            flush_cell<R>(pb, L, cur_a);
+            cur_a = a_last;
+        }
+        if (n0 + K <= pb.N && ldc(pb.step_row, n0) == a_last) {
+            // a whole segment in one time cell: no test between the steps, so the
+            // compiler can overlap one step's slice updates with the next step's
+            // arithmetic
 #pragma unroll
-        for (int j = K - 1; j >= 0; --j) {
-            const int n = n0 + j;
-            if (n < pb.N) {
-                xb += s_inj[j];
-                const int a = ldc(pb.step_row, n);
-                if (a != cur_a) {
-                    flush_cell<R>(pb, L, cur_a);
-                    cur_a = a;
+            for (int j = K - 1; j >= 0; --j) reverse_step(j);
+        } else {
+#pragma unroll
+            for (int j = K - 1; j >= 0; --j) {
+                const int n = n0 + j;
+                if (n < pb.N) {
+                    const int a = ldc(pb.step_row, n);
+                    if (a != cur_a) {
+                        flush_cell<R>(pb, L, cur_a);
+                        cur_a = a;
+                    }
+                    reverse_step(j);
                 }
-                const R sbar = xb * s_c[j];
-                xb = xb + sbar * s_d[j];
-                const R al = step_al<R>(pb, n);
-                const R w1 = sbar * s_be[j], w0 = sbar - w1;
-                float *col = my0 + s_b[j] * kBlock;
-                col[0] += (float)((1 - al) * w0);
-                col[kBlock] += (float)((1 - al) * w1);
-                col[pb.nK * kBlock] += (float)(al * w0);
-                col[(pb.nK + 1) * kBlock] += (float)(al * w1);
             }
         }
     }

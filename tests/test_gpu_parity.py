@@ -273,6 +273,24 @@ def test_forward_store_and_vjp_stored(orc, model, k):
     assert g_err(g_s.cpu().numpy(), orc.vjp(pb, th, lam)) <= 1e-4
 
 
+def test_vjp_stored_after_rerun_mode_gradient(heston_small):
+    """In CAL_CKPT_RERUN mode pass 2 writes the checkpoints itself, so
+    calibrate_vjp_stored after calibrate_gradient reproduces its gradient
+    (lambda = E y - C) bit for bit, and so does calibrate_forward_store followed
+    by calibrate_vjp_stored."""
+    pb, th0, tht, C = heston_small
+    th = W.heston_draws(2, 10)[9]
+    mc = MonteCarloCalibration(pb.with_(n_paths=5 * 256 + 3), precision="fp32", ckpt_every=16, ckpt_mode="rerun")
+    Ey, G, g = mc.gradient(th, C)
+    lam = Ey - torch.as_tensor(C, device=Ey.device)
+    assert torch.equal(mc.vjp_stored(th, lam), g)
+    Ey2 = mc.forward_store(th)
+    assert torch.equal(Ey2, Ey)
+    assert torch.equal(mc.vjp_stored(th, lam), g)
+    assert mc.status() == 0
+    mc.close()
+
+
 def test_vjp_stored_needs_checkpoints_of_this_theta(heston_small):
     pb, th0, tht, C = heston_small
     mc = MonteCarloCalibration(pb.with_(n_paths=3 * 256 + 1), precision="fp32")
