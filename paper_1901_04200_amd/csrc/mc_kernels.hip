@@ -149,7 +149,6 @@ __device__ __forceinline__ void pass2_block(const DevProblem &pb, const double *
     for (int sp = 0; sp < pb.ppl; ++sp) {
         const int64_t p = (blk * pb.ppl + sp) * kBlock + tid;
         const bool active = p < pb.P;
-        const int64_t pc = active ? p : 0;   // inactive lanes read path 0's checkpoints
         const uint32_t path = (uint32_t)p;
 
         if constexpr (!FROM_CKPT) {
@@ -182,10 +181,15 @@ __device__ __forceinline__ void pass2_block(const DevProblem &pb, const double *
 
         for (int seg = pb.nseg - 1; seg >= 0; --seg) {
             const int n0 = seg * K;
-            const int64_t base = (int64_t)(seg * T::NV) * pb.P + pc;
+            // inactive lanes (past the last path) load path 0's slot but run a
+            // harmless path from (0, v0) instead and add nothing: in the re-run
+            // mode another workgroup may still be writing that slot
+            const int64_t base = (int64_t)(seg * T::NV) * pb.P + (active ? p : 0);
             R x = ckpt[base];
             R v = (R)0;
             if constexpr (T::NV == 2) v = ckpt[base + pb.P];
+            x = active ? x : (R)0;
+            if constexpr (MODEL == kHeston) v = active ? v : c.v0;
             int dlo = dhi;
             while (dlo > 0 && ldc(pb.date_step, dlo - 1) > n0) --dlo;
             int d = dlo;

@@ -220,7 +220,6 @@ __global__ __launch_bounds__(kBlock) void k_slv_pass2(DevProblem pb, const doubl
     for (int sp = 0; sp < pb.ppl; ++sp) {
         const int64_t p = ((int64_t)blockIdx.x * pb.ppl + sp) * kBlock + tid;
         const bool active = p < pb.P;
-        const int64_t pc = active ? p : 0;   // inactive lanes run path 0 with zero adjoints
         const uint32_t path = (uint32_t)p;
         const double on = active ? 1.0 : 0.0;
         if constexpr (!FROM_CKPT) {
@@ -250,9 +249,16 @@ __global__ __launch_bounds__(kBlock) void k_slv_pass2(DevProblem pb, const doubl
         int dhi = pb.ndates;
         for (int seg = pb.nseg - 1; seg >= 0; --seg) {
             const int n0 = seg * K;
-            const int64_t base = (int64_t)(seg * 2) * pb.P + pc;
-            R x = ckpt[base];
-            R v = ckpt[base + pb.P];
+            // inactive lanes (past the last path) run a harmless path from
+            // (0, v0) with zero adjoints; they read no checkpoint, since in the
+            // re-run mode another workgroup may still be writing the one they
+            // would share
+            R x = (R)0, v = c.v0;
+            if (active) {
+                const int64_t base = (int64_t)(seg * 2) * pb.P + p;
+                x = ckpt[base];
+                v = ckpt[base + pb.P];
+            }
             int dlo = dhi;
             while (dlo > 0 && ldc(pb.date_step, dlo - 1) > n0) --dlo;
             int d = dlo;
