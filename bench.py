@@ -309,7 +309,7 @@ def main():
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU sharding of "
-              f"paths is described in DESIGN.md, not run.", file=sys.stderr)
+              f"paths over GPUs is a design note, not built.", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
