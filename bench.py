@@ -77,6 +77,40 @@ def pass2_traffic(ckpt_every, ppl):
     return value if ok else None
 
 
+GRID_VALU_PROFILE = os.path.join(ROOT, "profiles", "grid_kernels_valu_mix.md")
+
+
+def counted_slots(model, kernel, ckpt_every):
+    """VALU issue slots per path-step of a local-volatility or SLV kernel
+    ('pass1' or 'pass2' at this spacing), counted with SQ counters and
+    committed with the sources' hashes; None when not counted or stale."""
+    try:
+        lines = open(GRID_VALU_PROFILE).read().splitlines()
+    except OSError:
+        return None
+    want = [model, kernel, f"K={ckpt_every}" if kernel == "pass2" else "K=-"]
+    value, ok = None, True
+    for ln in lines:
+        f = ln.split()
+        if len(f) == 5 and f[0] == "valu_slots_per_path_step" and f[1:4] == want:
+            value = float(f[4])
+        elif len(f) == 3 and f[0] == "code-sha256":
+            ok = ok and os.path.exists(os.path.join(ROOT, f[1])) and code_hash(os.path.join(ROOT, f[1])) == f[2]
+    return value if ok else None
+
+
+def grid_roofline(model, kernel_name, ckpt_every, path_steps, ms_pass2):
+    """Issue-slot roofline of a grid model's pass-2 kernel: counted slots per
+    path-step x path-steps / the kernel's average duration, against the
+    7.86e13 lane-slots/s of the FP32 VALU peak."""
+    from paper_1901_04200_amd import roofline
+    sl = counted_slots(model, "pass2", ckpt_every)
+    achieved = sl * path_steps / (ms_pass2 * 1e-3) * 1e-12 if sl else None
+    return {"bound": "alu", "kernel": kernel_name, "achieved": achieved, "peak": roofline.PEAK_SLOTS * 1e-12,
+            "unit": "T VALU lane-slots/s", "frac": achieved / (roofline.PEAK_SLOTS * 1e-12) if achieved else None,
+            "slots_per_path_step": sl, "work": "VALU issue slots per path-step counted with SQ counters"}
+
+
 def time_ms(fn, reps):
     import torch
     torch.cuda.synchronize()
@@ -165,7 +199,8 @@ def slv_leg(reps):
             "paths_steps_per_s": ps / (ms_grad * 1e-3), "ms_per_step": ms_grad,
             "forward_paths_steps_per_s": ps / (ms_fwd * 1e-3), "ms_forward": ms_fwd,
             "ms_pass1_kernel": p1[0] / p1[1], "ms_pass2_kernel": t_2,
-            "kr_over_kf": costmodel.kr_over_kf(t_f, t_2)}
+            "kr_over_kf": costmodel.kr_over_kf(t_f, t_2),
+            "roofline": grid_roofline("slv", f"k_slv_pass2 (FP32, K={k})", k, ps, t_2)}
 
 
 def lv_leg(reps):
@@ -219,7 +254,8 @@ def lv_leg(reps):
             "forward_paths_steps_per_s": ps / (ms_fwd * 1e-3), "ms_forward": ms_fwd,
             "ms_pass1_kernel": p1[0] / p1[1], "ms_pass2_kernel": t_2,
             "kr_over_kf": costmodel.kr_over_kf(t_f, t_2),
-            "ms_autograd_step": ms_ag, "autograd_vs_gradient_rel_diff": agree}
+            "ms_autograd_step": ms_ag, "autograd_vs_gradient_rel_diff": agree,
+            "roofline": grid_roofline("lv", f"k_lv_pass2 (FP32, K={k})", k, ps, t_2)}
 
 
 def batched_leg(n_inst, reps):
