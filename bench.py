@@ -302,7 +302,21 @@ def batched_leg(n_inst, reps):
             "autotuned": {"ckpt_every": best[0], "workgroups_per_cu": best[1], "paths_per_lane": best[2],
                           "candidates_ms": {f"k{c[0]}_w{c[1]}_ppl{c[2]}": round(t * 1e3, 3) for c, t in table}},
             "ms_graph_step": ms_graph, "paths_steps_per_s": path_steps / (ms_graph * 1e-3),
-            "ms_one_context_at_a_time": ms_seq, "speedup": ms_seq / ms_graph}
+            "ms_one_context_at_a_time": ms_seq, "speedup": ms_seq / ms_graph,
+            "roofline": batched_roofline(path_steps, ms_graph)}
+
+
+def batched_roofline(path_steps, ms_step):
+    """Issue-slot roofline of one captured batched step (pass 1 storing
+    checkpoints and pass 2 from them over every instance): the Heston cost
+    model's F + (F + R) slots per path-step over the whole step's time."""
+    from paper_1901_04200_amd import roofline
+    slots = roofline.slots(roofline.per_path_step("heston", "pass1")) + \
+        roofline.slots(roofline.per_path_step("heston", "pass2"))
+    achieved = slots * path_steps / (ms_step * 1e-3) * 1e-12
+    return {"bound": "alu", "kernel": "k_batch_pass1 + k_batch_pass2 (whole step)", "achieved": achieved,
+            "peak": roofline.PEAK_SLOTS * 1e-12, "unit": "T VALU lane-slots/s",
+            "frac": achieved / (roofline.PEAK_SLOTS * 1e-12), "slots_per_path_step": slots}
 
 
 def copy_probe(nbytes):
