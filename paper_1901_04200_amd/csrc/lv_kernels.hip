@@ -285,11 +285,46 @@ __global__ __launch_bounds__(kBlock) void k_lv_pass2(DevProblem pb, const double
             cur_a = a_last;
         }
         if (n0 + K <= pb.N && ldc(pb.step_row, n0) == a_last) {
-            // a whole segment in one time cell: no test between the steps, so the
-            // compiler can overlap one step's slice updates with the next step's
-            // arithmetic
+            // a whole segment in one time cell, without tests between the steps.
+            // The slice values a step adds to are read one step ahead, before
+            // the previous step's writes; where the two steps share a node the
+            // value just written is forwarded instead, so the LDS latency overlaps
+            // a step's arithmetic and the sums are exactly those of one step at a
+            // time.
+            const int rowB = pb.nK * kBlock;
+            float *col = my0 + s_b[K - 1] * kBlock;
+            float r0 = col[0], r1 = col[kBlock], r2 = col[rowB], r3 = col[rowB + kBlock];
 #pragma unroll
-            for (int j = K - 1; j >= 0; --j) reverse_step(j);
+            for (int j = K - 1; j >= 0; --j) {
+                xb += s_inj[j];
+                const R sbar = xb * s_c[j];
+                xb = xb + sbar * s_d[j];
+                const R al = step_al<R>(pb, n0 + j);
+                const R w1 = sbar * s_be[j], w0 = sbar - w1;
+                float q0 = 0.f, q1 = 0.f, q2 = 0.f, q3 = 0.f;
+                float *ncol = col;
+                if (j > 0) {   // the next step's slice values, before this step's writes
+                    ncol = my0 + s_b[j - 1] * kBlock;
+                    q0 = ncol[0];
+                    q1 = ncol[kBlock];
+                    q2 = ncol[rowB];
+                    q3 = ncol[rowB + kBlock];
+                }
+                const float v0 = r0 + (float)((1 - al) * w0), v1 = r1 + (float)((1 - al) * w1);
+                const float v2 = r2 + (float)(al * w0), v3 = r3 + (float)(al * w1);
+                col[0] = v0;
+                col[kBlock] = v1;
+                col[rowB] = v2;
+                col[rowB + kBlock] = v3;
+                if (j > 0) {
+                    const int b = s_b[j], bn = s_b[j - 1];
+                    r0 = bn == b ? v0 : (bn == b + 1 ? v1 : q0);
+                    r1 = bn == b ? v1 : (bn + 1 == b ? v0 : q1);
+                    r2 = bn == b ? v2 : (bn == b + 1 ? v3 : q2);
+                    r3 = bn == b ? v3 : (bn + 1 == b ? v2 : q3);
+                    col = ncol;
+                }
+            }
         } else {
 #pragma unroll
             for (int j = K - 1; j >= 0; --j) {
