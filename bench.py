@@ -208,7 +208,9 @@ def lv_leg(reps):
     nodes): 2^22 paths x 256 steps over 2 years, FP32 state, checkpoints every
     16 steps.  Times calibrate_gradient, the forward pass, and one step through
     the torch.autograd wrapper (forward keeping checkpoints, G in torch,
-    backward = pass 2 from those checkpoints)."""
+    backward = pass 2 from those checkpoints); then the gradient again with the
+    spacing (8 or 16) and paths per lane (1 or 2, side by side) picked by
+    timing."""
     import torch
     from paper_1901_04200_amd import autograd as AG
     from paper_1901_04200_amd import capi, costmodel
@@ -245,8 +247,22 @@ def lv_leg(reps):
     agree = float(torch.max(torch.abs(thg.grad - g)) / torch.max(torch.abs(g)))
     status = mc.status()
     mc.close()
+    # the same gradient with the checkpoint spacing and paths per lane picked by timing
+    from paper_1901_04200_amd.mc import pick_config
+    (kt, pplt), table = pick_config(pb, g0, C, ks=(8, 16), ppls=(1, 2))
+    mct = MonteCarloCalibration(pb, ckpt_every=kt, ckpt_mode="store", paths_per_lane=pplt)
+    capi.calibrate_gradient(mct.ctx, th, C, Ey, G, g)
+    capi.cal_timing_enable(mct.ctx, True)
+    ms_tuned = time_ms(lambda: capi.calibrate_gradient(mct.ctx, th, C, Ey, G, g), reps)
+    p2t = capi.cal_timing_read(mct.ctx, 1)
+    status |= mct.status()
+    mct.close()
     ps = pb.n_paths * pb.n_steps
     t_f, t_2 = f[0] / f[1], p2[0] / p2[1]
+    tuned = {"ckpt_every": kt, "paths_per_lane": pplt,
+             "tuning_ms": {f"k{kk}_ppl{pp}": t * 1e3 for (kk, pp), t in table},
+             "ms_per_step": ms_tuned, "paths_steps_per_s": ps / (ms_tuned * 1e-3),
+             "ms_pass2_kernel": p2t[0] / p2t[1]}
     return {"workload": "local volatility: 2^22 paths x 256 steps over 2 years, bilinear 10 x 20 grid (M = 200), "
                         "m = 200 calls at the grid nodes, FP32 state, FP64 sums",
             "ckpt_every": k, "status": status,
@@ -255,7 +271,8 @@ def lv_leg(reps):
             "ms_pass1_kernel": p1[0] / p1[1], "ms_pass2_kernel": t_2,
             "kr_over_kf": costmodel.kr_over_kf(t_f, t_2),
             "ms_autograd_step": ms_ag, "autograd_vs_gradient_rel_diff": agree,
-            "roofline": grid_roofline("lv", f"k_lv_pass2 (FP32, K={k})", k, ps, t_2)}
+            "roofline": grid_roofline("lv", f"k_lv_pass2 (FP32, K={k})", k, ps, t_2),
+            "tuned": tuned}
 
 
 def batched_leg(n_inst, reps):

@@ -83,7 +83,9 @@ typedef struct cal_ctx cal_ctx;
  *   ckpt_every (k)    : 0 = auto, else 8, 16 or 32 steps between checkpoints
  *   paths_per_lane    : 0 = 1, else 1, 2 or 4 paths each lane runs one after
  *                       another (a workgroup then covers 256 x that many
- *                       paths); local volatility takes 1 only
+ *                       paths); local volatility takes 1 or 2 and runs
+ *                       the two side by side (interleaved, not one after
+ *                       the other)
  *   ckpt_mode         : CAL_CKPT_*
  *   s0, rate, t_max   : spot, risk-free rate (drift and discounting), horizon
  *   sqrt_eps          : must be 0 (plain full truncation, s = sqrt(v+)); any

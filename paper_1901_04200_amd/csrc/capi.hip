@@ -113,9 +113,9 @@ static std::string validate(const cal_problem *pb, int *code)
     if (pb->ckpt_mode < CAL_CKPT_AUTO || pb->ckpt_mode > CAL_CKPT_STORE) return "unknown ckpt_mode";
     if (pb->paths_per_lane != 0 && pb->paths_per_lane != 1 && pb->paths_per_lane != 2 && pb->paths_per_lane != 4)
         return "paths_per_lane must be 0, 1, 2 or 4";
-    if (pb->model == CAL_LV && pb->paths_per_lane > 1) {
+    if (pb->model == CAL_LV && pb->paths_per_lane > 2) {
         *code = CAL_EUNSUPPORTED;
-        return "local volatility runs one path per lane";
+        return "local volatility runs one or two paths per lane";
     }
     if (pb->max_batch < 0 || pb->max_batch > 65535) return "max_batch must be in 0..65535";
     if (pb->model == CAL_BS && pb->n_params != 1) return "Black-Scholes takes n_params = 1";

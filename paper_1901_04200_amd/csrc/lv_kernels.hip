@@ -104,7 +104,10 @@ __device__ __forceinline__ Cell<R> locate(const DevProblem &pb, const R *row, R 
     return c;
 }
 
-template <typename R, bool STORE>
+// Pass 1.  A lane runs PPL paths side by side (independent dependency
+// chains, which hide each other's latency): path i of the lane in workgroup
+// blk is (blk * PPL + i) * kBlock + tid.
+template <typename R, bool STORE, int PPL>
 __global__ __launch_bounds__(kBlock) void k_lv_pass1(DevProblem pb, const double *__restrict__ theta,
                                                      double *__restrict__ partial, R *__restrict__ ckpt)
 {
@@ -113,14 +116,20 @@ __global__ __launch_bounds__(kBlock) void k_lv_pass1(DevProblem pb, const double
     const int tid = threadIdx.x;
     const int lane = tid & (kWave - 1);
     const int wave = tid / kWave;
-    const int64_t p = (int64_t)blockIdx.x * kBlock + tid;
-    const bool active = p < pb.P;
-    const uint32_t path = (uint32_t)p;
+    int64_t p[PPL];
+    bool active[PPL];
+#pragma unroll
+    for (int i = 0; i < PPL; ++i) {
+        p[i] = ((int64_t)blockIdx.x * PPL + i) * kBlock + tid;
+        active[i] = p[i] < pb.P;
+    }
     if constexpr (STORE) save_theta(pb, theta, blockIdx.x);
 
     const R s0 = (R)pb.s0, rh = (R)(pb.rate * pb.h), hh = (R)(0.5 * pb.h), sq = (R)pb.sq;
     const R K0 = (R)pb.K0, invdK = (R)(1.0 / pb.dK), Klast = (R)(pb.K0 + (pb.nK - 1) * pb.dK);
-    R x = (R)0;
+    R x[PPL];
+#pragma unroll
+    for (int i = 0; i < PPL; ++i) x[i] = (R)0;
     int d = 0;
     int next = pb.ndates > 0 ? pb.date_step[0] : -1;
     const int cps = max(pb.K / 4, 1);   // Philox calls per segment (K is a multiple of 4)
@@ -131,22 +140,32 @@ __global__ __launch_bounds__(kBlock) void k_lv_pass1(DevProblem pb, const double
             n0 = call * 4;
             build_window<R>(pb, theta, L, n0);
             if constexpr (STORE) {
-                if (active) ckpt[(int64_t)(call / cps) * pb.P + p] = x;
+#pragma unroll
+                for (int i = 0; i < PPL; ++i)
+                    if (active[i]) ckpt[(int64_t)(call / cps) * pb.P + p[i]] = x[i];
             }
         }
-        R z[4];
-        normals4<R>((uint32_t)call, path, pb.inst, pb.k0, pb.k1, box_muller_scale<R>(1.0), z);
+        R z[PPL][4];
+#pragma unroll
+        for (int i = 0; i < PPL; ++i)
+            normals4<R>((uint32_t)call, (uint32_t)p[i], pb.inst, pb.k0, pb.k1, box_muller_scale<R>(1.0), z[i]);
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             const int n = call * 4 + j;
             if (n < pb.N) {
-                const R S = s0 * exp_t(x);
-                const Cell<R> c = locate<R>(pb, L.rows + (n - n0) * pb.nK, S, K0, invdK, Klast);
-                x = x + (rh - hh * c.sig * c.sig) + (sq * c.sig) * z[j];
+#pragma unroll
+                for (int i = 0; i < PPL; ++i) {
+                    const R S = s0 * exp_t(x[i]);
+                    const Cell<R> c = locate<R>(pb, L.rows + (n - n0) * pb.nK, S, K0, invdK, Klast);
+                    x[i] = x[i] + (rh - hh * c.sig * c.sig) + (sq * c.sig) * z[i][j];
+                }
                 if (n + 1 == next) {
-                    const double Sd = (double)(s0 * exp_t(x));
-                    payoff_sums(pb.strike, pb.disc, Sd, active, lane, pb.date_begin[d], pb.date_begin[d + 1],
-                                L.dbl + wave * pb.m);
+#pragma unroll
+                    for (int i = 0; i < PPL; ++i) {
+                        const double Sd = (double)(s0 * exp_t(x[i]));
+                        payoff_sums(pb.strike, pb.disc, Sd, active[i], lane, pb.date_begin[d], pb.date_begin[d + 1],
+                                    L.dbl + wave * pb.m, i > 0);
+                    }
                     ++d;
                     next = d < pb.ndates ? pb.date_step[d] : -1;
                 }
@@ -171,7 +190,9 @@ __device__ void flush_cell(const DevProblem &pb, LvLds<R> &L, int a)
     flush_slices(L.slices, 2 * pb.nK, L.dbl + a * pb.nK);
 }
 
-template <typename R, bool FROM_CKPT, int K>
+// Pass 2.  PPL paths per lane side by side, as in pass 1; their node
+// adjoints go to the lane's one column of slices, path 0 first at every step.
+template <typename R, bool FROM_CKPT, int K, int PPL>
 __global__ __launch_bounds__(kBlock) void k_lv_pass2(DevProblem pb, const double *__restrict__ theta,
                                                      const R *__restrict__ lamD, double *__restrict__ partial,
                                                      R *__restrict__ ckpt)
@@ -180,10 +201,13 @@ __global__ __launch_bounds__(kBlock) void k_lv_pass2(DevProblem pb, const double
     extern __shared__ __attribute__((aligned(16))) unsigned char lds_raw[];
     LvLds<R> L = carve<R>(pb, lds_raw, pb.nT * pb.nK);
     const int tid = threadIdx.x;
-    const int64_t p = (int64_t)blockIdx.x * kBlock + tid;
-    const bool active = p < pb.P;
-    const int64_t pc = active ? p : 0;
-    const uint32_t path = (uint32_t)p;
+    int64_t p[PPL];
+    bool active[PPL];
+#pragma unroll
+    for (int i = 0; i < PPL; ++i) {
+        p[i] = ((int64_t)blockIdx.x * PPL + i) * kBlock + tid;
+        active[i] = p[i] < pb.P;
+    }
     if constexpr (!FROM_CKPT) save_theta(pb, theta, blockIdx.x);
     for (int i = tid; i < pb.nT * pb.nK; i += kBlock) L.dbl[i] = 0.0;
     for (int i = tid; i < 2 * pb.nK * kBlock; i += kBlock) L.slices[i] = 0.f;
@@ -197,37 +221,52 @@ __global__ __launch_bounds__(kBlock) void k_lv_pass2(DevProblem pb, const double
 
     if constexpr (!FROM_CKPT) {
         // the forward re-run of the paper's step 2, storing every segment's start
-        R x = (R)0;
+        R x[PPL];
+#pragma unroll
+        for (int i = 0; i < PPL; ++i) x[i] = (R)0;
         const int ncalls = (pb.N + 3) / 4;
         int n0 = 0;
         for (int call = 0; call < ncalls; ++call) {
             if ((call * 4) % K == 0) {
                 n0 = call * 4;
                 build_window<R>(pb, theta, L, n0);
-                if (active) ckpt[(int64_t)(n0 / K) * pb.P + p] = x;
+#pragma unroll
+                for (int i = 0; i < PPL; ++i)
+                    if (active[i]) ckpt[(int64_t)(n0 / K) * pb.P + p[i]] = x[i];
             }
-            R z[4];
-            normals4<R>((uint32_t)call, path, pb.inst, pb.k0, pb.k1, box_muller_scale<R>(1.0), z);
+            R z[PPL][4];
+#pragma unroll
+            for (int i = 0; i < PPL; ++i)
+                normals4<R>((uint32_t)call, (uint32_t)p[i], pb.inst, pb.k0, pb.k1, box_muller_scale<R>(1.0), z[i]);
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
                 const int n = call * 4 + j;
                 if (n < pb.N) {
-                    const R S = s0 * exp_t(x);
-                    const Cell<R> c = locate<R>(pb, L.rows + (n - n0) * pb.nK, S, K0, invdK, Klast);
-                    x = x + (rh - hh * c.sig * c.sig) + (sq * c.sig) * z[j];
+#pragma unroll
+                    for (int i = 0; i < PPL; ++i) {
+                        const R S = s0 * exp_t(x[i]);
+                        const Cell<R> c = locate<R>(pb, L.rows + (n - n0) * pb.nK, S, K0, invdK, Klast);
+                        x[i] = x[i] + (rh - hh * c.sig * c.sig) + (sq * c.sig) * z[i][j];
+                    }
                 }
             }
         }
     }
 
-    R xb = (R)0;
+    R xb[PPL];
+#pragma unroll
+    for (int i = 0; i < PPL; ++i) xb[i] = (R)0;
     int cur_a = ldc(pb.step_row, pb.N - 1);
     int dhi = pb.ndates;
     float *my0 = L.slices + tid;   // this lane's column of the slices
+    const int rowB = pb.nK * kBlock;
     for (int seg = pb.nseg - 1; seg >= 0; --seg) {
         const int n0 = seg * K;
         build_window<R>(pb, theta, L, n0);
-        R x = active ? ckpt[(int64_t)seg * pb.P + pc] : (R)0;   // inactive lanes run a harmless path
+        R x[PPL];
+#pragma unroll
+        for (int i = 0; i < PPL; ++i)   // inactive lanes run a harmless path
+            x[i] = active[i] ? ckpt[(int64_t)seg * pb.P + (active[i] ? p[i] : 0)] : (R)0;
         int dlo = dhi;
         while (dlo > 0 && pb.date_step[dlo - 1] > n0) --dlo;
         int d = dlo;
@@ -236,47 +275,58 @@ __global__ __launch_bounds__(kBlock) void k_lv_pass2(DevProblem pb, const double
         // so that it reads no LDS but the slices it adds to:
         //   s_c = d x'/d sigma = -sigma h + sqrt(h) z,  s_d = d sigma/dS * S,
         //   the spot cell b and its weight be, the payoff adjoint injected
-        R s_c[K], s_d[K], s_be[K], s_inj[K];
-        int s_b[K];
-        R z[4];
+        R s_c[PPL][K], s_d[PPL][K], s_be[PPL][K], s_inj[PPL][K];
+        int s_b[PPL][K];
+        R z[PPL][4];
 #pragma unroll
         for (int j = 0; j < K; ++j) {
             const int n = n0 + j;
-            s_inj[j] = (R)0;
+#pragma unroll
+            for (int i = 0; i < PPL; ++i) s_inj[i][j] = (R)0;
             if (n < pb.N) {
-                if (j % 4 == 0) normals4<R>((uint32_t)(n / 4), path, pb.inst, pb.k0, pb.k1, box_muller_scale<R>(1.0), z);
-                const R S = s0 * exp_t(x);
-                const Cell<R> c = locate<R>(pb, L.rows + j * pb.nK, S, K0, invdK, Klast);
-                s_c[j] = -c.sig * h + sq * z[j % 4];
-                s_d[j] = (c.inside ? (c.r1 - c.r0) * invdK : (R)0) * S;
-                s_b[j] = c.b;
-                s_be[j] = c.be;
-                x = x + (rh - hh * c.sig * c.sig) + (sq * c.sig) * z[j % 4];
+                if (j % 4 == 0) {
+#pragma unroll
+                    for (int i = 0; i < PPL; ++i)
+                        normals4<R>((uint32_t)(n / 4), (uint32_t)p[i], pb.inst, pb.k0, pb.k1,
+                                    box_muller_scale<R>(1.0), z[i]);
+                }
+#pragma unroll
+                for (int i = 0; i < PPL; ++i) {
+                    const R S = s0 * exp_t(x[i]);
+                    const Cell<R> c = locate<R>(pb, L.rows + j * pb.nK, S, K0, invdK, Klast);
+                    s_c[i][j] = -c.sig * h + sq * z[i][j % 4];
+                    s_d[i][j] = (c.inside ? (c.r1 - c.r0) * invdK : (R)0) * S;
+                    s_b[i][j] = c.b;
+                    s_be[i][j] = c.be;
+                    x[i] = x[i] + (rh - hh * c.sig * c.sig) + (sq * c.sig) * z[i][j % 4];
+                }
                 if (n + 1 == next) {
-                    const R Sn = s0 * exp_t(x);
-                    R inj = (R)0;
-                    for (int k = pb.date_begin[d]; k < pb.date_begin[d + 1]; ++k)
-                        inj += Sn > strike_r[k] ? lamD[k] * Sn : (R)0;
-                    s_inj[j] = active ? inj : (R)0;
+#pragma unroll
+                    for (int i = 0; i < PPL; ++i) {
+                        const R Sn = s0 * exp_t(x[i]);
+                        R inj = (R)0;
+                        for (int k = pb.date_begin[d]; k < pb.date_begin[d + 1]; ++k)
+                            inj += Sn > strike_r[k] ? lamD[k] * Sn : (R)0;
+                        s_inj[i][j] = active[i] ? inj : (R)0;
+                    }
                     ++d;
                     next = d < dhi ? pb.date_step[d] : -1;
                 }
             }
         }
         dhi = dlo;
-        // one reverse step: the adjoint of x~ through step n0 + j, and the node
-        // adjoints of the step's spot cell into this lane's slices
-        auto reverse_step = [&](int j) {
-            xb += s_inj[j];
-            const R sbar = xb * s_c[j];
-            xb = xb + sbar * s_d[j];
+        // one reverse step of path i: the adjoint of x~ through step n0 + j; its
+        // four node adjoints (nodes b, b + 1 of rows a and a + 1) in u[0..3]
+        auto reverse_step = [&](int i, int j, float *u) {
+            xb[i] += s_inj[i][j];
+            const R sbar = xb[i] * s_c[i][j];
+            xb[i] = xb[i] + sbar * s_d[i][j];
             const R al = step_al<R>(pb, n0 + j);
-            const R w1 = sbar * s_be[j], w0 = sbar - w1;
-            float *col = my0 + s_b[j] * kBlock;
-            col[0] += (float)((1 - al) * w0);
-            col[kBlock] += (float)((1 - al) * w1);
-            col[pb.nK * kBlock] += (float)(al * w0);
-            col[(pb.nK + 1) * kBlock] += (float)(al * w1);
+            const R w1 = sbar * s_be[i][j], w0 = sbar - w1;
+            u[0] = (float)((1 - al) * w0);
+            u[1] = (float)((1 - al) * w1);
+            u[2] = (float)(al * w0);
+            u[3] = (float)(al * w1);
         };
         // the time cell of the segment's last step (cells do not decrease with n)
         const int a_last = ldc(pb.step_row, min(n0 + K, pb.N) - 1);
@@ -286,43 +336,44 @@ __global__ __launch_bounds__(kBlock) void k_lv_pass2(DevProblem pb, const double
         }
         if (n0 + K <= pb.N && ldc(pb.step_row, n0) == a_last) {
             // a whole segment in one time cell, without tests between the steps.
-            // The slice values a step adds to are read one step ahead, before
-            // the previous step's writes; where the two steps share a node the
+            // The slice values an update adds to are read one update ahead,
+            // before the previous update's writes; where the two share a node the
             // value just written is forwarded instead, so the LDS latency overlaps
-            // a step's arithmetic and the sums are exactly those of one step at a
-            // time.
-            const int rowB = pb.nK * kBlock;
-            float *col = my0 + s_b[K - 1] * kBlock;
+            // the arithmetic and the sums are exactly those of one update at a
+            // time (updates in the order: step K-1 path 0, path 1, ..., step 0).
+            float *col = my0 + s_b[0][K - 1] * kBlock;
             float r0 = col[0], r1 = col[kBlock], r2 = col[rowB], r3 = col[rowB + kBlock];
 #pragma unroll
             for (int j = K - 1; j >= 0; --j) {
-                xb += s_inj[j];
-                const R sbar = xb * s_c[j];
-                xb = xb + sbar * s_d[j];
-                const R al = step_al<R>(pb, n0 + j);
-                const R w1 = sbar * s_be[j], w0 = sbar - w1;
-                float q0 = 0.f, q1 = 0.f, q2 = 0.f, q3 = 0.f;
-                float *ncol = col;
-                if (j > 0) {   // the next step's slice values, before this step's writes
-                    ncol = my0 + s_b[j - 1] * kBlock;
-                    q0 = ncol[0];
-                    q1 = ncol[kBlock];
-                    q2 = ncol[rowB];
-                    q3 = ncol[rowB + kBlock];
-                }
-                const float v0 = r0 + (float)((1 - al) * w0), v1 = r1 + (float)((1 - al) * w1);
-                const float v2 = r2 + (float)(al * w0), v3 = r3 + (float)(al * w1);
-                col[0] = v0;
-                col[kBlock] = v1;
-                col[rowB] = v2;
-                col[rowB + kBlock] = v3;
-                if (j > 0) {
-                    const int b = s_b[j], bn = s_b[j - 1];
-                    r0 = bn == b ? v0 : (bn == b + 1 ? v1 : q0);
-                    r1 = bn == b ? v1 : (bn + 1 == b ? v0 : q1);
-                    r2 = bn == b ? v2 : (bn == b + 1 ? v3 : q2);
-                    r3 = bn == b ? v3 : (bn + 1 == b ? v2 : q3);
-                    col = ncol;
+#pragma unroll
+                for (int i = 0; i < PPL; ++i) {
+                    float u[4];
+                    reverse_step(i, j, u);
+                    const bool last = j == 0 && i == PPL - 1;
+                    const int inext = i + 1 < PPL ? i + 1 : 0;
+                    const int jnext = i + 1 < PPL ? j : j - 1;
+                    float q0 = 0.f, q1 = 0.f, q2 = 0.f, q3 = 0.f;
+                    float *ncol = col;
+                    if (!last) {   // the next update's slice values, before this update's writes
+                        ncol = my0 + s_b[inext][jnext] * kBlock;
+                        q0 = ncol[0];
+                        q1 = ncol[kBlock];
+                        q2 = ncol[rowB];
+                        q3 = ncol[rowB + kBlock];
+                    }
+                    const float v0 = r0 + u[0], v1 = r1 + u[1], v2 = r2 + u[2], v3 = r3 + u[3];
+                    col[0] = v0;
+                    col[kBlock] = v1;
+                    col[rowB] = v2;
+                    col[rowB + kBlock] = v3;
+                    if (!last) {
+                        const int b = s_b[i][j], bn = s_b[inext][jnext];
+                        r0 = bn == b ? v0 : (bn == b + 1 ? v1 : q0);
+                        r1 = bn == b ? v1 : (bn + 1 == b ? v0 : q1);
+                        r2 = bn == b ? v2 : (bn == b + 1 ? v3 : q2);
+                        r3 = bn == b ? v3 : (bn + 1 == b ? v2 : q3);
+                        col = ncol;
+                    }
                 }
             }
         } else {
@@ -335,7 +386,16 @@ __global__ __launch_bounds__(kBlock) void k_lv_pass2(DevProblem pb, const double
                         flush_cell<R>(pb, L, cur_a);
                         cur_a = a;
                     }
-                    reverse_step(j);
+#pragma unroll
+                    for (int i = 0; i < PPL; ++i) {
+                        float u[4];
+                        reverse_step(i, j, u);
+                        float *col = my0 + s_b[i][j] * kBlock;
+                        col[0] += u[0];
+                        col[kBlock] += u[1];
+                        col[rowB] += u[2];
+                        col[rowB + kBlock] += u[3];
+                    }
                 }
             }
         }
@@ -345,42 +405,64 @@ __global__ __launch_bounds__(kBlock) void k_lv_pass2(DevProblem pb, const double
     for (int i = tid; i < M; i += kBlock) partial[(int64_t)i * gridDim.x + blockIdx.x] = L.dbl[i];
 }
 
-template <typename R>
-hipError_t pass1_t(const DevProblem &pb, bool store, const double *theta, double *partial, void *ckpt, int64_t nb,
+template <typename R, int PPL>
+hipError_t pass1_p(const DevProblem &pb, bool store, const double *theta, double *partial, void *ckpt, int64_t nb,
                    hipStream_t st)
 {
     const size_t lds = lv_lds_bytes(pb, sizeof(R) == 8, 1);
     if (store)
-        hipLaunchKernelGGL((k_lv_pass1<R, true>), dim3((unsigned)nb), dim3(kBlock), lds, st, pb, theta, partial,
+        hipLaunchKernelGGL((k_lv_pass1<R, true, PPL>), dim3((unsigned)nb), dim3(kBlock), lds, st, pb, theta, partial,
                            (R *)ckpt);
     else
-        hipLaunchKernelGGL((k_lv_pass1<R, false>), dim3((unsigned)nb), dim3(kBlock), lds, st, pb, theta, partial,
-                           (R *)ckpt);
+        hipLaunchKernelGGL((k_lv_pass1<R, false, PPL>), dim3((unsigned)nb), dim3(kBlock), lds, st, pb, theta,
+                           partial, (R *)ckpt);
     return hipGetLastError();
 }
 
-template <typename R, int K>
+template <typename R>
+hipError_t pass1_t(const DevProblem &pb, bool store, const double *theta, double *partial, void *ckpt, int64_t nb,
+                   hipStream_t st)
+{
+    switch (pb.ppl) {
+    case 1: return pass1_p<R, 1>(pb, store, theta, partial, ckpt, nb, st);
+    case 2: return pass1_p<R, 2>(pb, store, theta, partial, ckpt, nb, st);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+template <typename R, int K, int PPL>
 hipError_t pass2_k(const DevProblem &pb, bool from_ckpt, const double *theta, const void *lamD, double *partial,
                    void *ckpt, int64_t nb, hipStream_t st)
 {
     const size_t lds = lv_lds_bytes(pb, sizeof(R) == 8, 2);
     if (from_ckpt)
-        hipLaunchKernelGGL((k_lv_pass2<R, true, K>), dim3((unsigned)nb), dim3(kBlock), lds, st, pb, theta,
+        hipLaunchKernelGGL((k_lv_pass2<R, true, K, PPL>), dim3((unsigned)nb), dim3(kBlock), lds, st, pb, theta,
                            (const R *)lamD, partial, (R *)ckpt);
     else
-        hipLaunchKernelGGL((k_lv_pass2<R, false, K>), dim3((unsigned)nb), dim3(kBlock), lds, st, pb, theta,
+        hipLaunchKernelGGL((k_lv_pass2<R, false, K, PPL>), dim3((unsigned)nb), dim3(kBlock), lds, st, pb, theta,
                            (const R *)lamD, partial, (R *)ckpt);
     return hipGetLastError();
+}
+
+template <typename R, int PPL>
+hipError_t pass2_p(const DevProblem &pb, bool from_ckpt, const double *theta, const void *lamD, double *partial,
+                   void *ckpt, int64_t nb, hipStream_t st)
+{
+    switch (pb.K) {
+    case 8: return pass2_k<R, 8, PPL>(pb, from_ckpt, theta, lamD, partial, ckpt, nb, st);
+    case 16: return pass2_k<R, 16, PPL>(pb, from_ckpt, theta, lamD, partial, ckpt, nb, st);
+    case 32: return pass2_k<R, 32, PPL>(pb, from_ckpt, theta, lamD, partial, ckpt, nb, st);
+    default: return hipErrorInvalidValue;
+    }
 }
 
 template <typename R>
 hipError_t pass2_t(const DevProblem &pb, bool from_ckpt, const double *theta, const void *lamD, double *partial,
                    void *ckpt, int64_t nb, hipStream_t st)
 {
-    switch (pb.K) {
-    case 8: return pass2_k<R, 8>(pb, from_ckpt, theta, lamD, partial, ckpt, nb, st);
-    case 16: return pass2_k<R, 16>(pb, from_ckpt, theta, lamD, partial, ckpt, nb, st);
-    case 32: return pass2_k<R, 32>(pb, from_ckpt, theta, lamD, partial, ckpt, nb, st);
+    switch (pb.ppl) {
+    case 1: return pass2_p<R, 1>(pb, from_ckpt, theta, lamD, partial, ckpt, nb, st);
+    case 2: return pass2_p<R, 2>(pb, from_ckpt, theta, lamD, partial, ckpt, nb, st);
     default: return hipErrorInvalidValue;
     }
 }

@@ -114,7 +114,8 @@ def test_paths_per_lane_validation(L):
         assert rc == capi.CAL_EINVAL and "paths_per_lane" in msg
     lv = W.lv_problem(n_paths=1024)[0]
     assert capi.cal_validate(lv, paths_per_lane=1)[0] == capi.CAL_OK
-    assert capi.cal_validate(lv, paths_per_lane=2)[0] == capi.CAL_EUNSUPPORTED
+    assert capi.cal_validate(lv, paths_per_lane=2)[0] == capi.CAL_OK
+    assert capi.cal_validate(lv, paths_per_lane=4)[0] == capi.CAL_EUNSUPPORTED
     slv = W.slv_problem(n_paths=1024)[0]
     assert capi.cal_validate(slv, paths_per_lane=4)[0] == capi.CAL_OK
     assert capi.cal_validate(slv.with_(n_params=204))[0] == capi.CAL_EINVAL

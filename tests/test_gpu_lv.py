@@ -132,6 +132,28 @@ def test_autograd_two_forwards_then_backward(lv_small):
     mc.close()
 
 
+@pytest.mark.parametrize("k", [8, 16])
+def test_lv_two_paths_per_lane(orc, k):
+    """Two paths side by side per lane (a ragged last workgroup of 512
+    paths): against the oracle in both precisions; store and re-run modes give
+    the same gradient bit for bit."""
+    pb, g0, gt, eps, _ = W.lv_problem(n_paths=3 * 512 + 77, n_steps=72, n_t=4, n_k=6)
+    C = np.linspace(2.0, 9.0, pb.n_instr)
+    Eo, Go, go = orc.gradient(pb, g0, C)
+    for prec, tol_y, tol_g in (("fp64", 1e-12, 1e-6), ("fp32", 1e-5, 1e-4)):
+        res = {}
+        for mode in ("store", "rerun"):
+            mc = MonteCarloCalibration(pb, precision=prec, ckpt_every=k, ckpt_mode=mode, paths_per_lane=2)
+            Ey, G, g = mc.gradient(g0, C)
+            assert mc.status() == 0
+            mc.close()
+            res[mode] = (Ey.cpu().numpy(), g.cpu().numpy())
+        say(f"  lv ppl=2 K={k} {prec}: Ey {ey_err(res['store'][0], Eo):.2e} grad {g_err(res['store'][1], go):.2e}")
+        assert ey_err(res["store"][0], Eo) <= tol_y
+        assert g_err(res["store"][1], go) <= tol_g
+        np.testing.assert_array_equal(res["store"][1], res["rerun"][1])
+
+
 def test_memory_budget_picks_spacing():
     pb = W.lv_problem()[0]     # 2^22 paths x 256 steps, one state variable
     assert AG.checkpoint_bytes(pb, "fp32", 16) == 16 * (1 << 22) * 4
