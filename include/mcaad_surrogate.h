@@ -50,7 +50,12 @@ int mlp_set_scaling(mlp_ctx *ctx, const float *d_in_shift, const float *d_in_sca
                     const float *d_out_scale, void *stream);
 
 /* Inference: d_theta [B x n_in] -> d_Y [B x n_out] prices and
- * d_J [B x n_out x n_in], J[b][i][j] = dy_i/dtheta_j.  B in 1..max_batch. */
+ * d_J [B x n_out x n_in], J[b][i][j] = dy_i/dtheta_j.  B in 1..max_batch.
+ * Batches of at most 64 samples (with n_in <= 8) run in one launch, one
+ * workgroup per sample; larger ones as products over the whole batch.  Both
+ * take the same MFMA products of the same bf16 operands in the same order and
+ * the same elementwise arithmetic, so a sample's outputs do not depend on the
+ * size of the batch it is evaluated in. */
 int mlp_forward(mlp_ctx *ctx, const float *d_theta, int32_t B, float *d_Y, float *d_J, void *stream);
 
 /* Loss and its gradient for one batch: with z the network output and zl, jl
@@ -58,7 +63,7 @@ int mlp_forward(mlp_ctx *ctx, const float *d_theta, int32_t B, float *d_Y, float
  * jl_ij = dy_i/dtheta_j / (out_scale_i in_scale_j)),
  *   L = mean_{b,i} (z - zl)^2 + w mean_{b,i,j} (dz_i/dx_j - jl_ij)^2.
  * Labels are given in price units: d_Ylab [B x n_out], d_Jlab
- * [B x n_out x n_in].  B must be a multiple of 64.  d_loss[1] (FP64) and
+ * [B x n_out x n_in].  B must be a multiple of 128.  d_loss[1] (FP64) and
  * d_grad [num_params] (FP32, packed like the parameters) are written. */
 int mlp_loss_grad(mlp_ctx *ctx, const float *d_theta, const float *d_Ylab, const float *d_Jlab, int32_t B,
                   float w, double *d_loss, float *d_grad, void *stream);

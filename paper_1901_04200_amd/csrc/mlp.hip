@@ -465,6 +465,203 @@ __global__ __launch_bounds__(kThreads) void k_calib_grad(const float *__restrict
     }
 }
 
+// ---------------------------------------------------------------------------
+// Small batches: one workgroup per sample runs the whole evaluation (the four
+// layers with the sample's primal row and n_in tangent rows, the outputs in
+// price units and, given targets, the calibration functional), so that a
+// calibration iteration on one parameter vector is one launch instead of
+// nine.  The layer products are the batched path's: the same MFMA
+// (v_mfma_f32_32x32x16_bf16) on the same bf16 operands, accumulated over k in
+// the same order from zero, and each product row depends on its own operand
+// row only, so a sample's pre-activations do not depend on the batch it came
+// in; the elementwise work is that of the batched kernels.  NR = n_in + 1
+// operand rows in LDS (bf16, row stride H + 8), padded to the MFMA's 32 rows
+// with a row of zeros.
+// ---------------------------------------------------------------------------
+constexpr int kSmallMaxB = 64;       // batches up to this size take the one-launch path
+constexpr int kSmallMaxRows = 9;     // n_in <= 8
+constexpr int kSmallThreads = 512;   // 8 waves: one 32-column tile each at H = 256
+constexpr int kSmallSteps = 16;      // k-steps whose B operands are loaded at once
+constexpr int kSmallUnits = 2;       // hidden units per thread (n_hidden <= 1024)
+
+// B operands (16 bytes per lane and k-step) of the first kSmallSteps k-steps
+// of this wave's first tile of z = act WT^T (N columns, K = k extent); issued
+// early so that their latency overlaps the work before the product.
+__device__ __forceinline__ void small_prefetch(const uint16_t *__restrict__ WT, int N, int K, bf16x8 *bv)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int n0 = wave * 32;
+    if (n0 >= N) return;
+    const uint16_t *brow = WT + (int64_t)(n0 + (lane & 31)) * K + 8 * (lane >> 5);
+    const int steps = min(kSmallSteps, K / 16);
+#pragma unroll
+    for (int q = 0; q < kSmallSteps; ++q)
+        if (q < steps) bv[q] = *(const bf16x8 *)(brow + 16 * q);
+}
+
+// z[row][n] (row < NR, n < N) = sum_k act[row][k] WT[n][k] over k < K, N a
+// multiple of 32: wave w takes the 32-column tiles w, w + 8, ...  act: LDS
+// bf16 rows of stride lda, row NR all zeros.  bv holds small_prefetch's
+// operands for this product.
+template <int NR>
+__device__ __forceinline__ void small_product(const uint16_t *act, int lda, const uint16_t *__restrict__ WT, int N,
+                                              int K, float *z, int ldz, bf16x8 *bv)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int r = lane & 31, kofs = 8 * (lane >> 5);
+    const uint16_t *arow = act + (r < NR ? r : NR) * lda + kofs;
+    bool loaded = true;
+    for (int n0 = wave * 32; n0 < N; n0 += (kSmallThreads / 64) * 32) {
+        const uint16_t *brow = WT + (int64_t)(n0 + r) * K + kofs;
+        f32x16 acc;
+#pragma unroll
+        for (int i = 0; i < 16; ++i) acc[i] = 0.f;
+        for (int k0 = 0; k0 < K; k0 += 16 * kSmallSteps) {
+            const int steps = min(kSmallSteps, (K - k0) / 16);
+            if (!loaded) {
+#pragma unroll
+                for (int q = 0; q < kSmallSteps; ++q)
+                    if (q < steps) bv[q] = *(const bf16x8 *)(brow + k0 + 16 * q);
+            }
+            loaded = false;
+#pragma unroll
+            for (int q = 0; q < kSmallSteps; ++q)
+                if (q < steps) {
+                    const bf16x8 a = *(const bf16x8 *)(arow + k0 + 16 * q);
+                    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bv[q], acc, 0, 0, 0);
+                }
+        }
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            const int row = (i >> 2) * 8 + (lane >> 5) * 4 + (i & 3);
+            if (row < NR) z[row * ldz + n0 + r] = acc[i];
+        }
+    }
+}
+
+// Bias, SiLU and tangents of a hidden layer, as k_act_fwd: act[0] = SiLU(z0 +
+// bias), act[q] = SiLU'(z0 + bias) z[q]; bias[u] is that of this thread's
+// unit t + u kSmallThreads.
+template <int NR>
+__device__ __forceinline__ void small_activate(const float *z, const float *bias, int H, uint16_t *act, int lda)
+{
+#pragma unroll
+    for (int u = 0; u < kSmallUnits; ++u) {
+        const int j = threadIdx.x + u * kSmallThreads;
+        if (j >= H) break;
+        const float zz = z[j] + bias[u];
+        const float s = sigm(zz);
+        const float d1 = s * (1.f + zz * (1.f - s));
+        act[j] = f2bf(zz * s);
+        for (int q = 1; q < NR; ++q) act[q * lda + j] = f2bf(d1 * z[q * H + j]);
+    }
+}
+
+template <int NR>
+__global__ __launch_bounds__(kSmallThreads) void k_small_eval(
+    const float *__restrict__ th, int H, int nout, const float *__restrict__ in_shift,
+    const float *__restrict__ in_scale, const float *__restrict__ W1, const float *__restrict__ b1,
+    const uint16_t *__restrict__ WT2, const float *__restrict__ b2, const uint16_t *__restrict__ WT3,
+    const float *__restrict__ b3, const uint16_t *__restrict__ WT4, const float *__restrict__ b4,
+    const float *__restrict__ out_shift, const float *__restrict__ out_scale, const double *__restrict__ C,
+    float *__restrict__ Y, float *__restrict__ J, double *__restrict__ G, double *__restrict__ grad)
+{
+    constexpr int nin = NR - 1;
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+    const int lda = H + 8;
+    uint16_t *act = (uint16_t *)smem;                          // [NR + 1][lda] bf16
+    float *z = (float *)(smem + (size_t)(NR + 1) * lda * 2);   // [NR][H] FP32
+    __shared__ float xs[nin];
+    __shared__ float ys[kOutPad];
+    __shared__ float js[kOutPad * nin];
+    __shared__ double r[kOutPad];
+    __shared__ float o_b[kOutPad], o_scale[kOutPad], o_shift[kOutPad], i_scale[nin];
+    __shared__ double cs[kOutPad];
+    const int b = blockIdx.x, t = threadIdx.x;
+    // everything the sample needs from memory but the output layer's weights
+    // and later batches of wider layers, requested at once
+    bf16x8 bv2[kSmallSteps], bv3[kSmallSteps];
+    small_prefetch(WT2, H, H, bv2);
+    small_prefetch(WT3, H, H, bv3);
+    float w1[kSmallUnits][NR], bias2[kSmallUnits], bias3[kSmallUnits];
+#pragma unroll
+    for (int u = 0; u < kSmallUnits; ++u) {
+        const int j = t + u * kSmallThreads;
+        if (j < H) {
+            w1[u][0] = b1[j];
+#pragma unroll
+            for (int k = 0; k < nin; ++k) w1[u][k + 1] = W1[k * H + j];
+            bias2[u] = b2[j];
+            bias3[u] = b3[j];
+        }
+    }
+    if (t < nin) {
+        xs[t] = (th[b * nin + t] - in_shift[t]) * in_scale[t];
+        i_scale[t] = in_scale[t];
+    }
+    if (t < nout) {
+        o_b[t] = b4[t];
+        o_scale[t] = out_scale[t];
+        o_shift[t] = out_shift[t];
+        if (C) cs[t] = C[t];
+    }
+    for (int i = t; i < H; i += kSmallThreads) act[NR * lda + i] = 0;
+    __syncthreads();
+    // layer 1 (n_in -> H), as k_l1_fwd: the tangent pre-activations are the rows of W1
+#pragma unroll
+    for (int u = 0; u < kSmallUnits; ++u) {
+        const int j = t + u * kSmallThreads;
+        if (j >= H) break;
+        float zz = w1[u][0];
+        for (int k = 0; k < nin; ++k) zz += xs[k] * w1[u][k + 1];
+        const float s = sigm(zz);
+        const float d1 = s * (1.f + zz * (1.f - s));
+        act[j] = f2bf(zz * s);
+#pragma unroll
+        for (int q = 1; q < NR; ++q) act[q * lda + j] = f2bf(d1 * w1[u][q]);
+    }
+    __syncthreads();
+    // hidden layers 2, 3
+    small_product<NR>(act, lda, WT2, H, H, z, H, bv2);
+    bf16x8 *bv4 = bv2;   // free again: the output layer's first operands
+    small_prefetch(WT4, kOutPad, H, bv4);
+    __syncthreads();
+    small_activate<NR>(z, bias2, H, act, lda);
+    __syncthreads();
+    small_product<NR>(act, lda, WT3, H, H, z, H, bv3);
+    __syncthreads();
+    small_activate<NR>(z, bias3, H, act, lda);
+    __syncthreads();
+    // output layer (units padded to kOutPad; WT4's padding rows are zero), as k_out_fwd
+    small_product<NR>(act, lda, WT4, kOutPad, H, z, kOutPad, bv4);
+    __syncthreads();
+    for (int q = t; q < NR * nout; q += kSmallThreads) {
+        const int row = q / nout, o = q % nout;
+        const float v = z[row * kOutPad + o];
+        if (row == 0) ys[o] = (v + o_b[o]) * o_scale[o] + o_shift[o];
+        else js[o * nin + row - 1] = v * o_scale[o] * i_scale[row - 1];
+    }
+    __syncthreads();
+    for (int q = t; q < nout * (nin + 1); q += kSmallThreads) {
+        if (q < nout) Y[(int64_t)b * nout + q] = ys[q];
+        else J[(int64_t)b * nout * nin + (q - nout)] = js[q - nout];
+    }
+    if (!C) return;   // uniform: inference only
+    // the calibration functional, as k_calib_grad
+    if (t < nout) r[t] = (double)ys[t] - cs[t];
+    __syncthreads();
+    if (t == 0) {
+        double sacc = 0.0;
+        for (int i = 0; i < nout; ++i) sacc += 0.5 * r[i] * r[i];
+        G[b] = sacc;
+    }
+    if (t < nin) {
+        double sacc = 0.0;
+        for (int i = 0; i < nout; ++i) sacc += (double)js[i * nin + t] * r[i];
+        grad[(int64_t)b * nin + t] = sacc;
+    }
+}
+
 __global__ void k_fill(float *p, int64_t n, float v)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -689,11 +886,54 @@ static hipError_t forward_core(mlp_ctx *c, int Bp, hipStream_t st)
     return e;
 }
 
+// Dynamic LDS of k_small_eval: NR + 1 bf16 operand rows of stride H + 8 and
+// NR FP32 rows of pre-activations.
+static size_t small_lds(int NR, int H) { return (size_t)(NR + 1) * (H + 8) * 2 + (size_t)NR * H * 4; }
+
+// Whether a batch of B samples takes the one-launch path (k_small_eval).
+static bool small_path(const mlp_ctx *c, int B)
+{
+    return B <= kSmallMaxB && c->nin + 1 <= kSmallMaxRows && c->H <= kSmallUnits * kSmallThreads &&
+           small_lds(c->nin + 1, c->H) <= 60 * 1024;
+}
+
+template <int NR>
+static void launch_small_t(const mlp_ctx *c, const float *th, int B, const double *C, float *Y, float *J, double *G,
+                           double *grad, hipStream_t st)
+{
+    const size_t lds = small_lds(NR, c->H);
+    const float *p = c->p;
+    hipLaunchKernelGGL((k_small_eval<NR>), dim3((unsigned)B), dim3(kSmallThreads), lds, st, th, c->H, c->nout, c->in_shift,
+                       c->in_scale, p + c->off[0], p + c->off[1], c->WT[1], p + c->off[3], c->WT[2], p + c->off[5],
+                       c->WT[3], p + c->off[7], c->out_shift, c->out_scale, C, Y, J, G, grad);
+}
+
+static hipError_t launch_small(const mlp_ctx *c, const float *th, int B, const double *C, float *Y, float *J,
+                               double *G, double *grad, hipStream_t st)
+{
+    switch (c->nin + 1) {
+    case 2: launch_small_t<2>(c, th, B, C, Y, J, G, grad, st); break;
+    case 3: launch_small_t<3>(c, th, B, C, Y, J, G, grad, st); break;
+    case 4: launch_small_t<4>(c, th, B, C, Y, J, G, grad, st); break;
+    case 5: launch_small_t<5>(c, th, B, C, Y, J, G, grad, st); break;
+    case 6: launch_small_t<6>(c, th, B, C, Y, J, G, grad, st); break;
+    case 7: launch_small_t<7>(c, th, B, C, Y, J, G, grad, st); break;
+    case 8: launch_small_t<8>(c, th, B, C, Y, J, G, grad, st); break;
+    case 9: launch_small_t<9>(c, th, B, C, Y, J, G, grad, st); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
 extern "C" int mlp_forward(mlp_ctx *c, const float *d_theta, int32_t B, float *d_Y, float *d_J, void *stream)
 {
     if (!c || !d_theta || !d_Y || !d_J) return mfail(c, -1, "null argument");
     if (B < 1 || B > c->Bmax) return mfail(c, -1, "batch outside 1..max_batch");
     hipStream_t st = (hipStream_t)stream;
+    if (small_path(c, B)) {
+        const hipError_t e = launch_small(c, d_theta, B, nullptr, d_Y, d_J, nullptr, nullptr, st);
+        return e == hipSuccess ? 0 : mfail(c, -3, hipGetErrorString(e));
+    }
     const int Bp = (B + 127) / 128 * 128;
     hipLaunchKernelGGL(k_normalize, dim3(nb((int64_t)Bp * c->nin)), dim3(kThreads), 0, st, d_theta, B, Bp, c->nin,
                        c->in_shift, c->in_scale, c->Xn);
@@ -775,6 +1015,10 @@ extern "C" int mlp_adam_step(mlp_ctx *c, const float *d_grad, float lr, float be
 extern "C" int mlp_calibration_gradient(mlp_ctx *c, const float *d_theta, int32_t B, const double *d_C, float *d_Y,
                                         float *d_J, double *d_G, double *d_grad, void *stream)
 {
+    if (c && d_theta && d_Y && d_J && d_C && d_G && d_grad && B >= 1 && B <= c->Bmax && small_path(c, B)) {
+        const hipError_t e = launch_small(c, d_theta, B, d_C, d_Y, d_J, d_G, d_grad, (hipStream_t)stream);
+        return e == hipSuccess ? 0 : mfail(c, -3, hipGetErrorString(e));
+    }
     int rc = mlp_forward(c, d_theta, B, d_Y, d_J, stream);
     if (rc) return rc;
     if (!d_C || !d_G || !d_grad) return mfail(c, -1, "null argument");

@@ -139,14 +139,28 @@ class MLP:
         self._check(lib().mlp_forward(self.ctx, _ptr(th), B, _ptr(Y), _ptr(J), _stream()))
         return Y, J
 
-    def calibration_gradient(self, theta, C):
-        """theta [B, n_in] FP32, C [n_out] FP64 (device) -> G [B], grad [B, n_in] (FP64)."""
+    def calibration_buffers(self, B: int):
+        """Output tensors (Y, J, G, grad) for calibration_gradient(..., out=)
+        on batches of B parameter vectors, for loops that evaluate again and
+        again without allocating."""
+        t, dev = self.torch, self.dev
+        return (t.empty(B, self.n_out, dtype=t.float32, device=dev),
+                t.empty(B, self.n_out, self.n_in, dtype=t.float32, device=dev),
+                t.empty(B, dtype=t.float64, device=dev), t.empty(B, self.n_in, dtype=t.float64, device=dev))
+
+    def calibration_gradient(self, theta, C, out=None):
+        """theta [B, n_in] FP32, C [n_out] FP64 (device) -> G [B], grad [B, n_in]
+        (FP64); out: tensors from calibration_buffers(B), written and returned
+        instead of new ones."""
         th = theta.contiguous()
         B = th.shape[0]
-        Y = self.torch.empty(B, self.n_out, dtype=self.torch.float32, device=self.dev)
-        J = self.torch.empty(B, self.n_out, self.n_in, dtype=self.torch.float32, device=self.dev)
-        G = self.torch.empty(B, dtype=self.torch.float64, device=self.dev)
-        g = self.torch.empty(B, self.n_in, dtype=self.torch.float64, device=self.dev)
+        Y, J, G, g = out if out is not None else self.calibration_buffers(B)
+        t = self.torch
+        want = ((Y, (B, self.n_out), t.float32), (J, (B, self.n_out, self.n_in), t.float32), (G, (B,), t.float64),
+                (g, (B, self.n_in), t.float64))
+        for x, shape, dt in want:
+            if tuple(x.shape) != shape or x.dtype != dt or not x.is_contiguous() or x.device != th.device:
+                raise ValueError("output buffers must be those of calibration_buffers(B) for this batch")
         self._check(lib().mlp_calibration_gradient(self.ctx, _ptr(th), B, _ptr(C.contiguous()), _ptr(Y), _ptr(J),
                                                    _ptr(G), _ptr(g), _stream()))
         return G, g

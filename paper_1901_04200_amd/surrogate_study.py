@@ -129,9 +129,10 @@ def run(n_train=1 << 14, train_paths=1 << 14, n_heldout=32, ref_paths=1 << 24, e
 
     # ---- 5. step costs ------------------------------------------------------
     th1 = torch.as_tensor(ho[:1], dtype=torch.float32, device="cuda")
+    bufs = net.calibration_buffers(1)
 
     def sur_step():
-        net.calibration_gradient(th1, C)
+        net.calibration_gradient(th1, C, out=bufs)
 
     t_sur = _time_call(sur_step, 50)
     P_time = max(256, p_star)

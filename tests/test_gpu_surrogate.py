@@ -74,6 +74,49 @@ def test_forward_and_jacobian(H, nout, B):
     net.close()
 
 
+@pytest.mark.parametrize("nin,H,nout,B", [(5, 1024, 40, 3), (8, 128, 7, 2), (9, 128, 7, 2), (1, 128, 3, 64)])
+def test_forward_shapes_against_oracle(nin, H, nout, B):
+    """Both evaluation paths (one launch per call for small batches with
+    n_in <= 8, the GEMM path otherwise) against the oracle."""
+    say(f"mlp forward n_in={nin} H={H} n_out={nout} B={B}")
+    net = S.MLP(nin, H, nout, max_batch=128)
+    params = rand_params([nin, H, H, H, nout], 11)
+    net.set_params(net.pack(params))
+    X = np.random.default_rng(12).uniform(-1, 1, (B, nin)).astype(np.float32)
+    Y, J = net.forward(torch.as_tensor(X, device="cuda"))
+    Yo, Jo = MO.forward_tangent(device_view(params), X.astype(np.float64))
+    ey = np.max(np.abs(Y.cpu().numpy() - Yo)) / np.max(np.abs(Yo))
+    ej = np.max(np.abs(J.cpu().numpy() - Jo)) / np.max(np.abs(Jo))
+    say(f"  rel err Y {ey:.2e} J {ej:.2e}")
+    assert ey < 2e-2 and ej < 2e-2
+    net.close()
+
+
+@pytest.mark.parametrize("H,nout", [(128, 7), (256, 40)])
+def test_small_batches_match_the_gemm_path(H, nout):
+    """A sample evaluated in a batch of 1 or 64 (one launch) and in a batch of
+    200 (GEMMs): the same MFMA products on the same bf16 operands, summed over
+    k in the same order, and the same elementwise arithmetic, so the outputs,
+    the functional and its gradient are bitwise the same."""
+    net = S.MLP(5, H, nout, max_batch=256)
+    net.set_params(net.pack(rand_params([5, H, H, H, nout], 13)))
+    X = torch.as_tensor(np.random.default_rng(14).uniform(-1, 1, (200, 5)), dtype=torch.float32, device="cuda")
+    C = torch.linspace(-1.0, 1.0, nout, dtype=torch.float64, device="cuda")
+    Yb, Jb = net.forward(X)
+    Gb, gb = net.calibration_gradient(X, C)
+    Yb, Jb, Gb, gb = (t.cpu().numpy() for t in (Yb, Jb, Gb, gb))
+    for B in (1, 64):
+        Ys, Js = net.forward(X[:B])
+        Gs, gs = net.calibration_gradient(X[:B], C)
+        Ys, Js, Gs, gs = (t.cpu().numpy() for t in (Ys, Js, Gs, gs))
+        ey = np.max(np.abs(Ys - Yb[:B])) / np.max(np.abs(Yb[:B]))
+        ej = np.max(np.abs(Js - Jb[:B])) / np.max(np.abs(Jb[:B]))
+        say(f"  H={H} B={B}: small vs GEMM path, rel diff Y {ey:.1e} J {ej:.1e}")
+        for a, c in ((Ys, Yb[:B]), (Js, Jb[:B]), (Gs, Gb[:B]), (gs, gb[:B])):
+            np.testing.assert_array_equal(a, c)
+    net.close()
+
+
 def test_scaling_maps_units():
     net = S.MLP(5, 128, 7, max_batch=128)
     params = rand_params([5, 128, 128, 128, 7], 3)
@@ -149,6 +192,17 @@ def test_calibration_gradient_kernel():
     np.testing.assert_allclose(G.cpu().numpy(), 0.5 * np.sum(r * r, axis=1), rtol=1e-12)
     np.testing.assert_allclose(g.cpu().numpy(), np.einsum("bij,bi->bj", J.double().cpu().numpy(), r), rtol=1e-10,
                                atol=1e-12)
+    # into preallocated buffers: the same values, twice in a row
+    bufs = net.calibration_buffers(9)
+    for _ in range(2):
+        G2, g2 = net.calibration_gradient(th, C, out=bufs)
+        assert G2.data_ptr() == bufs[2].data_ptr() and g2.data_ptr() == bufs[3].data_ptr()
+        assert torch.equal(G2, G) and torch.equal(g2, g)
+    with pytest.raises(ValueError):
+        net.calibration_gradient(th, C, out=net.calibration_buffers(8))
+    Y8, J8, G8, g8 = net.calibration_buffers(9)
+    with pytest.raises(ValueError):
+        net.calibration_gradient(th, C, out=(Y8, J8, G8.float(), g8))
     net.close()
 
 
