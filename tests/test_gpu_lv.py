@@ -154,6 +154,24 @@ def test_lv_two_paths_per_lane(orc, k):
         np.testing.assert_array_equal(res["store"][1], res["rerun"][1])
 
 
+def test_lv_edge_shapes(orc):
+    """The smallest grid (2 x 2: one cell, most paths leave its spot range
+    and take the flat extrapolation), a single path, segment ends that are
+    not a multiple of the spacing, a call maturing at the first step, one
+    and two paths per lane; FP64, store and re-run modes."""
+    for n_t, n_k, P, N, k, ppl in ((2, 2, 1, 21, 8, 1), (3, 5, 63, 37, 16, 2), (2, 4, 257, 50, 32, 1)):
+        pb, g0, gt, eps, _ = W.lv_problem(n_paths=P, n_steps=N, n_t=n_t, n_k=n_k)
+        pb = pb.with_(instr_step=np.concatenate([[1], pb.instr_step[1:]]).astype(np.int32))
+        C = np.linspace(2.0, 9.0, pb.n_instr)
+        Eo, Go, go = orc.gradient(pb, g0, C)
+        for mode in ("store", "rerun"):
+            say(f"  lv edge nT={n_t} nK={n_k} P={P} N={N} K={k} ppl={ppl} {mode}")
+            Ey_f, Ey, G, g = run(pb, g0, C, "fp64", ckpt_every=k, ckpt_mode=mode, paths_per_lane=ppl)
+            say(f"    Ey {ey_err(Ey, Eo):.2e} grad {g_err(g, go):.2e}")
+            assert ey_err(Ey_f, Eo) <= 1e-12 and ey_err(Ey, Eo) <= 1e-12
+            assert g_err(g, go) <= 1e-6
+
+
 def test_memory_budget_picks_spacing():
     pb = W.lv_problem()[0]     # 2^22 paths x 256 steps, one state variable
     assert AG.checkpoint_bytes(pb, "fp32", 16) == 16 * (1 << 22) * 4
