@@ -27,6 +27,16 @@ typedef __attribute__((ext_vector_type(16))) float f32x16;
 
 constexpr int kThreads = 256;
 constexpr int BM = 128, BN = 64, BK = 32, LDK = BK + 8;   // LDS row stride 80 bytes
+constexpr int LDT = 64;                                   // transposed operands: 128-byte rows
+
+// LDS element index of (row, k) for an operand staged with k contiguous (KC)
+// or transposed on the way in (k < BK; a k-aligned group of 8 stays contiguous).
+template <bool KC>
+__device__ __forceinline__ int lds_idx(int row, int k)
+{
+    if constexpr (KC) return row * LDK + k;
+    else return row * LDT + ((k + 8 * ((row + (row >> 3)) & 7)) & (LDT - 1));
+}
 constexpr int kOutPad = 64;                               // output units padded to one N tile
 constexpr int kMaxSplits = 64;
 
@@ -47,10 +57,17 @@ __device__ __forceinline__ float sigm(float z) { return 1.0f / (1.0f + __expf(-z
 // Tiles 128 x 64 x 32; wave w owns rows 32w..32w+31 and both 32-column
 // blocks.  Operands are staged in LDS with k contiguous, so every MFMA
 // operand is one 16-byte LDS read (8 bf16 along k for one row / column).
-// Two LDS buffers: the global loads of the next k-tile are issued into
-// registers before the current tile's MFMAs and written to the other buffer
-// after them, one barrier per k-tile.  The k order of the accumulation is
-// the plain one, so results do not depend on the pipelining.
+// An operand stored with k contiguous keeps its rows (stride LDK); one stored
+// with k as the slow index is transposed element by element on its way into
+// LDS, into 128-byte rows whose eight 16-byte groups are rotated by
+// (row + row / 8) mod 8: the 16 rows that one such store instruction writes
+// (8 apart) and the 16 rows that an operand read touches then spread over
+// the LDS banks instead of meeting in one.
+// Two LDS buffers and two register sets: the global loads of the next two
+// k-tiles are in flight while the current tile's MFMAs run; the next one is
+// written to the other buffer after them, one barrier per k-tile.  The k
+// order of the accumulation is the plain one, so results do not depend on
+// the pipelining.
 // Requires M % 128 == 0, N % 64 == 0, K % 32 == 0, k_split % 32 == 0.
 // ---------------------------------------------------------------------------
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));   // 16 bytes
@@ -86,7 +103,7 @@ __device__ __forceinline__ void gemm_store_a(uint16_t *sA, const u32x4 *ra)
             const int kr = c / (BM / 8), mc = c % (BM / 8);
             const uint16_t *e = (const uint16_t *)&ra[i];
 #pragma unroll
-            for (int q = 0; q < 8; ++q) sA[(mc * 8 + q) * LDK + kr] = e[q];
+            for (int q = 0; q < 8; ++q) sA[lds_idx<false>(mc * 8 + q, kr)] = e[q];
         }
     }
 }
@@ -115,7 +132,7 @@ __device__ __forceinline__ void gemm_store_b(uint16_t *sB, u32x4 rb)
         const int kr = c / (BN / 8), nc = c % (BN / 8);
         const uint16_t *e = (const uint16_t *)&rb;
 #pragma unroll
-        for (int q = 0; q < 8; ++q) sB[(nc * 8 + q) * LDK + kr] = e[q];
+        for (int q = 0; q < 8; ++q) sB[lds_idx<false>(nc * 8 + q, kr)] = e[q];
     }
 }
 
@@ -124,8 +141,8 @@ __global__ __launch_bounds__(kThreads) void k_gemm(const uint16_t *__restrict__ 
                                                    const uint16_t *__restrict__ B, int ldb, float *__restrict__ C,
                                                    int ldc, int64_t split_stride, int K, int k_split)
 {
-    __shared__ __attribute__((aligned(16))) uint16_t sA[2][BM * LDK];
-    __shared__ __attribute__((aligned(16))) uint16_t sB[2][BN * LDK];
+    __shared__ __attribute__((aligned(16))) uint16_t sA[2][BM * (A_KC ? LDK : LDT)];
+    __shared__ __attribute__((aligned(16))) uint16_t sB[2][BN * (B_KC ? LDK : LDT)];
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const int m0 = blockIdx.x * BM;
@@ -138,37 +155,63 @@ __global__ __launch_bounds__(kThreads) void k_gemm(const uint16_t *__restrict__ 
         acc0[i] = 0.f;
         acc1[i] = 0.f;
     }
-    u32x4 ra[kAChunks], rb;
-    if (kbeg < kend) {
-        gemm_load_a<A_KC>(A, lda, m0, kbeg, ra);
-        rb = gemm_load_b<B_KC>(B, ldb, n0, kbeg);
-        gemm_store_a<A_KC>(sA[0], ra);
-        gemm_store_b<B_KC>(sB[0], rb);
-    }
-    __syncthreads();
-    int cur = 0;
-    for (int k0 = kbeg; k0 < kend; k0 += BK) {
-        const bool more = k0 + BK < kend;
-        if (more) {   // next k-tile into registers while this one is multiplied
-            gemm_load_a<A_KC>(A, lda, m0, k0 + BK, ra);
-            rb = gemm_load_b<B_KC>(B, ldb, n0, k0 + BK);
-        }
-        const uint16_t *a_s = sA[cur], *b_s = sB[cur];
+    // k-tile t (k = kbeg + t BK) is multiplied from LDS buffer t % 2 while
+    // the global loads of tiles t + 1 and t + 2 are in flight in the two
+    // register sets (set (t + 1) % 2 holds tile t + 1); after tile t's MFMAs
+    // tile t + 1 goes to the other LDS buffer (last read before the previous
+    // barrier) and tile t + 3 is requested into the set just emptied.
+    const int nt = kbeg < kend ? (kend - kbeg + BK - 1) / BK : 0;
+    u32x4 ra0[kAChunks], rb0, ra1[kAChunks], rb1;
+    auto mma = [&](const uint16_t *a_s, const uint16_t *b_s) {
 #pragma unroll
         for (int kk = 0; kk < BK; kk += 16) {
             const int ko = kk + 8 * (lane >> 5);
-            const bf16x8 a = *(const bf16x8 *)(a_s + (wave * 32 + (lane & 31)) * LDK + ko);
-            const bf16x8 b0 = *(const bf16x8 *)(b_s + (lane & 31) * LDK + ko);
-            const bf16x8 b1 = *(const bf16x8 *)(b_s + (32 + (lane & 31)) * LDK + ko);
+            const bf16x8 a = *(const bf16x8 *)(a_s + lds_idx<A_KC>(wave * 32 + (lane & 31), ko));
+            const bf16x8 b0 = *(const bf16x8 *)(b_s + lds_idx<B_KC>(lane & 31, ko));
+            const bf16x8 b1 = *(const bf16x8 *)(b_s + lds_idx<B_KC>(32 + (lane & 31), ko));
             acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b0, acc0, 0, 0, 0);
             acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b1, acc1, 0, 0, 0);
         }
-        if (more) {   // the other buffer was last read before the previous barrier
-            gemm_store_a<A_KC>(sA[cur ^ 1], ra);
-            gemm_store_b<B_KC>(sB[cur ^ 1], rb);
+    };
+    if (nt > 0) {
+        gemm_load_a<A_KC>(A, lda, m0, kbeg, ra0);
+        rb0 = gemm_load_b<B_KC>(B, ldb, n0, kbeg);
+        gemm_store_a<A_KC>(sA[0], ra0);
+        gemm_store_b<B_KC>(sB[0], rb0);
+    }
+    if (nt > 1) {
+        gemm_load_a<A_KC>(A, lda, m0, kbeg + BK, ra1);
+        rb1 = gemm_load_b<B_KC>(B, ldb, n0, kbeg + BK);
+    }
+    if (nt > 2) {
+        gemm_load_a<A_KC>(A, lda, m0, kbeg + 2 * BK, ra0);
+        rb0 = gemm_load_b<B_KC>(B, ldb, n0, kbeg + 2 * BK);
+    }
+    __syncthreads();
+    for (int t = 0; t < nt; t += 2) {
+        // even tile t: LDS buffer 0; set 1 holds tile t + 1, set 0 tile t + 2
+        mma(sA[0], sB[0]);
+        if (t + 1 < nt) {
+            gemm_store_a<A_KC>(sA[1], ra1);
+            gemm_store_b<B_KC>(sB[1], rb1);
+        }
+        if (t + 3 < nt) {
+            gemm_load_a<A_KC>(A, lda, m0, kbeg + (t + 3) * BK, ra1);
+            rb1 = gemm_load_b<B_KC>(B, ldb, n0, kbeg + (t + 3) * BK);
         }
         __syncthreads();
-        cur ^= 1;
+        if (t + 1 >= nt) break;
+        // odd tile t + 1: LDS buffer 1; set 0 holds tile t + 2, set 1 tile t + 3
+        mma(sA[1], sB[1]);
+        if (t + 2 < nt) {
+            gemm_store_a<A_KC>(sA[0], ra0);
+            gemm_store_b<B_KC>(sB[0], rb0);
+        }
+        if (t + 4 < nt) {
+            gemm_load_a<A_KC>(A, lda, m0, kbeg + (t + 4) * BK, ra0);
+            rb0 = gemm_load_b<B_KC>(B, ldb, n0, kbeg + (t + 4) * BK);
+        }
+        __syncthreads();
     }
     float *Cz = C + (int64_t)blockIdx.z * split_stride;
     const int col = n0 + (lane & 31);
@@ -188,6 +231,8 @@ __global__ void k_split_reduce(const float *__restrict__ part, int S, int M, int
     if (idx >= (int64_t)M * ncols) return;
     const int i = (int)(idx / ncols), j = (int)(idx % ncols);
     float s = 0.f;
+    // unrolled so that the loads are in flight together; the sum keeps z order
+#pragma unroll 16
     for (int z = 0; z < S; ++z) s += part[(int64_t)z * M * N + (int64_t)i * N + j];
     out[(int64_t)i * ldo + j] = s;
 }
@@ -369,8 +414,10 @@ __global__ __launch_bounds__(kThreads) void k_chunk_reduce(const float *__restri
     const int q = threadIdx.x & 7;
     const int o = blockIdx.x * (kThreads / 8) + (threadIdx.x >> 3);
     float s = 0.f;
-    if (o < n)
+    if (o < n) {
+#pragma unroll 8
         for (int z = q; z < S; z += 8) s += part[(int64_t)z * n + o];
+    }
     sh[threadIdx.x] = s;
     __syncthreads();
     if (q == 0 && o < n) {
