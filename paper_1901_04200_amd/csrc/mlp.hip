@@ -223,18 +223,28 @@ __global__ __launch_bounds__(kThreads) void k_gemm(const uint16_t *__restrict__ 
     }
 }
 
-// out[i*ldo + j] = sum_z part[z][i][j] (fixed order), j < ncols
-__global__ void k_split_reduce(const float *__restrict__ part, int S, int M, int N, float *__restrict__ out,
-                               int ldo, int ncols)
+// out[i*ldo + j] = sum_z part[z][i][j], j < ncols: eight threads per output,
+// thread q adding splits q, q + 8, ... in order (all its loads in flight
+// together), then the eight sums in a fixed tree; 32 outputs per workgroup.
+__global__ __launch_bounds__(kThreads) void k_split_reduce(const float *__restrict__ part, int S, int M, int N,
+                                                           float *__restrict__ out, int ldo, int ncols)
 {
-    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= (int64_t)M * ncols) return;
-    const int i = (int)(idx / ncols), j = (int)(idx % ncols);
+    __shared__ float sh[kThreads];
+    const int q = threadIdx.x & 7;
+    const int64_t o = (int64_t)blockIdx.x * (kThreads / 8) + (threadIdx.x >> 3);
+    const bool live = o < (int64_t)M * ncols;
+    const int i = live ? (int)(o / ncols) : 0, j = live ? (int)(o % ncols) : 0;
     float s = 0.f;
-    // unrolled so that the loads are in flight together; the sum keeps z order
-#pragma unroll 16
-    for (int z = 0; z < S; ++z) s += part[(int64_t)z * M * N + (int64_t)i * N + j];
-    out[(int64_t)i * ldo + j] = s;
+    if (live) {
+#pragma unroll 8
+        for (int z = q; z < S; z += 8) s += part[(int64_t)z * M * N + (int64_t)i * N + j];
+    }
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    if (q == 0 && live) {
+        const float *v = sh + threadIdx.x;
+        out[(int64_t)i * ldo + j] = ((v[0] + v[1]) + (v[2] + v[3])) + ((v[4] + v[5]) + (v[6] + v[7]));
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -757,7 +767,8 @@ static hipError_t launch_gemm(bool akc, bool bkc, const uint16_t *A, int lda, co
     const int ks = ((K + splits - 1) / splits + BK - 1) / BK * BK;
     const dim3 grid(M / BM, N / BN, splits);
     const int64_t ss = (int64_t)M * N;
-    if (akc && bkc) hipLaunchKernelGGL((k_gemm<true, true>), grid, dim3(kThreads), 0, st, A, lda, B, ldb, C, ldc, ss, K, ks);
+    if (akc && bkc)
+        hipLaunchKernelGGL((k_gemm<true, true>), grid, dim3(kThreads), 0, st, A, lda, B, ldb, C, ldc, ss, K, ks);
     else if (!akc && !bkc)
         hipLaunchKernelGGL((k_gemm<false, false>), grid, dim3(kThreads), 0, st, A, lda, B, ldb, C, ldc, ss, K, ks);
     else if (akc)
@@ -950,9 +961,9 @@ static void launch_small_t(const mlp_ctx *c, const float *th, int B, const doubl
 {
     const size_t lds = small_lds(NR, c->H);
     const float *p = c->p;
-    hipLaunchKernelGGL((k_small_eval<NR>), dim3((unsigned)B), dim3(kSmallThreads), lds, st, th, c->H, c->nout, c->in_shift,
-                       c->in_scale, p + c->off[0], p + c->off[1], c->WT[1], p + c->off[3], c->WT[2], p + c->off[5],
-                       c->WT[3], p + c->off[7], c->out_shift, c->out_scale, C, Y, J, G, grad);
+    hipLaunchKernelGGL((k_small_eval<NR>), dim3((unsigned)B), dim3(kSmallThreads), lds, st, th, c->H, c->nout,
+                       c->in_shift, c->in_scale, p + c->off[0], p + c->off[1], c->WT[1], p + c->off[3], c->WT[2],
+                       p + c->off[5], c->WT[3], p + c->off[7], c->out_shift, c->out_scale, C, Y, J, G, grad);
 }
 
 static hipError_t launch_small(const mlp_ctx *c, const float *th, int B, const double *C, float *Y, float *J,
@@ -998,7 +1009,8 @@ extern "C" int mlp_loss_grad(mlp_ctx *c, const float *d_theta, const float *d_Yl
                              float w, double *d_loss, float *d_grad, void *stream)
 {
     if (!c || !d_theta || !d_Ylab || !d_Jlab || !d_loss || !d_grad) return mfail(c, -1, "null argument");
-    if (B < 128 || B > c->Bmax || B % 128) return mfail(c, -1, "training batch must be a multiple of 128 up to max_batch");
+    if (B < 128 || B > c->Bmax || B % 128)
+        return mfail(c, -1, "training batch must be a multiple of 128 up to max_batch");
     hipStream_t st = (hipStream_t)stream;
     const int H = c->H, nin = c->nin, R = (nin + 1) * B;
     float *g = d_grad;
@@ -1017,8 +1029,8 @@ extern "C" int mlp_loss_grad(mlp_ctx *c, const float *d_theta, const float *d_Yl
     const int S = std::min(kMaxSplits, std::max(1, R / 512));
     e = launch_gemm(false, false, c->A[3], H, c->G4, kOutPad, c->split, kOutPad, H, kOutPad, R, S, st);
     if (e == hipSuccess) {
-        hipLaunchKernelGGL(k_split_reduce, dim3(nb((int64_t)H * c->nout)), dim3(kThreads), 0, st, c->split, S, H, kOutPad,
-                           g + c->off[6], c->nout, c->nout);
+        hipLaunchKernelGGL(k_split_reduce, dim3(nb((int64_t)H * c->nout * 8)), dim3(kThreads), 0, st, c->split, S, H,
+                           kOutPad, g + c->off[6], c->nout, c->nout);
         e = launch_gemm(true, true, c->G4, kOutPad, c->Wb[3], kOutPad, c->Hbar, H, R, H, kOutPad, 1, st);
     }
     // hidden layers 3 and 2
@@ -1028,7 +1040,7 @@ extern "C" int mlp_loss_grad(mlp_ctx *c, const float *d_theta, const float *d_Yl
         colsum(c, c->ZbarP, B, H, H, g + c->off[2 * l - 1], st);
         e = launch_gemm(false, false, c->A[l - 1], H, c->Zbar, H, c->split, H, H, H, R, S, st);
         if (e != hipSuccess) break;
-        hipLaunchKernelGGL(k_split_reduce, dim3(nb((int64_t)H * H)), dim3(kThreads), 0, st, c->split, S, H, H,
+        hipLaunchKernelGGL(k_split_reduce, dim3(nb((int64_t)H * H * 8)), dim3(kThreads), 0, st, c->split, S, H, H,
                            g + c->off[2 * l - 2], H, H);
         e = launch_gemm(true, true, c->Zbar, H, c->Wb[l - 1], H, c->Hbar, H, R, H, H, 1, st);
     }
