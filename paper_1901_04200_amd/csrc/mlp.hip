@@ -442,35 +442,41 @@ __global__ __launch_bounds__(kThreads) void k_chunk_reduce(const float *__restri
 constexpr int kMaxIn = 16;
 constexpr int kChunkL1 = 8;
 
+template <int NI>   // n_in
 __global__ void k_l1_bwd_part(const float *__restrict__ Hbar, const float *__restrict__ Z,
-                              const float *__restrict__ X, int B, int nin, int H, float *__restrict__ part)
+                              const float *__restrict__ X, int B, int H, float *__restrict__ part)
 {
     const int j = blockIdx.y * blockDim.x + threadIdx.x;
     if (j >= H) return;
     const int b0 = blockIdx.x * kChunkL1;
-    float acc[kMaxIn + 1];
+    float acc[NI + 1];
 #pragma unroll
-    for (int t = 0; t <= kMaxIn; ++t) acc[t] = 0.f;
+    for (int t = 0; t <= NI; ++t) acc[t] = 0.f;
     for (int b = b0; b < b0 + kChunkL1; ++b) {
+        // the row's primal and tangent values, requested together
         const float z = Z[(int64_t)b * H + j];
+        const float hb0 = Hbar[(int64_t)b * H + j];
+        float hb[NI], zt[NI], xb[NI];
+#pragma unroll
+        for (int q = 0; q < NI; ++q) {
+            const int64_t r = (int64_t)(q + 1) * B + b;
+            hb[q] = Hbar[r * H + j];
+            zt[q] = Z[r * H + j];
+            xb[q] = X[b * NI + q];
+        }
         const float s = sigm(z);
         const float d1 = s * (1.f + z * (1.f - s));
         const float d2 = s * (1.f - s) * (2.f + z * (1.f - 2.f * s));
-        float zb = Hbar[(int64_t)b * H + j] * d1;
-        for (int q = 0; q < nin; ++q) {
-            const int64_t r = (int64_t)(q + 1) * B + b;
-            zb += Hbar[r * H + j] * Z[r * H + j] * d2;
-        }
+        float zb = hb0 * d1;
 #pragma unroll
-        for (int t = 0; t < kMaxIn; ++t)
-            if (t < nin) acc[t] += X[b * nin + t] * zb + Hbar[((int64_t)(t + 1) * B + b) * H + j] * d1;
-        acc[kMaxIn] += zb;
+        for (int q = 0; q < NI; ++q) zb += hb[q] * zt[q] * d2;
+#pragma unroll
+        for (int t = 0; t < NI; ++t) acc[t] += xb[t] * zb + hb[t] * d1;
+        acc[NI] += zb;
     }
-    float *pz = part + (int64_t)blockIdx.x * (nin + 1) * H;
+    float *pz = part + (int64_t)blockIdx.x * (NI + 1) * H;
 #pragma unroll
-    for (int t = 0; t < kMaxIn; ++t)
-        if (t < nin) pz[(int64_t)t * H + j] = acc[t];
-    pz[(int64_t)nin * H + j] = acc[kMaxIn];
+    for (int t = 0; t <= NI; ++t) pz[(int64_t)t * H + j] = acc[t];
 }
 
 __global__ void k_adam(float *__restrict__ p, const float *__restrict__ g, float *__restrict__ m,
@@ -761,6 +767,25 @@ static int mfail(mlp_ctx *c, int code, const std::string &m)
     return code;
 }
 
+template <int NI>
+static void launch_l1_bwd_t(dim3 grid, hipStream_t st, const float *Hbar, const float *Z, const float *X, int B, int H,
+                            float *part)
+{
+    hipLaunchKernelGGL((k_l1_bwd_part<NI>), grid, dim3(kThreads), 0, st, Hbar, Z, X, B, H, part);
+}
+
+// Layer-1 gradient partials for n_in = nin (1..16).
+static void launch_l1_bwd(int nin, dim3 grid, hipStream_t st, const float *Hbar, const float *Z, const float *X, int B,
+                          int H, float *part)
+{
+    typedef void (*fn)(dim3, hipStream_t, const float *, const float *, const float *, int, int, float *);
+    static const fn tab[kMaxIn] = {launch_l1_bwd_t<1>,  launch_l1_bwd_t<2>,  launch_l1_bwd_t<3>,  launch_l1_bwd_t<4>,
+                                   launch_l1_bwd_t<5>,  launch_l1_bwd_t<6>,  launch_l1_bwd_t<7>,  launch_l1_bwd_t<8>,
+                                   launch_l1_bwd_t<9>,  launch_l1_bwd_t<10>, launch_l1_bwd_t<11>, launch_l1_bwd_t<12>,
+                                   launch_l1_bwd_t<13>, launch_l1_bwd_t<14>, launch_l1_bwd_t<15>, launch_l1_bwd_t<16>};
+    tab[nin - 1](grid, st, Hbar, Z, X, B, H, part);
+}
+
 static hipError_t launch_gemm(bool akc, bool bkc, const uint16_t *A, int lda, const uint16_t *B, int ldb, float *C,
                               int ldc, int M, int N, int K, int splits, hipStream_t st)
 {
@@ -1047,8 +1072,7 @@ extern "C" int mlp_loss_grad(mlp_ctx *c, const float *d_theta, const float *d_Yl
     if (e == hipSuccess) {
         // W1bar (nin rows) and b1bar are contiguous in the gradient: one (nin + 1) x H reduction
         const int nchunk = B / kChunkL1;
-        hipLaunchKernelGGL(k_l1_bwd_part, dim3(nchunk, (H + kThreads - 1) / kThreads), dim3(kThreads), 0, st, c->Hbar,
-                           c->Z[1], c->Xn, B, nin, H, c->split);
+        launch_l1_bwd(nin, dim3(nchunk, (H + kThreads - 1) / kThreads), st, c->Hbar, c->Z[1], c->Xn, B, H, c->split);
         const int nout1 = (nin + 1) * H;
         hipLaunchKernelGGL(k_chunk_reduce, dim3((nout1 + kThreads / 8 - 1) / (kThreads / 8)), dim3(kThreads), 0, st,
                            c->split, nchunk, nout1, g + c->off[0]);
