@@ -273,11 +273,11 @@ __global__ void k_l1_fwd(const float *__restrict__ X, const float *__restrict__ 
     const float d1 = s * (1.f + z * (1.f - s));
     Z[(int64_t)b * H + j] = z;
     A[(int64_t)b * H + j] = f2bf(z * s);
+    // tangent rows: only their bf16 activations are stored; the pre-activations
+    // are the rows of W1, which the backward pass reads there
     for (int t = 0; t < nin; ++t) {
-        const float u = W1[t * H + j];
         const int64_t r = (int64_t)(t + 1) * Bp + b;
-        Z[r * H + j] = u;
-        A[r * H + j] = f2bf(d1 * u);
+        A[r * H + j] = f2bf(d1 * W1[t * H + j]);
     }
 }
 
@@ -444,7 +444,8 @@ constexpr int kChunkL1 = 8;
 
 template <int NI>   // n_in
 __global__ void k_l1_bwd_part(const float *__restrict__ Hbar, const float *__restrict__ Z,
-                              const float *__restrict__ X, int B, int H, float *__restrict__ part)
+                              const float *__restrict__ W1, const float *__restrict__ X, int B, int H,
+                              float *__restrict__ part)
 {
     const int j = blockIdx.y * blockDim.x + threadIdx.x;
     if (j >= H) return;
@@ -461,7 +462,7 @@ __global__ void k_l1_bwd_part(const float *__restrict__ Hbar, const float *__res
         for (int q = 0; q < NI; ++q) {
             const int64_t r = (int64_t)(q + 1) * B + b;
             hb[q] = Hbar[r * H + j];
-            zt[q] = Z[r * H + j];
+            zt[q] = W1[q * H + j];   // the tangent pre-activations of layer 1
             xb[q] = X[b * NI + q];
         }
         const float s = sigm(z);
@@ -768,22 +769,23 @@ static int mfail(mlp_ctx *c, int code, const std::string &m)
 }
 
 template <int NI>
-static void launch_l1_bwd_t(dim3 grid, hipStream_t st, const float *Hbar, const float *Z, const float *X, int B, int H,
-                            float *part)
+static void launch_l1_bwd_t(dim3 grid, hipStream_t st, const float *Hbar, const float *Z, const float *W1,
+                            const float *X, int B, int H, float *part)
 {
-    hipLaunchKernelGGL((k_l1_bwd_part<NI>), grid, dim3(kThreads), 0, st, Hbar, Z, X, B, H, part);
+    hipLaunchKernelGGL((k_l1_bwd_part<NI>), grid, dim3(kThreads), 0, st, Hbar, Z, W1, X, B, H, part);
 }
 
 // Layer-1 gradient partials for n_in = nin (1..16).
-static void launch_l1_bwd(int nin, dim3 grid, hipStream_t st, const float *Hbar, const float *Z, const float *X, int B,
-                          int H, float *part)
+static void launch_l1_bwd(int nin, dim3 grid, hipStream_t st, const float *Hbar, const float *Z, const float *W1,
+                          const float *X, int B, int H, float *part)
 {
-    typedef void (*fn)(dim3, hipStream_t, const float *, const float *, const float *, int, int, float *);
+    typedef void (*fn)(dim3, hipStream_t, const float *, const float *, const float *, const float *, int, int,
+                       float *);
     static const fn tab[kMaxIn] = {launch_l1_bwd_t<1>,  launch_l1_bwd_t<2>,  launch_l1_bwd_t<3>,  launch_l1_bwd_t<4>,
                                    launch_l1_bwd_t<5>,  launch_l1_bwd_t<6>,  launch_l1_bwd_t<7>,  launch_l1_bwd_t<8>,
                                    launch_l1_bwd_t<9>,  launch_l1_bwd_t<10>, launch_l1_bwd_t<11>, launch_l1_bwd_t<12>,
                                    launch_l1_bwd_t<13>, launch_l1_bwd_t<14>, launch_l1_bwd_t<15>, launch_l1_bwd_t<16>};
-    tab[nin - 1](grid, st, Hbar, Z, X, B, H, part);
+    tab[nin - 1](grid, st, Hbar, Z, W1, X, B, H, part);
 }
 
 static hipError_t launch_gemm(bool akc, bool bkc, const uint16_t *A, int lda, const uint16_t *B, int ldb, float *C,
@@ -1072,7 +1074,8 @@ extern "C" int mlp_loss_grad(mlp_ctx *c, const float *d_theta, const float *d_Yl
     if (e == hipSuccess) {
         // W1bar (nin rows) and b1bar are contiguous in the gradient: one (nin + 1) x H reduction
         const int nchunk = B / kChunkL1;
-        launch_l1_bwd(nin, dim3(nchunk, (H + kThreads - 1) / kThreads), st, c->Hbar, c->Z[1], c->Xn, B, H, c->split);
+        launch_l1_bwd(nin, dim3(nchunk, (H + kThreads - 1) / kThreads), st, c->Hbar, c->Z[1], c->p + c->off[0], c->Xn,
+                      B, H, c->split);
         const int nout1 = (nin + 1) * H;
         hipLaunchKernelGGL(k_chunk_reduce, dim3((nout1 + kThreads / 8 - 1) / (kThreads / 8)), dim3(kThreads), 0, st,
                            c->split, nchunk, nout1, g + c->off[0]);

@@ -246,15 +246,16 @@ def fit(net: MLP, theta, Y, J, *, epochs: int, batch: int = 4096, lr: float = 1e
     for ep in range(epochs):
         lr_e = lr * (lr_f / lr) ** (ep / max(epochs - 1, 1))
         perm = torch.randperm(n, generator=g).to(net.dev)
-        tot = 0.0
+        logged = (ep % log_every == 0) or ep == epochs - 1
+        tot = torch.zeros(1, dtype=torch.float64, device=net.dev)   # summed on the device: no sync per step
         for s in range(steps_per_epoch):
             idx = perm[s * batch:(s + 1) * batch]
             net.loss_grad(theta[idx].contiguous(), Y[idx].contiguous(), J[idx].contiguous(), w, grad, loss)
             net.adam_step(grad, lr_e)
-            if (ep % log_every == 0) or ep == epochs - 1:
-                tot += float(loss.item())
-        if (ep % log_every == 0) or ep == epochs - 1:
-            hist.append(TrainLog(ep, tot / steps_per_epoch, time.perf_counter() - t0))
+            if logged:
+                tot += loss
+        if logged:
+            hist.append(TrainLog(ep, float(tot.item()) / steps_per_epoch, time.perf_counter() - t0))
     torch.cuda.synchronize()
     return hist
 
