@@ -31,6 +31,21 @@ namespace mcaad {
 // ---------------------------------------------------------------------------
 // One workgroup's share: paths blk*256 .. blk*256+255; lds holds
 // [kWavesPerBlock][m] doubles.
+// Wave priority from the share of the wave's work still ahead (left of
+// total units, uniform in the wave): waves with more left are issued first, so
+// the waves sharing a SIMD finish closer together and fewer run alone,
+// latency-bound, at the end of the launch (the forward sweep: 4% shorter at
+// 2^20 paths; the reverse sweep gains nothing from it).
+__device__ __forceinline__ void prio_by_work_left(int left, int total)
+{
+    switch ((4 * left) / (total + 1)) {
+    case 0: __builtin_amdgcn_s_setprio(0); break;
+    case 1: __builtin_amdgcn_s_setprio(1); break;
+    case 2: __builtin_amdgcn_s_setprio(2); break;
+    default: __builtin_amdgcn_s_setprio(3); break;
+    }
+}
+
 template <int MODEL, typename R, bool STORE>
 __device__ __forceinline__ void pass1_block(const DevProblem &pb, const double *__restrict__ theta,
                                             double *__restrict__ partial, R *__restrict__ ckpt, int64_t blk,
@@ -62,6 +77,7 @@ __device__ __forceinline__ void pass1_block(const DevProblem &pb, const double *
         // segments of K steps; the state at a segment's start is its checkpoint
         R *cp = ckpt + p;
         for (int call = 0; call < ncalls; cp += (int64_t)T::NV * pb.P) {
+            prio_by_work_left((pb.ppl - sp) * ncalls - call, pb.ppl * ncalls);
             if constexpr (STORE) {
                 if (active) {
                     cp[0] = x;
