@@ -135,16 +135,20 @@ def test_scaling_maps_units():
     net.close()
 
 
-@pytest.mark.parametrize("H,nout,B", [(128, 7, 256), (256, 40, 4096)])
-def test_loss_and_double_backprop(H, nout, B):
-    say(f"mlp loss/grad H={H} n_out={nout} B={B}")
-    net = S.MLP(5, H, nout, max_batch=B)
-    params = rand_params([5, H, H, H, nout], 5)
+@pytest.mark.parametrize("nin,H,nout,B", [(5, 128, 7, 256), (5, 256, 40, 4096), (1, 512, 64, 128),
+                                         (16, 1024, 3, 128)])
+def test_loss_and_double_backprop(nin, H, nout, B):
+    """Widths 128 to 1024 (4 to 32 k-tiles per product, 1 to 48 split-K
+    partials of the weight gradients), one to sixteen inputs, the widest
+    output tile (64 units)."""
+    say(f"mlp loss/grad n_in={nin} H={H} n_out={nout} B={B}")
+    net = S.MLP(nin, H, nout, max_batch=B)
+    params = rand_params([nin, H, H, H, nout], 5)
     net.set_params(net.pack(params))
     rng = np.random.default_rng(6)
-    X = rng.uniform(-1, 1, (B, 5)).astype(np.float32)
+    X = rng.uniform(-1, 1, (B, nin)).astype(np.float32)
     Yl = rng.normal(0, 1, (B, nout)).astype(np.float32)
-    Jl = rng.normal(0, 1, (B, nout, 5)).astype(np.float32)
+    Jl = rng.normal(0, 1, (B, nout, nin)).astype(np.float32)
     w = 0.8
     loss, grad = net.loss_grad(*(torch.as_tensor(a, device="cuda") for a in (X, Yl, Jl)), w)
     L, go = MO.grads(device_view(params), X.astype(np.float64), Yl.astype(np.float64), Jl.astype(np.float64), w)
