@@ -35,7 +35,8 @@ namespace mcaad {
 // total units, uniform in the wave): waves with more left are issued first, so
 // the waves sharing a SIMD finish closer together and fewer run alone,
 // latency-bound, at the end of the launch (the forward sweep: 4% shorter at
-// 2^20 paths; the reverse sweep gains nothing from it).
+// 2^20 paths; the reverse sweep gains nothing from it, nor do the persistent
+// batched grids, whose waves keep taking new items until the queue is empty).
 __device__ __forceinline__ void prio_by_work_left(int left, int total)
 {
     switch ((4 * left) / (total + 1)) {
@@ -46,7 +47,7 @@ __device__ __forceinline__ void prio_by_work_left(int left, int total)
     }
 }
 
-template <int MODEL, typename R, bool STORE>
+template <int MODEL, typename R, bool STORE, bool PRIO>
 __device__ __forceinline__ void pass1_block(const DevProblem &pb, const double *__restrict__ theta,
                                             double *__restrict__ partial, R *__restrict__ ckpt, int64_t blk,
                                             double *lds)
@@ -77,7 +78,7 @@ __device__ __forceinline__ void pass1_block(const DevProblem &pb, const double *
         // segments of K steps; the state at a segment's start is its checkpoint
         R *cp = ckpt + p;
         for (int call = 0; call < ncalls; cp += (int64_t)T::NV * pb.P) {
-            prio_by_work_left((pb.ppl - sp) * ncalls - call, pb.ppl * ncalls);
+            if constexpr (PRIO) prio_by_work_left((pb.ppl - sp) * ncalls - call, pb.ppl * ncalls);
             if constexpr (STORE) {
                 if (active) {
                     cp[0] = x;
@@ -119,7 +120,7 @@ __global__ __launch_bounds__(kBlock) void k_pass1(DevProblem pb, const double *_
                                                   double *__restrict__ partial, R *__restrict__ ckpt)
 {
     extern __shared__ double lds[];
-    pass1_block<MODEL, R, STORE>(pb, theta, partial, ckpt, blockIdx.x, lds);
+    pass1_block<MODEL, R, STORE, true>(pb, theta, partial, ckpt, blockIdx.x, lds);
 }
 
 // ---------------------------------------------------------------------------
@@ -748,8 +749,8 @@ __global__ __launch_bounds__(kBlock) void k_batch_pass1(const BatchInst *__restr
         if (it >= n_items) break;
         const int2 w = items[it];
         const DevProblem pb = insts[w.x].pb;
-        pass1_block<MODEL, R, STORE>(pb, theta_all + (int64_t)w.x * Traits<MODEL>::NP, insts[w.x].part_y,
-                                     (R *)insts[w.x].ckpt, w.y, lds);
+        pass1_block<MODEL, R, STORE, false>(pb, theta_all + (int64_t)w.x * Traits<MODEL>::NP, insts[w.x].part_y,
+                                            (R *)insts[w.x].ckpt, w.y, lds);
     }
 }
 
