@@ -19,8 +19,12 @@
  *     cal_status and cal_timing_read, which synchronise.
  *   - The context owns all workspace (block partial sums, checkpoints,
  *     sorted instrument tables). It is allocated once in cal_create; the
- *     calibrate_* calls allocate nothing. One context serves one stream at a
- *     time: calls on one context that overlap on different streams race.
+ *     calibrate_* calls allocate nothing and only launch kernels (no copies,
+ *     memsets or synchronisation), so a call can be captured into a HIP graph
+ *     (with cal_timing_enable off) and replayed; the graph reads its
+ *     arguments' memory at replay time.
+ *     One context serves one stream at a time: calls on one context that
+ *     overlap on different streams race.
  *   - Return value 0 = success, negative = error (CAL_E*). On error nothing is
  *     enqueued and cal_last_error(ctx) describes it. Nothing throws or aborts
  *     across this boundary.

@@ -273,6 +273,50 @@ def test_forward_store_and_vjp_stored(orc, model, k):
     assert g_err(g_s.cpu().numpy(), orc.vjp(pb, th, lam)) <= 1e-4
 
 
+@pytest.mark.parametrize("model", ["heston", "lv", "slv"])
+@pytest.mark.parametrize("mode", ["store", "rerun"])
+def test_gradient_graph_replays(model, mode):
+    """calibrate_gradient launches kernels only (no allocation, copy, memset
+    or synchronisation), so it can be captured into a HIP graph: every replay,
+    with eager work of another context and synchronisations in between,
+    reproduces the eager result bit for bit."""
+    pb, th = _model_problem(model)
+    C = np.linspace(3.0, 8.0, pb.n_instr)
+    say(f"{model} fp32 {mode}: gradient captured in a graph, P={pb.n_paths} N={pb.n_steps}")
+    mc = MonteCarloCalibration(pb, precision="fp32", ckpt_mode=mode)
+    thd = torch.as_tensor(th, dtype=torch.float64, device="cuda")
+    Cd = torch.as_tensor(C, dtype=torch.float64, device="cuda")
+    Ey = torch.empty(pb.n_instr, dtype=torch.float64, device="cuda")
+    G = torch.empty(1, dtype=torch.float64, device="cuda")
+    g = torch.empty(pb.n_params, dtype=torch.float64, device="cuda")
+    capi.calibrate_gradient(mc.ctx, thd, Cd, Ey, G, g)
+    torch.cuda.synchronize()
+    ref = (Ey.clone(), G.clone(), g.clone())
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        capi.calibrate_gradient(mc.ctx, thd, Cd, Ey, G, g)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        capi.calibrate_gradient(mc.ctx, thd, Cd, Ey, G, g)
+    other = MonteCarloCalibration(pb, precision="fp32")
+    for r in range(3):
+        Ey.zero_()
+        G.zero_()
+        g.zero_()
+        graph.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(Ey, ref[0]) and torch.equal(G, ref[1]) and torch.equal(g, ref[2]), r
+        other.gradient(th, C)   # eager work between replays
+        torch.cuda.synchronize()
+    other.close()
+    assert mc.status() == 0
+    del graph
+    mc.close()
+
+
 def test_vjp_stored_after_rerun_mode_gradient(heston_small):
     """In CAL_CKPT_RERUN mode pass 2 writes the checkpoints itself, so
     calibrate_vjp_stored after calibrate_gradient reproduces its gradient
