@@ -501,15 +501,6 @@ extern "C" int calibrate_forward(cal_ctx *ctx, const double *d_theta, double *d_
     return CAL_OK;
 }
 
-// A sweep that writes every segment of the checkpoint buffer (pass 1 storing,
-// or pass 2 re-running the forward sweep) has been launched; its workgroup 0
-// copies theta to d_theta_ckpt (DevProblem::theta_save).
-static int ckpt_written(cal_ctx *c)
-{
-    c->ckpt_valid = true;
-    return CAL_OK;
-}
-
 extern "C" int calibrate_forward_store(cal_ctx *ctx, const double *d_theta, double *d_Ey, void *stream)
 {
     int rc = check_ctx(ctx);
@@ -519,8 +510,9 @@ extern "C" int calibrate_forward_store(cal_ctx *ctx, const double *d_theta, doub
     ctx->ckpt_valid = false;
     rc = run_pass1(ctx, d_theta, true, st);
     if (rc) return rc;
-    rc = ckpt_written(ctx);
-    if (rc) return rc;
+    // a sweep writing every checkpoint segment is enqueued; its workgroup 0
+    // copies theta beside the buffer (DevProblem::theta_save)
+    ctx->ckpt_valid = true;
     hipError_t e = launch_reduce_sorted(ctx->d_part_y, ctx->nblocks, ctx->m, ctx->d_id, 1.0 / (double)ctx->P,
                                         d_Ey, ctx->d_status, st);
     if (e != hipSuccess) return hip_fail(ctx, e, "reduce launch");
@@ -543,10 +535,7 @@ static int vjp(cal_ctx *ctx, const double *d_theta, const double *d_lambda, doub
     if (!from_ckpt) ctx->ckpt_valid = false;
     int rc = run_pass2(ctx, d_theta, from_ckpt, st);
     if (rc) return rc;
-    if (!from_ckpt) {
-        rc = ckpt_written(ctx);
-        if (rc) return rc;
-    }
+    if (!from_ckpt) ctx->ckpt_valid = true;   // the re-run wrote every segment
     e = launch_reduce_sorted(ctx->d_part_g, ctx->nblocks, ctx->M, nullptr, 1.0, d_grad, ctx->d_status, st);
     if (e != hipSuccess) return hip_fail(ctx, e, "reduce launch");
     return CAL_OK;
@@ -585,8 +574,7 @@ extern "C" int calibrate_gradient(cal_ctx *ctx, const double *d_theta, const dou
     if (e != hipSuccess) return hip_fail(ctx, e, "residual launch");
     rc = run_pass2(ctx, d_theta, store, st);
     if (rc) return rc;
-    rc = ckpt_written(ctx);   // either pass wrote every segment
-    if (rc) return rc;
+    ctx->ckpt_valid = true;   // either pass wrote every segment
     e = launch_reduce_sorted(ctx->d_part_g, ctx->nblocks, ctx->M, nullptr, 1.0, d_grad, ctx->d_status, st);
     if (e != hipSuccess) return hip_fail(ctx, e, "reduce launch");
     return CAL_OK;
