@@ -117,21 +117,29 @@ class BatchCalibration:
 
     def autotune(self, theta, C_flat, ks=(8, 16, 32), wpcs=(0, 1, 2, 4), ppls=(1, 2), reps: int = 5):
         """Time the captured step for every (checkpoint spacing, persistent
-        workgroups per CU, paths per lane) and keep the fastest.  Returns
-        (choice, table)."""
-        table = []
+        workgroups per CU, paths per lane), then the three fastest again in
+        reverse order (so that the first-timed candidates, which meet a GPU
+        whose clock has not settled, are not penalised), and keep the fastest.
+        Returns (choice, table)."""
+        def timed(cfg):
+            self.configure(*cfg)
+            self.capture(theta, C_flat)
+            self.replay()
+            self.torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                self.replay()
+            self.torch.cuda.synchronize()
+            return (time.perf_counter() - t0) / reps
+
+        best_t = {}
         for k in ks:
             for w in wpcs:
                 for ppl in ppls:
-                    self.configure(k, w, ppl)
-                    self.capture(theta, C_flat)
-                    self.replay()
-                    self.torch.cuda.synchronize()
-                    t0 = time.perf_counter()
-                    for _ in range(reps):
-                        self.replay()
-                    self.torch.cuda.synchronize()
-                    table.append(((k, w, ppl), (time.perf_counter() - t0) / reps))
+                    best_t[(k, w, ppl)] = timed((k, w, ppl))
+        for cfg in sorted(best_t, key=best_t.get)[:3][::-1]:
+            best_t[cfg] = min(best_t[cfg], timed(cfg))
+        table = list(best_t.items())
         best = min(table, key=lambda r: r[1])[0]
         self.configure(*best)
         self.capture(theta, C_flat)
