@@ -132,7 +132,7 @@ def test_autograd_two_forwards_then_backward(lv_small):
     mc.close()
 
 
-@pytest.mark.parametrize("k", [8, 16])
+@pytest.mark.parametrize("k", [8, 16, 32])
 def test_lv_two_paths_per_lane(orc, k):
     """Two paths side by side per lane (a ragged last workgroup of 512
     paths): against the oracle in both precisions; store and re-run modes give
