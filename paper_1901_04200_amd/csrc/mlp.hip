@@ -145,9 +145,19 @@ __global__ __launch_bounds__(kThreads) void k_gemm(const uint16_t *__restrict__ 
     __shared__ __attribute__((aligned(16))) uint16_t sB[2][BN * (B_KC ? LDK : LDT)];
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
-    const int m0 = blockIdx.x * BM;
-    const int n0 = blockIdx.y * BN;
-    const int kbeg = blockIdx.z * k_split;
+    // Tile of this workgroup.  Workgroups go to the 8 XCDs (each with its own
+    // L2) in turn by linear id, so the logical tiles are dealt out in 8
+    // contiguous runs, N-tile fastest: an XCD takes all column tiles of its
+    // row tiles and whole k-splits, and the A and B panels they share are read
+    // from memory once per XCD instead of once per workgroup.
+    const int nM = gridDim.x, nN = gridDim.y;
+    const int total = nM * nN * gridDim.z;
+    const int lin = blockIdx.x + nM * (blockIdx.y + nN * blockIdx.z);
+    const int lid = total % 8 == 0 ? (lin % 8) * (total / 8) + lin / 8 : lin;
+    const int tn = lid % nN, tm = (lid / nN) % nM, tz = lid / (nN * nM);
+    const int m0 = tm * BM;
+    const int n0 = tn * BN;
+    const int kbeg = tz * k_split;
     const int kend = min(K, kbeg + k_split);
     f32x16 acc0, acc1;
 #pragma unroll
@@ -213,7 +223,7 @@ __global__ __launch_bounds__(kThreads) void k_gemm(const uint16_t *__restrict__ 
         }
         __syncthreads();
     }
-    float *Cz = C + (int64_t)blockIdx.z * split_stride;
+    float *Cz = C + (int64_t)tz * split_stride;
     const int col = n0 + (lane & 31);
 #pragma unroll
     for (int i = 0; i < 16; ++i) {
