@@ -25,25 +25,70 @@ if ROOT not in sys.path:
 METRIC = "paths·steps/s for ∇G (F_v+R_v), K_R/K_F, % FP32 VALU peak; surrogate vs MC step"
 
 
-def cpu_baseline(pb, theta, C, sample_paths, min_seconds):
-    """The oracle, as it stands, on the first `sample_paths` paths, repeated
-    until at least `min_seconds` have passed."""
+def host_cpu_model():
+    try:
+        for ln in open("/proc/cpuinfo"):
+            if ln.startswith("model name"):
+                return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def oracle_leg(pb, theta, C, got, sample_paths_1t, min_seconds_1t, t_forward_gpu_ms):
+    """The FP64 oracle on the timed input: parity of the GPU result `got` =
+    (Ey, G, grad) with the oracle's two-pass gradient on all P paths (that
+    run, on every host thread, is also the multi-threaded CPU baseline), the
+    one-path share of every gradient component, and the oracle on one thread
+    on the first `sample_paths_1t` paths (forward alone and the gradient),
+    repeated for at least `min_seconds_1t` each: the analogue of the paper's
+    Cost(F), from which T_F,GPU / (P Cost_F,1 thread) is the K_F/c proxy."""
     from oracle import build as ob
     ob.build(force=False)
     from oracle import oracle as O
-    sub = pb.with_(n_paths=sample_paths)
-    reps = 0
+    from oracle import parity as PY
+    threads = O.get_threads()
     t0 = time.perf_counter()
-    while True:
-        O.gradient(sub, theta, C)
-        reps += 1
-        dt = time.perf_counter() - t0
-        if dt >= min_seconds:
-            break
-    return {"value": reps * sample_paths * pb.n_steps / dt, "unit": "paths*steps/s", "cores": O.get_threads(),
-            "kind": "oracle",
-            "sample": f"full two-pass gradient (forward, reverse sweep, FP64 sums) on the first {sample_paths} "
-                      f"of the {pb.n_paths} paths, {reps} time(s), {dt:.1f} s"}
+    Eo, Go, go = O.gradient(pb, theta, C)
+    t_all = time.perf_counter() - t0
+    shares = PY.gradient_shares(O, pb, theta, C, Eo)
+    Ey, G, g = got
+    par = {"theta": [float(v) for v in theta], "paths": pb.n_paths,
+           "ey_err": PY.ey_err(Ey, Eo), "grad_err": PY.grad_err(g, go), "grad_err_inf": PY.grad_err_inf(g, go),
+           "G_rel_err": abs(G - Go) / max(abs(Go), 1e-300),
+           "one_path_share": [float(v) for v in shares],
+           "tolerance": {"ey": PY.EY_TOL_FP32, "grad": PY.GRAD_TOL_FP32, "share_gate": PY.SHARE_GATE}}
+    par["within_tolerance"] = par["ey_err"] <= PY.EY_TOL_FP32 and par["grad_err"] <= PY.GRAD_TOL_FP32
+    par["well_conditioned"] = bool(max(shares) <= PY.SHARE_GATE)
+    sub = pb.with_(n_paths=sample_paths_1t)
+    O.set_threads(1)
+    try:
+        rates = {}
+        for name, fn in (("forward", lambda: O.forward(sub, theta)), ("gradient", lambda: O.gradient(sub, theta, C))):
+            reps, t0 = 0, time.perf_counter()
+            while True:
+                fn()
+                reps += 1
+                dt = time.perf_counter() - t0
+                if dt >= min_seconds_1t:
+                    break
+            rates[name] = (reps * sample_paths_1t * pb.n_steps / dt, reps, dt)
+    finally:
+        O.set_threads(threads)
+    cost_f_path_1t = pb.n_steps / rates["forward"][0]   # seconds per path of F, one thread
+    base = {"value": pb.n_paths * pb.n_steps / t_all, "unit": "paths*steps/s", "cores": threads,
+            "kind": "oracle", "cpu_model": host_cpu_model(),
+            "sample": f"full two-pass gradient (forward, reverse sweep, FP64 sums) on all {pb.n_paths} paths of "
+                      f"the timed input, once, {t_all:.2f} s on {threads} threads",
+            "single_thread": {
+                "forward_paths_steps_per_s": rates["forward"][0], "gradient_paths_steps_per_s": rates["gradient"][0],
+                "sample": f"first {sample_paths_1t} paths, forward {rates['forward'][1]}x in "
+                          f"{rates['forward'][2]:.1f} s, gradient {rates['gradient'][1]}x in "
+                          f"{rates['gradient'][2]:.1f} s"},
+            "kf_over_c_proxy": (t_forward_gpu_ms * 1e-3) / (pb.n_paths * cost_f_path_1t),
+            "kf_over_c_proxy_note": "T_F,GPU / (P Cost_F,oracle 1 thread); the oracle is plain scalar FP64, "
+                                    "not an optimised F, so this is a proxy for the paper's K_F/c"}
+    return par, base
 
 
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "mc_kernels_heston_2p20x256_hbm_counters.md")
@@ -71,6 +116,29 @@ def pass2_traffic(ckpt_every, ppl):
     for ln in lines:
         f = ln.split()
         if len(f) == 4 and f[0] == "k_pass2_bytes_per_launch" and f[1:3] == [f"K={ckpt_every}", f"ppl={ppl}"]:
+            value = float(f[3])
+        elif len(f) == 3 and f[0] == "code-sha256":
+            ok = ok and os.path.exists(os.path.join(ROOT, f[1])) and code_hash(os.path.join(ROOT, f[1])) == f[2]
+    return value if ok else None
+
+
+ISSUE_PROFILE = os.path.join(ROOT, "profiles", "mc_kernels_heston_2p20x256_valu_issue.md")
+
+
+def valu_issue_utilisation(ckpt_every):
+    """Measured VALU issue utilisation of the Heston pass-2 kernel at this
+    spacing: SQ_ACTIVE_INST_VALU over the busy cycles of every SIMD, scaled by
+    what the same ratio reads for a kernel of independent FP32 FMAs (one per
+    cycle and SIMD), from the committed counter summary; None when not taken
+    or stale."""
+    try:
+        lines = open(ISSUE_PROFILE).read().splitlines()
+    except OSError:
+        return None
+    value, ok = None, True
+    for ln in lines:
+        f = ln.split()
+        if len(f) == 4 and f[0] == "valu_issue_utilisation" and f[1:3] == ["k_pass2", f"K={ckpt_every}"]:
             value = float(f[3])
         elif len(f) == 3 and f[0] == "code-sha256":
             ok = ok and os.path.exists(os.path.join(ROOT, f[1])) and code_hash(os.path.join(ROOT, f[1])) == f[2]
@@ -348,20 +416,101 @@ def copy_probe(nbytes):
     print(json.dumps({"copy_probe_bytes": nbytes, "launches": 3}), flush=True)
 
 
+def timed_gradient(mc, theta_np, C, steps, warmup):
+    """Time `steps` calibrate_gradient calls and `steps` calibrate_forward
+    calls on one context (inputs resident on the device); returns the
+    timings, the library's per-pass kernel averages and the last outputs."""
+    import numpy as np
+    import torch
+    from paper_1901_04200_amd import capi
+    ctx = mc.ctx
+    theta = torch.tensor(theta_np, dtype=torch.float64, device="cuda")
+    Ey = torch.empty(mc.m, dtype=torch.float64, device="cuda")
+    G = torch.empty(1, dtype=torch.float64, device="cuda")
+    g = torch.empty(mc.M, dtype=torch.float64, device="cuda")
+
+    def grad_step():
+        capi.calibrate_gradient(ctx, theta, C, Ey, G, g)
+
+    def fwd_step():
+        capi.calibrate_forward(ctx, theta, Ey)
+
+    for _ in range(warmup):
+        grad_step()
+        fwd_step()
+    torch.cuda.synchronize()
+    capi.cal_timing_enable(ctx, True)
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record()
+    for _ in range(steps):
+        grad_step()
+    ev1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_step = ev0.elapsed_time(ev1) / steps
+    p1_ms, p1_n = capi.cal_timing_read(ctx, 0)
+    p2_ms, p2_n = capi.cal_timing_read(ctx, 1)
+    got = (Ey.cpu().numpy().copy(), float(G.item()), g.cpu().numpy().copy())
+    capi.cal_timing_enable(ctx, True)
+    ev0.record()
+    for _ in range(steps):
+        fwd_step()
+    ev1.record()
+    torch.cuda.synchronize()
+    ms_fwd = ev0.elapsed_time(ev1) / steps
+    f_ms, f_n = capi.cal_timing_read(ctx, 0)
+    capi.cal_timing_enable(ctx, False)
+    status = mc.status()
+    return {"ms_step": ms_step, "wall": wall, "ms_fwd": ms_fwd, "pass1_avg": p1_ms / max(p1_n, 1),
+            "pass2_avg": p2_ms / max(p2_n, 1), "t_f": f_ms / max(f_n, 1), "status": status, "got": got}
+
+
+def theta0_leg(pb, th0, C, ckpt_every, ppl, steps, warmup):
+    """The first draw of the Heston box (2 kappa theta_bar << xi^2): the FP32
+    gradient timed there and compared with the oracle, and the FP64 path at
+    the same point (its prices are the parity-checked ones there)."""
+    from oracle import parity as PY
+    from oracle import oracle as O
+    from paper_1901_04200_amd.mc import MonteCarloCalibration
+    out = {"theta": [float(v) for v in th0], "feller_ratio": float(2 * th0[0] * th0[1] / th0[2] ** 2)}
+    Eo, Go, go = O.gradient(pb, th0, C.cpu().numpy())
+    shares = PY.gradient_shares(O, pb, th0, C.cpu().numpy(), Eo)
+    out["one_path_share"] = [float(v) for v in shares]
+    for prec, k in (("fp32", ckpt_every), ("fp64", 8)):
+        mc = MonteCarloCalibration(pb, precision=prec, ckpt_every=k, ckpt_mode="store",
+                                   paths_per_lane=ppl if prec == "fp32" else 1)
+        r = timed_gradient(mc, th0, C, max(3, steps // 2), warmup)
+        mc.close()
+        Ey, G, g = r["got"]
+        out[prec] = {"ms_per_step": r["ms_step"], "paths_steps_per_s": pb.n_paths * pb.n_steps / (r["ms_step"] * 1e-3),
+                     "ckpt_every": k, "status": r["status"],
+                     "ey_err": PY.ey_err(Ey, Eo), "grad_err": PY.grad_err(g, go),
+                     "grad_err_inf": PY.grad_err_inf(g, go), "G_rel_err": abs(G - Go) / abs(Go),
+                     "ey_within_tolerance": PY.ey_err(Ey, Eo) <= PY.EY_TOL_FP32}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
+    ap.add_argument("--theta", default="feller", choices=["feller", "first"],
+                    help="timed parameter vector: the tenth draw of the Heston box (2 kappa theta_bar > xi^2, "
+                         "the full-size parity test's) or the first draw (Feller's condition badly violated)")
     ap.add_argument("--ckpt-mode", default="store", choices=["store", "rerun"])
     ap.add_argument("--ckpt-every", type=int, default=0, help="8, 16 or 32; 0 = tuned (8 or 16)")
     ap.add_argument("--paths-per-lane", type=int, default=0, help="1, 2 or 4; 0 = tuned (1 or 2)")
-    ap.add_argument("--cpu-sample-paths", type=int, default=1 << 20)
-    ap.add_argument("--cpu-min-seconds", type=float, default=10.0)
+    ap.add_argument("--cpu-sample-paths", type=int, default=1 << 13,
+                    help="paths of the single-thread oracle timing")
+    ap.add_argument("--cpu-min-seconds", type=float, default=4.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the extra legs")
-    ap.add_argument("--extras", default="slv,lv,e2_sweep,batched,surrogate_vs_mc",
+    ap.add_argument("--extras", default="theta0,rerun,slv,lv,e2_sweep,batched,surrogate_vs_mc",
                     help="comma-separated extra legs to run")
     ap.add_argument("--sweep-paths", type=int, default=1 << 20)
     ap.add_argument("--batch-instances", type=int, default=256)
@@ -379,15 +528,16 @@ def main():
               f"paths over GPUs is a design note, not built.", file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
 
-    from paper_1901_04200_amd import capi, costmodel, roofline
+    from paper_1901_04200_amd import costmodel, roofline
     from paper_1901_04200_amd import workloads as W
     from paper_1901_04200_amd.mc import MonteCarloCalibration
 
     torch.cuda.set_device(0)
     pb, th0, tht, eps = W.heston_problem()
+    th_feller = W.heston_draws(2, 10)[9]
+    theta_np = th_feller if args.theta == "feller" else th0
     P, N = pb.n_paths, pb.n_steps
     # targets: model prices at the target draw (Philox seed 2) plus 0.1 % noise
     gen = MonteCarloCalibration(pb.with_(seed=2), precision=args.precision)
@@ -396,74 +546,32 @@ def main():
     ckpt_every, ppl, tune_table = args.ckpt_every, args.paths_per_lane, None
     if ckpt_every == 0 or ppl == 0:
         from paper_1901_04200_amd.mc import pick_config
-        (ckpt_every, ppl), tune_table = pick_config(pb, th0, C, precision=args.precision,
+        (ckpt_every, ppl), tune_table = pick_config(pb, theta_np, C, precision=args.precision,
                                                     ks=(8, 16) if ckpt_every == 0 else (ckpt_every,),
                                                     ppls=(1, 2) if ppl == 0 else (ppl,))
         print(f"bench: checkpoint spacing {ckpt_every}, {ppl} path(s) per lane ({tune_table})", file=sys.stderr,
               flush=True)
     mc = MonteCarloCalibration(pb, precision=args.precision, ckpt_every=ckpt_every, ckpt_mode=args.ckpt_mode,
                                paths_per_lane=ppl)
-    theta = torch.tensor(th0, dtype=torch.float64, device="cuda")
-    Ey = torch.empty(pb.n_instr, dtype=torch.float64, device="cuda")
-    G = torch.empty(1, dtype=torch.float64, device="cuda")
-    g = torch.empty(5, dtype=torch.float64, device="cuda")
-    ctx = mc.ctx
-
-    def grad_step():
-        capi.calibrate_gradient(ctx, theta, C, Ey, G, g)
-
-    def fwd_step():
-        capi.calibrate_forward(ctx, theta, Ey)
-
-    for _ in range(args.warmup):
-        grad_step()
-        fwd_step()
-    torch.cuda.synchronize()
-    print(f"bench: warmup done ({args.warmup} gradient + forward calls)", file=sys.stderr, flush=True)
-
-    # --- timed region: K gradient steps --------------------------------------
-    capi.cal_timing_enable(ctx, True)
-    torch.cuda.synchronize()
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    t0 = time.perf_counter()
-    ev0.record()
-    for _ in range(args.steps):
-        grad_step()
-    ev1.record()
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    ms_step = ev0.elapsed_time(ev1) / args.steps
-    p1_ms, p1_n = capi.cal_timing_read(ctx, 0)
-    p2_ms, p2_n = capi.cal_timing_read(ctx, 1)
-    assert mc.status() == 0, "device status flags set"
-    print(f"bench: {args.steps} gradient steps, {ms_step:.3f} ms/step (wall {wall:.3f} s)", file=sys.stderr,
+    geo = mc.geometry()
+    r = timed_gradient(mc, theta_np, C, args.steps, args.warmup)
+    mc.close()
+    assert r["status"] == 0, "device status flags set"
+    ms_step = r["ms_step"]
+    print(f"bench: {args.steps} gradient steps, {ms_step:.3f} ms/step (wall {r['wall']:.3f} s)", file=sys.stderr,
           flush=True)
 
-    # --- forward pass alone (T_F) ----------------------------------------------
-    capi.cal_timing_enable(ctx, True)
-    ev0.record()
-    for _ in range(args.steps):
-        fwd_step()
-    ev1.record()
-    torch.cuda.synchronize()
-    ms_fwd = ev0.elapsed_time(ev1) / args.steps
-    f_ms, f_n = capi.cal_timing_read(ctx, 0)
-    capi.cal_timing_enable(ctx, False)
-
-    pass1_avg = p1_ms / max(p1_n, 1)
-    pass2_avg = p2_ms / max(p2_n, 1)
-    t_f = f_ms / max(f_n, 1)
+    pass2_avg, t_f = r["pass2_avg"], r["t_f"]
     kr_kf = costmodel.kr_over_kf(t_f, pass2_avg)
     path_steps = P * N
     model = "heston"
     kern = "pass2" if args.ckpt_mode == "store" else "pass2_rerun"
     w2 = roofline.per_path_step(model, kern)
-    slots2 = roofline.slots(w2) * path_steps
-    achieved = slots2 / (pass2_avg * 1e-3)
+    flops2 = w2["flops"] * path_steps                      # FP32 flops of one pass-2 launch
+    achieved = flops2 / (pass2_avg * 1e-3) / 1e12          # TFLOP/s
+    slots_frac = roofline.slots(w2) * path_steps / (pass2_avg * 1e-3) / roofline.PEAK_SLOTS
     flops_all = (roofline.per_path_step(model, "pass1")["flops"] + w2["flops"]) * path_steps
     fp32_tflops = flops_all / (ms_step * 1e-3) / 1e12
-    geo = mc.geometry()
 
     out = {
         "metric": METRIC,
@@ -481,37 +589,53 @@ def main():
         "config": {
             "workload": "Heston calibration gradient: 2^20 paths x 256 Euler steps, m=40 calls "
                         "(8 strikes x 5 maturities), M=5, full truncation, FP32 state, FP64 sums",
+            "theta": [float(v) for v in theta_np],
+            "theta_draw": "tenth draw of the Heston box (rng 2), 2 kappa theta_bar > xi^2" if args.theta == "feller"
+                          else "first draw of the Heston box (rng 2), 2 kappa theta_bar << xi^2",
             "n_paths": P, "n_steps": N, "n_instr": pb.n_instr, "n_params": 5,
             "ckpt_every": geo["ckpt_every"], "ckpt_mode": args.ckpt_mode,
             "paths_per_lane": ppl,
             "tuning_ms": None if tune_table is None else {f"k{k}_ppl{q}": t * 1e3 for (k, q), t in tune_table},
             "threads_per_block": geo["threads"], "blocks": geo["blocks"],
         },
-        "forward_value": path_steps / (ms_fwd * 1e-3),
-        "ms_forward": ms_fwd,
-        "ms_pass1_kernel": pass1_avg,
+        "forward_value": path_steps / (r["ms_fwd"] * 1e-3),
+        "ms_forward": r["ms_fwd"],
+        "ms_pass1_kernel": r["pass1_avg"],
         "ms_pass2_kernel": pass2_avg,
         "kr_over_kf": kr_kf,
         "cost_g_over_cost_f": costmodel.gradient_over_forward(kr_kf),
-        "fp32_tflops": fp32_tflops,
-        "fp32_valu_peak_frac": fp32_tflops / roofline.PEAK_FP32_TFLOPS,
+        "fp32_tflops_whole_step": fp32_tflops,
+        "fp32_peak_frac_whole_step": fp32_tflops / roofline.PEAK_FP32_TFLOPS,
+        "parity": None,
         "surrogate_vs_mc": None,
         "roofline": {
             "bound": "alu",
             "kernel": "k_pass2 (Heston, FP32, K=%d, %s)" % (geo["ckpt_every"], args.ckpt_mode),
-            "achieved": achieved / 1e12,
-            "peak": roofline.PEAK_SLOTS / 1e12,
-            "unit": "T VALU lane-slots/s",
-            "frac": achieved / roofline.PEAK_SLOTS,
+            "achieved": achieved,
+            "peak": roofline.PEAK_FP32_TFLOPS,
+            "unit": "TFLOP/s",
+            "frac": achieved / roofline.PEAK_FP32_TFLOPS,
+            "flops_per_path_step": w2["flops"],
+            "frac_ceiling_at_full_issue": roofline.flop_ceiling(w2),
+            "issue_slots_per_path_step": roofline.slots(w2),
+            "issue_frac_cost_model": slots_frac,
+            "issue_frac_counters": valu_issue_utilisation(geo["ckpt_every"]),
             "traffic": pass2_traffic(geo["ckpt_every"], ppl),
             "traffic_unit": "HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-scaled)",
             "traffic_algorithmic": roofline.pass2_bytes(pb.n_paths, geo["ckpt_every"], geo["blocks"], pb.n_instr,
                                                         pb.n_steps),
         },
     }
-    mc.close()
+    if not args.no_cpu_baseline:
+        print("bench: oracle parity of the timed input and CPU baseline ...", file=sys.stderr, flush=True)
+        out["parity"], out["cpu_baseline"] = oracle_leg(pb, theta_np, C.cpu().numpy(), r["got"],
+                                                        args.cpu_sample_paths, args.cpu_min_seconds, t_f)
+        print(f"bench: parity {out['parity']['ey_err']:.2e} (E y) {out['parity']['grad_err']:.2e} (grad)",
+              file=sys.stderr, flush=True)
     if not args.no_extras:
-        legs = (("slv", lambda: slv_leg(max(5, args.steps // 2))),
+        legs = (("theta0", lambda: theta0_leg(pb, th0, C, ckpt_every, ppl, args.steps, args.warmup)),
+                ("rerun", lambda: rerun_leg(pb, theta_np, C, ckpt_every, ppl, args.steps, args.warmup, t_f)),
+                ("slv", lambda: slv_leg(max(5, args.steps // 2))),
                 ("lv", lambda: lv_leg(max(5, args.steps // 2))),
                 ("e2_sweep", lambda: e2_sweep(args.sweep_paths)),
                 ("batched", lambda: batched_leg(args.batch_instances, max(3, args.steps // 4))),
@@ -526,11 +650,22 @@ def main():
             except Exception as exc:   # a failing extra leg must not hide the headline numbers
                 out[name] = {"error": f"{type(exc).__name__}: {exc}"}
             print(f"bench: {name} done", file=sys.stderr, flush=True)
-    if not args.no_cpu_baseline:
-        print("bench: oracle CPU baseline ...", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(pb, th0, C.cpu().numpy(), args.cpu_sample_paths,
-                                           args.cpu_min_seconds)
     print(json.dumps(out), flush=True)
+
+
+def rerun_leg(pb, theta_np, C, ckpt_every, ppl, steps, warmup, t_f):
+    """The paper's memory-lean case: pass 2 re-runs the forward sweep itself
+    (Cost(G) = (2 K_F + K_R)/c per path), beside the stored-checkpoint default."""
+    from paper_1901_04200_amd import costmodel
+    from paper_1901_04200_amd.mc import MonteCarloCalibration
+    mc = MonteCarloCalibration(pb, ckpt_every=ckpt_every, ckpt_mode="rerun", paths_per_lane=ppl)
+    r = timed_gradient(mc, theta_np, C, steps, warmup)
+    mc.close()
+    return {"ckpt_mode": "rerun", "ckpt_every": ckpt_every, "ms_per_step": r["ms_step"],
+            "paths_steps_per_s": pb.n_paths * pb.n_steps / (r["ms_step"] * 1e-3),
+            "ms_pass1_kernel": r["pass1_avg"], "ms_pass2_kernel": r["pass2_avg"], "status": r["status"],
+            "cost_g_over_cost_f": (r["pass1_avg"] + r["pass2_avg"]) / t_f,
+            "kr_over_kf": costmodel.kr_over_kf(t_f, r["pass2_avg"] - t_f)}
 
 
 def surrogate_leg(args):

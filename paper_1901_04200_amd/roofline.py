@@ -30,7 +30,16 @@ the scalar unit and are not counted):
     adjoint of v (3)                       = 17 valu + 1 trans            (21 slots)
   pass 1 (F)                               = F
   pass 2 from stored checkpoints (F + R)   = 8 mad64 + 42 valu + 6 trans  (98 slots)
-FP32 flops (FMA = 2) per path-step: F 18, R 23.
+FP32 flops per path-step, counting every FP32 arithmetic result: add, mul
+1, FMA 2, transcendental (log2, sqrt, sin, cos, rcp, exp2) 1:
+  F: uniforms 2, Box-Muller 3 + 4 trans, Euler 13 + 1 trans      = 23
+  R: 23 + 1 (rcp)                                                  = 24
+  pass 2 from checkpoints (F + R)                                  = 47
+The flop fraction of the FP32 peak that this work can reach is bounded by
+the issue slots it needs: 157.3 TFLOP/s counts two flops per lane-slot
+(packed or dual-issued FMA), so a kernel issuing one FP32 op per slot and
+nothing else reaches 0.5 of it; pass 2 spends 98 slots on 47 flops, so
+its ceiling at full issue is 47 / (2 x 98) = 0.24 of 157.3 TFLOP/s.
 """
 
 CUS = 256
@@ -42,10 +51,16 @@ PEAK_FP32_TFLOPS = 157.3        # published FP32 vector peak (FMA = 2 flops)
 COST_MAD64 = 4.0
 COST_TRANS = 4.0
 
-HESTON_F = {"mad64": 8, "valu": 25, "trans": 5, "flops": 18}
-HESTON_R = {"mad64": 0, "valu": 17, "trans": 1, "flops": 23}
-BS_F = {"mad64": 4, "valu": 10, "trans": 2, "flops": 5}     # quarter call + one normal per step
+HESTON_F = {"mad64": 8, "valu": 25, "trans": 5, "flops": 23}
+HESTON_R = {"mad64": 0, "valu": 17, "trans": 1, "flops": 24}
+BS_F = {"mad64": 4, "valu": 10, "trans": 2, "flops": 7}     # quarter call + one normal per step
 BS_R = {"mad64": 0, "valu": 3, "trans": 0, "flops": 3}
+
+
+def flop_ceiling(op: dict) -> float:
+    """Largest fraction of the FP32 peak (two flops per lane-slot) that work
+    `op` reaches when every slot issues."""
+    return op["flops"] / (2.0 * slots(op))
 
 
 def slots(op: dict) -> float:

@@ -16,6 +16,7 @@ import pytest
 torch = pytest.importorskip("torch")
 
 from paper_1901_04200_amd import autograd as AG
+from oracle import parity as PY
 from paper_1901_04200_amd import workloads as W
 from paper_1901_04200_amd.mc import MonteCarloCalibration
 
@@ -32,12 +33,8 @@ def gpu():
         pytest.skip("no HIP device")
 
 
-def ey_err(a, b):
-    return float(np.max(np.abs(np.asarray(a) - b) / np.maximum(np.abs(b), 1e-2)))
-
-
-def g_err(a, b):
-    return float(np.max(np.abs(np.asarray(a) - b)) / np.max(np.abs(b)))
+ey_err = PY.ey_err
+g_err = PY.grad_err          # per component: max_j |dg_j| / max(|g_j|, 1e-3 max|g|)
 
 
 def run(pb, th, C, precision, **kw):

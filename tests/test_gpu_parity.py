@@ -1,14 +1,18 @@
 """GPU parity: the HIP library through its C ABI against the FP64 CPU oracle
 on identical random streams.
 
-Tolerances (floating point, relative):
-  E y  : max_i |dEy_i| / max(|Ey_i|, 1e-2)  <= 1e-5 (FP32 state), 1e-12 (FP64)
-  grad : max_j |dg_j| / max_j |g_j|          <= 1e-4 (FP32 state), FP64 below
-Both precisions are held to these bounds where the problem is well
-conditioned (Heston draws with 2 kappa theta_bar > xi^2).  At the first
-Heston draw (2 kappa theta_bar << xi^2) a handful of paths whose variance
-nears zero carry most of the exact pathwise gradient and amplify rounding;
-there the errors against FP64 are stated and only loosely bounded.
+Tolerances (floating point, relative; oracle.parity):
+  E y  : max_i |dEy_i| / max(|Ey_i|, 1e-2)                        <= 1e-5 (FP32 state), 1e-12 (FP64)
+  grad : max_j |dg_j| / max(|g_j|, 1e-3 max_k |g_k|), per component <= 1e-4 (FP32 state), FP64 below
+The gradient bound is asserted where the sum over paths is well conditioned:
+no single path carries more than 5% of any gradient component (the
+one-path share, measured by the oracle's per-path reverse sweeps).  At the
+first Heston draw (2 kappa theta_bar << xi^2) one path carries most of
+dG/dkappa, and last-bit differences between two correct implementations
+along it decide the result; there the errors are stated with the share.
+Prices there are asserted in FP64; FP32 state cannot reach 1e-5 at that
+point (the variance recursion needs about 40-bit normals and arithmetic,
+see tests/test_precision_floor.py), so its error is stated.
 Integer work (Philox words) is compared bit for bit.
 """
 import sys
@@ -18,6 +22,7 @@ import pytest
 
 torch = pytest.importorskip("torch")
 
+from oracle import parity as PY
 from paper_1901_04200_amd import capi
 from paper_1901_04200_amd import workloads as W
 from paper_1901_04200_amd.mc import MonteCarloCalibration
@@ -38,14 +43,9 @@ def gpu():
     return torch.device("cuda", 0)
 
 
-def ey_err(a, b):
-    a, b = np.asarray(a), np.asarray(b)
-    return float(np.max(np.abs(a - b) / np.maximum(np.abs(b), 1e-2)))
-
-
-def g_err(a, b):
-    a, b = np.asarray(a), np.asarray(b)
-    return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300))
+ey_err = PY.ey_err
+g_err = PY.grad_err          # per component
+g_err_inf = PY.grad_err_inf  # relative to the largest component
 
 
 def run_all(pb, theta, C, precision="fp32", **kw):
@@ -144,7 +144,10 @@ def test_heston_fp32_well_conditioned(orc, heston_small):
     say("heston fp32 P=2^14+37 N=256 (Feller draw)")
     r = run_all(pb, th, C, "fp32")
     Ey, G, g = orc.gradient(pb, th, C)
-    say("heston fp32 errors: Ey %.3g grad %.3g" % (ey_err(r["Ey"], Ey), g_err(r["g"], g)))
+    share = PY.gradient_shares(orc, pb, th, C, Ey)
+    say("heston fp32 errors: Ey %.3g grad %.3g (inf %.3g); one-path shares %s" % (
+        ey_err(r["Ey"], Ey), g_err(r["g"], g), g_err_inf(r["g"], g), np.round(share, 4)))
+    assert share.max() <= PY.SHARE_GATE
     assert ey_err(r["Ey_f"], Ey) <= 1e-5
     assert ey_err(r["Ey"], Ey) <= 1e-5
     assert abs(r["G"] - G) <= 1e-4 * G
@@ -174,30 +177,40 @@ def test_heston_fp64_well_conditioned(orc, heston_small):
 
 def test_heston_fp64_first_draw(orc, heston_small):
     """At the first draw (2 kappa theta_bar << xi^2) last-bit differences
-    between the GPU's and the CPU's FP64 arithmetic are amplified by the
-    paths whose variance nears zero: prices still agree to ~1e-9, the exact
-    pathwise gradient does not (its value hinges on those few paths).  The
-    errors are reported; prices are asserted."""
+    between the GPU's and the CPU's FP64 arithmetic are amplified along the
+    paths whose variance nears zero: prices agree to ~1e-9 (asserted at the
+    FP32 bound with room to spare), the exact pathwise gradient does not,
+    because one path carries most of a component (the one-path share, which
+    gates the gradient assertion: above 5% the error is stated)."""
     pb, th0, tht, C = heston_small
     say("heston fp64 at the first draw (Feller violated)")
     r = run_all(pb, th0, C, "fp64")
     Ey, G, g = orc.gradient(pb, th0, C)
-    say("heston fp64 first-draw errors: Ey %.3g grad %.3g" % (ey_err(r["Ey"], Ey), g_err(r["g"], g)))
+    share = PY.gradient_shares(orc, pb, th0, C, Ey)
+    say("heston fp64 first-draw errors: Ey %.3g grad %.3g (inf %.3g); one-path shares %s" % (
+        ey_err(r["Ey"], Ey), g_err(r["g"], g), g_err_inf(r["g"], g), np.round(share, 4)))
     assert ey_err(r["Ey"], Ey) <= 1e-8
     assert np.all(np.isfinite(r["g"]))
+    if share.max() <= PY.SHARE_GATE:
+        assert g_err(r["g"], g) <= 1e-9
+    else:
+        assert share.max() > 0.5   # the documented ill-conditioning: one path decides a component
 
 
 def test_heston_fp32_first_draw_stated(orc, heston_small):
     """At the first draw the Euler variance recursion amplifies rounding along
     paths whose variance nears zero (the tangent of v is multiplied by about
-    1 + xi sqrt(h) w / (2 sqrt(v)) per step), so an FP32 trajectory drifts
-    from the FP64 one.  The errors are stated; the bound only guards against
-    regressions (measured: Ey 4e-4, gradient 0.6 at this size)."""
+    1 + xi sqrt(h) w / (2 sqrt(v)) per step, and a perturbation d of v near
+    zero moves the next variance by about xi sqrt(h d) w), so an FP32
+    trajectory drifts from the FP64 one.  The errors are stated; the bound
+    only guards against regressions (measured: Ey 4e-4, gradient ~1 at this
+    size)."""
     pb, th0, tht, C = heston_small
     say("heston fp32 at the first draw")
     r = run_all(pb, th0, C, "fp32")
     Ey, G, g = orc.gradient(pb, th0, C)
-    say("heston fp32 (first draw) errors: Ey %.3g grad %.3g" % (ey_err(r["Ey"], Ey), g_err(r["g"], g)))
+    say("heston fp32 (first draw) errors: Ey %.3g grad %.3g (inf %.3g)" % (
+        ey_err(r["Ey"], Ey), g_err(r["g"], g), g_err_inf(r["g"], g)))
     assert ey_err(r["Ey"], Ey) <= 2e-3
     assert np.all(np.isfinite(r["g"]))
 
@@ -440,6 +453,11 @@ def test_single_instrument_first_step(orc):
 # benchmark times
 # ---------------------------------------------------------------------------
 def test_heston_full_size(orc):
+    """The benchmark's workload at full size (2^20 paths x 256 steps, m = 40)
+    in the launch configuration it times.  At the Feller draw the benchmark
+    times, FP32 meets both bounds (the sum is well conditioned: every
+    one-path share <= 5%).  At the first draw, FP64 prices meet the FP32
+    bound; the FP32 price error and the conditioning there are stated."""
     pb, th0, tht, eps = W.heston_problem()
     th = W.heston_draws(2, 10)[9]
     say("full size: oracle targets at the target draw, 2^20 paths (seed 2)")
@@ -447,17 +465,25 @@ def test_heston_full_size(orc):
     say("full size: fp32 gradient at a Feller draw")
     r = run_all(pb, th, C, "fp32")
     Ey, G, g = orc.gradient(pb, th, C)
-    say("full-size fp32 errors: Ey %.3g grad %.3g" % (ey_err(r["Ey"], Ey), g_err(r["g"], g)))
+    share = PY.gradient_shares(orc, pb, th, C, Ey)
+    say("full-size fp32 errors: Ey %.3g grad %.3g (inf %.3g); shares %s" % (
+        ey_err(r["Ey"], Ey), g_err(r["g"], g), g_err_inf(r["g"], g), np.round(share, 5)))
+    assert share.max() <= PY.SHARE_GATE
     assert ey_err(r["Ey"], Ey) <= 1e-5
     assert g_err(r["g"], g) <= 1e-4
-    say("full size: fp32 forward at the first draw")
-    mc = MonteCarloCalibration(pb, precision="fp32")
-    Ey0_g = mc.forward(th0).cpu().numpy()
-    mc.close()
+    assert abs(r["G"] - G) <= 1e-4 * G
+    say("full size: fp32 and fp64 at the first draw")
     Ey0 = orc.forward(pb, th0)
-    say("full-size fp32 first-draw Ey error %.3g" % ey_err(Ey0_g, Ey0))
-    # ill-conditioned point (see test_heston_fp32_first_draw_stated): stated, guarded loosely
-    assert ey_err(Ey0_g, Ey0) <= 5e-4
+    out = {}
+    for prec in ("fp32", "fp64"):
+        mc = MonteCarloCalibration(pb, precision=prec)
+        out[prec] = ey_err(mc.forward(th0).cpu().numpy(), Ey0)
+        mc.close()
+    say("full-size first-draw Ey errors: fp32 %.3g, fp64 %.3g" % (out["fp32"], out["fp64"]))
+    assert out["fp64"] <= 1e-5
+    # FP32 state at this point: stated (its floor is the normals' and the
+    # variance recursion's precision), guarded loosely
+    assert out["fp32"] <= 5e-4
 
 
 @pytest.mark.parametrize("model", ["bs", "heston"])

@@ -1,0 +1,49 @@
+"""How many bits the Heston variance recursion needs for E y within 1e-5.
+
+tests/pins/precision_floor.c prices the Heston workload's 40 calls on 2^18
+paths twice on identical normals: in FP64, and with every normal and every
+result of the variance recursion rounded to k significant bits (k = 24 is
+FP32 storage).  At the Feller draw the benchmark times (2 kappa theta_bar >
+xi^2) 24 bits leave the prices within 1e-8 of FP64.  At the first draw of
+the Heston box (2 kappa theta_bar = 0.12 << xi^2 = 0.69) the variance often
+lands next to zero, where sqrt turns a perturbation d of v into about
+xi sqrt(h d) w of the next step; the price error then falls only slowly with
+k and needs about 40 bits to reach 1e-5: FP32 state cannot meet the price
+bound there however it rounds, FP64 meets it.  CPU only; no GPU involved.
+"""
+import os
+import subprocess
+
+import pytest
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "pins", "precision_floor.c")
+
+TH0 = (1.6772546, 0.0368642, 0.83280317, -0.81727565, 0.06400905)          # first draw (rounded)
+FELLER = (2.0256141859218952, 0.057054565353138756, 0.294601051917113, -0.8093667581833709,
+          0.013474371692887196)                                               # tenth draw
+
+
+@pytest.fixture(scope="module")
+def floor_exe(tmp_path_factory):
+    exe = str(tmp_path_factory.mktemp("pf") / "precision_floor")
+    subprocess.run(["gcc", "-O2", "-fopenmp", "-ffp-contract=off", "-o", exe, SRC, "-lm"], check=True)
+    return exe
+
+
+def price_err(exe, k, theta, paths=1 << 18):
+    out = subprocess.run([exe, str(paths), str(k), *map(repr, theta)], check=True, capture_output=True, text=True,
+                         env={**os.environ, "OMP_NUM_THREADS": str(min(8, os.cpu_count() or 1))})
+    return float(out.stdout)
+
+
+def test_feller_draw_is_well_conditioned(floor_exe):
+    assert price_err(floor_exe, 24, FELLER) < 1e-7
+
+
+def test_first_draw_needs_about_40_bits(floor_exe):
+    e = {k: price_err(floor_exe, k, TH0) for k in (24, 32, 40, 48)}
+    print("first-draw price error by bits:", {k: f"{v:.2e}" for k, v in e.items()})
+    assert e[24] > 1e-5 and e[32] > 1e-5      # FP32 storage, and 8 bits more, miss the bound
+    assert e[40] < 1e-5                        # about 40 bits meet it
+    assert e[48] < 1e-6 and e[48] < e[40]
