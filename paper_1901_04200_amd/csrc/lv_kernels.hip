@@ -13,8 +13,9 @@
 // get sigmabar (1-al)(1-be), (1-al) be, al (1-be), al be at (a, b), (a, b+1),
 // (a+1, b), (a+1, b+1).  b differs per lane, a and al do not: each lane
 // accumulates sum (1-al) w_k and sum al w_k over the steps of one time cell in
-// its own LDS slice (FP32), and when the time cell changes the workgroup sums
-// the slices over lanes in a fixed tree into FP64 node sums.
+// its own LDS slice (in the path precision: FP32, or FP64 in the FP64 mode),
+// and when the time cell changes the workgroup sums the slices over lanes in a
+// fixed tree into FP64 node sums.
 #include <hip/hip_runtime.h>
 
 #include "mc_device.hpp"
@@ -35,7 +36,7 @@ template <typename R>
 struct LvLds {
     double *dbl;   // pass 1: [waves][m] payoff sums; pass 2: [nT*nK] node sums
     R *rows;
-    float *slices;   // pass 2: [2*nK][kBlock]
+    R *slices;   // pass 2: [2*nK][kBlock], path precision
 };
 
 template <typename R>
@@ -48,7 +49,7 @@ __device__ LvLds<R> carve(const DevProblem &pb, unsigned char *base, int ndbl)
     L.rows = (R *)(base + o);
     o += sizeof(R) * pb.K * pb.nK;
     o = (o + 15) & ~(size_t)15;
-    L.slices = (float *)(base + o);
+    L.slices = (R *)(base + o);
     return L;
 }
 
@@ -210,7 +211,7 @@ __global__ __launch_bounds__(kBlock) void k_lv_pass2(DevProblem pb, const double
     }
     if constexpr (!FROM_CKPT) save_theta(pb, theta, blockIdx.x);
     for (int i = tid; i < pb.nT * pb.nK; i += kBlock) L.dbl[i] = 0.0;
-    for (int i = tid; i < 2 * pb.nK * kBlock; i += kBlock) L.slices[i] = 0.f;
+    for (int i = tid; i < 2 * pb.nK * kBlock; i += kBlock) L.slices[i] = (R)0;
     __syncthreads();
 
     const R s0 = (R)pb.s0, rh = (R)(pb.rate * pb.h), hh = (R)(0.5 * pb.h), sq = (R)pb.sq, h = (R)pb.h;
@@ -258,7 +259,7 @@ __global__ __launch_bounds__(kBlock) void k_lv_pass2(DevProblem pb, const double
     for (int i = 0; i < PPL; ++i) xb[i] = (R)0;
     int cur_a = ldc(pb.step_row, pb.N - 1);
     int dhi = pb.ndates;
-    float *my0 = L.slices + tid;   // this lane's column of the slices
+    R *my0 = L.slices + tid;   // this lane's column of the slices
     const int rowB = pb.nK * kBlock;
     for (int seg = pb.nseg - 1; seg >= 0; --seg) {
         const int n0 = seg * K;
@@ -317,16 +318,16 @@ __global__ __launch_bounds__(kBlock) void k_lv_pass2(DevProblem pb, const double
         dhi = dlo;
         // one reverse step of path i: the adjoint of x~ through step n0 + j; its
         // four node adjoints (nodes b, b + 1 of rows a and a + 1) in u[0..3]
-        auto reverse_step = [&](int i, int j, float *u) {
+        auto reverse_step = [&](int i, int j, R *u) {
             xb[i] += s_inj[i][j];
             const R sbar = xb[i] * s_c[i][j];
             xb[i] = xb[i] + sbar * s_d[i][j];
             const R al = step_al<R>(pb, n0 + j);
             const R w1 = sbar * s_be[i][j], w0 = sbar - w1;
-            u[0] = (float)((1 - al) * w0);
-            u[1] = (float)((1 - al) * w1);
-            u[2] = (float)(al * w0);
-            u[3] = (float)(al * w1);
+            u[0] = (1 - al) * w0;
+            u[1] = (1 - al) * w1;
+            u[2] = al * w0;
+            u[3] = al * w1;
         };
         // the time cell of the segment's last step (cells do not decrease with n)
         const int a_last = ldc(pb.step_row, min(n0 + K, pb.N) - 1);
@@ -341,19 +342,19 @@ __global__ __launch_bounds__(kBlock) void k_lv_pass2(DevProblem pb, const double
             // value just written is forwarded instead, so the LDS latency overlaps
             // the arithmetic and the sums are exactly those of one update at a
             // time (updates in the order: step K-1 path 0, path 1, ..., step 0).
-            float *col = my0 + s_b[0][K - 1] * kBlock;
-            float r0 = col[0], r1 = col[kBlock], r2 = col[rowB], r3 = col[rowB + kBlock];
+            R *col = my0 + s_b[0][K - 1] * kBlock;
+            R r0 = col[0], r1 = col[kBlock], r2 = col[rowB], r3 = col[rowB + kBlock];
 #pragma unroll
             for (int j = K - 1; j >= 0; --j) {
 #pragma unroll
                 for (int i = 0; i < PPL; ++i) {
-                    float u[4];
+                    R u[4];
                     reverse_step(i, j, u);
                     const bool last = j == 0 && i == PPL - 1;
                     const int inext = i + 1 < PPL ? i + 1 : 0;
                     const int jnext = i + 1 < PPL ? j : j - 1;
-                    float q0 = 0.f, q1 = 0.f, q2 = 0.f, q3 = 0.f;
-                    float *ncol = col;
+                    R q0 = 0, q1 = 0, q2 = 0, q3 = 0;
+                    R *ncol = col;
                     if (!last) {   // the next update's slice values, before this update's writes
                         ncol = my0 + s_b[inext][jnext] * kBlock;
                         q0 = ncol[0];
@@ -361,7 +362,7 @@ __global__ __launch_bounds__(kBlock) void k_lv_pass2(DevProblem pb, const double
                         q2 = ncol[rowB];
                         q3 = ncol[rowB + kBlock];
                     }
-                    const float v0 = r0 + u[0], v1 = r1 + u[1], v2 = r2 + u[2], v3 = r3 + u[3];
+                    const R v0 = r0 + u[0], v1 = r1 + u[1], v2 = r2 + u[2], v3 = r3 + u[3];
                     col[0] = v0;
                     col[kBlock] = v1;
                     col[rowB] = v2;
@@ -388,9 +389,9 @@ __global__ __launch_bounds__(kBlock) void k_lv_pass2(DevProblem pb, const double
                     }
 #pragma unroll
                     for (int i = 0; i < PPL; ++i) {
-                        float u[4];
+                        R u[4];
                         reverse_step(i, j, u);
-                        float *col = my0 + s_b[i][j] * kBlock;
+                        R *col = my0 + s_b[i][j] * kBlock;
                         col[0] += u[0];
                         col[kBlock] += u[1];
                         col[rowB] += u[2];
@@ -475,7 +476,7 @@ size_t lv_lds_bytes(const DevProblem &pb, bool fp64, int pass)
     size_t o = sizeof(double) * (pass == 1 ? (size_t)kWavesPerBlock * pb.m : (size_t)pb.nT * pb.nK);
     o += real * (size_t)pb.K * pb.nK;
     o = (o + 15) & ~(size_t)15;
-    if (pass == 2) o += sizeof(float) * 2 * (size_t)pb.nK * kBlock;
+    if (pass == 2) o += real * 2 * (size_t)pb.nK * kBlock;
     return o;
 }
 

@@ -227,12 +227,14 @@ __device__ __forceinline__ double wave_sum8(const double a[8])
 // per lane (slices[q * kBlock + tid]).  Adds the sum over the workgroup's
 // lanes of row q to dst[q] (FP64) and clears the slices.  Wave w takes rows
 // w, w + 4, ...: each lane loads four neighbouring columns of the row (one
-// 16-byte read, the wave covering the whole row), adds them in FP32, and the
+// 16-byte read in FP32, two in FP64: the wave covers the whole row), adds them
+// in the slices' precision, and the
 // wave sums the 64 lane values in FP64 along wave_sum's fixed tree, so the
 // sums are deterministic.  A rolled loop keeps the register footprint small
 // where this is inlined into a register-heavy sweep.  Called by all threads of
 // the workgroup (uniform control flow); slices must be 16-byte aligned.
-__device__ __forceinline__ void flush_slices(float *slices, int rows, double *dst)
+template <typename T>
+__device__ __forceinline__ void flush_slices(T *slices, int rows, double *dst)
 {
     const int tid = threadIdx.x;
     const int lane = tid & (kWave - 1);
@@ -240,10 +242,19 @@ __device__ __forceinline__ void flush_slices(float *slices, int rows, double *ds
     __syncthreads();
 #pragma unroll 1
     for (int q = wave; q < rows; q += kWavesPerBlock) {
-        float4 *cell = reinterpret_cast<float4 *>(slices + q * kBlock) + lane;
-        const float4 v = *cell;
-        *cell = make_float4(0.f, 0.f, 0.f, 0.f);
-        const double t = wave_sum((double)((v.x + v.y) + (v.z + v.w)));
+        T *cell = slices + q * kBlock + 4 * lane;
+        double t;
+        if constexpr (sizeof(T) == 4) {
+            const float4 v = *reinterpret_cast<float4 *>(cell);
+            *reinterpret_cast<float4 *>(cell) = make_float4(0.f, 0.f, 0.f, 0.f);
+            t = (double)((v.x + v.y) + (v.z + v.w));
+        } else {
+            const double2 v0 = reinterpret_cast<double2 *>(cell)[0], v1 = reinterpret_cast<double2 *>(cell)[1];
+            reinterpret_cast<double2 *>(cell)[0] = make_double2(0.0, 0.0);
+            reinterpret_cast<double2 *>(cell)[1] = make_double2(0.0, 0.0);
+            t = (v0.x + v0.y) + (v1.x + v1.y);
+        }
+        t = wave_sum(t);
         if (lane == 0) dst[q] += t;
     }
     __syncthreads();

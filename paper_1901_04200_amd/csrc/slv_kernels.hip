@@ -12,7 +12,8 @@
 //
 // Reverse sweep, per step (a = adjoint of x~, b = adjoint of v after it):
 //   Lbar = a (s z1' - h L v+), spread over the step's two spot nodes with
-//   weights 1 - be, be into per-lane FP32 LDS slices of the current time row,
+//   weights 1 - be, be into per-lane LDS slices of the current time row (in
+//   the path precision),
 //   which a fixed tree sums into FP64 node sums when the row changes;
 //   a += Lbar dL/dS S; the Heston part as in the Heston reverse sweep with
 //   sbar = b xi w' + a L z1' and v+bar = sbar/(2s) - (h/2) L^2 a - kappa h b.
@@ -29,15 +30,15 @@ constexpr int kHes = 5;   // Heston parameters ahead of the leverage nodes
 
 // LDS carve-up.  pass 1: [waves][m] payoff sums, leverage grid.
 // pass 2: [nT*nK] FP64 node sums, [waves][5] FP64 Heston sums, leverage grid,
-// [K][kBlock] payoff adjoints of the segment's dates, [nK][kBlock] FP32 node
-// slices of the current row (one column per lane).
+// [K][kBlock] payoff adjoints of the segment's dates, [nK][kBlock] node slices
+// of the current row in the path precision (one column per lane).
 template <typename R>
 struct SlvLds {
     double *sums;
     double *hes;
     R *lev;
     R *inj;
-    float *slices;
+    R *slices;
 };
 
 __host__ __device__ inline size_t align16(size_t o) { return (o + 15) & ~(size_t)15; }
@@ -57,7 +58,7 @@ __device__ SlvLds<R> carve(const DevProblem &pb, unsigned char *base, int pass)
     o = align16(o + sizeof(R) * nn);
     L.inj = (R *)(base + o);
     if (pass == 2) o = align16(o + sizeof(R) * (size_t)pb.K * kBlock);
-    L.slices = (float *)(base + o);
+    L.slices = (R *)(base + o);
     return L;
 }
 
@@ -200,7 +201,7 @@ __global__ __launch_bounds__(kBlock) void k_slv_pass2(DevProblem pb, const doubl
     load_grid<R>(pb, theta, L.lev);
     if constexpr (!FROM_CKPT) save_theta(pb, theta, blockIdx.x);
     for (int i = tid; i < pb.nT * pb.nK; i += kBlock) L.sums[i] = 0.0;
-    for (int i = tid; i < pb.nK * kBlock; i += kBlock) L.slices[i] = 0.f;
+    for (int i = tid; i < pb.nK * kBlock; i += kBlock) L.slices[i] = (R)0;
     __syncthreads();
 
     Consts<R> c;
@@ -214,7 +215,7 @@ __global__ __launch_bounds__(kBlock) void k_slv_pass2(DevProblem pb, const doubl
     double g[kHes];
 #pragma unroll
     for (int j = 0; j < kHes; ++j) g[j] = 0.0;
-    float *my = L.slices + tid;   // this lane's column of the slices
+    R *my = L.slices + tid;   // this lane's column of the slices
     int cur_a = ldc(pb.step_row, pb.N - 1);
     // the workgroup's paths: ppl runs of kBlock consecutive paths, one after another
     for (int sp = 0; sp < pb.ppl; ++sp) {
@@ -329,8 +330,8 @@ __global__ __launch_bounds__(kBlock) void k_slv_pass2(DevProblem pb, const doubl
                     t2 += t * w;
                     t3 += t * (z1 - c.rho * w);
                     const R w1 = Lbar * q.be;
-                    my[q.b * kBlock] += (float)(Lbar - w1);
-                    my[(q.b + 1) * kBlock] += (float)w1;
+                    my[q.b * kBlock] += Lbar - w1;
+                    my[(q.b + 1) * kBlock] += w1;
                     xb = xb + Lbar * (q.inside ? (q.r1 - q.r0) * invdK : (R)0) * S;
                     vb = sv > (R)0 ? b + vpbar : b;
                 }
@@ -411,7 +412,7 @@ size_t slv_lds_bytes(const DevProblem &pb, bool fp64, int pass)
     o = align16(o + real * nn);
     if (pass == 2) {
         o = align16(o + real * (size_t)pb.K * kBlock);
-        o += sizeof(float) * (size_t)pb.nK * kBlock;
+        o += real * (size_t)pb.nK * kBlock;
     }
     return o;
 }

@@ -280,65 +280,241 @@ class StepRecord:
     seconds_surrogate: float
     seconds_mc: float
     mc_calls: int = 1
+    radius: float = 0.0
+    ratio: float = 0.0
+    inner_launches: int = 0
 
 
-def surrogate_calibration(net: MLP, mc, targets, theta0, lo, hi, *, iters: int = 20, alpha: float = 0.5,
-                          feller: bool = True, max_backtracks: int = 12, g_stop: float = 0.0):
-    """Each iteration proposes a step from the surrogate's gradient
-    (projected, Armijo on the surrogate's G), then judges it with the Monte
-    Carlo gradient at the proposal: accepted if the Monte Carlo G decreases,
-    otherwise a Monte Carlo gradient step (with backtracking on the Monte
-    Carlo G) is taken instead.  Every iteration logs the surrogate gradient's
-    relative error against the Monte Carlo gradient and its Monte Carlo
-    calls; the loop ends after `iters` iterations or once the Monte Carlo G
-    is at most g_stop."""
-    import torch
-    from .calibrate import project
+class DeviceSurrogate:
+    """The trained network as the calibration step's model: prices at one
+    parameter vector, and G, grad G at a batch of parameter vectors (all
+    trial points of one line search in one launch, one copy back, one
+    synchronisation).  Buffers are made once; the targets are uploaded only
+    when they change."""
+
+    def __init__(self, net: MLP, max_points: int = 32):
+        import torch
+        self.net, self.torch = net, torch
+        self.max_points = max_points
+        dev = net.dev
+        self.th_host = torch.empty(max_points, net.n_in, dtype=torch.float32, pin_memory=True)
+        self.th_dev = torch.empty(max_points, net.n_in, dtype=torch.float32, device=dev)
+        self.C_host = torch.empty(net.n_out, dtype=torch.float64, pin_memory=True)
+        self.C_dev = torch.zeros(net.n_out, dtype=torch.float64, device=dev)
+        self.C_now = None
+        self.Y = torch.empty(max_points, net.n_out, dtype=torch.float32, device=dev)
+        self.J = torch.empty(max_points, net.n_out, net.n_in, dtype=torch.float32, device=dev)
+        # G [B] and grad [B, n_in] side by side in one buffer: one copy back
+        self.Gg = torch.empty(max_points * (1 + net.n_in), dtype=torch.float64, device=dev)
+        self.Gg_host = torch.empty(max_points * (1 + net.n_in), dtype=torch.float64, pin_memory=True)
+        self.launches = 0
+
+    def _launch(self, thetas, C):
+        t = self.torch
+        B = len(thetas)
+        if B > self.max_points:
+            raise ValueError(f"at most {self.max_points} points per launch")
+        self.th_host[:B].copy_(t.from_numpy(np.ascontiguousarray(thetas, dtype=np.float32)))
+        self.th_dev[:B].copy_(self.th_host[:B], non_blocking=True)
+        if C is not None and (self.C_now is None or not np.array_equal(C, self.C_now)):
+            self.C_now = np.array(C, dtype=np.float64)
+            self.C_host.copy_(t.from_numpy(self.C_now))
+            self.C_dev.copy_(self.C_host, non_blocking=True)
+        n = self.net.n_in
+        G = self.Gg[:B]
+        g = self.Gg[B:B * (1 + n)].view(B, n)
+        self.net.calibration_gradient(self.th_dev[:B], self.C_dev, out=(self.Y[:B], self.J[:B], G, g))
+        self.launches += 1
+        return B
+
+    def prices(self, theta) -> np.ndarray:
+        self._launch(np.asarray(theta)[None, :], None)
+        return self.Y[0].cpu().numpy().astype(np.float64)
+
+    def value_grad(self, thetas, C):
+        """G [B] and grad [B, M] (FP64, host) at the rows of thetas."""
+        B = self._launch(thetas, C)
+        n = self.net.n_in
+        k = B * (1 + n)
+        self.Gg_host[:k].copy_(self.Gg[:k], non_blocking=True)
+        self.torch.cuda.current_stream().synchronize()
+        out = self.Gg_host[:k].numpy()
+        return out[:B].copy(), out[B:].reshape(B, n).copy()
+
+
+def _minimise_model(model_vg, u0, g0, lo_u, hi_u, proj, *, iters: int, n_alpha: int, c_armijo: float = 1e-4):
+    """Minimise the corrected model over the box [lo_u, hi_u] (box-scaled
+    coordinates) from u0, where its gradient is g0, by projected L-BFGS whose
+    line search evaluates n_alpha step lengths 1, 1/2, ... in one call of
+    model_vg (B points -> values, gradients) and keeps the longest that
+    passes the Armijo test.  proj maps an array of points [B, M] onto the
+    feasible set.  Returns (u, model value, launches)."""
+    from .calibrate import LbfgsMemory
+    mem = LbfgsMemory(6)
+    u, gu = u0.copy(), g0.copy()
+    mval = None
+    launches = 0
+    scales = 0.5 ** np.arange(n_alpha)
+    for t in range(iters):
+        free = ~(((u <= lo_u) & (gu > 0.0)) | ((u >= hi_u) & (gu < 0.0)))
+        d = mem.apply(gu, free)
+        if not float(gu @ d) < 0.0:
+            mem.clear()
+            d = -np.where(free, gu, 0.0)
+        dmax = float(np.max(np.abs(d)))
+        if dmax == 0.0:
+            break
+        a0 = 1.0 if mem.s else min(1.0, 0.5 * float(np.max(hi_u - lo_u)) / dmax)
+        cands = proj(u[None, :] + (a0 * scales)[:, None] * d[None, :])
+        pts = cands if mval is not None else np.vstack([u[None, :], cands])
+        vals, grads = model_vg(pts)
+        launches += 1
+        if mval is None:
+            mval, vals, grads = vals[0], vals[1:], grads[1:]
+        steps = cands - u[None, :]
+        ok = np.isfinite(vals) & (vals <= mval + c_armijo * (steps @ gu)) & np.any(steps != 0.0, axis=1)
+        if not np.any(ok):
+            if mem.s:
+                mem.clear()
+                continue
+            break
+        pick = int(np.argmax(ok))     # the longest step that passes
+        mem.push(steps[pick], grads[pick] - gu)
+        u, gu, mval = cands[pick], grads[pick], vals[pick]
+        if dmax * a0 * scales[pick] < 1e-7:
+            break
+    return u, (mval if mval is not None else 0.0), launches
+
+
+def trust_region_calibration(mc_value_grad, sur_prices, sur_value_grad, targets, theta0, lo, hi, *,
+                             iters: int = 50, g_stop: float = 0.0, feller: bool = True, radius0: float = 0.25,
+                             inner_iters: int = 6, n_alpha: int = 12, eta: float = 0.05):
+    """Surrogate-assisted calibration: a trust-region iteration whose model
+    is the surrogate made exact to first order at the current point, and
+    whose judge is the Monte Carlo gradient.
+
+    At theta_k the Monte Carlo path gives E y_k, G_k and g_k (one two-pass
+    gradient).  The surrogate's prices y_s are shifted so that they equal
+    E y_k at theta_k (the surrogate's functional with targets
+    C' = C - E y_k + y_s(theta_k)), and a linear term c (theta - theta_k) with
+    c = g_k - grad G_s(theta_k; C') makes its gradient there g_k:
+        m(theta) = G_s(theta; C') + c (theta - theta_k),  m(theta_k) = G_k.
+    m is minimised over the box intersected with |u - u_k|_inf <= radius
+    (u: box-scaled coordinates) by projected L-BFGS on the surrogate alone;
+    the Monte Carlo gradient at the result theta_c decides: accepted when
+    G(theta_c) < G_k (then its gradient is the next iteration's), the radius
+    grows when the actual decrease is at least 3/4 of the predicted one at a
+    step on the boundary and shrinks to a quarter of the step when the
+    ratio is below eta.  After two rejections in a row the next trial point
+    is a projected L-BFGS step on the Monte Carlo gradients themselves (the
+    curvature pairs every Monte Carlo call leaves), inside the radius.  So
+    every iteration costs one Monte Carlo gradient; the surrogate supplies
+    the curvature, the Monte Carlo gradient the first-order term, the
+    verdict and the fallback.
+
+    mc_value_grad(theta) -> (E y, G, grad); sur_prices(theta) -> y_s;
+    sur_value_grad(thetas [B, M], C) -> (G [B], grad [B, M]).  Returns
+    (theta, [StepRecord])."""
+    from .calibrate import LbfgsMemory
     lo, hi = np.asarray(lo, np.float64), np.asarray(hi, np.float64)
-    D = (hi - lo) ** 2
-    C = torch.as_tensor(np.asarray(targets, np.float64), device=mc.device)
-    th = project(theta0, lo, hi, feller)
-    recs = []
+    w = hi - lo
+    C = np.asarray(targets, np.float64)
 
-    def sur(th_):
-        t = torch.as_tensor(np.asarray(th_, np.float32)[None, :], device=net.dev)
-        G, g = net.calibration_gradient(t, C)
-        return float(G.item()), g[0].cpu().numpy()
+    def feasible(u, lo_u, hi_u):
+        """Points [B, M] clipped to [lo_u, hi_u], then (Heston) xi lowered
+        onto Feller's condition 2 kappa theta_bar >= xi^2."""
+        u = np.clip(u, lo_u, hi_u)
+        if feller:
+            th = lo + w * u
+            xi_max = np.maximum(np.sqrt(np.maximum(2.0 * th[:, 0] * th[:, 1], 0.0)), lo[2])
+            th[:, 2] = np.minimum(th[:, 2], xi_max)
+            u = (th - lo) / w
+        return u
 
-    Ey, G_mc, g_mc = mc.gradient(th, C)
-    G_mc, g_mc = float(G_mc.item()), g_mc.cpu().numpy()
+    u = feasible(((np.asarray(theta0, np.float64) - lo) / w)[None, :], 0.0, 1.0)[0]
+    th = lo + w * u
+    t1 = time.perf_counter()
+    Ey, G, g = mc_value_grad(th)
+    t_mc = time.perf_counter() - t1
+    radius = radius0
+    mc_mem = LbfgsMemory(8)
+    rejected = 0
+    recs: List[StepRecord] = []
     for it in range(iters):
-        if G_mc <= g_stop:
+        if G <= g_stop or radius < 1e-9:
             break
         t0 = time.perf_counter()
-        Gs, gs = sur(th)
-        a = alpha
-        cand = th
-        for _ in range(max_backtracks):
-            cand = project(th - a * D * gs, lo, hi, feller)
-            if sur(cand)[0] <= Gs + 1e-4 * float(gs @ (cand - th)):
-                break
-            a *= 0.5
-        ts = time.perf_counter() - t0
-        t1 = time.perf_counter()
-        Ey_c, G_c, g_c = mc.gradient(cand, C)
-        G_c = float(G_c.item())
-        tm = time.perf_counter() - t1
-        err = float(np.linalg.norm(gs - g_mc) / max(np.linalg.norm(g_mc), 1e-300))
-        accepted = G_c < G_mc
-        calls = 1
-        if accepted:
-            th, G_mc, g_mc = cand, G_c, g_c.cpu().numpy()
+        lo_u, hi_u = np.maximum(0.0, u - radius), np.minimum(1.0, u + radius)
+        proj = lambda pts: feasible(pts, lo_u, hi_u)
+        gk_u = np.asarray(g) * w
+        err, launches = float("nan"), 0
+        if rejected >= 2:
+            # fallback: projected L-BFGS step on the Monte Carlo gradients
+            free = ~(((u <= 0.0) & (gk_u > 0.0)) | ((u >= 1.0) & (gk_u < 0.0)))
+            d = mc_mem.apply(gk_u, free)
+            if not float(gk_u @ d) < 0.0:
+                d = -np.where(free, gk_u, 0.0)
+            a = 1.0 if mc_mem.s else radius / max(float(np.max(np.abs(d))), 1e-300)
+            u_c = proj((u + a * d)[None, :])[0]
+            m_c = G + float(gk_u @ (u_c - u))       # the linear model's value
+            source = False
         else:
-            # fall back to a Monte Carlo gradient step
-            a = alpha
-            for _ in range(max_backtracks):
-                cand = project(th - a * D * g_mc / max(np.max(np.abs(D * g_mc)), 1e-300) * 0.05, lo, hi, feller)
-                Ey_c, G_c, g_c = mc.gradient(cand, C)
-                calls += 1
-                if float(G_c.item()) < G_mc:
-                    th, G_mc, g_mc = cand, float(G_c.item()), g_c.cpu().numpy()
-                    break
-                a *= 0.5
-        recs.append(StepRecord(it, G_mc, accepted, err, ts, tm, calls))
+            Cp = C - np.asarray(Ey) + sur_prices(th)
+            corr = {}
+
+            def model_vg(pts_u):
+                pts_th = lo + w * pts_u
+                vals, grads = sur_value_grad(pts_th, Cp)
+                if "c" not in corr:       # the first batch starts with theta_k itself
+                    corr["sg0"] = grads[0]
+                    corr["c"] = np.asarray(g) - grads[0]
+                c = corr["c"]
+                return vals + (pts_th - th) @ c, (grads + c[None, :]) * w[None, :]
+
+            u_c, m_c, launches = _minimise_model(model_vg, u, gk_u, lo_u, hi_u, proj, iters=inner_iters,
+                                                 n_alpha=n_alpha)
+            if "sg0" in corr:
+                err = float(np.linalg.norm(corr["sg0"] - g) / max(np.linalg.norm(g), 1e-300))
+            source = True
+        th_c = lo + w * u_c
+        t_s = time.perf_counter() - t0
+        pred = G - m_c
+        step = float(np.max(np.abs(u_c - u)))
+        if step == 0.0 or not pred > 0.0:
+            radius *= 0.25
+            rejected += 1
+            recs.append(StepRecord(it, float(G), False, err, t_s, 0.0, 0, radius, 0.0, launches))
+            continue
+        t1 = time.perf_counter()
+        Ey_c, G_c, g_c = mc_value_grad(th_c)
+        t_mc = time.perf_counter() - t1
+        ratio = (G - G_c) / pred
+        accepted = bool(np.isfinite(G_c) and G_c < G)
+        if np.all(np.isfinite(g_c)):
+            mc_mem.push(u_c - u, np.asarray(g_c) * w - gk_u)
+        if accepted:
+            u, th, Ey, G, g = u_c, th_c, Ey_c, G_c, g_c
+            rejected = 0
+        else:
+            rejected += 1
+        if ratio >= 0.75 and step >= 0.8 * radius:
+            radius = min(2.0 * radius, 1.0)
+        elif ratio < eta or not accepted:
+            radius = 0.25 * step
+        recs.append(StepRecord(it, float(G), accepted and source, err, t_s, t_mc, 1, radius, float(ratio), launches))
     return th, recs
+
+
+def surrogate_calibration(net: MLP, mc, targets, theta0, lo, hi, *, iters: int = 50, feller: bool = True,
+                          g_stop: float = 0.0, **kw):
+    """trust_region_calibration with the trained network on the device as
+    the model and the library's two-pass Monte Carlo gradient as the judge.
+    Returns (theta, [StepRecord])."""
+    C = np.asarray(targets, np.float64)
+    from .calibrate import MonteCarloObjective
+    sur = DeviceSurrogate(net, max_points=1 + kw.get("n_alpha", 12))
+    obj = MonteCarloObjective(mc, C)
+    mc_vg = obj.prices_value_and_grad
+
+    return trust_region_calibration(mc_vg, sur.prices, sur.value_grad, C, theta0, lo, hi, iters=iters,
+                                    g_stop=g_stop, feller=feller, **kw)

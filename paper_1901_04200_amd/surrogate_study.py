@@ -12,10 +12,10 @@
   5. cost of one gradient step: surrogate (network forward, batch 1) vs the
      Monte Carlo adjoint (calibrate_gradient) at P* paths;
   6. gain test: on n_gain calibration instances (start and target draws),
-     wall time and Monte Carlo evaluations to bring G below g_frac G(theta0)
-     by Monte Carlo gradient descent alone and by the surrogate-assisted
-     iteration (surrogate proposes, Monte Carlo judges), both at the
-     benchmark's 2^20 paths.
+     wall time and Monte Carlo gradient calls to bring G below
+     g_frac G(theta0) by Monte Carlo projected L-BFGS alone and by the
+     surrogate-assisted trust-region iteration (surrogate model, Monte Carlo
+     judge), both at the benchmark's 2^20 paths.
 Everything is on the Feller-satisfying part of the Heston box, where the
 pathwise gradient is well conditioned.
 """
@@ -49,38 +49,10 @@ def run(n_train=1 << 14, train_paths=1 << 14, n_heldout=32, ref_paths=1 << 24, e
     pb, th0, tht, eps = W.heston_problem()
     lo, hi = W.HESTON_LO, W.HESTON_HI
 
-    # ---- 1. labels -------------------------------------------------------
-    draws = W.surrogate_draws(n_train, rng_seed=6)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    Ey, J = S.generate_labels(pb, draws, n_paths=train_paths, seed=4, chunk=256)
-    torch.cuda.synchronize()
-    t_lab = time.perf_counter() - t0
-    out["labels"] = {"draws": n_train, "paths_per_draw": train_paths, "seconds": t_lab,
-                     "path_steps_per_s": n_train * train_paths * pb.n_steps / t_lab}
-    log(f"surrogate: labels for {n_train} draws x {train_paths} paths in {t_lab:.2f} s")
-
-    # ---- 2. training -----------------------------------------------------
-    net = S.MLP(5, 256, pb.n_instr, max_batch=batch)
-    net.init_params(0)
-    sh, sc, mu, sd = S.standard_scaling(lo, hi, Ey.cpu().numpy())
-    net.set_scaling(sh, sc, mu, sd)
-    thd = torch.as_tensor(draws, dtype=torch.float32, device="cuda")
-    t0 = time.perf_counter()
-    hist = S.fit(net, thd, Ey.float(), J.float(), epochs=epochs, batch=min(batch, n_train), lr=lr,
-                 lr_final=lr_final, w=w, log_every=max(1, epochs // 10))
-    t_fit = time.perf_counter() - t0
-    steps = epochs * (n_train // min(batch, n_train))
-    # useful GEMM work of one step: forward, input gradient and weight gradient
-    # of the layers 256x256, 256x256 and 256xm over the primal and 5 tangent row
-    # blocks (the 5x256 first layer is elementwise)
-    rows = 6 * min(batch, n_train)
-    flops = 3 * 2 * rows * (2 * 256 * 256 + 256 * pb.n_instr)
-    out["training"] = {"epochs": epochs, "seconds": t_fit, "loss_first": hist[0].loss, "loss_last": hist[-1].loss,
-                       "steps": steps, "gemm_flop_per_step": flops,
-                       "gemm_tflops": flops * steps / t_fit * 1e-12,
-                       "bf16_peak_frac": flops * steps / t_fit / 2.5e15}
-    log(f"surrogate: {epochs} epochs in {t_fit:.2f} s, loss {hist[0].loss:.4g} -> {hist[-1].loss:.4g}")
+    # ---- 1.-2. labels and training ------------------------------------------
+    net, info = train_surrogate(pb, n_train, train_paths, epochs, batch=batch, lr=lr, lr_final=lr_final, w=w,
+                                log=log)
+    out.update(info)
 
     # ---- 3. accuracy on held-out draws -------------------------------------
     # targets: prices at the target draw (seed 2) plus 0.1 % noise
@@ -150,51 +122,128 @@ def run(n_train=1 << 14, train_paths=1 << 14, n_heldout=32, ref_paths=1 << 24, e
     return out
 
 
-def gain_test(net, pb, n_inst, g_frac, max_iter, log=print):
-    """Calibrate n_inst instances (theta0, theta_target: Feller draws of
-    rng(11); targets = prices at theta_target, Philox seed 2, times 1 + 1e-3
-    eps) to G <= g_frac G(theta0), by Monte Carlo gradient descent and by the
-    surrogate-assisted iteration; wall time and Monte Carlo calls each."""
+def train_surrogate(pb, n_train, train_paths, epochs, batch=4096, lr=2e-3, lr_final=5e-5, w=1.0, log=print):
+    """Labels (E y and dE y/dtheta by the Monte Carlo tangent kernel, each of
+    n_train draws its own Philox instance, seed 4) and the network trained on
+    them with the differential loss; returns (net, timings and losses)."""
+    import torch
+    lo, hi = W.HESTON_LO, W.HESTON_HI
+    out = {}
+    draws = W.surrogate_draws(n_train, rng_seed=6)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    Ey, J = S.generate_labels(pb, draws, n_paths=train_paths, seed=4, chunk=256)
+    torch.cuda.synchronize()
+    t_lab = time.perf_counter() - t0
+    out["labels"] = {"draws": n_train, "paths_per_draw": train_paths, "seconds": t_lab,
+                     "path_steps_per_s": n_train * train_paths * pb.n_steps / t_lab}
+    log(f"surrogate: labels for {n_train} draws x {train_paths} paths in {t_lab:.2f} s")
+    net = S.MLP(5, 256, pb.n_instr, max_batch=batch)
+    net.init_params(0)
+    sh, sc, mu, sd = S.standard_scaling(lo, hi, Ey.cpu().numpy())
+    net.set_scaling(sh, sc, mu, sd)
+    thd = torch.as_tensor(draws, dtype=torch.float32, device="cuda")
+    t0 = time.perf_counter()
+    hist = S.fit(net, thd, Ey.float(), J.float(), epochs=epochs, batch=min(batch, n_train), lr=lr,
+                 lr_final=lr_final, w=w, log_every=max(1, epochs // 10))
+    t_fit = time.perf_counter() - t0
+    steps = epochs * (n_train // min(batch, n_train))
+    # useful GEMM work of one step: forward, input gradient and weight gradient
+    # of the layers 256x256, 256x256 and 256xm over the primal and 5 tangent row
+    # blocks (the 5x256 first layer is elementwise)
+    rows = 6 * min(batch, n_train)
+    flops = 3 * 2 * rows * (2 * 256 * 256 + 256 * pb.n_instr)
+    out["training"] = {"epochs": epochs, "seconds": t_fit, "loss_first": hist[0].loss, "loss_last": hist[-1].loss,
+                       "steps": steps, "gemm_flop_per_step": flops,
+                       "gemm_tflops": flops * steps / t_fit * 1e-12,
+                       "bf16_peak_frac": flops * steps / t_fit / 2.5e15}
+    log(f"surrogate: {epochs} epochs in {t_fit:.2f} s, loss {hist[0].loss:.4g} -> {hist[-1].loss:.4g}")
+    return net, out
+
+
+def gain_instances(pb, n_inst, g_frac=1e-3, rng_seed=11, margin=2.0):
+    """Calibration instances for the gain test: pairs (theta0, theta_target)
+    of Feller draws of rng(rng_seed) with targets priced at theta_target
+    (Philox seed 2) times 1 + 1e-3 eps (eps from rng(rng_seed + 1)), in draw
+    order, keeping those whose target level g_frac G(theta0) lies above
+    margin G(theta_target): G cannot go much below what the target
+    parameters themselves reach (the targets carry noise and another seed's
+    paths), so a pair with a lower target level does not test speed.
+    Returns [(theta0, theta_target, C, G0, G_target)]."""
+    gen = MonteCarloCalibration(pb.with_(seed=2))
+    mc = MonteCarloCalibration(pb)
+    rng = np.random.default_rng(rng_seed + 1)
+    pool = W.heston_feller_draws(rng_seed, 16 * n_inst)
+    out, k = [], 0
+    try:
+        while len(out) < n_inst and 2 * k + 1 < len(pool):
+            th0, tht = pool[2 * k], pool[2 * k + 1]
+            eps = rng.standard_normal(pb.n_instr)
+            k += 1
+            C = W.noisy_targets(gen.forward(tht).cpu().numpy(), eps)
+            G0 = float(mc.gradient(th0, C)[1].item())
+            Gt = float(mc.gradient(tht, C)[1].item())
+            if g_frac * G0 > margin * Gt:
+                out.append((th0, tht, C, G0, Gt))
+    finally:
+        gen.close()
+        mc.close()
+    return out
+
+
+def gain_test(net, pb, n_inst, g_frac, max_iter, log=print, instances=None):
+    """Calibrate n_inst instances (gain_instances) to G <= g_frac G(theta0)
+    by Monte Carlo projected L-BFGS alone and by the surrogate-assisted
+    trust-region iteration (surrogate model, Monte Carlo judge), both on the
+    same 2^20-path Monte Carlo gradient; wall time and Monte Carlo gradient
+    calls each."""
     import torch
     from .calibrate import MonteCarloObjective, calibrate
     lo, hi = W.HESTON_LO, W.HESTON_HI
-    draws = W.heston_feller_draws(11, 2 * n_inst)
-    eps = np.random.default_rng(12).standard_normal((n_inst, pb.n_instr))
-    gen = MonteCarloCalibration(pb.with_(seed=2))
+    if instances is None:
+        instances = gain_instances(pb, n_inst, g_frac)
     mc = MonteCarloCalibration(pb)
     rows = []
-    for i in range(n_inst):
-        th0, tht = draws[2 * i], draws[2 * i + 1]
-        C = W.noisy_targets(gen.forward(tht).cpu().numpy(), eps[i])
-        obj = MonteCarloObjective(mc, C)
-        G0, _ = obj.value_and_grad(th0)
+    # one warm-up calibration of each kind (first-call costs out of the timings)
+    th0, tht, C, G0, Gt = instances[0]
+    calibrate(MonteCarloObjective(mc, C).value_and_grad, None, th0, lo, hi, max_iter=2, feller=True)
+    S.surrogate_calibration(net, mc, C, th0, lo, hi, iters=2, feller=True)
+    for th0, tht, C, G0, Gt in instances:
         g_tol = g_frac * G0
+        obj = MonteCarloObjective(mc, C)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        obj.n_grad = obj.n_value = 0
         r = calibrate(obj.value_and_grad, obj.value, th0, lo, hi, max_iter=max_iter, g_tol=g_tol, feller=True)
         t_mc = time.perf_counter() - t0
         mc_calls = obj.n_grad + obj.n_value
+        torch.cuda.synchronize()
         t0 = time.perf_counter()
         th_s, recs = S.surrogate_calibration(net, mc, C, th0, lo, hi, iters=max_iter, feller=True, g_stop=g_tol)
         t_s = time.perf_counter() - t0
         G_s = recs[-1].G_mc if recs else G0
-        rows.append({"G0": G0, "mc": {"reached": r.G <= g_tol, "G": r.G, "seconds": t_mc, "mc_calls": mc_calls,
-                                      "iters": len(r.history)},
+        rows.append({"G0": G0, "G_target": Gt,
+                     "mc": {"reached": r.G <= g_tol, "G": r.G, "seconds": t_mc, "mc_calls": mc_calls,
+                            "iters": len(r.history), "status": r.status},
                      "surrogate": {"reached": G_s <= g_tol, "G": G_s, "seconds": t_s,
-                                   "mc_calls": sum(x.mc_calls for x in recs), "iters": len(recs),
-                                   "accepted": sum(1 for x in recs if x.accepted_surrogate)}})
-    gen.close()
+                                   "mc_calls": 1 + sum(x.mc_calls for x in recs), "iters": len(recs),
+                                   "accepted": sum(1 for x in recs if x.accepted_surrogate),
+                                   "surrogate_launches": sum(x.inner_launches + 1 for x in recs)}})
     mc.close()
     both = [r_ for r_ in rows if r_["mc"]["reached"] and r_["surrogate"]["reached"]]
-    summ = {"instances": n_inst, "g_frac": g_frac, "paths": pb.n_paths,
+    med = lambda key, sub: float(np.median([r_[sub][key] for r_ in both])) if both else None
+    summ = {"instances": len(rows), "g_frac": g_frac, "paths": pb.n_paths,
+            "selection": "Feller pairs of rng(11) in draw order with g_frac G(theta0) > 2 G(theta_target)",
             "reached_mc": sum(r_["mc"]["reached"] for r_ in rows),
             "reached_surrogate": sum(r_["surrogate"]["reached"] for r_ in rows),
-            "median_seconds_mc": float(np.median([r_["mc"]["seconds"] for r_ in both])) if both else None,
-            "median_seconds_surrogate": float(np.median([r_["surrogate"]["seconds"] for r_ in both])) if both else None,
-            "median_mc_calls_mc": float(np.median([r_["mc"]["mc_calls"] for r_ in both])) if both else None,
-            "median_mc_calls_surrogate": float(np.median([r_["surrogate"]["mc_calls"] for r_ in both])) if both else None,
+            "median_seconds_mc": med("seconds", "mc"), "median_seconds_surrogate": med("seconds", "surrogate"),
+            "median_mc_calls_mc": med("mc_calls", "mc"), "median_mc_calls_surrogate": med("mc_calls", "surrogate"),
             "per_instance": rows}
-    log(f"surrogate: gain test reached {summ['reached_mc']}/{n_inst} (MC) and {summ['reached_surrogate']}/{n_inst} "
-        f"(surrogate-assisted); median seconds {summ['median_seconds_mc']} vs {summ['median_seconds_surrogate']}")
+    if both:
+        summ["median_speedup"] = float(np.median([r_["mc"]["seconds"] / r_["surrogate"]["seconds"] for r_ in both]))
+        summ["median_mc_call_ratio"] = float(np.median([r_["mc"]["mc_calls"] / r_["surrogate"]["mc_calls"]
+                                                        for r_ in both]))
+    log(f"surrogate: gain test reached {summ['reached_mc']}/{len(rows)} (MC L-BFGS) and "
+        f"{summ['reached_surrogate']}/{len(rows)} (surrogate-assisted); median seconds {summ['median_seconds_mc']} vs "
+        f"{summ['median_seconds_surrogate']}, MC calls {summ['median_mc_calls_mc']} vs "
+        f"{summ['median_mc_calls_surrogate']}")
     return summ

@@ -12,7 +12,7 @@
  * N = 256 steps over 2 years; S0 = 100, r = 0.02; Philox key 1, counter
  * (call, path, 0, 0).
  *
- * usage: precision_floor P k kappa theta_bar xi rho v0 */
+ * usage: precision_floor P k kappa theta_bar xi rho v0 [kz]   (kz defaults to k) */
 #include <math.h>
 #include <stdint.h>
 #include <stdio.h>
@@ -48,9 +48,10 @@ static double rnd(double v, int k)
 
 int main(int argc, char **argv)
 {
-    if (argc != 8) return 2;
+    if (argc != 8 && argc != 9) return 2;
     const long P = atol(argv[1]);
     const int k = atoi(argv[2]);
+    const int kz = argc == 9 ? atoi(argv[8]) : k;
     const double kap = atof(argv[3]), thb = atof(argv[4]), xi = atof(argv[5]), rho = atof(argv[6]),
                  v0 = atof(argv[7]);
     const double h = 2.0 / NSTEP, sq = sqrt(h), r = 0.02, s0 = 100.0, rhop = sqrt(1.0 - rho * rho);
@@ -74,7 +75,7 @@ int main(int argc, char **argv)
                 va = va + kap * (thb - vp) * h + xi * s * sq * (rho * z1 + rhop * z2);
                 xa = xn;
                 /* the same with k-bit normals and variance recursion */
-                const double y1 = rnd(z1, k), y2 = rnd(z2, k);
+                const double y1 = rnd(z1, kz), y2 = rnd(z2, kz);
                 vp = rnd(vb > 0 ? vb : 0, k);
                 s = rnd(sqrt(vp), k);
                 const double ww = rnd(rho * y1 + rhop * y2, k);

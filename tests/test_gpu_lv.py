@@ -2,11 +2,10 @@
 torch.autograd wrapper, and the central-difference check of the adjoint.
 
 Parity bounds, relative, against the FP64 oracle on the same streams: E y
-1e-5 (FP32) / 1e-12 (FP64); gradient 1e-4 (FP32) / 1e-6 (FP64: the per-lane
-node-adjoint slices that the reverse sweep accumulates in LDS are FP32 in
-both precisions, to fit one workgroup's LDS).  The pathwise derivative of
-this model is bounded (the grid is Lipschitz), so every draw is well
-conditioned.
+1e-5 (FP32) / 1e-12 (FP64); gradient, per component, 1e-4 (FP32) / 1e-9
+(FP64: path state, node-adjoint slices and sums all in FP64).  The pathwise
+derivative of this model is bounded (the grid is Lipschitz); how well the
+sums over paths are conditioned is measured by the one-path share.
 """
 import sys
 
@@ -66,8 +65,8 @@ def test_lv_fp32_matches_oracle(orc, lv_small):
 
 
 def test_lv_fp64_matches_oracle(orc):
-    """FP64 path state; the node adjoints are gathered in FP32 lane slices
-    (the LDS budget of one workgroup), which bounds the gradient at ~1e-7."""
+    """FP64 throughout (path state, the lanes' node-adjoint slices in LDS,
+    the sums): the full 10 x 20 grid, both checkpoint modes."""
     pb, g0, gt, eps, _ = W.lv_problem(n_paths=4096 + 3, n_steps=64)
     C = W.noisy_targets(orc.forward(pb, gt), eps)
     say("lv fp64 P=4099 N=64")
@@ -76,7 +75,7 @@ def test_lv_fp64_matches_oracle(orc):
         Eo, Go, go = orc.gradient(pb, g0, C)
         say(f"  {mode}: errors Ey {ey_err(Ey, Eo):.2e} grad {g_err(g, go):.2e}")
         assert ey_err(Ey, Eo) <= 1e-12
-        assert g_err(g, go) <= 1e-6
+        assert g_err(g, go) <= 1e-9
 
 
 def test_lv_checkpoint_spacings(lv_small):
@@ -137,7 +136,7 @@ def test_lv_two_paths_per_lane(orc, k):
     pb, g0, gt, eps, _ = W.lv_problem(n_paths=3 * 512 + 77, n_steps=72, n_t=4, n_k=6)
     C = np.linspace(2.0, 9.0, pb.n_instr)
     Eo, Go, go = orc.gradient(pb, g0, C)
-    for prec, tol_y, tol_g in (("fp64", 1e-12, 1e-6), ("fp32", 1e-5, 1e-4)):
+    for prec, tol_y, tol_g in (("fp64", 1e-12, 1e-9), ("fp32", 1e-5, 1e-4)):
         res = {}
         for mode in ("store", "rerun"):
             mc = MonteCarloCalibration(pb, precision=prec, ckpt_every=k, ckpt_mode=mode, paths_per_lane=2)
@@ -166,7 +165,7 @@ def test_lv_edge_shapes(orc):
             Ey_f, Ey, G, g = run(pb, g0, C, "fp64", ckpt_every=k, ckpt_mode=mode, paths_per_lane=ppl)
             say(f"    Ey {ey_err(Ey, Eo):.2e} grad {g_err(g, go):.2e}")
             assert ey_err(Ey_f, Eo) <= 1e-12 and ey_err(Ey, Eo) <= 1e-12
-            assert g_err(g, go) <= 1e-6
+            assert g_err(g, go) <= 1e-9
 
 
 def test_memory_budget_picks_spacing():

@@ -2,9 +2,9 @@
 5 Heston parameters + a 10 x 20 leverage grid, 200 calls at the grid nodes)
 against the FP64 oracle on the same streams.
 
-Bounds as for local volatility: E y 1e-5 (FP32) / 1e-12 (FP64); gradient
-1e-4 (FP32) / 1e-6 (FP64: the per-lane leverage-node slices in LDS are
-FP32 in both precisions).  Heston parameters come from the Feller part of
+Bounds as for local volatility: E y 1e-5 (FP32) / 1e-12 (FP64); gradient,
+per component, 1e-4 (FP32) / 1e-9 (FP64: path state, leverage-node slices
+and sums all in FP64).  Heston parameters come from the Feller part of
 the box, where the pathwise gradient is well conditioned.
 """
 import numpy as np
@@ -72,7 +72,7 @@ def test_slv_fp64_matches_oracle(orc):
         say(f"  {mode}: errors Ey {ey_err(Ey, Eo):.2e} grad {g_err(g, go):.2e} "
             f"(Heston part {g_err(g[:5], go[:5]):.2e})")
         assert ey_err(Ey, Eo) <= 1e-12
-        assert g_err(g, go) <= 1e-6
+        assert g_err(g, go) <= 1e-9
 
 
 def test_slv_checkpoint_spacings(slv_small):
@@ -100,7 +100,7 @@ def test_slv_edge_shapes(orc):
         Eo, Go, go = orc.gradient(pb, th0, C)
         say(f"  nT={n_t} P={P} N={N} K={k}: Ey {ey_err(Ey, Eo):.2e} grad {g_err(g, go):.2e}")
         assert ey_err(Ey, Eo) <= 1e-12
-        assert g_err(g, go) <= 1e-6
+        assert g_err(g, go) <= 1e-9
 
 
 def test_slv_invalid_theta_sets_status(slv_small):
@@ -167,7 +167,7 @@ def test_slv_paths_per_lane(orc):
     C = np.linspace(2.0, 9.0, pb.n_instr)
     Eo, Go, go = orc.gradient(pb, th0, C)
     for ppl, k in ((2, 8), (4, 8), (2, 16), (2, 32)):
-        for prec, tol_y, tol_g in (("fp64", 1e-12, 1e-6), ("fp32", 1e-5, 1e-4)):
+        for prec, tol_y, tol_g in (("fp64", 1e-12, 1e-9), ("fp32", 1e-5, 1e-4)):
             Ey_f, Ey, G, g = run(pb, th0, C, prec, paths_per_lane=ppl, ckpt_every=k)
             say(f"  ppl={ppl} K={k} {prec}: Ey {ey_err(Ey, Eo):.2e} grad {g_err(g, go):.2e}")
             assert ey_err(Ey, Eo) <= tol_y

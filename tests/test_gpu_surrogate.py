@@ -257,7 +257,8 @@ def test_training_reduces_loss():
 
 def test_surrogate_assisted_calibration():
     """The surrogate-assisted iteration only accepts Monte Carlo improvements
-    (G never rises), counts its Monte Carlo calls, and stops at g_stop."""
+    (G never rises), makes at most one Monte Carlo call per iteration, and
+    stops at g_stop."""
     from paper_1901_04200_amd.mc import MonteCarloCalibration
     pb, _, _, _ = W.heston_problem(n_paths=1 << 14)
     draws = W.heston_feller_draws(12, 1024)
@@ -277,7 +278,7 @@ def test_surrogate_assisted_calibration():
     say("  G:", " ".join(f"{g:.3g}" for g in Gs), "accepted", sum(r.accepted_surrogate for r in recs))
     assert all(b <= a for a, b in zip(Gs, Gs[1:]))
     assert Gs[-1] < G0
-    assert all(r.mc_calls >= 1 for r in recs)
+    assert all(r.mc_calls in (0, 1) for r in recs) and sum(r.mc_calls for r in recs) >= 1
     stop = 0.5 * (G0 + Gs[-1])
     _, recs2 = S.surrogate_calibration(net, mc, C, th0, W.HESTON_LO, W.HESTON_HI, iters=12, g_stop=stop)
     assert len(recs2) <= len(recs) and recs2[-1].G_mc <= stop

@@ -9,7 +9,8 @@ the Heston box (2 kappa theta_bar = 0.12 << xi^2 = 0.69) the variance often
 lands next to zero, where sqrt turns a perturbation d of v into about
 xi sqrt(h d) w of the next step; the price error then falls only slowly with
 k and needs about 40 bits to reach 1e-5: FP32 state cannot meet the price
-bound there however it rounds, FP64 meets it.  CPU only; no GPU involved.
+bound there however it rounds, and neither can FP32 normals under an FP64
+variance recursion; FP64 meets it.  CPU only; no GPU involved.
 """
 import os
 import subprocess
@@ -31,8 +32,10 @@ def floor_exe(tmp_path_factory):
     return exe
 
 
-def price_err(exe, k, theta, paths=1 << 18):
-    out = subprocess.run([exe, str(paths), str(k), *map(repr, theta)], check=True, capture_output=True, text=True,
+def price_err(exe, k, theta, paths=1 << 18, kz=None):
+    extra = [] if kz is None else [str(kz)]
+    out = subprocess.run([exe, str(paths), str(k), *map(repr, theta), *extra], check=True, capture_output=True,
+                         text=True,
                          env={**os.environ, "OMP_NUM_THREADS": str(min(8, os.cpu_count() or 1))})
     return float(out.stdout)
 
@@ -47,3 +50,12 @@ def test_first_draw_needs_about_40_bits(floor_exe):
     assert e[24] > 1e-5 and e[32] > 1e-5      # FP32 storage, and 8 bits more, miss the bound
     assert e[40] < 1e-5                        # about 40 bits meet it
     assert e[48] < 1e-6 and e[48] < e[40]
+
+
+def test_first_draw_fp32_normals_alone_miss(floor_exe):
+    """FP32 normals with the variance recursion in FP64 still miss 1e-5 at the
+    first draw: a mixed mode cannot reach the bound there, FP64 throughout
+    (the library's FP64 mode) does."""
+    assert price_err(floor_exe, 53, TH0, kz=24) > 1e-5
+    assert price_err(floor_exe, 24, TH0, kz=53) > 1e-5
+    assert price_err(floor_exe, 53, TH0, kz=53) == 0.0
