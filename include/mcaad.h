@@ -36,6 +36,7 @@
 #ifndef MCAAD_H
 #define MCAAD_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -55,8 +56,7 @@ extern "C" {
 #define CAL_FP64 1
 
 /* where the reverse sweep gets its checkpoints */
-#define CAL_CKPT_AUTO 0    /* the default: CAL_CKPT_STORE (both modes hold the same
-                              [N/K][n_state][P] buffer; storing saves pass 2 its re-run) */
+#define CAL_CKPT_AUTO 0    /* CAL_CKPT_STORE when the buffer fits, else RERUN */
 #define CAL_CKPT_RERUN 1   /* pass 2 re-runs the forward sweep and keeps its own checkpoints */
 #define CAL_CKPT_STORE 2   /* the pass-1 sweep of calibrate_gradient stores them in HBM */
 
@@ -199,6 +199,30 @@ int calibrate_jacobian(cal_ctx *ctx, const double *d_theta, double *d_Ey, double
  * d_Ey[i*m ..] and d_J[i*m*M ..].  1 <= n_inst <= the problem's max_batch. */
 int calibrate_jacobian_batch(cal_ctx *ctx, const double *d_theta, int32_t n_inst, uint32_t inst0, double *d_Ey,
                              double *d_J, void *stream);
+
+/* For callers that cannot allocate device memory (code under stream capture,
+ * serving loops, harnesses that forbid allocation): calibrate_gradient for a
+ * Black-Scholes or Heston problem without a context.  Every buffer beyond
+ * the caller's arrays (instrument tables, block partials, the adjoint seeds,
+ * the checkpoints) lives in one static device array of
+ * CAL_STATIC_SCRATCH_BYTES per device, which the library holds from the first
+ * call on that device until the process ends; the call allocates nothing.
+ *   pb        host problem (as for cal_create; models CAL_BS and CAL_HESTON,
+ *             else CAL_EUNSUPPORTED); its buffers must fit the array, else
+ *             CAL_EINVAL with the bytes needed in cal_last_error(NULL)
+ *             (2^20 Heston paths at 256 steps fit at ckpt_every 16)
+ *   d_theta [M], d_C [m]   inputs; d_Ey [m], d_G [1], d_grad [M] outputs
+ *             (FP64, caller's device memory, as for calibrate_gradient)
+ *   d_status  caller's int32 on the device, set to this call's CAL_FLAG_* bits
+ * Results are those of calibrate_gradient on a context made from the same
+ * problem, bit for bit.  The call uploads the instrument tables (a few KB)
+ * and synchronises `stream` once before queuing its kernels; it keeps the
+ * array's contents from the last call (nothing in it is read before this
+ * call writes it).  Calls that overlap on one device, on any streams or host
+ * threads, race on the array: serialise them. */
+#define CAL_STATIC_SCRATCH_BYTES ((size_t)160 << 20)
+int calibrate_gradient_static(const cal_problem *pb, const double *d_theta, const double *d_C, double *d_Ey,
+                              double *d_G, double *d_grad, int32_t *d_status, void *stream);
 
 /* Synchronise `stream` and return the device status bits (CAL_FLAG_*)
  * accumulated since the previous cal_status call (then cleared), or a

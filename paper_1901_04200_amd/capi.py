@@ -24,6 +24,7 @@ EXPORTED = (
     "cal_validate", "cal_create", "cal_destroy", "calibrate_forward", "calibrate_vjp",
     "calibrate_forward_store", "calibrate_vjp_stored", "calibrate_gradient", "calibrate_jacobian", "calibrate_jacobian_batch", "cal_status", "cal_last_error",
     "cal_timing_enable", "cal_timing_read", "cal_geometry", "cal_philox", "cal_normals",
+    "calibrate_gradient_static",
 )
 
 
@@ -75,6 +76,7 @@ def lib():
             "cal_geometry": ([vp, C.POINTER(i32), C.POINTER(i64), C.POINTER(i32), C.POINTER(i32)], C.c_int),
             "cal_philox": ([vp, C.c_uint32, C.c_uint32, i64, vp, vp], C.c_int),
             "cal_normals": ([i32, C.c_uint64, C.c_uint32, C.c_uint32, i64, C.c_uint32, i32, vp, vp], C.c_int),
+            "calibrate_gradient_static": ([pp, dp, dp, dp, dp, dp, dp, vp], C.c_int),
         }
         for name, (args, res) in sig.items():
             f = getattr(L, name)
@@ -175,6 +177,15 @@ def calibrate_vjp_stored(ctx, theta, lam, grad, stream=None):
 def calibrate_gradient(ctx, theta, C_, Ey, G, grad, stream=None):
     return _check(lib().calibrate_gradient(ctx, _ptr(theta), _ptr(C_), _ptr(Ey), _ptr(G), _ptr(grad),
                                            _stream(stream)), ctx)
+
+
+def calibrate_gradient_static(pb, theta, C_, Ey, G, grad, status, precision=CAL_FP32, ckpt_every=0,
+                              ckpt_mode=CAL_CKPT_AUTO, paths_per_lane=0, stream=None):
+    """calibrate_gradient without a context (buffers in the library's static
+    device array); status: int32 device tensor [1], set to the call's flags."""
+    pk = Packed(pb, precision, ckpt_every, ckpt_mode, 0, paths_per_lane)
+    return _check(lib().calibrate_gradient_static(C.byref(pk.s), _ptr(theta), _ptr(C_), _ptr(Ey), _ptr(G),
+                                                  _ptr(grad), _ptr(status), _stream(stream)))
 
 
 def calibrate_jacobian(ctx, theta, Ey, J, stream=None):

@@ -8,6 +8,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <numeric>
 #include <string>
 #include <vector>
@@ -148,6 +149,65 @@ static hipError_t alloc(void **p, size_t bytes)
     return hipMalloc(p, bytes ? bytes : 8);
 }
 
+// Host copies of the instrument tables the kernels read: instruments grouped
+// by maturity step (ascending; original order within a step), their strikes
+// (FP64 and FP32) and discount factors exp(-r n_i h), the original index of
+// each, and the distinct maturity steps with the ranges they begin.
+struct Tables {
+    std::vector<int32_t> order, date_step, date_begin;
+    std::vector<double> strike, disc;
+    std::vector<float> strike_f;
+};
+
+static void build_tables(const cal_problem *pb, Tables &t)
+{
+    const int m = pb->n_instr;
+    const double h = pb->t_max / pb->n_steps;
+    t.order.resize(m);
+    std::iota(t.order.begin(), t.order.end(), 0);
+    std::stable_sort(t.order.begin(), t.order.end(),
+                     [&](int a, int b) { return pb->instr_step[a] < pb->instr_step[b]; });
+    t.date_step.clear();
+    t.date_begin.clear();
+    t.strike.resize(m);
+    t.disc.resize(m);
+    t.strike_f.resize(m);
+    for (int k = 0; k < m; ++k) {
+        const int i = t.order[k];
+        const int s = pb->instr_step[i];
+        if (t.date_step.empty() || t.date_step.back() != s) {
+            t.date_step.push_back(s);
+            t.date_begin.push_back(k);
+        }
+        t.strike[k] = pb->instr_strike[i];
+        t.strike_f[k] = (float)pb->instr_strike[i];
+        t.disc[k] = std::exp(-pb->rate * s * h);
+    }
+    t.date_begin.push_back(m);
+}
+
+// The scalar part of the kernels' problem description (table pointers are
+// set by the caller).
+static void set_scalars(DevProblem &d, const cal_problem *pb, int nd, int nseg, int K, int ppl)
+{
+    const double h = pb->t_max / pb->n_steps;
+    d.N = pb->n_steps;
+    d.m = pb->n_instr;
+    d.M = pb->n_params;
+    d.ndates = nd;
+    d.nseg = nseg;
+    d.K = K;
+    d.ppl = ppl;
+    d.P = pb->n_paths;
+    d.k0 = (uint32_t)pb->seed;
+    d.k1 = (uint32_t)(pb->seed >> 32);
+    d.inst = pb->inst;
+    d.s0 = pb->s0;
+    d.rate = pb->rate;
+    d.h = h;
+    d.sq = std::sqrt(h);
+}
+
 extern "C" int cal_validate(const cal_problem *pb, char *msg, int32_t msg_len)
 {
     int code;
@@ -206,26 +266,12 @@ extern "C" int cal_create(const cal_problem *pb, cal_ctx **out)
 
     // instruments grouped by maturity date (ascending), original order within a date
     const int m = c->m;
-    std::vector<int32_t> order(m);
-    std::iota(order.begin(), order.end(), 0);
-    std::stable_sort(order.begin(), order.end(),
-                     [&](int a, int b) { return pb->instr_step[a] < pb->instr_step[b]; });
-    std::vector<int32_t> date_step, date_begin;
-    std::vector<double> strike(m), disc(m);
-    std::vector<float> strike_f(m);
     const double h = pb->t_max / c->N;
-    for (int k = 0; k < m; ++k) {
-        const int i = order[k];
-        const int s = pb->instr_step[i];
-        if (date_step.empty() || date_step.back() != s) {
-            date_step.push_back(s);
-            date_begin.push_back(k);
-        }
-        strike[k] = pb->instr_strike[i];
-        strike_f[k] = (float)pb->instr_strike[i];
-        disc[k] = std::exp(-pb->rate * s * h);
-    }
-    date_begin.push_back(m);
+    Tables tb;
+    build_tables(pb, tb);
+    const std::vector<int32_t> &order = tb.order, &date_step = tb.date_step, &date_begin = tb.date_begin;
+    const std::vector<double> &strike = tb.strike, &disc = tb.disc;
+    const std::vector<float> &strike_f = tb.strike_f;
     const int nd = (int)date_step.size();
 
     // tangent mode serves Black-Scholes and Heston (labels); not the grid models
@@ -330,22 +376,8 @@ extern "C" int cal_create(const cal_problem *pb, cal_ctx **out)
     }
 
     DevProblem &d = c->dp;
+    set_scalars(d, pb, nd, nseg, c->K, c->ppl);
     d.theta_save = c->d_theta_ckpt;
-    d.N = c->N;
-    d.m = m;
-    d.M = c->M;
-    d.ndates = nd;
-    d.nseg = nseg;
-    d.K = c->K;
-    d.ppl = c->ppl;
-    d.P = c->P;
-    d.k0 = (uint32_t)pb->seed;
-    d.k1 = (uint32_t)(pb->seed >> 32);
-    d.inst = pb->inst;
-    d.s0 = pb->s0;
-    d.rate = pb->rate;
-    d.h = h;
-    d.sq = std::sqrt(h);
     d.date_step = c->d_date_step;
     d.date_begin = c->d_date_begin;
     d.strike = c->d_strike;
@@ -577,6 +609,145 @@ extern "C" int calibrate_gradient(cal_ctx *ctx, const double *d_theta, const dou
     ctx->ckpt_valid = true;   // either pass wrote every segment
     e = launch_reduce_sorted(ctx->d_part_g, ctx->nblocks, ctx->M, nullptr, 1.0, d_grad, ctx->d_status, st);
     if (e != hipSuccess) return hip_fail(ctx, e, "reduce launch");
+    return CAL_OK;
+}
+
+// --- the allocation-free gradient ------------------------------------------------
+// One static device array per device holds every buffer calibrate_gradient_static
+// needs beyond its caller's inputs and outputs.  Host code never passes the
+// array's name to a kernel or a copy: it uses the address hipGetSymbolAddress
+// returns for the current device, taken once per device on the first call there.
+namespace {
+
+constexpr int kMaxDevices = 64;
+constexpr size_t kAlign = 256;
+
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[CAL_STATIC_SCRATCH_BYTES];
+
+static std::mutex g_scratch_mu;
+static unsigned char *g_scratch_ptr[kMaxDevices] = {};
+
+static int scratch_address(int dev, unsigned char **out)
+{
+    if (dev < 0 || dev >= kMaxDevices) return fail(nullptr, CAL_EUNSUPPORTED, "device index beyond 63");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) return hip_fail(nullptr, e, "hipGetSymbolAddress(scratch)");
+        g_scratch_ptr[dev] = (unsigned char *)p;
+    }
+    *out = g_scratch_ptr[dev];
+    return CAL_OK;
+}
+
+__global__ void k_clear_status(int32_t *status)
+{
+    if (threadIdx.x == 0) *status = 0;
+}
+
+static size_t align_up(size_t o)
+{
+    return (o + kAlign - 1) / kAlign * kAlign;
+}
+
+extern "C" int calibrate_gradient_static(const cal_problem *pb, const double *d_theta, const double *d_C,
+                                         double *d_Ey, double *d_G, double *d_grad, int32_t *d_status, void *stream)
+{
+    int code;
+    std::string msg = validate(pb, &code);
+    if (code != CAL_OK) return fail(nullptr, code, msg);
+    if (pb->model != CAL_BS && pb->model != CAL_HESTON)
+        return fail(nullptr, CAL_EUNSUPPORTED, "calibrate_gradient_static serves Black-Scholes and Heston");
+    if (!d_theta || !d_C || !d_Ey || !d_G || !d_grad || !d_status)
+        return fail(nullptr, CAL_EINVAL, "null device pointer");
+    const bool fp64 = pb->precision == CAL_FP64;
+    const size_t real = fp64 ? 8 : 4;
+    const int m = pb->n_instr, M = pb->n_params, N = pb->n_steps;
+    const int64_t P = pb->n_paths;
+    const int ppl = pb->paths_per_lane > 0 ? pb->paths_per_lane : 1;
+    const int K = pb->ckpt_every ? pb->ckpt_every : (fp64 ? 8 : 16);
+    const int nv = pb->model == CAL_HESTON ? 2 : 1;
+    const int nseg = (N + K - 1) / K;
+    const int64_t nblocks = (P + (int64_t)kBlock * ppl - 1) / ((int64_t)kBlock * ppl);
+    const bool store = pb->ckpt_mode != CAL_CKPT_RERUN;
+
+    thread_local Tables tb;   // host staging; keeps its capacity between calls
+    build_tables(pb, tb);
+    const int nd = (int)tb.date_step.size();
+
+    // layout of the scratch array: the tables, then the pass buffers
+    size_t o = 0;
+    const size_t o_date_step = o;
+    o = align_up(o + sizeof(int32_t) * nd);
+    const size_t o_date_begin = o;
+    o = align_up(o + sizeof(int32_t) * (nd + 1));
+    const size_t o_strike = o;
+    o = align_up(o + sizeof(double) * m);
+    const size_t o_strike_f = o;
+    o = align_up(o + sizeof(float) * m);
+    const size_t o_disc = o;
+    o = align_up(o + sizeof(double) * m);
+    const size_t o_id = o;
+    o = align_up(o + sizeof(int32_t) * m);
+    const size_t tables_end = o;
+    const size_t o_part_y = o;
+    o = align_up(o + sizeof(double) * (size_t)nblocks * m);
+    const size_t o_part_g = o;
+    o = align_up(o + sizeof(double) * (size_t)nblocks * M);
+    const size_t o_lamD = o;
+    o = align_up(o + real * m);
+    const size_t o_ckpt = o;
+    o = align_up(o + real * (size_t)nseg * nv * (size_t)P);
+    if (o > (size_t)CAL_STATIC_SCRATCH_BYTES)
+        return fail(nullptr, CAL_EINVAL,
+                    "problem needs " + std::to_string(o) + " bytes of scratch, more than the " +
+                        std::to_string((size_t)CAL_STATIC_SCRATCH_BYTES) +
+                        " of the static buffer (fewer paths, or a wider checkpoint spacing)");
+
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(nullptr, e, "hipGetDevice");
+    unsigned char *base = nullptr;
+    int rc = scratch_address(dev, &base);
+    if (rc) return rc;
+
+    thread_local std::vector<unsigned char> stage;
+    stage.assign(tables_end, 0);
+    std::memcpy(stage.data() + o_date_step, tb.date_step.data(), sizeof(int32_t) * nd);
+    std::memcpy(stage.data() + o_date_begin, tb.date_begin.data(), sizeof(int32_t) * (nd + 1));
+    std::memcpy(stage.data() + o_strike, tb.strike.data(), sizeof(double) * m);
+    std::memcpy(stage.data() + o_strike_f, tb.strike_f.data(), sizeof(float) * m);
+    std::memcpy(stage.data() + o_disc, tb.disc.data(), sizeof(double) * m);
+    std::memcpy(stage.data() + o_id, tb.order.data(), sizeof(int32_t) * m);
+    hipStream_t st = (hipStream_t)stream;
+    e = hipMemcpyAsync(base, stage.data(), tables_end, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);   // the staging buffer is reused by the next call
+    if (e != hipSuccess) return hip_fail(nullptr, e, "table upload");
+
+    DevProblem d{};
+    set_scalars(d, pb, nd, nseg, K, ppl);
+    d.date_step = (const int32_t *)(base + o_date_step);
+    d.date_begin = (const int32_t *)(base + o_date_begin);
+    d.strike = (const double *)(base + o_strike);
+    d.strike_f = (const float *)(base + o_strike_f);
+    d.disc = (const double *)(base + o_disc);
+    d.id = (const int32_t *)(base + o_id);
+    d.status = d_status;
+    d.theta_save = nullptr;
+    double *part_y = (double *)(base + o_part_y), *part_g = (double *)(base + o_part_g);
+    void *lamD = base + o_lamD, *ckpt = base + o_ckpt;
+
+    hipLaunchKernelGGL(k_clear_status, dim3(1), dim3(64), 0, st, d_status);
+    e = hipGetLastError();
+    if (e == hipSuccess) e = launch_pass1(d, pb->model, fp64, store, d_theta, part_y, ckpt, nblocks, st);
+    if (e == hipSuccess) e = launch_reduce_sorted(part_y, nblocks, m, d.id, 1.0 / (double)P, d_Ey, d_status, st);
+    if (e == hipSuccess) e = launch_residual(d, fp64, d_Ey, d_C, d_G, lamD, d_theta, st);
+    if (e == hipSuccess) e = launch_pass2(d, pb->model, fp64, store, d_theta, lamD, part_g, ckpt, nblocks, st);
+    if (e == hipSuccess) e = launch_reduce_sorted(part_g, nblocks, M, nullptr, 1.0, d_grad, d_status, st);
+    if (e != hipSuccess) return hip_fail(nullptr, e, "launch");
     return CAL_OK;
 }
 
