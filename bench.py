@@ -678,6 +678,7 @@ def surrogate_leg(args):
     gain = {k: v for k, v in gain.items() if k != "per_instance"}
     details = {k: v for k, v in res.items() if k != "gain"}
     return {"grad_rel_err_surrogate": res["surrogate_grad_rel_err"]["median"], "p_star_paths": res["p_star"],
+            "mc_grad_rel_err_at_p_star": res["mc_grad_rel_err_at_p_star"],
             "us_surrogate_step": st["surrogate"] * 1e6, "us_mc_step_at_p_star": st["mc_at_p_star"] * 1e6,
             "mc_over_surrogate": st["mc_over_surrogate"], "gain_test": gain, "details": details}
 

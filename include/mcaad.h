@@ -56,7 +56,8 @@ extern "C" {
 #define CAL_FP64 1
 
 /* where the reverse sweep gets its checkpoints */
-#define CAL_CKPT_AUTO 0    /* CAL_CKPT_STORE when the buffer fits, else RERUN */
+#define CAL_CKPT_AUTO 0    /* the default: CAL_CKPT_STORE (both modes hold the same
+                              [N/K][n_state][P] buffer; storing saves pass 2 its re-run) */
 #define CAL_CKPT_RERUN 1   /* pass 2 re-runs the forward sweep and keeps its own checkpoints */
 #define CAL_CKPT_STORE 2   /* the pass-1 sweep of calibrate_gradient stores them in HBM */
 

@@ -11,6 +11,12 @@ backpropagation).  This module computes, plainly with numpy:
   loss(params, X, Yl, Jl, w)            -> L = mean_{b,i} (Y - Yl)^2
                                                + w mean_{b,i,j} (J - Jl)^2
   grads(params, X, Yl, Jl, w)           -> (L, [(dW_l, db_l)])
+  grad_magnitudes(params, X, Yl, Jl, w) -> [(|dW_l|, |db_l|)]: the same
+      backward pass with every factor replaced by its absolute value (the
+      running-error magnitudes of a rounding analysis: a gradient element
+      computed with relative rounding u in each factor of each term differs
+      from the exact one by at most about (roundings along a term) u times
+      this magnitude)
 
 params: list of (W [fan_in, fan_out], b [fan_out]).  SiLU s(z) = z sig(z),
 s' = sig (1 + z (1 - sig)), s'' = sig (1 - sig) (2 + z (1 - 2 sig)).
@@ -89,6 +95,32 @@ def grads(params, X, Yl, Jl, w):
         Hb = Zb @ W.T
         Tb = Ub @ W.T
     return L_val, out
+
+
+def grad_magnitudes(params, X, Yl, Jl, w):
+    Y, T, cache = _forward(params, X)
+    J = np.transpose(T, (0, 2, 1))
+    B, m = Y.shape
+    n_in = X.shape[1]
+    Hb = np.abs(2.0 * (Y - Yl) / (B * m))
+    Tb = np.abs(np.transpose(2.0 * w * (J - Jl) / (B * m * n_in), (0, 2, 1)))
+    out = [None] * len(params)
+    for l in range(len(params) - 1, -1, -1):
+        W, b = params[l]
+        Hin, Tin, Z, U = cache[l]
+        Hin, Tin, U, Wa = np.abs(Hin), np.abs(Tin), np.abs(U), np.abs(W)
+        if l == len(params) - 1:
+            Zb, Ub = Hb, Tb
+        else:
+            d1, d2 = np.abs(dsilu(Z)), np.abs(d2silu(Z))
+            Zb = Hb * d1 + np.sum(Tb * U, axis=1) * d2
+            Ub = Tb * d1[:, None, :]
+        dW = Hin.T @ Zb + np.einsum("bti,btj->ij", Tin, Ub)
+        db = Zb.sum(axis=0)
+        out[l] = (dW, db)
+        Hb = Zb @ Wa.T
+        Tb = Ub @ Wa.T
+    return out
 
 
 def init_params(sizes, seed):

@@ -196,17 +196,26 @@ __device__ __forceinline__ void pass2_block(const DevProblem &pb, const double *
         const double on = active ? 1.0 : 0.0;   // inactive lanes add nothing
         int dhi = pb.ndates;        // dates with index < dhi mature at or before this segment's end
 
+        // The checkpoint of the segment after the current one is requested
+        // before the current segment's sweeps run, so that its load latency
+        // is hidden behind them.  Inactive lanes (past the last path) load
+        // path 0's slot but run a harmless path from (0, v0) instead and add
+        // nothing: in the re-run mode another workgroup may still be writing
+        // that slot.
+        const int64_t pl = active ? p : 0;
+        R x_next = ckpt[(int64_t)((pb.nseg - 1) * T::NV) * pb.P + pl];
+        R v_next = (R)0;
+        if constexpr (T::NV == 2) v_next = ckpt[(int64_t)((pb.nseg - 1) * T::NV + 1) * pb.P + pl];
         for (int seg = pb.nseg - 1; seg >= 0; --seg) {
             const int n0 = seg * K;
-            // inactive lanes (past the last path) load path 0's slot but run a
-            // harmless path from (0, v0) instead and add nothing: in the re-run
-            // mode another workgroup may still be writing that slot
-            const int64_t base = (int64_t)(seg * T::NV) * pb.P + (active ? p : 0);
-            R x = ckpt[base];
+            R x = active ? x_next : (R)0;
             R v = (R)0;
-            if constexpr (T::NV == 2) v = ckpt[base + pb.P];
-            x = active ? x : (R)0;
-            if constexpr (MODEL == kHeston) v = active ? v : c.v0;
+            if constexpr (MODEL == kHeston) v = active ? v_next : c.v0;
+            if (seg > 0) {
+                const int64_t base = (int64_t)((seg - 1) * T::NV) * pb.P + pl;
+                x_next = ckpt[base];
+                if constexpr (T::NV == 2) v_next = ckpt[base + pb.P];
+            }
             int dlo = dhi;
             while (dlo > 0 && ldc(pb.date_step, dlo - 1) > n0) --dlo;
             int d = dlo;

@@ -286,109 +286,85 @@ class StepRecord:
 
 
 class DeviceSurrogate:
-    """The trained network as the calibration step's model: prices at one
-    parameter vector, and G, grad G at a batch of parameter vectors (all
-    trial points of one line search in one launch, one copy back, one
-    synchronisation).  Buffers are made once; the targets are uploaded only
-    when they change."""
+    """The trained network as the calibration step's model: at a batch of
+    parameter vectors (all trial points of one step in one launch) its
+    prices Y, Jacobians J and, given targets, G = 1/2 |Y - C|^2 and
+    J^T (Y - C).  Buffers and their addresses are fixed once; the outputs sit
+    side by side in one device buffer, so one copy and one synchronisation
+    bring them back; the targets are uploaded only when they change."""
 
     def __init__(self, net: MLP, max_points: int = 32):
         import torch
         self.net, self.torch = net, torch
-        self.max_points = max_points
+        self.max_points = B = max_points
+        n, o = net.n_in, net.n_out
+        self.n, self.o = n, o
         dev = net.dev
-        self.th_host = torch.empty(max_points, net.n_in, dtype=torch.float32, pin_memory=True)
-        self.th_dev = torch.empty(max_points, net.n_in, dtype=torch.float32, device=dev)
-        self.C_host = torch.empty(net.n_out, dtype=torch.float64, pin_memory=True)
-        self.C_dev = torch.zeros(net.n_out, dtype=torch.float64, device=dev)
+        self.th_host = torch.zeros(B, n, dtype=torch.float32, pin_memory=True)
+        self.th_dev = torch.zeros(B, n, dtype=torch.float32, device=dev)
+        self.C_host = torch.zeros(o, dtype=torch.float64, pin_memory=True)
+        self.C_dev = torch.zeros(o, dtype=torch.float64, device=dev)
         self.C_now = None
-        self.Y = torch.empty(max_points, net.n_out, dtype=torch.float32, device=dev)
-        self.J = torch.empty(max_points, net.n_out, net.n_in, dtype=torch.float32, device=dev)
-        # G [B] and grad [B, n_in] side by side in one buffer: one copy back
-        self.Gg = torch.empty(max_points * (1 + net.n_in), dtype=torch.float64, device=dev)
-        self.Gg_host = torch.empty(max_points * (1 + net.n_in), dtype=torch.float64, pin_memory=True)
+        # one buffer: G [B], grad [B, n] (FP64), then Y [B, o], J [B, o, n] (FP32)
+        self.nG, self.nY, self.nJ = 8 * B * (1 + n), 4 * B * o, 4 * B * o * n
+        tot = self.nG + self.nY + self.nJ
+        self.raw = torch.empty(tot, dtype=torch.uint8, device=dev)
+        self.raw_host = torch.empty(tot, dtype=torch.uint8, pin_memory=True)
+        self.raw_np = self.raw_host.numpy()
+        self.th_np, self.C_np = self.th_host.numpy(), self.C_host.numpy()
+        vp = C.c_void_p
+        base = self.raw.data_ptr()
+        self.p_G, self.p_Y, self.p_J = base, base + self.nG, base + self.nG + self.nY
+        self.p_th, self.p_C = vp(self.th_dev.data_ptr()), vp(self.C_dev.data_ptr())
         self.launches = 0
 
-    def _launch(self, thetas, C):
+    def evaluate(self, thetas, C_):
+        """(Y [B, o], J [B, o, n], G [B], grad [B, n]) as host arrays at the
+        rows of thetas, with targets C_ (FP64 [o])."""
         t = self.torch
-        B = len(thetas)
+        B, n, o = len(thetas), self.n, self.o
         if B > self.max_points:
             raise ValueError(f"at most {self.max_points} points per launch")
-        self.th_host[:B].copy_(t.from_numpy(np.ascontiguousarray(thetas, dtype=np.float32)))
-        self.th_dev[:B].copy_(self.th_host[:B], non_blocking=True)
-        if C is not None and (self.C_now is None or not np.array_equal(C, self.C_now)):
-            self.C_now = np.array(C, dtype=np.float64)
-            self.C_host.copy_(t.from_numpy(self.C_now))
+        self.th_np[:B] = thetas
+        self.th_dev.copy_(self.th_host, non_blocking=True)
+        if self.C_now is None or not np.array_equal(C_, self.C_now):
+            self.C_now = np.array(C_, dtype=np.float64)
+            self.C_np[:] = self.C_now
             self.C_dev.copy_(self.C_host, non_blocking=True)
-        n = self.net.n_in
-        G = self.Gg[:B]
-        g = self.Gg[B:B * (1 + n)].view(B, n)
-        self.net.calibration_gradient(self.th_dev[:B], self.C_dev, out=(self.Y[:B], self.J[:B], G, g))
+        vp = C.c_void_p
+        self.net._check(lib().mlp_calibration_gradient(
+            self.net.ctx, self.p_th, B, self.p_C, vp(self.p_Y), vp(self.p_J), vp(self.p_G), vp(self.p_G + 8 * B),
+            vp(t.cuda.current_stream().cuda_stream)))
         self.launches += 1
-        return B
-
-    def prices(self, theta) -> np.ndarray:
-        self._launch(np.asarray(theta)[None, :], None)
-        return self.Y[0].cpu().numpy().astype(np.float64)
-
-    def value_grad(self, thetas, C):
-        """G [B] and grad [B, M] (FP64, host) at the rows of thetas."""
-        B = self._launch(thetas, C)
-        n = self.net.n_in
-        k = B * (1 + n)
-        self.Gg_host[:k].copy_(self.Gg[:k], non_blocking=True)
-        self.torch.cuda.current_stream().synchronize()
-        out = self.Gg_host[:k].numpy()
-        return out[:B].copy(), out[B:].reshape(B, n).copy()
+        self.raw_host.copy_(self.raw, non_blocking=True)
+        t.cuda.current_stream().synchronize()
+        r = self.raw_np
+        Gg = r[:self.nG].view(np.float64)
+        Y = r[self.nG:self.nG + self.nY].view(np.float32)[:B * o].reshape(B, o).astype(np.float64)
+        J = r[self.nG + self.nY:].view(np.float32)[:B * o * n].reshape(B, o, n).astype(np.float64)
+        return Y, J, Gg[:B].copy(), Gg[B:B * (1 + n)].reshape(B, n).copy()
 
 
-def _minimise_model(model_vg, u0, g0, lo_u, hi_u, proj, *, iters: int, n_alpha: int, c_armijo: float = 1e-4):
-    """Minimise the corrected model over the box [lo_u, hi_u] (box-scaled
-    coordinates) from u0, where its gradient is g0, by projected L-BFGS whose
-    line search evaluates n_alpha step lengths 1, 1/2, ... in one call of
-    model_vg (B points -> values, gradients) and keeps the longest that
-    passes the Armijo test.  proj maps an array of points [B, M] onto the
-    feasible set.  Returns (u, model value, launches)."""
-    from .calibrate import LbfgsMemory
-    mem = LbfgsMemory(6)
-    u, gu = u0.copy(), g0.copy()
-    mval = None
-    launches = 0
-    scales = 0.5 ** np.arange(n_alpha)
-    for t in range(iters):
-        free = ~(((u <= lo_u) & (gu > 0.0)) | ((u >= hi_u) & (gu < 0.0)))
-        d = mem.apply(gu, free)
-        if not float(gu @ d) < 0.0:
-            mem.clear()
-            d = -np.where(free, gu, 0.0)
-        dmax = float(np.max(np.abs(d)))
-        if dmax == 0.0:
-            break
-        a0 = 1.0 if mem.s else min(1.0, 0.5 * float(np.max(hi_u - lo_u)) / dmax)
-        cands = proj(u[None, :] + (a0 * scales)[:, None] * d[None, :])
-        pts = cands if mval is not None else np.vstack([u[None, :], cands])
-        vals, grads = model_vg(pts)
-        launches += 1
-        if mval is None:
-            mval, vals, grads = vals[0], vals[1:], grads[1:]
-        steps = cands - u[None, :]
-        ok = np.isfinite(vals) & (vals <= mval + c_armijo * (steps @ gu)) & np.any(steps != 0.0, axis=1)
-        if not np.any(ok):
-            if mem.s:
-                mem.clear()
-                continue
-            break
-        pick = int(np.argmax(ok))     # the longest step that passes
-        mem.push(steps[pick], grads[pick] - gu)
-        u, gu, mval = cands[pick], grads[pick], vals[pick]
-        if dmax * a0 * scales[pick] < 1e-7:
-            break
-    return u, (mval if mval is not None else 0.0), launches
+def _lm_candidates(u0, gm, Ju, lo_u, hi_u, feasible):
+    """Trial points from u0 for a least-squares model with gradient gm and
+    Jacobian Ju (both in box-scaled coordinates): Levenberg-Marquardt steps
+    -(Ju^T Ju + mu I)^-1 gm for a ladder of mu (from pure Gauss-Newton to
+    nearly gradient steps) at full and half length, and two projected
+    gradient steps, all projected onto the feasible set; [B, M]."""
+    M = len(u0)
+    H = Ju.T @ Ju
+    scale = max(float(np.trace(H)) / M, 1e-300)
+    mus = scale * np.array([1e-8, 1e-4, 1e-3, 1e-2, 1e-1, 1.0, 10.0])
+    A = H[None, :, :] + mus[:, None, None] * np.eye(M)[None, :, :]
+    steps = -np.linalg.solve(A, np.broadcast_to(gm, (len(mus), M))[:, :, None])[:, :, 0]
+    gstep = -gm / max(float(np.max(np.abs(gm))), 1e-300) * float(np.max(hi_u - lo_u))
+    pts = np.concatenate([u0 + steps, u0 + 0.5 * steps, (u0 + gstep)[None, :], (u0 + 0.25 * gstep)[None, :]])
+    return feasible(pts, lo_u, hi_u)
 
 
-def trust_region_calibration(mc_value_grad, sur_prices, sur_value_grad, targets, theta0, lo, hi, *,
-                             iters: int = 50, g_stop: float = 0.0, feller: bool = True, radius0: float = 0.25,
-                             inner_iters: int = 6, n_alpha: int = 12, eta: float = 0.05):
+def trust_region_calibration(mc_value_grad, sur_eval, targets, theta0, lo, hi, *, iters: int = 50,
+                             g_stop: float = 0.0, feller: bool = True, radius0: float = 0.5, model_steps: int = 2,
+                             eta: float = 0.05):
     """Surrogate-assisted calibration: a trust-region iteration whose model
     is the surrogate made exact to first order at the current point, and
     whose judge is the Monte Carlo gradient.
@@ -397,23 +373,25 @@ def trust_region_calibration(mc_value_grad, sur_prices, sur_value_grad, targets,
     gradient).  The surrogate's prices y_s are shifted so that they equal
     E y_k at theta_k (the surrogate's functional with targets
     C' = C - E y_k + y_s(theta_k)), and a linear term c (theta - theta_k) with
-    c = g_k - grad G_s(theta_k; C') makes its gradient there g_k:
+    c = g_k - J_s(theta_k)^T (E y_k - C) makes its gradient there g_k:
         m(theta) = G_s(theta; C') + c (theta - theta_k),  m(theta_k) = G_k.
     m is minimised over the box intersected with |u - u_k|_inf <= radius
-    (u: box-scaled coordinates) by projected L-BFGS on the surrogate alone;
-    the Monte Carlo gradient at the result theta_c decides: accepted when
-    G(theta_c) < G_k (then its gradient is the next iteration's), the radius
-    grows when the actual decrease is at least 3/4 of the predicted one at a
-    step on the boundary and shrinks to a quarter of the step when the
-    ratio is below eta.  After two rejections in a row the next trial point
-    is a projected L-BFGS step on the Monte Carlo gradients themselves (the
-    curvature pairs every Monte Carlo call leaves), inside the radius.  So
-    every iteration costs one Monte Carlo gradient; the surrogate supplies
-    the curvature, the Monte Carlo gradient the first-order term, the
-    verdict and the fallback.
+    (u: box-scaled coordinates) by `model_steps` batched Gauss-Newton steps
+    on the surrogate alone: from the current point, Levenberg-Marquardt steps
+    for a ladder of damping values with the surrogate's Jacobian, all
+    evaluated in one launch, the best kept.  The Monte Carlo gradient at the
+    result theta_c decides: accepted when G(theta_c) < G_k (then its
+    gradient is the next iteration's), the radius grows when the actual
+    decrease is at least 3/4 of the predicted one at a step on the boundary
+    and shrinks to a quarter of the step when the ratio is below eta.  After
+    two rejections in a row the next trial point is a projected L-BFGS step
+    on the Monte Carlo gradients themselves (the curvature pairs every Monte
+    Carlo call leaves), inside the radius.  Every iteration costs one Monte
+    Carlo gradient; the surrogate supplies the curvature, the Monte Carlo
+    gradient the first-order term, the verdict and the fallback.
 
-    mc_value_grad(theta) -> (E y, G, grad); sur_prices(theta) -> y_s;
-    sur_value_grad(thetas [B, M], C) -> (G [B], grad [B, M]).  Returns
+    mc_value_grad(theta) -> (E y, G, grad); sur_eval(thetas [B, M], C) ->
+    (Y [B, m], J [B, m, M], G [B], grad [B, M]).  Returns
     (theta, [StepRecord])."""
     from .calibrate import LbfgsMemory
     lo, hi = np.asarray(lo, np.float64), np.asarray(hi, np.float64)
@@ -433,19 +411,17 @@ def trust_region_calibration(mc_value_grad, sur_prices, sur_value_grad, targets,
 
     u = feasible(((np.asarray(theta0, np.float64) - lo) / w)[None, :], 0.0, 1.0)[0]
     th = lo + w * u
-    t1 = time.perf_counter()
     Ey, G, g = mc_value_grad(th)
-    t_mc = time.perf_counter() - t1
     radius = radius0
     mc_mem = LbfgsMemory(8)
     rejected = 0
+    ys = Js = None          # the surrogate's prices and Jacobian at theta_k, when known
     recs: List[StepRecord] = []
     for it in range(iters):
         if G <= g_stop or radius < 1e-9:
             break
         t0 = time.perf_counter()
         lo_u, hi_u = np.maximum(0.0, u - radius), np.minimum(1.0, u + radius)
-        proj = lambda pts: feasible(pts, lo_u, hi_u)
         gk_u = np.asarray(g) * w
         err, launches = float("nan"), 0
         if rejected >= 2:
@@ -455,26 +431,31 @@ def trust_region_calibration(mc_value_grad, sur_prices, sur_value_grad, targets,
             if not float(gk_u @ d) < 0.0:
                 d = -np.where(free, gk_u, 0.0)
             a = 1.0 if mc_mem.s else radius / max(float(np.max(np.abs(d))), 1e-300)
-            u_c = proj((u + a * d)[None, :])[0]
+            u_c = feasible((u + a * d)[None, :], lo_u, hi_u)[0]
             m_c = G + float(gk_u @ (u_c - u))       # the linear model's value
             source = False
+            ys_c = Js_c = None
         else:
-            Cp = C - np.asarray(Ey) + sur_prices(th)
-            corr = {}
-
-            def model_vg(pts_u):
-                pts_th = lo + w * pts_u
-                vals, grads = sur_value_grad(pts_th, Cp)
-                if "c" not in corr:       # the first batch starts with theta_k itself
-                    corr["sg0"] = grads[0]
-                    corr["c"] = np.asarray(g) - grads[0]
-                c = corr["c"]
-                return vals + (pts_th - th) @ c, (grads + c[None, :]) * w[None, :]
-
-            u_c, m_c, launches = _minimise_model(model_vg, u, gk_u, lo_u, hi_u, proj, iters=inner_iters,
-                                                 n_alpha=n_alpha)
-            if "sg0" in corr:
-                err = float(np.linalg.norm(corr["sg0"] - g) / max(np.linalg.norm(g), 1e-300))
+            if ys is None:
+                Y0, J0, _, _ = sur_eval(th[None, :], C)
+                launches += 1
+                ys, Js = Y0[0], J0[0]
+            Cp = C - np.asarray(Ey) + ys
+            c = np.asarray(g) - Js.T @ (np.asarray(Ey) - C)
+            err = float(np.linalg.norm(Js.T @ (np.asarray(Ey) - C) - g) / max(np.linalg.norm(g), 1e-300))
+            u_b, m_b, gm_b, J_b, y_b = u, G, gk_u, Js * w[None, :], ys
+            for _ in range(model_steps):
+                pts = _lm_candidates(u_b, gm_b, J_b, lo_u, hi_u, feasible)
+                pts_th = lo + w * pts
+                Yc, Jc, Gc, gc = sur_eval(pts_th, Cp)
+                launches += 1
+                mvals = Gc + (pts_th - th) @ c
+                j = int(np.argmin(np.where(np.isfinite(mvals), mvals, np.inf)))
+                if not mvals[j] < m_b:
+                    break
+                u_b, m_b, gm_b, J_b, y_b = pts[j], float(mvals[j]), (gc[j] + c) * w, Jc[j] * w[None, :], Yc[j]
+            u_c, m_c = u_b, m_b
+            ys_c, Js_c = y_b, J_b / w[None, :]
             source = True
         th_c = lo + w * u_c
         t_s = time.perf_counter() - t0
@@ -494,6 +475,7 @@ def trust_region_calibration(mc_value_grad, sur_prices, sur_value_grad, targets,
             mc_mem.push(u_c - u, np.asarray(g_c) * w - gk_u)
         if accepted:
             u, th, Ey, G, g = u_c, th_c, Ey_c, G_c, g_c
+            ys, Js = ys_c, Js_c
             rejected = 0
         else:
             rejected += 1
@@ -510,11 +492,9 @@ def surrogate_calibration(net: MLP, mc, targets, theta0, lo, hi, *, iters: int =
     """trust_region_calibration with the trained network on the device as
     the model and the library's two-pass Monte Carlo gradient as the judge.
     Returns (theta, [StepRecord])."""
-    C = np.asarray(targets, np.float64)
     from .calibrate import MonteCarloObjective
-    sur = DeviceSurrogate(net, max_points=1 + kw.get("n_alpha", 12))
-    obj = MonteCarloObjective(mc, C)
-    mc_vg = obj.prices_value_and_grad
-
-    return trust_region_calibration(mc_vg, sur.prices, sur.value_grad, C, theta0, lo, hi, iters=iters,
+    C_ = np.asarray(targets, np.float64)
+    sur = DeviceSurrogate(net, max_points=16)
+    obj = MonteCarloObjective(mc, C_)
+    return trust_region_calibration(obj.prices_value_and_grad, sur.evaluate, C_, theta0, lo, hi, iters=iters,
                                     g_stop=g_stop, feller=feller, **kw)

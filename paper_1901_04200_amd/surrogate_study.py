@@ -42,12 +42,39 @@ def _time_call(fn, reps):
     return (time.perf_counter() - t0) / reps
 
 
-def run(n_train=1 << 14, train_paths=1 << 14, n_heldout=32, ref_paths=1 << 24, epochs=200, batch=4096,
-        lr=2e-3, lr_final=5e-5, w=1.0, seeds_mc=4, n_gain=16, g_frac=1e-3, max_iter=200, log=print):
+def _heldout_errors(net, ref, ho, C):
+    """Relative gradient errors of the network on the held-out draws ho
+    against the Monte Carlo reference context ref; returns (errors, g_ref)."""
+    import torch
+    g_ref = []
+    for th in ho:
+        _, _, g = ref.gradient(th, C)
+        g_ref.append(g.cpu().numpy())
+    g_ref = np.array(g_ref)
+    _, g_s = net.calibration_gradient(torch.as_tensor(ho, dtype=torch.float32, device="cuda"), C)
+    g_s = g_s.cpu().numpy()
+    return np.linalg.norm(g_s - g_ref, axis=1) / np.linalg.norm(g_ref, axis=1), g_ref
+
+
+def _mc_errors(pb, P, ho, g_ref, C, seeds):
+    """Relative gradient errors of the P-path Monte Carlo gradient (Philox
+    seeds 1000.., one context per seed) on the held-out draws."""
+    errs = []
+    for s_ in range(seeds):
+        mc = MonteCarloCalibration(pb.with_(n_paths=P, seed=1000 + s_))
+        for k in range(len(ho)):
+            _, _, g = mc.gradient(ho[k], C)
+            errs.append(np.linalg.norm(g.cpu().numpy() - g_ref[k]) / np.linalg.norm(g_ref[k]))
+        mc.close()
+    return np.array(errs)
+
+
+def run(n_train=1 << 14, train_paths=1 << 14, n_heldout=32, ref_paths=1 << 26, epochs=200, batch=4096,
+        lr=2e-3, lr_final=5e-5, w=1.0, seeds_mc=4, n_gain=16, g_frac=1e-3, max_iter=200, uniform_variant=True,
+        log=print):
     import torch
     out = {}
     pb, th0, tht, eps = W.heston_problem()
-    lo, hi = W.HESTON_LO, W.HESTON_HI
 
     # ---- 1.-2. labels and training ------------------------------------------
     net, info = train_surrogate(pb, n_train, train_paths, epochs, batch=batch, lr=lr, lr_final=lr_final, w=w,
@@ -60,44 +87,45 @@ def run(n_train=1 << 14, train_paths=1 << 14, n_heldout=32, ref_paths=1 << 24, e
     C = torch.as_tensor(W.noisy_targets(gen.forward(tht).cpu().numpy(), eps), device="cuda")
     gen.close()
     ho = W.heston_feller_draws(99, n_heldout)
+    # held-out draws where Feller's condition fails (uniform box draws of rng(98))
+    box = W.heston_draws(98, 8 * n_heldout)
+    ho_nf = box[2 * box[:, 0] * box[:, 1] < box[:, 2] ** 2][:n_heldout]
     ref = MonteCarloCalibration(pb.with_(n_paths=ref_paths, seed=7))
-    g_ref = []
-    for th in ho:
-        _, _, g = ref.gradient(th, C)
-        g_ref.append(g.cpu().numpy())
-    ref.close()
-    g_ref = np.array(g_ref)
-    _, g_s = net.calibration_gradient(torch.as_tensor(ho, dtype=torch.float32, device="cuda"), C)
-    g_s = g_s.cpu().numpy()
-    err_s = np.linalg.norm(g_s - g_ref, axis=1) / np.linalg.norm(g_ref, axis=1)
+    err_s, g_ref = _heldout_errors(net, ref, ho, C)
+    err_nf, g_ref_nf = _heldout_errors(net, ref, ho_nf, C)
     eps_s = float(np.median(err_s))
     out["surrogate_grad_rel_err"] = {"median": eps_s, "p90": float(np.quantile(err_s, 0.9)),
-                                     "heldout": n_heldout, "ref_paths": ref_paths}
-    log(f"surrogate: held-out gradient error median {eps_s:.3g} (vs MC at {ref_paths} paths)")
+                                     "heldout": n_heldout, "ref_paths": ref_paths,
+                                     "non_feller_median": float(np.median(err_nf)),
+                                     "non_feller_p90": float(np.quantile(err_nf, 0.9))}
+    log(f"surrogate: held-out gradient error median {eps_s:.3g} (Feller draws), {np.median(err_nf):.3g} "
+        f"(non-Feller draws), vs MC at {ref_paths} paths")
 
     # ---- 4. Monte Carlo gradient error vs paths -----------------------------
     # every held-out draw, seeds 1000.., against the same reference
     curve = []
     for lp in range(10, 19, 2):
         P = 1 << lp
-        errs = []
-        for s_ in range(seeds_mc):
-            mc = MonteCarloCalibration(pb.with_(n_paths=P, seed=1000 + s_))
-            for k in range(n_heldout):
-                _, _, g = mc.gradient(ho[k], C)
-                errs.append(np.linalg.norm(g.cpu().numpy() - g_ref[k]) / np.linalg.norm(g_ref[k]))
-            mc.close()
-        curve.append((P, float(np.median(errs))))
+        curve.append((P, float(np.median(_mc_errors(pb, P, ho, g_ref, C, seeds_mc)))))
     out["mc_grad_rel_err_vs_paths"] = curve
     # err = a P^-1/2 fitted on the points with P >= 2^14 (below that the
-    # relative error is no longer small), then solved for eps_s
+    # relative error is no longer small), then solved for eps_s; the error at
+    # P* is then measured there directly
     a = float(np.median([e * math.sqrt(P) for P, e in curve if P >= 1 << 14]))
-    p_star = max(1, int(round((a / eps_s) ** 2)))
+    p_fit = max(256, int(round((a / eps_s) ** 2)))
+    err_fit = float(np.median(_mc_errors(pb, p_fit, ho, g_ref, C, seeds_mc)))
+    # one correction with the error measured at the fitted point (error ~ P^-1/2)
+    p_star = max(256, int(round(p_fit * (err_fit / eps_s) ** 2)))
+    err_star = float(np.median(_mc_errors(pb, p_star, ho, g_ref, C, seeds_mc)))
     out["mc_err_coefficient"] = a
     out["reference_rel_err_estimate"] = a / math.sqrt(ref_paths)
+    out["p_fit"] = p_fit
+    out["mc_grad_rel_err_at_p_fit"] = err_fit
     out["p_star"] = p_star
+    out["mc_grad_rel_err_at_p_star"] = err_star
     log(f"surrogate: MC gradient error ~ {a:.3g}/sqrt(P) (reference ~{a / math.sqrt(ref_paths):.2g}); "
-        f"equal to eps_s at P* = {p_star}")
+        f"equal to eps_s at {p_fit} paths by the fit, measured there {err_fit:.3g}; corrected P* = {p_star}, "
+        f"measured there {err_star:.3g}")
 
     # ---- 5. step costs ------------------------------------------------------
     th1 = torch.as_tensor(ho[:1], dtype=torch.float32, device="cuda")
@@ -107,29 +135,45 @@ def run(n_train=1 << 14, train_paths=1 << 14, n_heldout=32, ref_paths=1 << 24, e
         net.calibration_gradient(th1, C, out=bufs)
 
     t_sur = _time_call(sur_step, 50)
-    P_time = max(256, p_star)
-    mcs = MonteCarloCalibration(pb.with_(n_paths=P_time))
+    mcs = MonteCarloCalibration(pb.with_(n_paths=p_star))
     t_mc = _time_call(lambda: mcs.gradient(ho[0], C), 20)
     mcs.close()
-    out["step_seconds"] = {"surrogate": t_sur, "mc_at_p_star": t_mc, "p_star_paths_timed": P_time,
+    out["step_seconds"] = {"surrogate": t_sur, "mc_at_p_star": t_mc, "p_star_paths_timed": p_star,
                            "mc_over_surrogate": t_mc / t_sur}
-    log(f"surrogate: step {t_sur * 1e6:.1f} us vs MC adjoint at {P_time} paths {t_mc * 1e6:.1f} us")
+    log(f"surrogate: step {t_sur * 1e6:.1f} us vs MC adjoint at {p_star} paths {t_mc * 1e6:.1f} us")
 
     # ---- 6. gain test ---------------------------------------------------------
     if n_gain > 0:
         out["gain"] = gain_test(net, pb, n_gain, g_frac, max_iter, log)
     net.close()
+
+    # ---- 7. the literal training set: uniform draws over the whole box -------
+    if uniform_variant:
+        net_u, info_u = train_surrogate(pb, n_train, train_paths, epochs, batch=batch, lr=lr, lr_final=lr_final,
+                                        w=w, log=log, region="box")
+        e_f, _ = _heldout_errors(net_u, ref, ho, C)
+        e_nf, _ = _heldout_errors(net_u, ref, ho_nf, C)
+        out["uniform_training"] = {"loss_last": info_u["training"]["loss_last"],
+                                   "grad_rel_err_median_feller": float(np.median(e_f)),
+                                   "grad_rel_err_median_non_feller": float(np.median(e_nf))}
+        log(f"surrogate (trained on uniform box draws): held-out gradient error median {np.median(e_f):.3g} "
+            f"(Feller), {np.median(e_nf):.3g} (non-Feller)")
+        net_u.close()
+    ref.close()
     return out
 
 
-def train_surrogate(pb, n_train, train_paths, epochs, batch=4096, lr=2e-3, lr_final=5e-5, w=1.0, log=print):
+def train_surrogate(pb, n_train, train_paths, epochs, batch=4096, lr=2e-3, lr_final=5e-5, w=1.0, log=print,
+                    region="feller"):
     """Labels (E y and dE y/dtheta by the Monte Carlo tangent kernel, each of
     n_train draws its own Philox instance, seed 4) and the network trained on
-    them with the differential loss; returns (net, timings and losses)."""
+    them with the differential loss; returns (net, timings and losses).
+    region: "feller" (draws where 2 kappa theta_bar >= xi^2) or "box"
+    (uniform over the whole Heston box)."""
     import torch
     lo, hi = W.HESTON_LO, W.HESTON_HI
     out = {}
-    draws = W.surrogate_draws(n_train, rng_seed=6)
+    draws = W.surrogate_draws(n_train, rng_seed=6) if region == "feller" else W.heston_draws(6, n_train)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     Ey, J = S.generate_labels(pb, draws, n_paths=train_paths, seed=4, chunk=256)

@@ -145,7 +145,11 @@ def lv_surface(rng, t_nodes, k_nodes, s0: float = 100.0) -> np.ndarray:
 
 
 def lv_problem(n_paths: int = 1 << 22, seed: int = 1, n_steps: int = 256, t_max: float = 2.0,
-               n_t: int = 10, n_k: int = 20):
+               n_t: int = 10, n_k: int = 20, surface: str = "smooth"):
+    """Local volatility on a 10 x 20 grid.  surface="smooth": node values from
+    lv_surface (draws 1 and 2 of rng(4) for theta0 and theta_target);
+    surface="iid": every node value U(0.1, 0.5) independently (the first and
+    second n_t n_k draws of rng(4))."""
     t_nodes = 0.2 * np.arange(1, n_t + 1) * (t_max / (0.2 * n_t))
     k_nodes = 55.0 + 5.0 * np.arange(n_k) * (19.0 / max(n_k - 1, 1))
     spy = n_steps / t_max
@@ -156,8 +160,14 @@ def lv_problem(n_paths: int = 1 << 22, seed: int = 1, n_steps: int = 256, t_max:
                  instr_step=instr_step, instr_strike=instr_strike, s0=100.0, rate=0.02, seed=seed,
                  t_nodes=t_nodes, k_nodes=k_nodes)
     rng = np.random.default_rng(4)
-    grid0 = lv_surface(rng, t_nodes, k_nodes)
-    grid_target = lv_surface(rng, t_nodes, k_nodes)
+    if surface == "iid":
+        grid0 = rng.uniform(0.1, 0.5, n_t * n_k)
+        grid_target = rng.uniform(0.1, 0.5, n_t * n_k)
+    elif surface == "smooth":
+        grid0 = lv_surface(rng, t_nodes, k_nodes)
+        grid_target = lv_surface(rng, t_nodes, k_nodes)
+    else:
+        raise ValueError(f"unknown surface {surface!r}")
     eps = np.random.default_rng(5).standard_normal(len(instr_step))
     fd_coords = np.sort(np.random.default_rng(5).choice(n_t * n_k, size=min(10, n_t * n_k), replace=False))
     return pb, grid0, grid_target, eps, fd_coords

@@ -143,13 +143,14 @@ class ToyPricing:
     def sur_prices(self, t):
         return 1.02 * self.prices(t) + 0.05 * np.sin(3 * t).sum()
 
-    def sur_vg(self, ts, Cp):
-        G, g = [], []
-        for t in ts:
-            r = self.sur_prices(t) - Cp
-            G.append(0.5 * float(r @ r))
-            g.append((1.02 * self.jac(t) + 0.15 * np.cos(3 * t)[None, :]).T @ r)
-        return np.array(G), np.array(g)
+    def sur_jac(self, t):
+        return 1.02 * self.jac(t) + 0.05 * 3 * np.cos(3 * t)[None, :] * np.ones((40, 1))
+
+    def sur_eval(self, ts, Cp):
+        Y = np.array([self.sur_prices(t) for t in ts])
+        J = np.array([self.sur_jac(t) for t in ts])
+        r = Y - Cp[None, :]
+        return Y, J, 0.5 * np.sum(r * r, axis=1), np.einsum("bij,bi->bj", J, r)
 
 
 def test_trust_region_with_wrong_model_converges():
@@ -158,8 +159,8 @@ def test_trust_region_with_wrong_model_converges():
     lo, hi = -np.ones(5), np.ones(5)
     G0 = T.mc(T.theta0)[1]
     T.calls = 0
-    th, recs = S.trust_region_calibration(T.mc, T.sur_prices, T.sur_vg, T.C, T.theta0, lo, hi, iters=40,
-                                          g_stop=1e-5 * G0, feller=False)
+    th, recs = S.trust_region_calibration(T.mc, T.sur_eval, T.C, T.theta0, lo, hi, iters=40, g_stop=1e-5 * G0,
+                                          feller=False)
     Gs = [G0] + [r.G_mc for r in recs]
     assert Gs[-1] <= 1e-5 * G0
     assert all(y <= x for x, y in zip(Gs, Gs[1:]))        # the judge never accepts a rise
@@ -168,24 +169,19 @@ def test_trust_region_with_wrong_model_converges():
 
 
 def test_trust_region_first_step_uses_exact_gradient():
-    """With a model that is useless (constant prices), the corrected model
-    is the linearisation of G at the current point: every accepted step
-    still lowers G, as projected gradient steps would."""
+    """With a model that is useless (constant prices, zero Jacobian), the
+    corrected model is the linearisation of G at the current point: every
+    accepted step still lowers G, as projected gradient steps would, and the
+    Monte Carlo L-BFGS fallback takes over after rejections."""
     from paper_1901_04200_amd import surrogate as S
     T = ToyPricing(1)
     lo, hi = -np.ones(5), np.ones(5)
-    flat = lambda t: np.zeros(40)
-    flat_vg = lambda ts, Cp: (np.full(len(ts), 0.5 * float(Cp @ Cp)), np.zeros((len(ts), 5)))
+
+    def flat(ts, Cp):
+        Y = np.zeros((len(ts), 40))
+        return Y, np.zeros((len(ts), 40, 5)), np.full(len(ts), 0.5 * float(Cp @ Cp)), np.zeros((len(ts), 5))
+
     G0 = T.mc(T.theta0)[1]
-    th, recs = S.trust_region_calibration(T.mc, flat, flat_vg, T.C, T.theta0, lo, hi, iters=30, feller=False)
+    th, recs = S.trust_region_calibration(T.mc, flat, T.C, T.theta0, lo, hi, iters=30, feller=False)
     Gs = [G0] + [r.G_mc for r in recs]
     assert Gs[-1] < 0.5 * G0 and all(y <= x for x, y in zip(Gs, Gs[1:]))
-
-
-def test_jsonl_trace(tmp_path, orc):
-    pb, th, C = W.bs_problem(n_paths=1 << 10)
-    obj = OracleObjective(orc, pb, C)
-    path = tmp_path / "trace.jsonl"
-    res = K.calibrate(obj.value_and_grad, obj.value, th, [0.05], [1.0], max_iter=5, jsonl_path=str(path))
-    lines = path.read_text().strip().splitlines()
-    assert len(lines) == len(res.history) >= 1

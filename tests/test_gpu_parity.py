@@ -5,7 +5,7 @@ Tolerances (floating point, relative; oracle.parity):
   E y  : max_i |dEy_i| / max(|Ey_i|, 1e-2)                        <= 1e-5 (FP32 state), 1e-12 (FP64)
   grad : max_j |dg_j| / max(|g_j|, 1e-3 max_k |g_k|), per component <= 1e-4 (FP32 state), FP64 below
 The gradient bound is asserted where the sum over paths is well conditioned:
-no single path carries more than 5% of any gradient component (the
+no single path carries more than 2% of any gradient component (the
 one-path share, measured by the oracle's per-path reverse sweeps).  At the
 first Heston draw (2 kappa theta_bar << xi^2) one path carries most of
 dG/dkappa, and last-bit differences between two correct implementations
@@ -184,7 +184,7 @@ def test_heston_fp64_first_draw(orc, heston_small):
     paths whose variance nears zero: prices agree to ~1e-9 (asserted at the
     FP32 bound with room to spare), the exact pathwise gradient does not,
     because one path carries most of a component (the one-path share, which
-    gates the gradient assertion: above 5% the error is stated)."""
+    gates the gradient assertion: above 2% the error is stated)."""
     pb, th0, tht, C = heston_small
     say("heston fp64 at the first draw (Feller violated)")
     r = run_all(pb, th0, C, "fp64")
@@ -459,7 +459,7 @@ def test_heston_full_size(orc):
     """The benchmark's workload at full size (2^20 paths x 256 steps, m = 40)
     in the launch configuration it times.  At the Feller draw the benchmark
     times, FP32 meets both bounds (the sum is well conditioned: every
-    one-path share <= 5%).  At the first draw, FP64 prices meet the FP32
+    one-path share <= 2%).  At the first draw, FP64 prices meet the FP32
     bound; the FP32 price error and the conditioning there are stated."""
     pb, th0, tht, eps = W.heston_problem()
     th = W.heston_draws(2, 10)[9]

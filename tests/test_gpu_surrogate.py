@@ -3,10 +3,14 @@ its training labels against the FP64 Monte Carlo oracle.
 
 Tolerance (derived from the arithmetic): the oracle is given the device's
 bf16-rounded weights, so the remaining difference is the bf16 rounding of
-activations and adjoints where they enter the products (relative 2^-9 per
-rounding, a few roundings deep) plus FP32 accumulation: outputs within
-2e-2 of their largest magnitude, weight gradients within 5e-2 in relative
-norm per parameter block.  Labels (FP32 Monte Carlo) follow the Monte Carlo
+activations and adjoints where they enter the products (relative u = 2^-9
+per rounding, a few roundings deep) plus FP32 accumulation: outputs within
+2e-2 of their largest magnitude; every weight-gradient element within
+16 u times its running-error magnitude (the oracle's backward pass with
+every factor taken in absolute value: a term whose factors carry relative
+errors e1, e2, ... is off by at most (e1 + e2 + ...) times its magnitude;
+16 covers the roundings along the deepest term, three forward and three
+backward products with their activations, with room).  Labels (FP32 Monte Carlo) follow the Monte Carlo
 bounds: 1e-5 on prices, 1e-4 on the Jacobian.
 """
 import sys
@@ -17,6 +21,7 @@ import pytest
 torch = pytest.importorskip("torch")
 
 from oracle import mlp_oracle as MO
+from oracle import parity as PY
 from paper_1901_04200_amd import surrogate as S
 from paper_1901_04200_amd import workloads as W
 
@@ -155,12 +160,17 @@ def test_loss_and_double_backprop(nin, H, nout, B):
     say(f"  loss gpu {loss.item():.6g} oracle {L:.6g}")
     assert abs(loss.item() - L) < 2e-2 * L
     gg = net.unpack(grad.cpu().numpy())
+    mag = MO.grad_magnitudes(device_view(params), X.astype(np.float64), Yl.astype(np.float64),
+                             Jl.astype(np.float64), w)
+    u = 2.0 ** -9
     for l in range(4):
         for k in range(2):
-            a, b = gg[l][k], go[l][k]
+            a, b, mg = gg[l][k], go[l][k], mag[l][k]
+            ratio = np.abs(a - b) / np.maximum(u * mg, 1e-30)
             e = np.linalg.norm(a - b) / np.linalg.norm(b)
-            say(f"  layer {l + 1} {'W' if k == 0 else 'b'} rel err {e:.2e}")
-            assert e < 5e-2, (l, k, e)
+            say(f"  layer {l + 1} {'W' if k == 0 else 'b'}: rel norm err {e:.2e}, largest |error| / (u magnitude) "
+                f"{ratio.max():.2f}, median {np.median(ratio):.3f}")
+            assert np.all(np.abs(a - b) <= 16 * u * mg + 1e-7 * np.max(np.abs(b))), (l, k)
     net.close()
 
 
@@ -211,13 +221,15 @@ def test_calibration_gradient_kernel():
 
 
 def test_labels_match_oracle_jacobian(orc):
-    """calibrate_jacobian_batch on 4 draws (own Philox instance each) against
-    the oracle's tangent mode with the same streams."""
-    pb, _, _, _ = W.heston_problem(n_paths=1 << 14)
-    draws = W.heston_feller_draws(6, 4)
-    Ey, J = S.generate_labels(pb, draws, n_paths=1 << 14, seed=4, inst0=100, chunk=4)
+    """calibrate_jacobian_batch on 8 draws at 2^16 paths (own Philox
+    instance each) against the oracle's tangent mode with the same streams;
+    the FP32 Jacobian is asserted on the draws where no path carries more
+    than 2% of any Jacobian entry, the rest stated."""
+    pb, _, _, _ = W.heston_problem(n_paths=1 << 16)
+    draws = W.heston_feller_draws(6, 8)
+    Ey, J = S.generate_labels(pb, draws, n_paths=1 << 16, seed=4, inst0=100, chunk=8)
     Ey, J = Ey.cpu().numpy(), J.cpu().numpy()
-    Ey64, J64 = S.generate_labels(pb, draws, n_paths=1 << 14, seed=4, inst0=100, chunk=4, precision="fp64")
+    Ey64, J64 = S.generate_labels(pb, draws, n_paths=1 << 16, seed=4, inst0=100, chunk=8, precision="fp64")
     Ey64, J64 = Ey64.cpu().numpy(), J64.cpu().numpy()
     n_checked = 0
     for i, th in enumerate(draws):
@@ -233,10 +245,10 @@ def test_labels_match_oracle_jacobian(orc):
         assert np.max(np.abs(Ey64[i] - Eo) / np.maximum(np.abs(Eo), 1e-2)) <= 1e-12
         assert ej64 <= 1e-9
         assert ey <= 1e-5
-        if share <= 0.05:
+        if share <= PY.SHARE_GATE:
             assert ej <= 1e-4
             n_checked += 1
-    assert n_checked >= 2
+    assert n_checked >= 4
 
 
 def test_training_reduces_loss():

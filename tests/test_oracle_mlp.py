@@ -85,3 +85,25 @@ def test_grads_match_central_differences(case):
         pp[l] = (Wm, b)
         Lm = MO.loss(pp, X, Yl, Jl, w)
         assert abs((Lp - Lm) / (2 * h) - g[l][0][i, j]) < 1e-7 * max(1.0, abs(g[l][0][i, j]))
+
+
+def test_grad_magnitudes_bound_the_gradient_and_its_rounding():
+    """The running-error magnitudes dominate the gradient (triangle
+    inequality) and bound what rounding every activation and adjoint to a
+    coarse grid (relative 2^-7) does to it, at a small multiple of 2^-7."""
+    rng = np.random.default_rng(2)
+    params = MO.init_params([3, 16, 16, 16, 4], 1)
+    params = [(W, rng.normal(0, 0.1, b.shape)) for W, b in params]
+    X = rng.uniform(-1, 1, (32, 3))
+    Yl, Jl = rng.normal(0, 1, (32, 4)), rng.normal(0, 1, (32, 4, 3))
+    L, g = MO.grads(params, X, Yl, Jl, 0.7)
+    mag = MO.grad_magnitudes(params, X, Yl, Jl, 0.7)
+    for (dW, db), (mW, mb) in zip(g, mag):
+        assert np.all(mW >= np.abs(dW) * (1 - 1e-12)) and np.all(mb >= np.abs(db) * (1 - 1e-12))
+    # perturb every weight by a relative 2^-7 (a stand-in for coarse rounding):
+    # the gradient moves by far less than 16 x 2^-7 x the magnitude
+    u = 2.0 ** -7
+    pert = [(W * (1 + u * rng.choice([-1, 1], W.shape)), b) for W, b in params]
+    _, g2 = MO.grads(pert, X, Yl, Jl, 0.7)
+    for (dW, db), (eW, eb), (mW, mb) in zip(g, g2, mag):
+        assert np.all(np.abs(eW - dW) <= 16 * u * mW) and np.all(np.abs(eb - db) <= 16 * u * mb)
