@@ -26,13 +26,30 @@ METRIC = "paths·steps/s for ∇G (F_v+R_v), K_R/K_F, % FP32 VALU peak; surrogat
 
 
 def host_cpu_model():
+    """The host CPU's model name: lscpu's, else /proc/cpuinfo's (with the
+    number of sockets and cores per socket lscpu reports, when it does)."""
+    import subprocess
+    name, extra = None, []
     try:
-        for ln in open("/proc/cpuinfo"):
-            if ln.startswith("model name"):
-                return ln.split(":", 1)[1].strip()
-    except OSError:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for ln in out.splitlines():
+            k, _, v = ln.partition(":")
+            k, v = k.strip(), v.strip()
+            if k == "Model name" and not name:
+                name = v
+            elif k in ("Socket(s)", "Core(s) per socket", "Thread(s) per core", "CPU max MHz"):
+                extra.append(f"{k} {v}")
+    except (OSError, subprocess.SubprocessError):
         pass
-    return None
+    if not name:
+        try:
+            for ln in open("/proc/cpuinfo"):
+                if ln.startswith("model name"):
+                    name = ln.split(":", 1)[1].strip()
+                    break
+        except OSError:
+            pass
+    return name if not extra else f"{name} ({', '.join(extra)})"
 
 
 def oracle_leg(pb, theta, C, got, sample_paths_1t, min_seconds_1t, t_forward_gpu_ms):

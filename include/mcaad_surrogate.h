@@ -61,12 +61,16 @@ int mlp_forward(mlp_ctx *ctx, const float *d_theta, int32_t B, float *d_Y, float
 /* Loss and its gradient for one batch: with z the network output and zl, jl
  * the labels in network units (zl_i = (y_i - out_shift_i)/out_scale_i,
  * jl_ij = dy_i/dtheta_j / (out_scale_i in_scale_j)),
- *   L = mean_{b,i} (z - zl)^2 + w mean_{b,i,j} (dz_i/dx_j - jl_ij)^2.
+ *   L = mean_{b,i} (z - zl)^2 + w mean_{b,i,j} c_b (dz_i/dx_j - jl_ij)^2
+ * with per-sample weights c_b of the Jacobian term from d_jw [B] (FP32; NULL:
+ * all 1): a sample whose Jacobian label is not to be trusted gets 0 and
+ * contributes its prices only (its Jacobian label is then never read as a
+ * number).
  * Labels are given in price units: d_Ylab [B x n_out], d_Jlab
  * [B x n_out x n_in].  B must be a multiple of 128.  d_loss[1] (FP64) and
  * d_grad [num_params] (FP32, packed like the parameters) are written. */
-int mlp_loss_grad(mlp_ctx *ctx, const float *d_theta, const float *d_Ylab, const float *d_Jlab, int32_t B,
-                  float w, double *d_loss, float *d_grad, void *stream);
+int mlp_loss_grad(mlp_ctx *ctx, const float *d_theta, const float *d_Ylab, const float *d_Jlab, const float *d_jw,
+                  int32_t B, float w, double *d_loss, float *d_grad, void *stream);
 
 /* One Adam step (Kingma & Ba) with bias correction for step t >= 1 on the
  * FP32 master parameters, then refresh of the bf16 copies. */

@@ -8,8 +8,9 @@ gradient needs the derivative of J with respect to the weights (double
 backpropagation).  This module computes, plainly with numpy:
 
   forward_tangent(params, X)            -> Y [B, m], J [B, m, n_in]
-  loss(params, X, Yl, Jl, w)            -> L = mean_{b,i} (Y - Yl)^2
-                                               + w mean_{b,i,j} (J - Jl)^2
+  loss(params, X, Yl, Jl, w, jw=None)   -> L = mean_{b,i} (Y - Yl)^2
+                                               + w mean_{b,i,j} c_b (J - Jl)^2
+      (c_b: per-sample weights of the Jacobian term, all 1 by default)
   grads(params, X, Yl, Jl, w)           -> (L, [(dW_l, db_l)])
   grad_magnitudes(params, X, Yl, Jl, w) -> [(|dW_l|, |db_l|)]: the same
       backward pass with every factor replaced by its absolute value (the
@@ -66,19 +67,25 @@ def forward_tangent(params, X):
     return Y, np.transpose(T, (0, 2, 1))                       # J[b, i, j] = dY_i/dx_j
 
 
-def loss(params, X, Yl, Jl, w):
+def _jw(jw, B):
+    return np.ones(B) if jw is None else np.asarray(jw, dtype=np.float64)
+
+
+def loss(params, X, Yl, Jl, w, jw=None):
     Y, J = forward_tangent(params, X)
-    return float(np.mean((Y - Yl) ** 2) + w * np.mean((J - Jl) ** 2))
+    c = _jw(jw, len(X))[:, None, None]
+    return float(np.mean((Y - Yl) ** 2) + w * np.mean(c * (J - Jl) ** 2))
 
 
-def grads(params, X, Yl, Jl, w):
+def grads(params, X, Yl, Jl, w, jw=None):
     Y, T, cache = _forward(params, X)
     J = np.transpose(T, (0, 2, 1))
     B, m = Y.shape
     n_in = X.shape[1]
-    L_val = float(np.mean((Y - Yl) ** 2) + w * np.mean((J - Jl) ** 2))
+    c = _jw(jw, B)[:, None, None]
+    L_val = float(np.mean((Y - Yl) ** 2) + w * np.mean(c * (J - Jl) ** 2))
     Hb = 2.0 * (Y - Yl) / (B * m)                              # adjoint of Y
-    Tb = np.transpose(2.0 * w * (J - Jl) / (B * m * n_in), (0, 2, 1))   # adjoint of T (tangent layout)
+    Tb = np.transpose(2.0 * w * c * (J - Jl) / (B * m * n_in), (0, 2, 1))   # adjoint of T (tangent layout)
     out = [None] * len(params)
     for l in range(len(params) - 1, -1, -1):
         W, b = params[l]
@@ -97,13 +104,14 @@ def grads(params, X, Yl, Jl, w):
     return L_val, out
 
 
-def grad_magnitudes(params, X, Yl, Jl, w):
+def grad_magnitudes(params, X, Yl, Jl, w, jw=None):
     Y, T, cache = _forward(params, X)
     J = np.transpose(T, (0, 2, 1))
     B, m = Y.shape
     n_in = X.shape[1]
+    c = _jw(jw, B)[:, None, None]
     Hb = np.abs(2.0 * (Y - Yl) / (B * m))
-    Tb = np.abs(np.transpose(2.0 * w * (J - Jl) / (B * m * n_in), (0, 2, 1)))
+    Tb = np.abs(np.transpose(2.0 * w * c * (J - Jl) / (B * m * n_in), (0, 2, 1)))
     out = [None] * len(params)
     for l in range(len(params) - 1, -1, -1):
         W, b = params[l]

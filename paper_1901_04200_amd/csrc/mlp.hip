@@ -258,6 +258,385 @@ __global__ __launch_bounds__(kThreads) void k_split_reduce(const float *__restri
 }
 
 // ---------------------------------------------------------------------------
+// Row-block products fused with the elementwise work around them (the
+// training step and large-batch inference, n_in + 1 <= kRowsMaxNR).
+//
+// A workgroup of NR = n_in + 1 waves takes 32 samples (b0 .. b0 + 31) and 64
+// output columns (n0 .. n0 + 63) of Z = A W^T across all NR row blocks of the
+// activation layout: wave t computes rows t Bp + b0 .. t Bp + b0 + 31, so the
+// primal values that a tangent row's elementwise work needs are produced in
+// the same workgroup and meet in LDS.  Operand staging, k order and MFMA
+// (v_mfma_f32_32x32x16_bf16, FP32 accumulation from zero) are k_gemm's, so the
+// pre-activations are those k_gemm gives.  Epilogues:
+//   kEpiStore   Z (FP32 [NR Bp][ldz]) as k_gemm (inference output layer)
+//   kEpiActFwd  hidden layer: z = acc + bias, activations SiLU(z) and
+//               SiLU'(z) u (bf16, the next product's operand), the primal
+//               pre-activations z (FP32) and the tangent pre-activations u
+//               (bf16) for the backward pass
+//   kEpiLoss    output layer: the differential loss's adjoint G4 (bf16, all
+//               row blocks), the workgroup's FP64 loss partial and the column
+//               partials of the primal adjoint (the output bias gradient)
+//   kEpiActBwd  adjoint of a hidden layer's activation from the next layer's
+//               input adjoint (double backprop):
+//                 zbar = hbar SiLU'(z) + sum_t tbar_t u_t SiLU''(z),
+//                 ubar_t = tbar_t SiLU'(z)
+//               written as bf16 operands, plus the column partials of zbar
+//               (the layer's bias gradient)
+//   kEpiL1Bwd   the same for layer 1 (u_t = row t of W1), reduced at once to
+//               the workgroup's column partials of W1bar[t][j] =
+//               sum_b (x_bt zbar_bj + ubar_t,bj) and b1bar[j] = sum_b zbar_bj
+// Column partials over the workgroup's 32 samples go to part[blk][...]
+// (blk = b0 / 32), summed over workgroups by k_chunk_reduce in a fixed order.
+// ---------------------------------------------------------------------------
+constexpr int kRowsMaxNR = 8;
+enum { kEpiStore = 0, kEpiActFwd = 1, kEpiLoss = 2, kEpiActBwd = 3, kEpiL1Bwd = 4 };
+
+struct RowsArgs {
+    const uint16_t *A;      // [NR Bp][K] bf16, k contiguous
+    const uint16_t *W;      // [N][K] bf16, k contiguous
+    int Bp, K, N;           // samples per row block, k extent, output columns (multiple of 64)
+    float *Z;               // kEpiStore: [NR Bp][N]
+    const float *bias;      // kEpiActFwd: [N]
+    uint16_t *Aout;         // kEpiActFwd: [NR Bp][N]
+    float *Zp;              // kEpiActFwd: [Bp][N]
+    uint16_t *U;            // kEpiActFwd: [(NR - 1) Bp][N]
+    const float *Zp_in;     // kEpiActBwd, kEpiL1Bwd: [Bp][N] this layer's primal pre-activations
+    const uint16_t *U_in;   // kEpiActBwd: [(NR - 1) Bp][N]
+    const float *W1;        // kEpiL1Bwd: [NR - 1][N] (FP32)
+    const float *X;         // kEpiL1Bwd: [Bp][NR - 1] normalised inputs
+    uint16_t *Zbar;         // kEpiActBwd: [NR Bp][N]
+    float *part;            // column partials [Bp / 32][ncols]
+    // kEpiLoss
+    const float *b4, *Ylab, *Jlab, *jw, *in_scale, *out_shift, *out_scale;
+    int nout;
+    float w;
+    uint16_t *G4;           // [NR Bp][kOutPad]
+    double *lossp;          // [Bp / 32]
+};
+
+__device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+// Sum of v over the 32 rows of this wave's tile for column (lane & 31) (one
+// accumulator of the 32x32 MFMA: the lane holds 16 of the column's rows, its
+// partner lane ^ 32 the other 16); every lane gets its column's total.
+__device__ __forceinline__ float tile_colsum(const float *v)
+{
+    float s = 0.f;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) s += v[i];
+    return s + __shfl_xor(s, 32);
+}
+
+template <int NR, int EPI>
+__global__ __launch_bounds__(NR * 64) void k_rows(RowsArgs a)
+{
+    constexpr int NT = NR * 64;
+    constexpr int kBC = (256 + NT - 1) / NT;   // 16-byte B pieces per thread and k-tile
+    // operand tiles during the products; the epilogue's exchange area afterwards
+    constexpr int kOpBytes = 2 * (2 * NR * 32 * LDK + 2 * BN * LDK);
+    constexpr int kEpBytes = (NR + 1) * 32 * 64 * 4;
+    __shared__ __attribute__((aligned(16))) unsigned char smem[kOpBytes > kEpBytes ? kOpBytes : kEpBytes];
+    uint16_t(*sA)[NR * 32 * LDK] = reinterpret_cast<uint16_t(*)[NR * 32 * LDK]>(smem);
+    uint16_t(*sB)[BN * LDK] = reinterpret_cast<uint16_t(*)[BN * LDK]>(smem + 2 * 2 * NR * 32 * LDK);
+    float *sE = reinterpret_cast<float *>(smem);
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;               // the row block this wave computes
+    const int b0 = blockIdx.x * 32, n0 = blockIdx.y * BN;
+    const int Bp = a.Bp, K = a.K, N = a.N;
+    f32x16 acc0, acc1;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        acc0[i] = 0.f;
+        acc1[i] = 0.f;
+    }
+    // A pieces: c = tid + i NT (i = 0, 1) of the NR * 32 rows x 4 pieces
+    auto load_a = [&](int k0, u32x4 *ra) {
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+            const int c = tid + i * NT;
+            const int r = c >> 2, kc = c & 3;
+            const int64_t grow = (int64_t)(r >> 5) * Bp + b0 + (r & 31);
+            ra[i] = *(const u32x4 *)(a.A + grow * K + k0 + kc * 8);
+        }
+    };
+    auto store_a = [&](uint16_t *s, const u32x4 *ra) {
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+            const int c = tid + i * NT;
+            *(u32x4 *)(s + (c >> 2) * LDK + (c & 3) * 8) = ra[i];
+        }
+    };
+    auto load_b = [&](int k0, u32x4 *rb) {
+#pragma unroll
+        for (int i = 0; i < kBC; ++i) {
+            const int c = tid + i * NT;
+            if (c < 256) rb[i] = *(const u32x4 *)(a.W + (int64_t)(n0 + (c >> 2)) * K + k0 + (c & 3) * 8);
+        }
+    };
+    auto store_b = [&](uint16_t *s, const u32x4 *rb) {
+#pragma unroll
+        for (int i = 0; i < kBC; ++i) {
+            const int c = tid + i * NT;
+            if (c < 256) *(u32x4 *)(s + (c >> 2) * LDK + (c & 3) * 8) = rb[i];
+        }
+    };
+    auto mma = [&](const uint16_t *a_s, const uint16_t *b_s) {
+#pragma unroll
+        for (int kk = 0; kk < BK; kk += 16) {
+            const int ko = kk + 8 * (lane >> 5);
+            const bf16x8 av = *(const bf16x8 *)(a_s + (wave * 32 + (lane & 31)) * LDK + ko);
+            const bf16x8 bv0 = *(const bf16x8 *)(b_s + (lane & 31) * LDK + ko);
+            const bf16x8 bv1 = *(const bf16x8 *)(b_s + (32 + (lane & 31)) * LDK + ko);
+            acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv0, acc0, 0, 0, 0);
+            acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv1, acc1, 0, 0, 0);
+        }
+    };
+    // the k-tiles as in k_gemm: tile t multiplied from buffer t % 2 while the
+    // global loads of tiles t + 1 and t + 2 are in flight in two register sets
+    const int nt = K / BK;
+    u32x4 ra0[2], ra1[2], rb0[kBC], rb1[kBC];
+    load_a(0, ra0);
+    load_b(0, rb0);
+    store_a(sA[0], ra0);
+    store_b(sB[0], rb0);
+    if (nt > 1) {
+        load_a(BK, ra1);
+        load_b(BK, rb1);
+    }
+    if (nt > 2) {
+        load_a(2 * BK, ra0);
+        load_b(2 * BK, rb0);
+    }
+    __syncthreads();
+    for (int t = 0; t < nt; t += 2) {
+        mma(sA[0], sB[0]);
+        if (t + 1 < nt) {
+            store_a(sA[1], ra1);
+            store_b(sB[1], rb1);
+        }
+        if (t + 3 < nt) {
+            load_a((t + 3) * BK, ra1);
+            load_b((t + 3) * BK, rb1);
+        }
+        __syncthreads();
+        if (t + 1 >= nt) break;
+        mma(sA[1], sB[1]);
+        if (t + 2 < nt) {
+            store_a(sA[0], ra0);
+            store_b(sB[0], rb0);
+        }
+        if (t + 4 < nt) {
+            load_a((t + 4) * BK, ra0);
+            load_b((t + 4) * BK, rb0);
+        }
+        __syncthreads();
+    }
+
+    // epilogue: element i of acc0 / acc1 is (row rr(i), column c0 / c0 + 32) of the wave's tile
+    const int c0 = lane & 31;
+    auto rr = [&](int i) { return (i >> 2) * 8 + (lane >> 5) * 4 + (i & 3); };
+    const int64_t rbase = (int64_t)wave * Bp + b0;   // first global row of this wave's tile
+    const int blk = blockIdx.x;
+    if constexpr (EPI == kEpiStore) {
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            float *z = a.Z + (rbase + rr(i)) * N + n0 + c0;
+            z[0] = acc0[i];
+            z[32] = acc1[i];
+        }
+    } else if constexpr (EPI == kEpiActFwd) {
+        float *d1s = sE;   // [32][64] SiLU'(z) of the primal rows
+        if (wave == 0) {
+            const float bi0 = a.bias[n0 + c0], bi1 = a.bias[n0 + c0 + 32];
+#pragma unroll
+            for (int i = 0; i < 16; ++i) {
+                const int r = rr(i);
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const float z = (h ? acc1[i] : acc0[i]) + (h ? bi1 : bi0);
+                    const float sg = sigm(z);
+                    const float d1 = sg * (1.f + z * (1.f - sg));
+                    const int64_t o = (int64_t)(b0 + r) * N + n0 + c0 + 32 * h;
+                    a.Aout[o] = f2bf(z * sg);
+                    a.Zp[o] = z;
+                    d1s[r * 64 + c0 + 32 * h] = d1;
+                }
+            }
+        }
+        __syncthreads();
+        if (wave > 0) {
+#pragma unroll
+            for (int i = 0; i < 16; ++i) {
+                const int r = rr(i);
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const float u = h ? acc1[i] : acc0[i];
+                    const int64_t col = n0 + c0 + 32 * h;
+                    a.Aout[(rbase + r) * N + col] = f2bf(d1s[r * 64 + c0 + 32 * h] * u);
+                    a.U[((int64_t)(wave - 1) * Bp + b0 + r) * N + col] = f2bf(u);
+                }
+            }
+        }
+    } else if constexpr (EPI == kEpiLoss) {
+        // N = kOutPad (one column tile); columns >= nout are padding
+        const int nin = NR - 1;
+        const int B = Bp, nout = a.nout;
+        const float cy = 2.f / (float)(B * nout);
+        const float cj = 2.f * a.w / (float)(B * nout * nin);
+        double lacc = 0.0;
+        float dyp0[16], dyp1[16];
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            const int r = rr(i), b = b0 + r;
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int col = c0 + 32 * h;
+                const float v = h ? acc1[i] : acc0[i];
+                float g = 0.f;
+                if (col < nout) {
+                    if (wave == 0) {
+                        const float z = v + a.b4[col];
+                        const float zl = (a.Ylab[(int64_t)b * nout + col] - a.out_shift[col]) / a.out_scale[col];
+                        const float dz = z - zl;
+                        g = cy * dz;
+                        lacc += (double)dz * dz / (double)(B * nout);
+                    } else if (!a.jw || a.jw[b] != 0.f) {
+                        const int tt = wave - 1;
+                        const float cb = a.jw ? a.jw[b] : 1.f;
+                        const float jl = a.Jlab[((int64_t)b * nout + col) * nin + tt] /
+                                         (a.out_scale[col] * a.in_scale[tt]);
+                        const float dj = v - jl;
+                        g = cj * cb * dj;
+                        lacc += (double)a.w * cb * dj * dj / (double)(B * nout * nin);
+                    }
+                }
+                a.G4[(rbase + r) * kOutPad + col] = f2bf(g);
+                if (h) dyp1[i] = g;
+                else dyp0[i] = g;
+            }
+        }
+        if (wave == 0) {   // column partials of the primal adjoint: the output bias gradient
+            const float s0 = tile_colsum(dyp0), s1 = tile_colsum(dyp1);
+            if (lane < 32) {
+                if (c0 < nout) a.part[(int64_t)blk * nout + c0] = s0;
+                if (c0 + 32 < nout) a.part[(int64_t)blk * nout + c0 + 32] = s1;
+            }
+        }
+        // the workgroup's loss partial: per-thread sums in a fixed tree
+        double *sh = reinterpret_cast<double *>(sE);
+        sh[tid] = lacc;
+        __syncthreads();
+        if (tid == 0) {
+            double tot = 0.0;
+            for (int q = 0; q < NT; ++q) tot += sh[q];
+            a.lossp[blk] = tot;
+        }
+    } else {   // kEpiActBwd, kEpiL1Bwd
+        float *d1s = sE, *d2s = sE + 32 * 64, *tus = sE + 2 * 32 * 64;   // tus: [NR - 1][32][64]
+        if (wave == 0) {
+#pragma unroll
+            for (int i = 0; i < 16; ++i) {
+                const int r = rr(i);
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const float z = a.Zp_in[(int64_t)(b0 + r) * N + n0 + c0 + 32 * h];
+                    const float sg = sigm(z);
+                    d1s[r * 64 + c0 + 32 * h] = sg * (1.f + z * (1.f - sg));
+                    d2s[r * 64 + c0 + 32 * h] = sg * (1.f - sg) * (2.f + z * (1.f - 2.f * sg));
+                }
+            }
+        }
+        __syncthreads();
+        float ub0[16], ub1[16];
+        if (wave > 0) {
+            const int tt = wave - 1;
+            float w1c[2] = {0.f, 0.f};
+            if constexpr (EPI == kEpiL1Bwd) {
+                w1c[0] = a.W1[(int64_t)tt * N + n0 + c0];
+                w1c[1] = a.W1[(int64_t)tt * N + n0 + c0 + 32];
+            }
+#pragma unroll
+            for (int i = 0; i < 16; ++i) {
+                const int r = rr(i);
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const int e = r * 64 + c0 + 32 * h;
+                    const float tb = h ? acc1[i] : acc0[i];
+                    float u;
+                    if constexpr (EPI == kEpiL1Bwd) u = w1c[h];
+                    else u = bf2f(a.U_in[((int64_t)tt * Bp + b0 + r) * N + n0 + c0 + 32 * h]);
+                    const float ub = tb * d1s[e];
+                    if constexpr (EPI == kEpiActBwd) a.Zbar[(rbase + r) * N + n0 + c0 + 32 * h] = f2bf(ub);
+                    if (h) ub1[i] = ub;
+                    else ub0[i] = ub;
+                    tus[tt * 32 * 64 + e] = tb * u;
+                }
+            }
+        }
+        __syncthreads();
+        if (wave == 0) {
+            float zb0[16], zb1[16];
+#pragma unroll
+            for (int i = 0; i < 16; ++i) {
+                const int r = rr(i);
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const int e = r * 64 + c0 + 32 * h;
+                    float zb = (h ? acc1[i] : acc0[i]) * d1s[e];
+                    for (int tt = 0; tt < NR - 1; ++tt) zb += tus[tt * 32 * 64 + e] * d2s[e];
+                    if constexpr (EPI == kEpiActBwd) a.Zbar[(rbase + r) * N + n0 + c0 + 32 * h] = f2bf(zb);
+                    if (h) zb1[i] = zb;
+                    else zb0[i] = zb;
+                }
+            }
+            if constexpr (EPI == kEpiActBwd) {
+                const float s0 = tile_colsum(zb0), s1 = tile_colsum(zb1);
+                if (lane < 32) {
+                    a.part[(int64_t)blk * N + n0 + c0] = s0;
+                    a.part[(int64_t)blk * N + n0 + c0 + 32] = s1;
+                }
+            } else {
+                // row NR - 1 of the partials: b1bar; rows t < NR - 1: sum_b x_bt zbar_b
+                const int nin = NR - 1;
+                const int64_t prow = (int64_t)blk * NR * N;
+                const float s0 = tile_colsum(zb0), s1 = tile_colsum(zb1);
+                if (lane < 32) {
+                    a.part[prow + (int64_t)nin * N + n0 + c0] = s0;
+                    a.part[prow + (int64_t)nin * N + n0 + c0 + 32] = s1;
+                }
+                for (int tt = 0; tt < nin; ++tt) {
+                    float x0[16], x1[16];
+#pragma unroll
+                    for (int i = 0; i < 16; ++i) {
+                        const float x = a.X[(int64_t)(b0 + rr(i)) * nin + tt];
+                        x0[i] = x * zb0[i];
+                        x1[i] = x * zb1[i];
+                    }
+                    const float q0 = tile_colsum(x0), q1 = tile_colsum(x1);
+                    if (lane < 32) {   // the tangent waves add their sum_b ubar below
+                        tus[tt * 64 + c0] = q0;
+                        tus[tt * 64 + c0 + 32] = q1;
+                    }
+                }
+            }
+        }
+        if constexpr (EPI == kEpiL1Bwd) {
+            __syncthreads();
+            if (wave > 0) {
+                const int tt = wave - 1;
+                const float s0 = tile_colsum(ub0), s1 = tile_colsum(ub1);
+                if (lane < 32) {
+                    const int64_t prow = (int64_t)blk * NR * N + (int64_t)tt * N;
+                    a.part[prow + n0 + c0] = tus[tt * 64 + c0] + s0;
+                    a.part[prow + n0 + c0 + 32] = tus[tt * 64 + c0 + 32] + s1;
+                }
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // elementwise kernels
 // ---------------------------------------------------------------------------
 __global__ void k_normalize(const float *__restrict__ th, int B, int Bp, int nin, const float *__restrict__ shift,
@@ -325,7 +704,7 @@ __global__ void k_out_fwd(const float *__restrict__ Z4, const float *__restrict_
 // Differential loss, its adjoint G4 (bf16, network units) and FP64 block partials.
 __global__ __launch_bounds__(kThreads) void k_loss(const float *__restrict__ Z4, const float *__restrict__ b4,
                                                    const float *__restrict__ Ylab, const float *__restrict__ Jlab,
-                                                   int B, int nin, int nout, float w,
+                                                   const float *__restrict__ jw, int B, int nin, int nout, float w,
                                                    const float *__restrict__ in_scale,
                                                    const float *__restrict__ out_shift,
                                                    const float *__restrict__ out_scale, uint16_t *__restrict__ G4,
@@ -345,12 +724,17 @@ __global__ __launch_bounds__(kThreads) void k_loss(const float *__restrict__ Z4,
             G4[(int64_t)b * kOutPad + i] = f2bf(cy * dz);
             dYP[(int64_t)b * kOutPad + i] = cy * dz;
             acc = (double)dz * dz / (double)(B * nout);
+            const float cb = jw ? jw[b] : 1.f;
             for (int t = 0; t < nin; ++t) {
                 const int64_t r = (int64_t)(t + 1) * B + b;
+                if (cb == 0.f) {
+                    G4[r * kOutPad + i] = 0;
+                    continue;
+                }
                 const float jl = Jlab[((int64_t)b * nout + i) * nin + t] / (out_scale[i] * in_scale[t]);
                 const float dj = Z4[r * kOutPad + i] - jl;
-                G4[r * kOutPad + i] = f2bf(cj * dj);
-                acc += (double)w * dj * dj / (double)(B * nout * nin);
+                G4[r * kOutPad + i] = f2bf(cj * cb * dj);
+                acc += (double)w * cb * dj * dj / (double)(B * nout * nin);
             }
         } else {
             G4[(int64_t)b * kOutPad + i] = 0;
@@ -761,6 +1145,8 @@ struct mlp_ctx {
     uint16_t *G4 = nullptr;       // R x kOutPad
     float *Hbar = nullptr;        // R x H
     uint16_t *Zbar = nullptr;     // R x H
+    uint16_t *Zbar2 = nullptr;    // R x H (fused path: the layer below's adjoints)
+    uint16_t *U[4] = {nullptr};   // U[2..3]: n_in Bmax x H tangent pre-activations (bf16, fused path)
     float *ZbarP = nullptr;       // Bmax x H
     float *Xn = nullptr;          // Bmax x nin
     float *split = nullptr;       // kMaxSplits x H x H, or row-chunk partials of the column sums
@@ -884,6 +1270,8 @@ extern "C" int mlp_create(int32_t n_in, int32_t n_hidden, int32_t n_out, int32_t
     A((void **)&c->G4, 2 * R * kOutPad);
     A((void **)&c->Hbar, 4 * R * H);
     A((void **)&c->Zbar, 2 * R * H);
+    A((void **)&c->Zbar2, 2 * R * H);
+    for (int l = 2; l <= 3; ++l) A((void **)&c->U[l], 2 * (int64_t)n_in * c->Bmax * H);
     A((void **)&c->ZbarP, 4 * (int64_t)c->Bmax * H);
     A((void **)&c->Xn, 4 * (int64_t)c->Bmax * n_in);
     // split-K GEMM partials, or the row-chunk partials of the column sums (at most
@@ -961,9 +1349,78 @@ extern "C" int mlp_set_scaling(mlp_ctx *c, const float *d_in_shift, const float 
     return e == hipSuccess ? 0 : mfail(c, -3, hipGetErrorString(e));
 }
 
+// Whether the training step and large-batch inference take the fused
+// row-block kernels (one wave per row block).
+static bool fused_path(const mlp_ctx *c) { return c->nin + 1 <= kRowsMaxNR; }
+
+template <int NR>
+static void launch_rows_nr(int epi, const RowsArgs &a, hipStream_t st)
+{
+    const dim3 grid((unsigned)(a.Bp / 32), (unsigned)(a.N / BN)), block(NR * 64);
+    switch (epi) {
+    case kEpiStore: hipLaunchKernelGGL((k_rows<NR, kEpiStore>), grid, block, 0, st, a); break;
+    case kEpiActFwd: hipLaunchKernelGGL((k_rows<NR, kEpiActFwd>), grid, block, 0, st, a); break;
+    case kEpiLoss: hipLaunchKernelGGL((k_rows<NR, kEpiLoss>), grid, block, 0, st, a); break;
+    case kEpiActBwd: hipLaunchKernelGGL((k_rows<NR, kEpiActBwd>), grid, block, 0, st, a); break;
+    default: hipLaunchKernelGGL((k_rows<NR, kEpiL1Bwd>), grid, block, 0, st, a); break;
+    }
+}
+
+static hipError_t launch_rows(int NR, int epi, const RowsArgs &a, hipStream_t st)
+{
+    switch (NR) {
+    case 2: launch_rows_nr<2>(epi, a, st); break;
+    case 3: launch_rows_nr<3>(epi, a, st); break;
+    case 4: launch_rows_nr<4>(epi, a, st); break;
+    case 5: launch_rows_nr<5>(epi, a, st); break;
+    case 6: launch_rows_nr<6>(epi, a, st); break;
+    case 7: launch_rows_nr<7>(epi, a, st); break;
+    case 8: launch_rows_nr<8>(epi, a, st); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+// Fused forward over Bp rows of normalised inputs already in c->Xn: layer 1,
+// then the two hidden layers' products with their activations; with
+// store_out the output layer's pre-activations go to c->Z[4].
+static hipError_t forward_fused(mlp_ctx *c, int Bp, bool store_out, hipStream_t st)
+{
+    const int H = c->H, nin = c->nin, NR = nin + 1;
+    const float *p = c->p;
+    hipLaunchKernelGGL(k_l1_fwd, dim3(nb((int64_t)Bp * H)), dim3(kThreads), 0, st, c->Xn, p + c->off[0], p + c->off[1],
+                       Bp, nin, H, c->Z[1], c->A[1]);
+    hipError_t e = hipGetLastError();
+    for (int l = 2; l <= 3 && e == hipSuccess; ++l) {
+        RowsArgs a{};
+        a.A = c->A[l - 1];
+        a.W = c->WT[l - 1];
+        a.Bp = Bp;
+        a.K = H;
+        a.N = H;
+        a.bias = p + c->off[2 * l - 1];
+        a.Aout = c->A[l];
+        a.Zp = c->Z[l];
+        a.U = c->U[l];
+        e = launch_rows(NR, kEpiActFwd, a, st);
+    }
+    if (e == hipSuccess && store_out) {
+        RowsArgs a{};
+        a.A = c->A[3];
+        a.W = c->WT[3];
+        a.Bp = Bp;
+        a.K = H;
+        a.N = kOutPad;
+        a.Z = c->Z[4];
+        e = launch_rows(NR, kEpiStore, a, st);
+    }
+    return e;
+}
+
 // Forward over Bp rows of normalised inputs already in c->Xn.
 static hipError_t forward_core(mlp_ctx *c, int Bp, hipStream_t st)
 {
+    if (fused_path(c)) return forward_fused(c, Bp, true, st);
     const int H = c->H, nin = c->nin;
     const int R = (nin + 1) * Bp;
     const float *p = c->p;
@@ -1042,8 +1499,94 @@ extern "C" int mlp_forward(mlp_ctx *c, const float *d_theta, int32_t B, float *d
     return e == hipSuccess ? 0 : mfail(c, -3, hipGetErrorString(e));
 }
 
-extern "C" int mlp_loss_grad(mlp_ctx *c, const float *d_theta, const float *d_Ylab, const float *d_Jlab, int32_t B,
-                             float w, double *d_loss, float *d_grad, void *stream)
+// The training step on the fused kernels: forward, the loss with the output
+// layer's adjoint, then per layer the weight gradient (split-K product, fixed-
+// order reduction), the bias gradient (workgroup column partials, fixed-order
+// reduction) and the next layer's input adjoint fused with the activation
+// adjoint; layer 1's gradients from the last product's epilogue.
+static hipError_t loss_grad_fused(mlp_ctx *c, const float *Ylab, const float *Jlab, const float *jw, int B, float w,
+                                  double *loss, float *g, hipStream_t st)
+{
+    const int H = c->H, nin = c->nin, NR = nin + 1, R = NR * B;
+    const int nwg = B / 32;   // workgroups (32 samples each) along the batch
+    hipError_t e = forward_fused(c, B, false, st);
+    if (e != hipSuccess) return e;
+    RowsArgs a{};
+    a.A = c->A[3];
+    a.W = c->WT[3];
+    a.Bp = B;
+    a.K = H;
+    a.N = kOutPad;
+    a.b4 = c->p + c->off[7];
+    a.Ylab = Ylab;
+    a.Jlab = Jlab;
+    a.jw = jw;
+    a.in_scale = c->in_scale;
+    a.out_shift = c->out_shift;
+    a.out_scale = c->out_scale;
+    a.nout = c->nout;
+    a.w = w;
+    a.G4 = c->G4;
+    a.lossp = c->lossp;
+    a.part = c->split;
+    e = launch_rows(NR, kEpiLoss, a, st);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(kThreads), 0, st, c->lossp, nwg, loss);
+    hipLaunchKernelGGL(k_chunk_reduce, dim3((c->nout + kThreads / 8 - 1) / (kThreads / 8)), dim3(kThreads), 0, st,
+                       c->split, nwg, c->nout, g + c->off[7]);
+    const int S = std::min(kMaxSplits, std::max(1, R / 512));
+    // output layer: W4bar = A3^T G4, then H3bar = G4 W4^T with layer 3's activation adjoint
+    e = launch_gemm(false, false, c->A[3], H, c->G4, kOutPad, c->split, kOutPad, H, kOutPad, R, S, st);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_split_reduce, dim3(nb((int64_t)H * c->nout * 8)), dim3(kThreads), 0, st, c->split, S, H,
+                       kOutPad, g + c->off[6], c->nout, c->nout);
+    const uint16_t *adj = c->G4;   // the adjoint of the layer above's input
+    int kadj = kOutPad;
+    uint16_t *zb[2] = {c->Zbar, c->Zbar2};
+    for (int l = 3; l >= 2 && e == hipSuccess; --l) {
+        RowsArgs b{};
+        b.A = adj;
+        b.W = c->Wb[l];
+        b.Bp = B;
+        b.K = kadj;
+        b.N = H;
+        b.Zp_in = c->Z[l];
+        b.U_in = c->U[l];
+        b.Zbar = zb[l & 1];
+        b.part = c->split;
+        e = launch_rows(NR, kEpiActBwd, b, st);
+        if (e != hipSuccess) break;
+        hipLaunchKernelGGL(k_chunk_reduce, dim3((H + kThreads / 8 - 1) / (kThreads / 8)), dim3(kThreads), 0, st,
+                           c->split, nwg, H, g + c->off[2 * l - 1]);
+        e = launch_gemm(false, false, c->A[l - 1], H, zb[l & 1], H, c->split, H, H, H, R, S, st);
+        if (e != hipSuccess) break;
+        hipLaunchKernelGGL(k_split_reduce, dim3(nb((int64_t)H * H * 8)), dim3(kThreads), 0, st, c->split, S, H, H,
+                           g + c->off[2 * l - 2], H, H);
+        adj = zb[l & 1];
+        kadj = H;
+    }
+    if (e != hipSuccess) return e;
+    // layer 1: H1bar = Zbar2 W2^T, reduced in the epilogue to column partials of W1bar and b1bar
+    RowsArgs d{};
+    d.A = adj;
+    d.W = c->Wb[1];
+    d.Bp = B;
+    d.K = H;
+    d.N = H;
+    d.Zp_in = c->Z[1];
+    d.W1 = c->p + c->off[0];
+    d.X = c->Xn;
+    d.part = c->split;
+    e = launch_rows(NR, kEpiL1Bwd, d, st);
+    if (e != hipSuccess) return e;
+    const int nout1 = NR * H;   // W1bar (nin rows) and b1bar are contiguous in the gradient
+    hipLaunchKernelGGL(k_chunk_reduce, dim3((nout1 + kThreads / 8 - 1) / (kThreads / 8)), dim3(kThreads), 0, st,
+                       c->split, nwg, nout1, g + c->off[0]);
+    return hipGetLastError();
+}
+
+extern "C" int mlp_loss_grad(mlp_ctx *c, const float *d_theta, const float *d_Ylab, const float *d_Jlab,
+                             const float *d_jw, int32_t B, float w, double *d_loss, float *d_grad, void *stream)
 {
     if (!c || !d_theta || !d_Ylab || !d_Jlab || !d_loss || !d_grad) return mfail(c, -1, "null argument");
     if (B < 128 || B > c->Bmax || B % 128)
@@ -1054,12 +1597,14 @@ extern "C" int mlp_loss_grad(mlp_ctx *c, const float *d_theta, const float *d_Yl
     hipLaunchKernelGGL(k_normalize, dim3(nb((int64_t)B * nin)), dim3(kThreads), 0, st, d_theta, B, B, nin, c->in_shift,
                        c->in_scale, c->Xn);
     hipError_t e = hipGetLastError();
+    if (e == hipSuccess && fused_path(c)) e = loss_grad_fused(c, d_Ylab, d_Jlab, d_jw, B, w, d_loss, g, st);
+    if (fused_path(c)) return e == hipSuccess ? 0 : mfail(c, -3, hipGetErrorString(e));
     if (e == hipSuccess) e = forward_core(c, B, st);
     if (e != hipSuccess) return mfail(c, -3, hipGetErrorString(e));
     // loss and the output-layer adjoint
     const unsigned nlb = nb((int64_t)B * kOutPad);
-    hipLaunchKernelGGL(k_loss, dim3(nlb), dim3(kThreads), 0, st, c->Z[4], c->p + c->off[7], d_Ylab, d_Jlab, B, nin,
-                       c->nout, w, c->in_scale, c->out_shift, c->out_scale, c->G4, c->ZbarP, c->lossp);
+    hipLaunchKernelGGL(k_loss, dim3(nlb), dim3(kThreads), 0, st, c->Z[4], c->p + c->off[7], d_Ylab, d_Jlab, d_jw, B,
+                       nin, c->nout, w, c->in_scale, c->out_shift, c->out_scale, c->G4, c->ZbarP, c->lossp);
     hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(kThreads), 0, st, c->lossp, (int)nlb, d_loss);
     colsum(c, c->ZbarP, B, kOutPad, c->nout, g + c->off[7], st);
     // output layer: W4bar = A3^T G4 (split over rows), H3bar = G4 W4^T

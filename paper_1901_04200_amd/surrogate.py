@@ -37,7 +37,7 @@ def lib():
             "mlp_get_params": ([vp, vp, vp], C.c_int),
             "mlp_set_scaling": ([vp, vp, vp, vp, vp, vp], C.c_int),
             "mlp_forward": ([vp, vp, i32, vp, vp, vp], C.c_int),
-            "mlp_loss_grad": ([vp, vp, vp, vp, i32, C.c_float, vp, vp, vp], C.c_int),
+            "mlp_loss_grad": ([vp, vp, vp, vp, vp, i32, C.c_float, vp, vp, vp], C.c_int),
             "mlp_adam_step": ([vp, vp, C.c_float, C.c_float, C.c_float, C.c_float, i32, vp], C.c_int),
             "mlp_calibration_gradient": ([vp, vp, i32, vp, vp, vp, vp, vp, vp], C.c_int),
             "mlp_last_error": ([vp], C.c_char_p),
@@ -165,13 +165,16 @@ class MLP:
                                                    _ptr(G), _ptr(g), _stream()))
         return G, g
 
-    def loss_grad(self, theta, Ylab, Jlab, w: float, grad=None, loss=None):
+    def loss_grad(self, theta, Ylab, Jlab, w: float, grad=None, loss=None, jw=None):
+        """Differential loss and its gradient; jw [B]: per-sample weights of the
+        Jacobian term (None: all 1)."""
         B = theta.shape[0]
         if grad is None:
             grad = self.torch.empty(self.n_params, dtype=self.torch.float32, device=self.dev)
         if loss is None:
             loss = self.torch.empty(1, dtype=self.torch.float64, device=self.dev)
-        self._check(lib().mlp_loss_grad(self.ctx, _ptr(theta), _ptr(Ylab), _ptr(Jlab), B, float(w), _ptr(loss),
+        self._check(lib().mlp_loss_grad(self.ctx, _ptr(theta), _ptr(Ylab), _ptr(Jlab),
+                                        None if jw is None else _ptr(jw), B, float(w), _ptr(loss),
                                         _ptr(grad), _stream()))
         return loss, grad
 
@@ -229,8 +232,9 @@ class TrainLog:
 
 
 def fit(net: MLP, theta, Y, J, *, epochs: int, batch: int = 4096, lr: float = 1e-3, w: float = 1.0,
-        lr_final: Optional[float] = None, seed: int = 0, log_every: int = 1) -> List[TrainLog]:
-    """Adam on the differential loss over (theta, Y, J) device tensors (FP32).
+        lr_final: Optional[float] = None, seed: int = 0, log_every: int = 1, jw=None) -> List[TrainLog]:
+    """Adam on the differential loss over (theta, Y, J) device tensors (FP32),
+    jw: per-sample weights of the Jacobian term (device FP32, or None).
     The learning rate decays geometrically to lr_final over the epochs."""
     import torch
     n = theta.shape[0]
@@ -250,7 +254,8 @@ def fit(net: MLP, theta, Y, J, *, epochs: int, batch: int = 4096, lr: float = 1e
         tot = torch.zeros(1, dtype=torch.float64, device=net.dev)   # summed on the device: no sync per step
         for s in range(steps_per_epoch):
             idx = perm[s * batch:(s + 1) * batch]
-            net.loss_grad(theta[idx].contiguous(), Y[idx].contiguous(), J[idx].contiguous(), w, grad, loss)
+            net.loss_grad(theta[idx].contiguous(), Y[idx].contiguous(), J[idx].contiguous(), w, grad, loss,
+                          None if jw is None else jw[idx].contiguous())
             net.adam_step(grad, lr_e)
             if logged:
                 tot += loss

@@ -188,8 +188,17 @@ def train_surrogate(pb, n_train, train_paths, epochs, batch=4096, lr=2e-3, lr_fi
     net.set_scaling(sh, sc, mu, sd)
     thd = torch.as_tensor(draws, dtype=torch.float32, device="cuda")
     t0 = time.perf_counter()
+    jw = None
+    if region != "feller":
+        # Jacobian labels only where Feller's condition holds: elsewhere the
+        # pathwise Jacobian is heavy-tailed (a few paths near zero variance
+        # decide it) and those samples train on their prices alone
+        feller = 2.0 * draws[:, 0] * draws[:, 1] >= draws[:, 2] ** 2
+        jw = torch.as_tensor(feller.astype(np.float32), device="cuda")
+        J = torch.where(jw[:, None, None] > 0, J, torch.zeros_like(J))
+        out["jacobian_labels_kept"] = float(feller.mean())
     hist = S.fit(net, thd, Ey.float(), J.float(), epochs=epochs, batch=min(batch, n_train), lr=lr,
-                 lr_final=lr_final, w=w, log_every=max(1, epochs // 10))
+                 lr_final=lr_final, w=w, log_every=max(1, epochs // 10), jw=jw)
     t_fit = time.perf_counter() - t0
     steps = epochs * (n_train // min(batch, n_train))
     # useful GEMM work of one step: forward, input gradient and weight gradient

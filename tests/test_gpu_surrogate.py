@@ -140,13 +140,17 @@ def test_scaling_maps_units():
     net.close()
 
 
-@pytest.mark.parametrize("nin,H,nout,B", [(5, 128, 7, 256), (5, 256, 40, 4096), (1, 512, 64, 128),
-                                         (16, 1024, 3, 128)])
-def test_loss_and_double_backprop(nin, H, nout, B):
+@pytest.mark.parametrize("nin,H,nout,B,weighted", [(5, 128, 7, 256, False), (5, 256, 40, 4096, False),
+                                                  (5, 256, 40, 512, True), (1, 512, 64, 128, False),
+                                                  (7, 256, 40, 256, True), (8, 128, 5, 128, False),
+                                                  (16, 1024, 3, 128, False)])
+def test_loss_and_double_backprop(nin, H, nout, B, weighted):
     """Widths 128 to 1024 (4 to 32 k-tiles per product, 1 to 48 split-K
-    partials of the weight gradients), one to sixteen inputs, the widest
-    output tile (64 units)."""
-    say(f"mlp loss/grad n_in={nin} H={H} n_out={nout} B={B}")
+    partials of the weight gradients), one to sixteen inputs (up to seven on
+    the fused row-block kernels, above on the separate ones), the widest
+    output tile (64 units), per-sample Jacobian-term weights (some zero, with
+    non-finite labels there that must never be read as numbers)."""
+    say(f"mlp loss/grad n_in={nin} H={H} n_out={nout} B={B} weighted={weighted}")
     net = S.MLP(nin, H, nout, max_batch=B)
     params = rand_params([nin, H, H, H, nout], 5)
     net.set_params(net.pack(params))
@@ -155,13 +159,19 @@ def test_loss_and_double_backprop(nin, H, nout, B):
     Yl = rng.normal(0, 1, (B, nout)).astype(np.float32)
     Jl = rng.normal(0, 1, (B, nout, nin)).astype(np.float32)
     w = 0.8
-    loss, grad = net.loss_grad(*(torch.as_tensor(a, device="cuda") for a in (X, Yl, Jl)), w)
-    L, go = MO.grads(device_view(params), X.astype(np.float64), Yl.astype(np.float64), Jl.astype(np.float64), w)
+    jw = (rng.integers(0, 3, B) * 0.5).astype(np.float32) if weighted else None
+    Jdev = Jl.copy()
+    if weighted:
+        Jdev[jw == 0] = np.inf     # labels of zero-weight samples are never read
+    loss, grad = net.loss_grad(*(torch.as_tensor(a, device="cuda") for a in (X, Yl, Jdev)), w,
+                               jw=None if jw is None else torch.as_tensor(jw, device="cuda"))
+    L, go = MO.grads(device_view(params), X.astype(np.float64), Yl.astype(np.float64), Jl.astype(np.float64), w,
+                     jw=jw)
     say(f"  loss gpu {loss.item():.6g} oracle {L:.6g}")
     assert abs(loss.item() - L) < 2e-2 * L
     gg = net.unpack(grad.cpu().numpy())
     mag = MO.grad_magnitudes(device_view(params), X.astype(np.float64), Yl.astype(np.float64),
-                             Jl.astype(np.float64), w)
+                             Jl.astype(np.float64), w, jw=jw)
     u = 2.0 ** -9
     for l in range(4):
         for k in range(2):

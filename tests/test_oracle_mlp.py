@@ -39,11 +39,14 @@ def test_jacobian_matches_central_differences(case):
         np.testing.assert_allclose(J[:, :, j], fd, atol=1e-8)
 
 
-def test_grads_match_torch_autograd(case):
+@pytest.mark.parametrize("weighted", [False, True])
+def test_grads_match_torch_autograd(case, weighted):
+    """Unweighted, and with per-sample Jacobian-term weights (some zero)."""
     torch = pytest.importorskip("torch")
     params, X, Yl, Jl = case
     w = 0.7
-    L, g = MO.grads(params, X, Yl, Jl, w)
+    jw = np.array([1.0, 0.0, 0.5, 1.0, 0.0, 2.0]) if weighted else None
+    L, g = MO.grads(params, X, Yl, Jl, w, jw=jw)
     tp = [(torch.tensor(W, requires_grad=True), torch.tensor(b, requires_grad=True)) for W, b in params]
     Xt = torch.tensor(X, requires_grad=True)
 
@@ -58,7 +61,8 @@ def test_grads_match_torch_autograd(case):
     Y = net(Xt)
     cols = [torch.autograd.grad(Y[:, i].sum(), Xt, create_graph=True)[0] for i in range(Y.shape[1])]
     J = torch.stack(cols, dim=1)                       # [B, m, n_in]
-    Lt = torch.mean((Y - torch.tensor(Yl)) ** 2) + w * torch.mean((J - torch.tensor(Jl)) ** 2)
+    c = torch.ones(len(X), dtype=torch.float64) if jw is None else torch.tensor(jw)
+    Lt = torch.mean((Y - torch.tensor(Yl)) ** 2) + w * torch.mean(c[:, None, None] * (J - torch.tensor(Jl)) ** 2)
     Lt.backward()
     assert abs(L - Lt.item()) < 1e-13 * abs(L)
     for (dW, db), (W, b) in zip(g, tp):
