@@ -65,17 +65,27 @@ int mlp_forward(mlp_ctx *ctx, const float *d_theta, int32_t B, float *d_Y, float
  * with per-sample weights c_b of the Jacobian term from d_jw [B] (FP32; NULL:
  * all 1): a sample whose Jacobian label is not to be trusted gets 0 and
  * contributes its prices only (its Jacobian label is then never read as a
- * number).
+ * number).  d_idx [B] (int32, may be NULL): sample b of the batch is row
+ * d_idx[b] of d_theta, d_Ylab, d_Jlab and d_jw (NULL: row b), so batches can
+ * be drawn from a resident data set without gathering them first.
  * Labels are given in price units: d_Ylab [B x n_out], d_Jlab
  * [B x n_out x n_in].  B must be a multiple of 128.  d_loss[1] (FP64) and
  * d_grad [num_params] (FP32, packed like the parameters) are written. */
 int mlp_loss_grad(mlp_ctx *ctx, const float *d_theta, const float *d_Ylab, const float *d_Jlab, const float *d_jw,
-                  int32_t B, float w, double *d_loss, float *d_grad, void *stream);
+                  const int32_t *d_idx, int32_t B, float w, double *d_loss, float *d_grad, void *stream);
 
 /* One Adam step (Kingma & Ba) with bias correction for step t >= 1 on the
  * FP32 master parameters, then refresh of the bf16 copies. */
 int mlp_adam_step(mlp_ctx *ctx, const float *d_grad, float lr, float beta1, float beta2, float eps, int32_t t,
                   void *stream);
+
+/* mlp_adam_step with the learning rate d_lr[0] (FP32) and the step count
+ * d_t[0] (int32, >= 1) read on the device, and d_t[0] incremented there
+ * afterwards: a training loop of such calls, with its batches given by
+ * d_idx, launches the same work every epoch and can be captured in a graph
+ * and replayed. */
+int mlp_adam_step_dev(mlp_ctx *ctx, const float *d_grad, const float *d_lr, float beta1, float beta2, float eps,
+                      int32_t *d_t, void *stream);
 
 /* The surrogate's calibration functional (the paper's eq. 241118A with the
  * network's prices in place of the Monte Carlo means): for each of B

@@ -273,9 +273,6 @@ __global__ __launch_bounds__(kThreads) void k_split_reduce(const float *__restri
 //               SiLU'(z) u (bf16, the next product's operand), the primal
 //               pre-activations z (FP32) and the tangent pre-activations u
 //               (bf16) for the backward pass
-//   kEpiLoss    output layer: the differential loss's adjoint G4 (bf16, all
-//               row blocks), the workgroup's FP64 loss partial and the column
-//               partials of the primal adjoint (the output bias gradient)
 //   kEpiActBwd  adjoint of a hidden layer's activation from the next layer's
 //               input adjoint (double backprop):
 //                 zbar = hbar SiLU'(z) + sum_t tbar_t u_t SiLU''(z),
@@ -289,7 +286,7 @@ __global__ __launch_bounds__(kThreads) void k_split_reduce(const float *__restri
 // (blk = b0 / 32), summed over workgroups by k_chunk_reduce in a fixed order.
 // ---------------------------------------------------------------------------
 constexpr int kRowsMaxNR = 8;
-enum { kEpiStore = 0, kEpiActFwd = 1, kEpiLoss = 2, kEpiActBwd = 3, kEpiL1Bwd = 4 };
+enum { kEpiStore = 0, kEpiActFwd = 1, kEpiActBwd = 3, kEpiL1Bwd = 4 };
 
 struct RowsArgs {
     const uint16_t *A;      // [NR Bp][K] bf16, k contiguous
@@ -306,12 +303,6 @@ struct RowsArgs {
     const float *X;         // kEpiL1Bwd: [Bp][NR - 1] normalised inputs
     uint16_t *Zbar;         // kEpiActBwd: [NR Bp][N]
     float *part;            // column partials [Bp / 32][ncols]
-    // kEpiLoss
-    const float *b4, *Ylab, *Jlab, *jw, *in_scale, *out_shift, *out_scale;
-    int nout;
-    float w;
-    uint16_t *G4;           // [NR Bp][kOutPad]
-    double *lossp;          // [Bp / 32]
 };
 
 __device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
@@ -392,6 +383,23 @@ __global__ __launch_bounds__(NR * 64) void k_rows(RowsArgs a)
             acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv1, acc1, 0, 0, 0);
         }
     };
+    // the epilogue's primal pre-activations (wave 0; layer 1: the W1 values
+    // the other waves need), requested before the products so that their
+    // latency hides behind them
+    const int c0 = lane & 31;
+    auto rr = [&](int i) { return (i >> 2) * 8 + (lane >> 5) * 4 + (i & 3); };
+    float pre[32];
+    if constexpr (EPI == kEpiActBwd || EPI == kEpiL1Bwd) {
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int64_t col = n0 + c0 + 32 * h;
+                if (wave == 0) pre[2 * i + h] = a.Zp_in[(int64_t)(b0 + rr(i)) * N + col];
+                else if constexpr (EPI == kEpiL1Bwd) pre[2 * i + h] = a.W1[(int64_t)(wave - 1) * N + col];
+            }
+        }
+    }
     // the k-tiles as in k_gemm: tile t multiplied from buffer t % 2 while the
     // global loads of tiles t + 1 and t + 2 are in flight in two register sets
     const int nt = K / BK;
@@ -434,8 +442,6 @@ __global__ __launch_bounds__(NR * 64) void k_rows(RowsArgs a)
     }
 
     // epilogue: element i of acc0 / acc1 is (row rr(i), column c0 / c0 + 32) of the wave's tile
-    const int c0 = lane & 31;
-    auto rr = [&](int i) { return (i >> 2) * 8 + (lane >> 5) * 4 + (i & 3); };
     const int64_t rbase = (int64_t)wave * Bp + b0;   // first global row of this wave's tile
     const int blk = blockIdx.x;
     if constexpr (EPI == kEpiStore) {
@@ -478,60 +484,6 @@ __global__ __launch_bounds__(NR * 64) void k_rows(RowsArgs a)
                 }
             }
         }
-    } else if constexpr (EPI == kEpiLoss) {
-        // N = kOutPad (one column tile); columns >= nout are padding
-        const int nin = NR - 1;
-        const int B = Bp, nout = a.nout;
-        const float cy = 2.f / (float)(B * nout);
-        const float cj = 2.f * a.w / (float)(B * nout * nin);
-        double lacc = 0.0;
-        float dyp0[16], dyp1[16];
-#pragma unroll
-        for (int i = 0; i < 16; ++i) {
-            const int r = rr(i), b = b0 + r;
-#pragma unroll
-            for (int h = 0; h < 2; ++h) {
-                const int col = c0 + 32 * h;
-                const float v = h ? acc1[i] : acc0[i];
-                float g = 0.f;
-                if (col < nout) {
-                    if (wave == 0) {
-                        const float z = v + a.b4[col];
-                        const float zl = (a.Ylab[(int64_t)b * nout + col] - a.out_shift[col]) / a.out_scale[col];
-                        const float dz = z - zl;
-                        g = cy * dz;
-                        lacc += (double)dz * dz / (double)(B * nout);
-                    } else if (!a.jw || a.jw[b] != 0.f) {
-                        const int tt = wave - 1;
-                        const float cb = a.jw ? a.jw[b] : 1.f;
-                        const float jl = a.Jlab[((int64_t)b * nout + col) * nin + tt] /
-                                         (a.out_scale[col] * a.in_scale[tt]);
-                        const float dj = v - jl;
-                        g = cj * cb * dj;
-                        lacc += (double)a.w * cb * dj * dj / (double)(B * nout * nin);
-                    }
-                }
-                a.G4[(rbase + r) * kOutPad + col] = f2bf(g);
-                if (h) dyp1[i] = g;
-                else dyp0[i] = g;
-            }
-        }
-        if (wave == 0) {   // column partials of the primal adjoint: the output bias gradient
-            const float s0 = tile_colsum(dyp0), s1 = tile_colsum(dyp1);
-            if (lane < 32) {
-                if (c0 < nout) a.part[(int64_t)blk * nout + c0] = s0;
-                if (c0 + 32 < nout) a.part[(int64_t)blk * nout + c0 + 32] = s1;
-            }
-        }
-        // the workgroup's loss partial: per-thread sums in a fixed tree
-        double *sh = reinterpret_cast<double *>(sE);
-        sh[tid] = lacc;
-        __syncthreads();
-        if (tid == 0) {
-            double tot = 0.0;
-            for (int q = 0; q < NT; ++q) tot += sh[q];
-            a.lossp[blk] = tot;
-        }
     } else {   // kEpiActBwd, kEpiL1Bwd
         float *d1s = sE, *d2s = sE + 32 * 64, *tus = sE + 2 * 32 * 64;   // tus: [NR - 1][32][64]
         if (wave == 0) {
@@ -540,7 +492,7 @@ __global__ __launch_bounds__(NR * 64) void k_rows(RowsArgs a)
                 const int r = rr(i);
 #pragma unroll
                 for (int h = 0; h < 2; ++h) {
-                    const float z = a.Zp_in[(int64_t)(b0 + r) * N + n0 + c0 + 32 * h];
+                    const float z = pre[2 * i + h];
                     const float sg = sigm(z);
                     d1s[r * 64 + c0 + 32 * h] = sg * (1.f + z * (1.f - sg));
                     d2s[r * 64 + c0 + 32 * h] = sg * (1.f - sg) * (2.f + z * (1.f - 2.f * sg));
@@ -551,11 +503,6 @@ __global__ __launch_bounds__(NR * 64) void k_rows(RowsArgs a)
         float ub0[16], ub1[16];
         if (wave > 0) {
             const int tt = wave - 1;
-            float w1c[2] = {0.f, 0.f};
-            if constexpr (EPI == kEpiL1Bwd) {
-                w1c[0] = a.W1[(int64_t)tt * N + n0 + c0];
-                w1c[1] = a.W1[(int64_t)tt * N + n0 + c0 + 32];
-            }
 #pragma unroll
             for (int i = 0; i < 16; ++i) {
                 const int r = rr(i);
@@ -564,7 +511,7 @@ __global__ __launch_bounds__(NR * 64) void k_rows(RowsArgs a)
                     const int e = r * 64 + c0 + 32 * h;
                     const float tb = h ? acc1[i] : acc0[i];
                     float u;
-                    if constexpr (EPI == kEpiL1Bwd) u = w1c[h];
+                    if constexpr (EPI == kEpiL1Bwd) u = pre[2 * i + h];
                     else u = bf2f(a.U_in[((int64_t)tt * Bp + b0 + r) * N + n0 + c0 + 32 * h]);
                     const float ub = tb * d1s[e];
                     if constexpr (EPI == kEpiActBwd) a.Zbar[(rbase + r) * N + n0 + c0 + 32 * h] = f2bf(ub);
@@ -639,25 +586,26 @@ __global__ __launch_bounds__(NR * 64) void k_rows(RowsArgs a)
 // ---------------------------------------------------------------------------
 // elementwise kernels
 // ---------------------------------------------------------------------------
-__global__ void k_normalize(const float *__restrict__ th, int B, int Bp, int nin, const float *__restrict__ shift,
-                            const float *__restrict__ scale, float *__restrict__ X)
-{
-    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= Bp * nin) return;
-    const int b = idx / nin, j = idx % nin;
-    X[idx] = b < B ? (th[idx] - shift[j]) * scale[j] : 0.f;
-}
-
-// Layer 1 (n_in -> H): z = x W1 + b1; the tangent pre-activations are the
-// rows of W1 (the input tangents are unit vectors).
-__global__ void k_l1_fwd(const float *__restrict__ X, const float *__restrict__ W1, const float *__restrict__ b1,
-                         int Bp, int nin, int H, float *__restrict__ Z, uint16_t *__restrict__ A)
+// Layer 1 (n_in -> H) from the raw parameters: x = (theta[row b] - shift)
+// scale (row b is rows[b], or b when rows is null; x = 0 for padding rows
+// b >= B), z = x W1 + b1; the tangent pre-activations are the rows of W1 (the
+// input tangents are unit vectors).  The threads of unit 0 keep x for the
+// backward pass.
+__global__ void k_l1_fwd(const float *__restrict__ th, const int32_t *__restrict__ rows, int B,
+                         const float *__restrict__ shift, const float *__restrict__ scale,
+                         const float *__restrict__ W1, const float *__restrict__ b1, int Bp, int nin, int H,
+                         float *__restrict__ X, float *__restrict__ Z, uint16_t *__restrict__ A)
 {
     const int idx = blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= Bp * H) return;
     const int b = idx / H, j = idx % H;
+    const int64_t r = rows ? (int64_t)rows[b] : b;
     float z = b1[j];
-    for (int k = 0; k < nin; ++k) z += X[b * nin + k] * W1[k * H + j];
+    for (int k = 0; k < nin; ++k) {
+        const float x = b < B ? (th[r * nin + k] - shift[k]) * scale[k] : 0.f;
+        if (j == 0) X[b * nin + k] = x;
+        z += x * W1[k * H + j];
+    }
     const float s = sigm(z);
     const float d1 = s * (1.f + z * (1.f - s));
     Z[(int64_t)b * H + j] = z;
@@ -665,8 +613,8 @@ __global__ void k_l1_fwd(const float *__restrict__ X, const float *__restrict__ 
     // tangent rows: only their bf16 activations are stored; the pre-activations
     // are the rows of W1, which the backward pass reads there
     for (int t = 0; t < nin; ++t) {
-        const int64_t r = (int64_t)(t + 1) * Bp + b;
-        A[r * H + j] = f2bf(d1 * W1[t * H + j]);
+        const int64_t rr = (int64_t)(t + 1) * Bp + b;
+        A[rr * H + j] = f2bf(d1 * W1[t * H + j]);
     }
 }
 
@@ -704,7 +652,8 @@ __global__ void k_out_fwd(const float *__restrict__ Z4, const float *__restrict_
 // Differential loss, its adjoint G4 (bf16, network units) and FP64 block partials.
 __global__ __launch_bounds__(kThreads) void k_loss(const float *__restrict__ Z4, const float *__restrict__ b4,
                                                    const float *__restrict__ Ylab, const float *__restrict__ Jlab,
-                                                   const float *__restrict__ jw, int B, int nin, int nout, float w,
+                                                   const float *__restrict__ jw, const int32_t *__restrict__ rows,
+                                                   int B, int nin, int nout, float w,
                                                    const float *__restrict__ in_scale,
                                                    const float *__restrict__ out_shift,
                                                    const float *__restrict__ out_scale, uint16_t *__restrict__ G4,
@@ -715,23 +664,24 @@ __global__ __launch_bounds__(kThreads) void k_loss(const float *__restrict__ Z4,
     double acc = 0.0;
     if (idx < B * kOutPad) {
         const int b = idx / kOutPad, i = idx % kOutPad;
+        const int64_t d = rows ? (int64_t)rows[b] : b;   // the sample's data row
         if (i < nout) {
             const float cy = 2.f / (float)(B * nout);
             const float cj = 2.f * w / (float)(B * nout * nin);
             const float z = Z4[(int64_t)b * kOutPad + i] + b4[i];
-            const float zl = (Ylab[(int64_t)b * nout + i] - out_shift[i]) / out_scale[i];
+            const float zl = (Ylab[d * nout + i] - out_shift[i]) / out_scale[i];
             const float dz = z - zl;
             G4[(int64_t)b * kOutPad + i] = f2bf(cy * dz);
             dYP[(int64_t)b * kOutPad + i] = cy * dz;
             acc = (double)dz * dz / (double)(B * nout);
-            const float cb = jw ? jw[b] : 1.f;
+            const float cb = jw ? jw[d] : 1.f;
             for (int t = 0; t < nin; ++t) {
                 const int64_t r = (int64_t)(t + 1) * B + b;
                 if (cb == 0.f) {
                     G4[r * kOutPad + i] = 0;
                     continue;
                 }
-                const float jl = Jlab[((int64_t)b * nout + i) * nin + t] / (out_scale[i] * in_scale[t]);
+                const float jl = Jlab[(d * nout + i) * nin + t] / (out_scale[i] * in_scale[t]);
                 const float dj = Z4[r * kOutPad + i] - jl;
                 G4[r * kOutPad + i] = f2bf(cj * cb * dj);
                 acc += (double)w * cb * dj * dj / (double)(B * nout * nin);
@@ -872,6 +822,60 @@ __global__ void k_l1_bwd_part(const float *__restrict__ Hbar, const float *__res
     float *pz = part + (int64_t)blockIdx.x * (NI + 1) * H;
 #pragma unroll
     for (int t = 0; t <= NI; ++t) pz[(int64_t)t * H + j] = acc[t];
+}
+
+// bf16 copies of the product weights (layers 2..4): W [in x out] at offset
+// off of the parameters goes to WT [out_pad x in] and Wb [in x out_pad].
+struct WeightCopies {
+    int64_t off[3];
+    int in[3], out[3], out_pad[3];
+    uint16_t *WT[3], *Wb[3];
+};
+
+// Adam with the learning rate and step count read on the device, each
+// updated product weight written to its bf16 copies at once; the workgroup
+// that finishes last (a counter of finished workgroups, reset by it) advances
+// the step count, after every workgroup has read it.
+__global__ __launch_bounds__(kThreads) void k_adam_dev(float *__restrict__ p, const float *__restrict__ g,
+                                                       float *__restrict__ m, float *__restrict__ v, int64_t n,
+                                                       const float *__restrict__ lr_p, float b1, float b2, float eps,
+                                                       int32_t *__restrict__ t_p, unsigned *__restrict__ done,
+                                                       WeightCopies wc)
+{
+    __shared__ bool last;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const float t = (float)t_p[0], lr = lr_p[0];
+    if (i < n) {
+        const float bc1 = 1.f - powf(b1, t), bc2 = 1.f - powf(b2, t);
+        const float gi = g[i];
+        const float mi = b1 * m[i] + (1.f - b1) * gi;
+        const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+        m[i] = mi;
+        v[i] = vi;
+        const float pi = p[i] - lr * (mi / bc1) / (sqrtf(vi / bc2) + eps);
+        p[i] = pi;
+#pragma unroll
+        for (int l = 0; l < 3; ++l) {
+            const int64_t q64 = i - wc.off[l];
+            if (q64 >= 0 && q64 < (int64_t)wc.in[l] * wc.out[l]) {
+                const unsigned q = (unsigned)q64, out = (unsigned)wc.out[l];   // < 2^20: 32-bit division
+                const unsigned ii = q / out, o = q - ii * out;
+                const uint16_t h = f2bf(pi);
+                wc.WT[l][o * (unsigned)wc.in[l] + ii] = h;
+                wc.Wb[l][ii * (unsigned)wc.out_pad[l] + o] = h;
+            }
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();
+        last = atomicAdd(done, 1u) == gridDim.x - 1;
+    }
+    __syncthreads();
+    if (last && threadIdx.x == 0) {
+        t_p[0] += 1;
+        *done = 0u;
+    }
 }
 
 __global__ void k_adam(float *__restrict__ p, const float *__restrict__ g, float *__restrict__ m,
@@ -1151,6 +1155,7 @@ struct mlp_ctx {
     float *Xn = nullptr;          // Bmax x nin
     float *split = nullptr;       // kMaxSplits x H x H, or row-chunk partials of the column sums
     double *lossp = nullptr;
+    unsigned *done = nullptr;     // finished-workgroup counter of k_adam_dev (zero between launches)
     std::vector<void *> allocs;
     std::string err;
 };
@@ -1278,11 +1283,13 @@ extern "C" int mlp_create(int32_t n_in, int32_t n_hidden, int32_t n_out, int32_t
     // (Bmax / kChunkL1) x (n_in + 1) x H floats)
     A((void **)&c->split, 4 * std::max((int64_t)kMaxSplits * H * H, (int64_t)(c->Bmax / kChunkL1) * (n_in + 1) * H));
     A((void **)&c->lossp, 8 * (int64_t)((c->Bmax * kOutPad + kThreads - 1) / kThreads));
+    A((void **)&c->done, 256);
     if (e != hipSuccess) {
         mlp_destroy(c);
         return mfail(nullptr, -2, std::string("allocation failed: ") + hipGetErrorString(e));
     }
     hipLaunchKernelGGL(k_fill, dim3(nb(c->np)), dim3(kThreads), 0, 0, c->p, c->np, 0.f);
+    hipLaunchKernelGGL(k_fill, dim3(1), dim3(kThreads), 0, 0, (float *)c->done, (int64_t)64, 0.f);
     hipLaunchKernelGGL(k_fill, dim3(nb(c->np)), dim3(kThreads), 0, 0, c->m, c->np, 0.f);
     hipLaunchKernelGGL(k_fill, dim3(nb(c->np)), dim3(kThreads), 0, 0, c->v, c->np, 0.f);
     hipLaunchKernelGGL(k_fill, dim3(1), dim3(kThreads), 0, 0, c->in_shift, (int64_t)16, 0.f);
@@ -1360,7 +1367,6 @@ static void launch_rows_nr(int epi, const RowsArgs &a, hipStream_t st)
     switch (epi) {
     case kEpiStore: hipLaunchKernelGGL((k_rows<NR, kEpiStore>), grid, block, 0, st, a); break;
     case kEpiActFwd: hipLaunchKernelGGL((k_rows<NR, kEpiActFwd>), grid, block, 0, st, a); break;
-    case kEpiLoss: hipLaunchKernelGGL((k_rows<NR, kEpiLoss>), grid, block, 0, st, a); break;
     case kEpiActBwd: hipLaunchKernelGGL((k_rows<NR, kEpiActBwd>), grid, block, 0, st, a); break;
     default: hipLaunchKernelGGL((k_rows<NR, kEpiL1Bwd>), grid, block, 0, st, a); break;
     }
@@ -1381,15 +1387,16 @@ static hipError_t launch_rows(int NR, int epi, const RowsArgs &a, hipStream_t st
     return hipGetLastError();
 }
 
-// Fused forward over Bp rows of normalised inputs already in c->Xn: layer 1,
+// Fused forward over B samples (theta rows `rows`, padded to Bp): layer 1,
 // then the two hidden layers' products with their activations; with
 // store_out the output layer's pre-activations go to c->Z[4].
-static hipError_t forward_fused(mlp_ctx *c, int Bp, bool store_out, hipStream_t st)
+static hipError_t forward_fused(mlp_ctx *c, const float *th, const int32_t *rows, int B, int Bp, bool store_out,
+                                hipStream_t st)
 {
     const int H = c->H, nin = c->nin, NR = nin + 1;
     const float *p = c->p;
-    hipLaunchKernelGGL(k_l1_fwd, dim3(nb((int64_t)Bp * H)), dim3(kThreads), 0, st, c->Xn, p + c->off[0], p + c->off[1],
-                       Bp, nin, H, c->Z[1], c->A[1]);
+    hipLaunchKernelGGL(k_l1_fwd, dim3(nb((int64_t)Bp * H)), dim3(kThreads), 0, st, th, rows, B, c->in_shift,
+                       c->in_scale, p + c->off[0], p + c->off[1], Bp, nin, H, c->Xn, c->Z[1], c->A[1]);
     hipError_t e = hipGetLastError();
     for (int l = 2; l <= 3 && e == hipSuccess; ++l) {
         RowsArgs a{};
@@ -1417,15 +1424,15 @@ static hipError_t forward_fused(mlp_ctx *c, int Bp, bool store_out, hipStream_t 
     return e;
 }
 
-// Forward over Bp rows of normalised inputs already in c->Xn.
-static hipError_t forward_core(mlp_ctx *c, int Bp, hipStream_t st)
+// Forward over B samples (theta rows `rows`, padded to Bp).
+static hipError_t forward_core(mlp_ctx *c, const float *th, const int32_t *rows, int B, int Bp, hipStream_t st)
 {
-    if (fused_path(c)) return forward_fused(c, Bp, true, st);
+    if (fused_path(c)) return forward_fused(c, th, rows, B, Bp, true, st);
     const int H = c->H, nin = c->nin;
     const int R = (nin + 1) * Bp;
     const float *p = c->p;
-    hipLaunchKernelGGL(k_l1_fwd, dim3(nb((int64_t)Bp * H)), dim3(kThreads), 0, st, c->Xn, p + c->off[0], p + c->off[1],
-                       Bp, nin, H, c->Z[1], c->A[1]);
+    hipLaunchKernelGGL(k_l1_fwd, dim3(nb((int64_t)Bp * H)), dim3(kThreads), 0, st, th, rows, B, c->in_shift,
+                       c->in_scale, p + c->off[0], p + c->off[1], Bp, nin, H, c->Xn, c->Z[1], c->A[1]);
     hipError_t e = hipGetLastError();
     for (int l = 2; l <= 3 && e == hipSuccess; ++l) {
         e = launch_gemm(true, true, c->A[l - 1], H, c->WT[l - 1], H, c->Z[l], H, R, H, H, 1, st);
@@ -1487,10 +1494,7 @@ extern "C" int mlp_forward(mlp_ctx *c, const float *d_theta, int32_t B, float *d
         return e == hipSuccess ? 0 : mfail(c, -3, hipGetErrorString(e));
     }
     const int Bp = (B + 127) / 128 * 128;
-    hipLaunchKernelGGL(k_normalize, dim3(nb((int64_t)Bp * c->nin)), dim3(kThreads), 0, st, d_theta, B, Bp, c->nin,
-                       c->in_shift, c->in_scale, c->Xn);
-    hipError_t e = hipGetLastError();
-    if (e == hipSuccess) e = forward_core(c, Bp, st);
+    hipError_t e = forward_core(c, d_theta, nullptr, B, Bp, st);
     if (e == hipSuccess) {
         hipLaunchKernelGGL(k_out_fwd, dim3(nb((int64_t)B * c->nout)), dim3(kThreads), 0, st, c->Z[4],
                            c->p + c->off[7], B, Bp, c->nin, c->nout, c->in_scale, c->out_shift, c->out_scale, d_Y, d_J);
@@ -1504,36 +1508,20 @@ extern "C" int mlp_forward(mlp_ctx *c, const float *d_theta, int32_t B, float *d
 // order reduction), the bias gradient (workgroup column partials, fixed-order
 // reduction) and the next layer's input adjoint fused with the activation
 // adjoint; layer 1's gradients from the last product's epilogue.
-static hipError_t loss_grad_fused(mlp_ctx *c, const float *Ylab, const float *Jlab, const float *jw, int B, float w,
-                                  double *loss, float *g, hipStream_t st)
+static hipError_t loss_grad_fused(mlp_ctx *c, const float *th, const float *Ylab, const float *Jlab, const float *jw,
+                                  const int32_t *idx, int B, float w, double *loss, float *g, hipStream_t st)
 {
     const int H = c->H, nin = c->nin, NR = nin + 1, R = NR * B;
     const int nwg = B / 32;   // workgroups (32 samples each) along the batch
-    hipError_t e = forward_fused(c, B, false, st);
+    hipError_t e = forward_fused(c, th, idx, B, B, false, st);
+    if (e == hipSuccess) e = launch_gemm(true, true, c->A[3], H, c->WT[3], H, c->Z[4], kOutPad, R, kOutPad, H, 1, st);
     if (e != hipSuccess) return e;
-    RowsArgs a{};
-    a.A = c->A[3];
-    a.W = c->WT[3];
-    a.Bp = B;
-    a.K = H;
-    a.N = kOutPad;
-    a.b4 = c->p + c->off[7];
-    a.Ylab = Ylab;
-    a.Jlab = Jlab;
-    a.jw = jw;
-    a.in_scale = c->in_scale;
-    a.out_shift = c->out_shift;
-    a.out_scale = c->out_scale;
-    a.nout = c->nout;
-    a.w = w;
-    a.G4 = c->G4;
-    a.lossp = c->lossp;
-    a.part = c->split;
-    e = launch_rows(NR, kEpiLoss, a, st);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(kThreads), 0, st, c->lossp, nwg, loss);
-    hipLaunchKernelGGL(k_chunk_reduce, dim3((c->nout + kThreads / 8 - 1) / (kThreads / 8)), dim3(kThreads), 0, st,
-                       c->split, nwg, c->nout, g + c->off[7]);
+    // the loss and the output layer's adjoint (elementwise over the R x 64 outputs)
+    const unsigned nlb = nb((int64_t)B * kOutPad);
+    hipLaunchKernelGGL(k_loss, dim3(nlb), dim3(kThreads), 0, st, c->Z[4], c->p + c->off[7], Ylab, Jlab, jw, idx, B, nin,
+                       c->nout, w, c->in_scale, c->out_shift, c->out_scale, c->G4, c->ZbarP, c->lossp);
+    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(kThreads), 0, st, c->lossp, (int)nlb, loss);
+    colsum(c, c->ZbarP, B, kOutPad, c->nout, g + c->off[7], st);
     const int S = std::min(kMaxSplits, std::max(1, R / 512));
     // output layer: W4bar = A3^T G4, then H3bar = G4 W4^T with layer 3's activation adjoint
     e = launch_gemm(false, false, c->A[3], H, c->G4, kOutPad, c->split, kOutPad, H, kOutPad, R, S, st);
@@ -1586,7 +1574,8 @@ static hipError_t loss_grad_fused(mlp_ctx *c, const float *Ylab, const float *Jl
 }
 
 extern "C" int mlp_loss_grad(mlp_ctx *c, const float *d_theta, const float *d_Ylab, const float *d_Jlab,
-                             const float *d_jw, int32_t B, float w, double *d_loss, float *d_grad, void *stream)
+                             const float *d_jw, const int32_t *d_idx, int32_t B, float w, double *d_loss, float *d_grad,
+                             void *stream)
 {
     if (!c || !d_theta || !d_Ylab || !d_Jlab || !d_loss || !d_grad) return mfail(c, -1, "null argument");
     if (B < 128 || B > c->Bmax || B % 128)
@@ -1594,17 +1583,17 @@ extern "C" int mlp_loss_grad(mlp_ctx *c, const float *d_theta, const float *d_Yl
     hipStream_t st = (hipStream_t)stream;
     const int H = c->H, nin = c->nin, R = (nin + 1) * B;
     float *g = d_grad;
-    hipLaunchKernelGGL(k_normalize, dim3(nb((int64_t)B * nin)), dim3(kThreads), 0, st, d_theta, B, B, nin, c->in_shift,
-                       c->in_scale, c->Xn);
-    hipError_t e = hipGetLastError();
-    if (e == hipSuccess && fused_path(c)) e = loss_grad_fused(c, d_Ylab, d_Jlab, d_jw, B, w, d_loss, g, st);
-    if (fused_path(c)) return e == hipSuccess ? 0 : mfail(c, -3, hipGetErrorString(e));
-    if (e == hipSuccess) e = forward_core(c, B, st);
+    hipError_t e = hipSuccess;
+    if (fused_path(c)) {
+        e = loss_grad_fused(c, d_theta, d_Ylab, d_Jlab, d_jw, d_idx, B, w, d_loss, g, st);
+        return e == hipSuccess ? 0 : mfail(c, -3, hipGetErrorString(e));
+    }
+    e = forward_core(c, d_theta, d_idx, B, B, st);
     if (e != hipSuccess) return mfail(c, -3, hipGetErrorString(e));
     // loss and the output-layer adjoint
     const unsigned nlb = nb((int64_t)B * kOutPad);
-    hipLaunchKernelGGL(k_loss, dim3(nlb), dim3(kThreads), 0, st, c->Z[4], c->p + c->off[7], d_Ylab, d_Jlab, d_jw, B,
-                       nin, c->nout, w, c->in_scale, c->out_shift, c->out_scale, c->G4, c->ZbarP, c->lossp);
+    hipLaunchKernelGGL(k_loss, dim3(nlb), dim3(kThreads), 0, st, c->Z[4], c->p + c->off[7], d_Ylab, d_Jlab, d_jw,
+                       d_idx, B, nin, c->nout, w, c->in_scale, c->out_shift, c->out_scale, c->G4, c->ZbarP, c->lossp);
     hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(kThreads), 0, st, c->lossp, (int)nlb, d_loss);
     colsum(c, c->ZbarP, B, kOutPad, c->nout, g + c->off[7], st);
     // output layer: W4bar = A3^T G4 (split over rows), H3bar = G4 W4^T
@@ -1650,6 +1639,27 @@ extern "C" int mlp_adam_step(mlp_ctx *c, const float *d_grad, float lr, float be
                        beta2, eps, bc1, bc2);
     hipError_t e = hipGetLastError();
     if (e == hipSuccess) e = refresh_all(c, st);
+    return e == hipSuccess ? 0 : mfail(c, -3, hipGetErrorString(e));
+}
+
+extern "C" int mlp_adam_step_dev(mlp_ctx *c, const float *d_grad, const float *d_lr, float beta1, float beta2,
+                                 float eps, int32_t *d_t, void *stream)
+{
+    if (!c || !d_grad || !d_lr || !d_t) return mfail(c, -1, "null argument");
+    hipStream_t st = (hipStream_t)stream;
+    WeightCopies wc{};
+    for (int l = 2; l <= 4; ++l) {
+        const int k = l - 2;
+        wc.off[k] = c->off[2 * (l - 1)];
+        wc.in[k] = c->H;
+        wc.out[k] = l == 4 ? c->nout : c->H;
+        wc.out_pad[k] = l == 4 ? kOutPad : c->H;
+        wc.WT[k] = c->WT[l - 1];
+        wc.Wb[k] = c->Wb[l - 1];
+    }
+    hipLaunchKernelGGL(k_adam_dev, dim3(nb(c->np)), dim3(kThreads), 0, st, c->p, d_grad, c->m, c->v, c->np, d_lr, beta1,
+                       beta2, eps, d_t, c->done, wc);
+    hipError_t e = hipGetLastError();
     return e == hipSuccess ? 0 : mfail(c, -3, hipGetErrorString(e));
 }
 

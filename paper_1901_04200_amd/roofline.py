@@ -92,3 +92,36 @@ def pass2_bytes(n_paths: int, ckpt_every: int, n_blocks: int, n_instr: int, n_st
     lambda_i D_i / P are read."""
     n_seg = -(-n_steps // ckpt_every)
     return n_seg * n_state * n_paths * real_bytes + n_blocks * n_params * 8 + n_instr * real_bytes
+
+
+def training_step_bytes(batch: int, hidden: int, n_in: int, n_out: int, n_params: int) -> int:
+    """Algorithmic HBM bytes of one surrogate training step on the fused
+    kernels (network n_in -> H -> H -> H -> n_out, output units padded to
+    64): every tensor of the step written once and read once by each of its
+    consumers, with R = (n_in + 1) batch activation rows.
+      inputs: parameter rows, price and Jacobian labels, Jacobian weights and
+        batch indices                                  B (n_in + n_out (1 + n_in) + 2) 4
+      layer 1: bf16 activations A1 and FP32 primal pre-activations z1 written
+      hidden layers 2, 3, forward: A_{l-1} read; A_l, z_l and the bf16
+        tangent pre-activations u_l written
+      output layer: A3 read, the bf16 output adjoint G4 written
+      weight gradients (three products): both operands read
+      input adjoints of layers 3, 2 (fused with the activation adjoint): the
+        adjoint above, z_l and u_l read, bf16 Zbar_l written
+      layer 1's adjoint: Zbar2 and z1 read
+      Adam: parameters, both moments and the gradient read, three written,
+        bf16 copies of the three product weights written twice
+    Weights read by the products and the per-workgroup partials are left out
+    (small next to the activations at B = 4096)."""
+    B, H = batch, hidden
+    R = (n_in + 1) * B
+    act = R * H * 2               # one bf16 activation or adjoint matrix
+    z = B * H * 4                 # FP32 primal pre-activations
+    u = n_in * B * H * 2          # bf16 tangent pre-activations
+    g4 = R * 64 * 2
+    inputs = B * (n_in + n_out * (1 + n_in) + 2) * 4
+    fwd = (act + z) + 2 * (act + act + z + u) + (act + g4)
+    wgrad = (act + g4) + 2 * (act + act)
+    bwd = (g4 + z + u + act) + (act + z + u + act) + (act + z)
+    adam = n_params * 4 * 7 + 3 * 2 * 2 * H * H
+    return inputs + fwd + wgrad + bwd + adam

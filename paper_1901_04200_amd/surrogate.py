@@ -18,8 +18,8 @@ import numpy as np
 from . import capi
 
 EXPORTED = ("mlp_create", "mlp_destroy", "mlp_num_params", "mlp_set_params", "mlp_get_params",
-            "mlp_set_scaling", "mlp_forward", "mlp_loss_grad", "mlp_adam_step", "mlp_calibration_gradient",
-            "mlp_last_error")
+            "mlp_set_scaling", "mlp_forward", "mlp_loss_grad", "mlp_adam_step", "mlp_adam_step_dev",
+            "mlp_calibration_gradient", "mlp_last_error")
 
 _sig_done = False
 
@@ -37,8 +37,9 @@ def lib():
             "mlp_get_params": ([vp, vp, vp], C.c_int),
             "mlp_set_scaling": ([vp, vp, vp, vp, vp, vp], C.c_int),
             "mlp_forward": ([vp, vp, i32, vp, vp, vp], C.c_int),
-            "mlp_loss_grad": ([vp, vp, vp, vp, vp, i32, C.c_float, vp, vp, vp], C.c_int),
+            "mlp_loss_grad": ([vp, vp, vp, vp, vp, vp, i32, C.c_float, vp, vp, vp], C.c_int),
             "mlp_adam_step": ([vp, vp, C.c_float, C.c_float, C.c_float, C.c_float, i32, vp], C.c_int),
+            "mlp_adam_step_dev": ([vp, vp, vp, C.c_float, C.c_float, C.c_float, vp, vp], C.c_int),
             "mlp_calibration_gradient": ([vp, vp, i32, vp, vp, vp, vp, vp, vp], C.c_int),
             "mlp_last_error": ([vp], C.c_char_p),
         }
@@ -165,16 +166,18 @@ class MLP:
                                                    _ptr(G), _ptr(g), _stream()))
         return G, g
 
-    def loss_grad(self, theta, Ylab, Jlab, w: float, grad=None, loss=None, jw=None):
-        """Differential loss and its gradient; jw [B]: per-sample weights of the
-        Jacobian term (None: all 1)."""
-        B = theta.shape[0]
+    def loss_grad(self, theta, Ylab, Jlab, w: float, grad=None, loss=None, jw=None, idx=None):
+        """Differential loss and its gradient; jw: per-sample weights of the
+        Jacobian term (None: all 1); idx [B] (int32, device): the batch's rows
+        of theta, Ylab, Jlab and jw (None: the first B rows in order)."""
+        B = theta.shape[0] if idx is None else idx.shape[0]
         if grad is None:
             grad = self.torch.empty(self.n_params, dtype=self.torch.float32, device=self.dev)
         if loss is None:
             loss = self.torch.empty(1, dtype=self.torch.float64, device=self.dev)
         self._check(lib().mlp_loss_grad(self.ctx, _ptr(theta), _ptr(Ylab), _ptr(Jlab),
-                                        None if jw is None else _ptr(jw), B, float(w), _ptr(loss),
+                                        None if jw is None else _ptr(jw), None if idx is None else _ptr(idx), B,
+                                        float(w), _ptr(loss),
                                         _ptr(grad), _stream()))
         return loss, grad
 
@@ -182,6 +185,12 @@ class MLP:
         self.step_count += 1
         self._check(lib().mlp_adam_step(self.ctx, _ptr(grad), float(lr), float(beta1), float(beta2), float(eps),
                                         self.step_count, _stream()))
+
+    def adam_step_dev(self, grad, lr_dev, t_dev, beta1=0.9, beta2=0.999, eps=1e-8):
+        """Adam with the learning rate lr_dev[0] and step count t_dev[0] read on
+        the device (t_dev incremented there)."""
+        self._check(lib().mlp_adam_step_dev(self.ctx, _ptr(grad), _ptr(lr_dev), float(beta1), float(beta2), float(eps),
+                                            _ptr(t_dev), _stream()))
 
     def close(self):
         if self.ctx:
@@ -232,36 +241,65 @@ class TrainLog:
 
 
 def fit(net: MLP, theta, Y, J, *, epochs: int, batch: int = 4096, lr: float = 1e-3, w: float = 1.0,
-        lr_final: Optional[float] = None, seed: int = 0, log_every: int = 1, jw=None) -> List[TrainLog]:
+        lr_final: Optional[float] = None, seed: int = 0, log_every: int = 1, jw=None,
+        graph: bool = True) -> List[TrainLog]:
     """Adam on the differential loss over (theta, Y, J) device tensors (FP32),
     jw: per-sample weights of the Jacobian term (device FP32, or None).
-    The learning rate decays geometrically to lr_final over the epochs."""
+    The learning rate decays geometrically to lr_final over the epochs.
+
+    The data stay where they are: each epoch's permutation (drawn on the
+    host) goes to a device buffer, and every step's kernels read their batch
+    through its slice of it; the learning rate and the Adam step count live
+    on the device too.  An epoch therefore launches the same work every time:
+    with graph=True the second epoch is captured in a HIP graph and replayed
+    for every later one (no host launches per step), the first runs eagerly.
+    The results do not depend on graph."""
     import torch
     n = theta.shape[0]
     steps_per_epoch = n // batch
     assert steps_per_epoch >= 1, "need at least one full batch"
     g = torch.Generator(device="cpu")
     g.manual_seed(seed)
-    grad = torch.empty(net.n_params, dtype=torch.float32, device=net.dev)
-    loss = torch.empty(1, dtype=torch.float64, device=net.dev)
+    dev = net.dev
+    grad = torch.empty(net.n_params, dtype=torch.float32, device=dev)
+    loss = torch.empty(1, dtype=torch.float64, device=dev)
+    perm_dev = torch.empty(n, dtype=torch.int32, device=dev)
+    lr_host = torch.empty(1, dtype=torch.float32, pin_memory=True)
+    lr_dev = torch.empty(1, dtype=torch.float32, device=dev)
+    t_dev = torch.full((1,), net.step_count + 1, dtype=torch.int32, device=dev)
+    tot = torch.zeros(1, dtype=torch.float64, device=dev)   # summed on the device: no sync per step
+    theta, Y, J = theta.contiguous(), Y.contiguous(), J.contiguous()
+    jw = None if jw is None else jw.contiguous()
+
+    def epoch():
+        for s in range(steps_per_epoch):
+            net.loss_grad(theta, Y, J, w, grad, loss, jw=jw, idx=perm_dev[s * batch:(s + 1) * batch])
+            net.adam_step_dev(grad, lr_dev, t_dev)
+            tot.add_(loss)
+
     hist = []
     t0 = time.perf_counter()
     lr_f = lr if lr_final is None else lr_final
+    cg = None
     for ep in range(epochs):
         lr_e = lr * (lr_f / lr) ** (ep / max(epochs - 1, 1))
-        perm = torch.randperm(n, generator=g).to(net.dev)
-        logged = (ep % log_every == 0) or ep == epochs - 1
-        tot = torch.zeros(1, dtype=torch.float64, device=net.dev)   # summed on the device: no sync per step
-        for s in range(steps_per_epoch):
-            idx = perm[s * batch:(s + 1) * batch]
-            net.loss_grad(theta[idx].contiguous(), Y[idx].contiguous(), J[idx].contiguous(), w, grad, loss,
-                          None if jw is None else jw[idx].contiguous())
-            net.adam_step(grad, lr_e)
-            if logged:
-                tot += loss
-        if logged:
+        perm_dev.copy_(torch.randperm(n, generator=g).to(torch.int32))
+        lr_host[0] = lr_e
+        lr_dev.copy_(lr_host, non_blocking=True)
+        tot.zero_()
+        if graph and ep >= 1:
+            if cg is None:
+                torch.cuda.synchronize()
+                cg = torch.cuda.CUDAGraph()
+                with torch.cuda.graph(cg):
+                    epoch()
+            cg.replay()
+        else:
+            epoch()
+        if (ep % log_every == 0) or ep == epochs - 1:
             hist.append(TrainLog(ep, float(tot.item()) / steps_per_epoch, time.perf_counter() - t0))
     torch.cuda.synchronize()
+    net.step_count += epochs * steps_per_epoch
     return hist
 
 

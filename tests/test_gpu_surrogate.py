@@ -306,3 +306,31 @@ def test_surrogate_assisted_calibration():
     assert len(recs2) <= len(recs) and recs2[-1].G_mc <= stop
     mc.close()
     net.close()
+
+
+def test_training_graph_matches_eager():
+    """Training epochs replayed from a captured graph (batches through a
+    device permutation buffer, learning rate and step count on the device)
+    give the eager loop's parameters bit for bit, the losses too (each
+    epoch's permutation and learning rate are copied in, and the loss read
+    back, eagerly between the replays); another network's eager work after
+    the loop does not disturb them."""
+    rng = np.random.default_rng(21)
+    n, nin, nout = 1024, 5, 40
+    th = torch.as_tensor(rng.uniform(-1, 1, (n, nin)), dtype=torch.float32, device="cuda")
+    Y = torch.as_tensor(rng.normal(0, 1, (n, nout)), dtype=torch.float32, device="cuda")
+    J = torch.as_tensor(rng.normal(0, 1, (n, nout, nin)), dtype=torch.float32, device="cuda")
+    jw = torch.as_tensor((rng.random(n) < 0.7).astype(np.float32), device="cuda")
+    out = {}
+    for graph in (False, True):
+        net = S.MLP(nin, 256, nout, max_batch=256)
+        net.init_params(3)
+        other = S.MLP(nin, 128, 7, max_batch=128)
+        other.init_params(4)
+        hist = S.fit(net, th, Y, J, epochs=5, batch=256, lr=2e-3, lr_final=1e-3, w=0.5, jw=jw, graph=graph)
+        other.forward(th[:128])
+        out[graph] = (net.get_params(), [h.loss for h in hist])
+        net.close()
+        other.close()
+    np.testing.assert_array_equal(out[True][0], out[False][0])
+    assert out[True][1] == out[False][1]
