@@ -139,15 +139,15 @@ def pass2_traffic(ckpt_every, ppl):
     return value if ok else None
 
 
-ISSUE_PROFILE = os.path.join(ROOT, "profiles", "mc_kernels_heston_2p20x256_valu_issue.md")
+ISSUE_PROFILE = os.path.join(ROOT, "profiles", "mc_kernels_heston_2p20x256_valu_mix.md")
 
 
 def valu_issue_utilisation(ckpt_every):
     """Measured VALU issue utilisation of the Heston pass-2 kernel at this
-    spacing: SQ_ACTIVE_INST_VALU over the busy cycles of every SIMD, scaled by
-    what the same ratio reads for a kernel of independent FP32 FMAs (one per
-    cycle and SIMD), from the committed counter summary; None when not taken
-    or stale."""
+    spacing: issue slots counted with SQ counters (SQ_INSTS_VALU, with the
+    64-bit integer and transcendental instructions at four slots) over the
+    kernel's traced duration x 7.86e13 lane-slots/s, from the committed
+    counter summary; None when not taken or stale."""
     try:
         lines = open(ISSUE_PROFILE).read().splitlines()
     except OSError:
@@ -165,31 +165,32 @@ def valu_issue_utilisation(ckpt_every):
 GRID_VALU_PROFILE = os.path.join(ROOT, "profiles", "grid_kernels_valu_mix.md")
 
 
-def counted_slots(model, kernel, ckpt_every):
+def counted_slots(model, kernel, ckpt_every, ppl=1):
     """VALU issue slots per path-step of a local-volatility or SLV kernel
-    ('pass1' or 'pass2' at this spacing), counted with SQ counters and
-    committed with the sources' hashes; None when not counted or stale."""
+    ('pass1' or 'pass2' at this spacing) with ppl paths per lane, counted with
+    SQ counters and committed with the sources' hashes; None when not counted
+    or stale."""
     try:
         lines = open(GRID_VALU_PROFILE).read().splitlines()
     except OSError:
         return None
-    want = [model, kernel, f"K={ckpt_every}" if kernel == "pass2" else "K=-"]
+    want = [model, kernel, f"K={ckpt_every}" if kernel == "pass2" else "K=-", f"ppl={ppl}"]
     value, ok = None, True
     for ln in lines:
         f = ln.split()
-        if len(f) == 5 and f[0] == "valu_slots_per_path_step" and f[1:4] == want:
-            value = float(f[4])
+        if len(f) == 6 and f[0] == "valu_slots_per_path_step" and f[1:5] == want:
+            value = float(f[5])
         elif len(f) == 3 and f[0] == "code-sha256":
             ok = ok and os.path.exists(os.path.join(ROOT, f[1])) and code_hash(os.path.join(ROOT, f[1])) == f[2]
     return value if ok else None
 
 
-def grid_roofline(model, kernel_name, ckpt_every, path_steps, ms_pass2):
+def grid_roofline(model, kernel_name, ckpt_every, path_steps, ms_pass2, ppl=1):
     """Issue-slot roofline of a grid model's pass-2 kernel: counted slots per
     path-step x path-steps / the kernel's average duration, against the
     7.86e13 lane-slots/s of the FP32 VALU peak."""
     from paper_1901_04200_amd import roofline
-    sl = counted_slots(model, "pass2", ckpt_every)
+    sl = counted_slots(model, "pass2", ckpt_every, ppl)
     achieved = sl * path_steps / (ms_pass2 * 1e-3) * 1e-12 if sl else None
     return {"bound": "alu", "kernel": kernel_name, "achieved": achieved, "peak": roofline.PEAK_SLOTS * 1e-12,
             "unit": "T VALU lane-slots/s", "frac": achieved / (roofline.PEAK_SLOTS * 1e-12) if achieved else None,
@@ -285,7 +286,8 @@ def slv_leg(reps):
             "forward_paths_steps_per_s": ps / (ms_fwd * 1e-3), "ms_forward": ms_fwd,
             "ms_pass1_kernel": p1[0] / p1[1], "ms_pass2_kernel": t_2,
             "kr_over_kf": costmodel.kr_over_kf(t_f, t_2),
-            "roofline": grid_roofline("slv", f"k_slv_pass2 (FP32, K={k})", k, ps, t_2)}
+            "roofline": grid_roofline("slv", f"k_slv_pass2 (FP32, K={k}, {ppl} path(s) per lane)", k, ps, t_2,
+                                      ppl)}
 
 
 def lv_leg(reps):
@@ -347,7 +349,9 @@ def lv_leg(reps):
     tuned = {"ckpt_every": kt, "paths_per_lane": pplt,
              "tuning_ms": {f"k{kk}_ppl{pp}": t * 1e3 for (kk, pp), t in table},
              "ms_per_step": ms_tuned, "paths_steps_per_s": ps / (ms_tuned * 1e-3),
-             "ms_pass2_kernel": p2t[0] / p2t[1]}
+             "ms_pass2_kernel": p2t[0] / p2t[1],
+             "roofline": grid_roofline("lv", f"k_lv_pass2 (FP32, K={kt}, {pplt} path(s) per lane)", kt, ps,
+                                       p2t[0] / p2t[1], pplt)}
     return {"workload": "local volatility: 2^22 paths x 256 steps over 2 years, bilinear 10 x 20 grid (M = 200), "
                         "m = 200 calls at the grid nodes, FP32 state, FP64 sums",
             "ckpt_every": k, "status": status,
