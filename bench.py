@@ -165,13 +165,16 @@ def valu_issue_utilisation(ckpt_every):
 GRID_VALU_PROFILE = os.path.join(ROOT, "profiles", "grid_kernels_valu_mix.md")
 
 
-def counted_slots(model, kernel, ckpt_every, ppl=1):
+BATCH_VALU_PROFILE = os.path.join(ROOT, "profiles", "batch_kernels_heston_valu_mix.md")
+
+
+def counted_slots(model, kernel, ckpt_every, ppl=1, profile=GRID_VALU_PROFILE):
     """VALU issue slots per path-step of a local-volatility or SLV kernel
     ('pass1' or 'pass2' at this spacing) with ppl paths per lane, counted with
     SQ counters and committed with the sources' hashes; None when not counted
     or stale."""
     try:
-        lines = open(GRID_VALU_PROFILE).read().splitlines()
+        lines = open(profile).read().splitlines()
     except OSError:
         return None
     want = [model, kernel, f"K={ckpt_every}" if kernel == "pass2" else "K=-", f"ppl={ppl}"]
@@ -409,20 +412,27 @@ def batched_leg(n_inst, reps):
                           "candidates_ms": {f"k{c[0]}_w{c[1]}_ppl{c[2]}": round(t * 1e3, 3) for c, t in table}},
             "ms_graph_step": ms_graph, "paths_steps_per_s": path_steps / (ms_graph * 1e-3),
             "ms_one_context_at_a_time": ms_seq, "speedup": ms_seq / ms_graph,
-            "roofline": batched_roofline(path_steps, ms_graph)}
+            "roofline": batched_roofline(path_steps, ms_graph, best[0])}
 
 
-def batched_roofline(path_steps, ms_step):
+def batched_roofline(path_steps, ms_step, ckpt_every):
     """Issue-slot roofline of one captured batched step (pass 1 storing
-    checkpoints and pass 2 from them over every instance): the Heston cost
-    model's F + (F + R) slots per path-step over the whole step's time."""
+    checkpoints and pass 2 from them over every instance): the slots per
+    path-step of both persistent kernels, counted with SQ counters, over the
+    whole step's time (the cost model's F + (F + R) when no count is
+    committed for these sources)."""
     from paper_1901_04200_amd import roofline
-    slots = roofline.slots(roofline.per_path_step("heston", "pass1")) + \
+    s1 = counted_slots("batch", "pass1", ckpt_every, "-", BATCH_VALU_PROFILE)
+    s2 = counted_slots("batch", "pass2", ckpt_every, "-", BATCH_VALU_PROFILE)
+    counted = s1 is not None and s2 is not None
+    slots = s1 + s2 if counted else roofline.slots(roofline.per_path_step("heston", "pass1")) + \
         roofline.slots(roofline.per_path_step("heston", "pass2"))
     achieved = slots * path_steps / (ms_step * 1e-3) * 1e-12
     return {"bound": "alu", "kernel": "k_batch_pass1 + k_batch_pass2 (whole step)", "achieved": achieved,
             "peak": roofline.PEAK_SLOTS * 1e-12, "unit": "T VALU lane-slots/s",
-            "frac": achieved / (roofline.PEAK_SLOTS * 1e-12), "slots_per_path_step": slots}
+            "frac": achieved / (roofline.PEAK_SLOTS * 1e-12), "slots_per_path_step": slots,
+            "work": "VALU issue slots per path-step counted with SQ counters" if counted
+            else "VALU issue slots per path-step of the cost model"}
 
 
 def copy_probe(nbytes):
