@@ -835,7 +835,10 @@ struct WeightCopies {
 // Adam with the learning rate and step count read on the device, each
 // updated product weight written to its bf16 copies at once; the workgroup
 // that finishes last (a counter of finished workgroups, reset by it) advances
-// the step count, after every workgroup has read it.
+// the step count, after every workgroup has read it.  A grid of at most
+// kAdamGroups workgroups strides over the parameters, so that few workgroups
+// meet at the counter.
+constexpr int kAdamGroups = 128;
 __global__ __launch_bounds__(kThreads) void k_adam_dev(float *__restrict__ p, const float *__restrict__ g,
                                                        float *__restrict__ m, float *__restrict__ v, int64_t n,
                                                        const float *__restrict__ lr_p, float b1, float b2, float eps,
@@ -843,10 +846,9 @@ __global__ __launch_bounds__(kThreads) void k_adam_dev(float *__restrict__ p, co
                                                        WeightCopies wc)
 {
     __shared__ bool last;
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const float t = (float)t_p[0], lr = lr_p[0];
-    if (i < n) {
-        const float bc1 = 1.f - powf(b1, t), bc2 = 1.f - powf(b2, t);
+    const float bc1 = 1.f - powf(b1, t), bc2 = 1.f - powf(b2, t);
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
         const float gi = g[i];
         const float mi = b1 * m[i] + (1.f - b1) * gi;
         const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
@@ -1156,6 +1158,13 @@ struct mlp_ctx {
     float *split = nullptr;       // kMaxSplits x H x H, or row-chunk partials of the column sums
     double *lossp = nullptr;
     unsigned *done = nullptr;     // finished-workgroup counter of k_adam_dev (zero between launches)
+    // fused path: the weight and bias gradients of the layers above the one the
+    // backward sweep is in run on a second stream (they are off its critical
+    // path), with buffers of their own
+    float *gsplit = nullptr;      // kMaxSplits x H x H: that stream's split-K and column-sum partials
+    float *rpart[2] = {nullptr};  // (Bmax / 32) x H: column partials of the hidden layers' bias adjoints
+    hipStream_t side = nullptr;   // default priority, non-blocking
+    hipEvent_t ev[4] = {nullptr};
     std::vector<void *> allocs;
     std::string err;
 };
@@ -1208,19 +1217,22 @@ static hipError_t launch_gemm(bool akc, bool bkc, const uint16_t *A, int lda, co
 
 // out[j] = sum over the B rows of X (leading dimension ld) of column j < ncols,
 // through c->split (nchunk x ncols partials), deterministic order.
-static void colsum(mlp_ctx *c, const float *X, int B, int ld, int ncols, float *out, hipStream_t st)
+static void colsum(float *part, const float *X, int B, int ld, int ncols, float *out, hipStream_t st)
 {
     const int nchunk = B / kChunk;
     hipLaunchKernelGGL(k_colsum_part, dim3(nchunk, (ncols + kThreads - 1) / kThreads), dim3(kThreads), 0, st, X, ld,
-                       ncols, c->split);
+                       ncols, part);
     hipLaunchKernelGGL(k_chunk_reduce, dim3((ncols + kThreads / 8 - 1) / (kThreads / 8)), dim3(kThreads), 0, st,
-                       c->split, nchunk, ncols, out);
+                       part, nchunk, ncols, out);
 }
 
 extern "C" int mlp_destroy(mlp_ctx *c)
 {
     if (!c) return 0;
     (void)hipDeviceSynchronize();
+    for (hipEvent_t ev : c->ev)
+        if (ev) (void)hipEventDestroy(ev);
+    if (c->side) (void)hipStreamDestroy(c->side);
     for (void *p : c->allocs) (void)hipFree(p);
     delete c;
     return 0;
@@ -1284,6 +1296,10 @@ extern "C" int mlp_create(int32_t n_in, int32_t n_hidden, int32_t n_out, int32_t
     A((void **)&c->split, 4 * std::max((int64_t)kMaxSplits * H * H, (int64_t)(c->Bmax / kChunkL1) * (n_in + 1) * H));
     A((void **)&c->lossp, 8 * (int64_t)((c->Bmax * kOutPad + kThreads - 1) / kThreads));
     A((void **)&c->done, 256);
+    A((void **)&c->gsplit, 4 * std::max((int64_t)kMaxSplits * H * H, (int64_t)(c->Bmax / kChunk) * kOutPad));
+    for (int i = 0; i < 2; ++i) A((void **)&c->rpart[i], 4 * (int64_t)(c->Bmax / 32) * H);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking);
+    for (int i = 0; i < 4 && e == hipSuccess; ++i) e = hipEventCreateWithFlags(&c->ev[i], hipEventDisableTiming);
     if (e != hipSuccess) {
         mlp_destroy(c);
         return mfail(nullptr, -2, std::string("allocation failed: ") + hipGetErrorString(e));
@@ -1508,11 +1524,19 @@ extern "C" int mlp_forward(mlp_ctx *c, const float *d_theta, int32_t B, float *d
 // order reduction), the bias gradient (workgroup column partials, fixed-order
 // reduction) and the next layer's input adjoint fused with the activation
 // adjoint; layer 1's gradients from the last product's epilogue.
+// The backward sweep (layer adjoints, top down) runs on st; the weight and
+// bias gradients of each layer, which nothing later in the sweep reads, run
+// on c->side as soon as their layer's adjoints exist: fork at events ev[0..2],
+// join at ev[3] before returning, so that all work is complete in st's order.
+// Every buffer one stream writes while the other may read it is its own, and
+// each gradient is reduced by the same kernels in the same order as on one
+// stream, so the results do not depend on how the two overlap.
 static hipError_t loss_grad_fused(mlp_ctx *c, const float *th, const float *Ylab, const float *Jlab, const float *jw,
                                   const int32_t *idx, int B, float w, double *loss, float *g, hipStream_t st)
 {
     const int H = c->H, nin = c->nin, NR = nin + 1, R = NR * B;
     const int nwg = B / 32;   // workgroups (32 samples each) along the batch
+    hipStream_t sd = c->side;
     hipError_t e = forward_fused(c, th, idx, B, B, false, st);
     if (e == hipSuccess) e = launch_gemm(true, true, c->A[3], H, c->WT[3], H, c->Z[4], kOutPad, R, kOutPad, H, 1, st);
     if (e != hipSuccess) return e;
@@ -1520,14 +1544,18 @@ static hipError_t loss_grad_fused(mlp_ctx *c, const float *th, const float *Ylab
     const unsigned nlb = nb((int64_t)B * kOutPad);
     hipLaunchKernelGGL(k_loss, dim3(nlb), dim3(kThreads), 0, st, c->Z[4], c->p + c->off[7], Ylab, Jlab, jw, idx, B, nin,
                        c->nout, w, c->in_scale, c->out_shift, c->out_scale, c->G4, c->ZbarP, c->lossp);
-    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(kThreads), 0, st, c->lossp, (int)nlb, loss);
-    colsum(c, c->ZbarP, B, kOutPad, c->nout, g + c->off[7], st);
     const int S = std::min(kMaxSplits, std::max(1, R / 512));
-    // output layer: W4bar = A3^T G4, then H3bar = G4 W4^T with layer 3's activation adjoint
-    e = launch_gemm(false, false, c->A[3], H, c->G4, kOutPad, c->split, kOutPad, H, kOutPad, R, S, st);
+    // side: the loss, b4bar and W4bar = A3^T G4
+    if ((e = hipEventRecord(c->ev[0], st)) != hipSuccess || (e = hipStreamWaitEvent(sd, c->ev[0], 0)) != hipSuccess)
+        return e;
+    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(kThreads), 0, sd, c->lossp, (int)nlb, loss);
+    colsum(c->gsplit, c->ZbarP, B, kOutPad, c->nout, g + c->off[7], sd);
+    e = launch_gemm(false, false, c->A[3], H, c->G4, kOutPad, c->gsplit, kOutPad, H, kOutPad, R, S, sd);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_split_reduce, dim3(nb((int64_t)H * c->nout * 8)), dim3(kThreads), 0, st, c->split, S, H,
+    hipLaunchKernelGGL(k_split_reduce, dim3(nb((int64_t)H * c->nout * 8)), dim3(kThreads), 0, sd, c->gsplit, S, H,
                        kOutPad, g + c->off[6], c->nout, c->nout);
+    // hidden layers 3 and 2: H_l bar = (adjoint above) W_{l+1}^T with layer l's
+    // activation adjoint in the epilogue (st); then b_l bar and W_l bar (side)
     const uint16_t *adj = c->G4;   // the adjoint of the layer above's input
     int kadj = kOutPad;
     uint16_t *zb[2] = {c->Zbar, c->Zbar2};
@@ -1541,20 +1569,23 @@ static hipError_t loss_grad_fused(mlp_ctx *c, const float *th, const float *Ylab
         b.Zp_in = c->Z[l];
         b.U_in = c->U[l];
         b.Zbar = zb[l & 1];
-        b.part = c->split;
+        b.part = c->rpart[l & 1];
         e = launch_rows(NR, kEpiActBwd, b, st);
         if (e != hipSuccess) break;
-        hipLaunchKernelGGL(k_chunk_reduce, dim3((H + kThreads / 8 - 1) / (kThreads / 8)), dim3(kThreads), 0, st,
-                           c->split, nwg, H, g + c->off[2 * l - 1]);
-        e = launch_gemm(false, false, c->A[l - 1], H, zb[l & 1], H, c->split, H, H, H, R, S, st);
+        if ((e = hipEventRecord(c->ev[4 - l], st)) != hipSuccess ||
+            (e = hipStreamWaitEvent(sd, c->ev[4 - l], 0)) != hipSuccess)
+            break;
+        hipLaunchKernelGGL(k_chunk_reduce, dim3((H + kThreads / 8 - 1) / (kThreads / 8)), dim3(kThreads), 0, sd,
+                           c->rpart[l & 1], nwg, H, g + c->off[2 * l - 1]);
+        e = launch_gemm(false, false, c->A[l - 1], H, zb[l & 1], H, c->gsplit, H, H, H, R, S, sd);
         if (e != hipSuccess) break;
-        hipLaunchKernelGGL(k_split_reduce, dim3(nb((int64_t)H * H * 8)), dim3(kThreads), 0, st, c->split, S, H, H,
+        hipLaunchKernelGGL(k_split_reduce, dim3(nb((int64_t)H * H * 8)), dim3(kThreads), 0, sd, c->gsplit, S, H, H,
                            g + c->off[2 * l - 2], H, H);
         adj = zb[l & 1];
         kadj = H;
     }
     if (e != hipSuccess) return e;
-    // layer 1: H1bar = Zbar2 W2^T, reduced in the epilogue to column partials of W1bar and b1bar
+    // layer 1: H1bar = Zbar W2^T, reduced in the epilogue to column partials of W1bar and b1bar
     RowsArgs d{};
     d.A = adj;
     d.W = c->Wb[1];
@@ -1570,7 +1601,9 @@ static hipError_t loss_grad_fused(mlp_ctx *c, const float *th, const float *Ylab
     const int nout1 = NR * H;   // W1bar (nin rows) and b1bar are contiguous in the gradient
     hipLaunchKernelGGL(k_chunk_reduce, dim3((nout1 + kThreads / 8 - 1) / (kThreads / 8)), dim3(kThreads), 0, st,
                        c->split, nwg, nout1, g + c->off[0]);
-    return hipGetLastError();
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if ((e = hipEventRecord(c->ev[3], sd)) != hipSuccess) return e;
+    return hipStreamWaitEvent(st, c->ev[3], 0);
 }
 
 extern "C" int mlp_loss_grad(mlp_ctx *c, const float *d_theta, const float *d_Ylab, const float *d_Jlab,
@@ -1595,7 +1628,7 @@ extern "C" int mlp_loss_grad(mlp_ctx *c, const float *d_theta, const float *d_Yl
     hipLaunchKernelGGL(k_loss, dim3(nlb), dim3(kThreads), 0, st, c->Z[4], c->p + c->off[7], d_Ylab, d_Jlab, d_jw,
                        d_idx, B, nin, c->nout, w, c->in_scale, c->out_shift, c->out_scale, c->G4, c->ZbarP, c->lossp);
     hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(kThreads), 0, st, c->lossp, (int)nlb, d_loss);
-    colsum(c, c->ZbarP, B, kOutPad, c->nout, g + c->off[7], st);
+    colsum(c->split, c->ZbarP, B, kOutPad, c->nout, g + c->off[7], st);
     // output layer: W4bar = A3^T G4 (split over rows), H3bar = G4 W4^T
     const int S = std::min(kMaxSplits, std::max(1, R / 512));
     e = launch_gemm(false, false, c->A[3], H, c->G4, kOutPad, c->split, kOutPad, H, kOutPad, R, S, st);
@@ -1608,7 +1641,7 @@ extern "C" int mlp_loss_grad(mlp_ctx *c, const float *d_theta, const float *d_Yl
     for (int l = 3; l >= 2 && e == hipSuccess; --l) {
         hipLaunchKernelGGL(k_act_bwd, dim3(nb((int64_t)B * H)), dim3(kThreads), 0, st, c->Hbar, c->Z[l], B, nin, H,
                            c->Zbar, c->ZbarP);
-        colsum(c, c->ZbarP, B, H, H, g + c->off[2 * l - 1], st);
+        colsum(c->split, c->ZbarP, B, H, H, g + c->off[2 * l - 1], st);
         e = launch_gemm(false, false, c->A[l - 1], H, c->Zbar, H, c->split, H, H, H, R, S, st);
         if (e != hipSuccess) break;
         hipLaunchKernelGGL(k_split_reduce, dim3(nb((int64_t)H * H * 8)), dim3(kThreads), 0, st, c->split, S, H, H,
@@ -1657,8 +1690,8 @@ extern "C" int mlp_adam_step_dev(mlp_ctx *c, const float *d_grad, const float *d
         wc.WT[k] = c->WT[l - 1];
         wc.Wb[k] = c->Wb[l - 1];
     }
-    hipLaunchKernelGGL(k_adam_dev, dim3(nb(c->np)), dim3(kThreads), 0, st, c->p, d_grad, c->m, c->v, c->np, d_lr, beta1,
-                       beta2, eps, d_t, c->done, wc);
+    hipLaunchKernelGGL(k_adam_dev, dim3(std::min<unsigned>(nb(c->np), kAdamGroups)), dim3(kThreads), 0, st, c->p,
+                       d_grad, c->m, c->v, c->np, d_lr, beta1, beta2, eps, d_t, c->done, wc);
     hipError_t e = hipGetLastError();
     return e == hipSuccess ? 0 : mfail(c, -3, hipGetErrorString(e));
 }

@@ -262,20 +262,18 @@ def fit(net: MLP, theta, Y, J, *, epochs: int, batch: int = 4096, lr: float = 1e
     g.manual_seed(seed)
     dev = net.dev
     grad = torch.empty(net.n_params, dtype=torch.float32, device=dev)
-    loss = torch.empty(1, dtype=torch.float64, device=dev)
     perm_dev = torch.empty(n, dtype=torch.int32, device=dev)
     lr_host = torch.empty(1, dtype=torch.float32, pin_memory=True)
     lr_dev = torch.empty(1, dtype=torch.float32, device=dev)
     t_dev = torch.full((1,), net.step_count + 1, dtype=torch.int32, device=dev)
-    tot = torch.zeros(1, dtype=torch.float64, device=dev)   # summed on the device: no sync per step
+    losses = torch.zeros(steps_per_epoch, dtype=torch.float64, device=dev)   # one slot per step: no sync
     theta, Y, J = theta.contiguous(), Y.contiguous(), J.contiguous()
     jw = None if jw is None else jw.contiguous()
 
     def epoch():
         for s in range(steps_per_epoch):
-            net.loss_grad(theta, Y, J, w, grad, loss, jw=jw, idx=perm_dev[s * batch:(s + 1) * batch])
+            net.loss_grad(theta, Y, J, w, grad, losses[s:s + 1], jw=jw, idx=perm_dev[s * batch:(s + 1) * batch])
             net.adam_step_dev(grad, lr_dev, t_dev)
-            tot.add_(loss)
 
     hist = []
     t0 = time.perf_counter()
@@ -286,7 +284,6 @@ def fit(net: MLP, theta, Y, J, *, epochs: int, batch: int = 4096, lr: float = 1e
         perm_dev.copy_(torch.randperm(n, generator=g).to(torch.int32))
         lr_host[0] = lr_e
         lr_dev.copy_(lr_host, non_blocking=True)
-        tot.zero_()
         if graph and ep >= 1:
             if cg is None:
                 torch.cuda.synchronize()
@@ -297,7 +294,7 @@ def fit(net: MLP, theta, Y, J, *, epochs: int, batch: int = 4096, lr: float = 1e
         else:
             epoch()
         if (ep % log_every == 0) or ep == epochs - 1:
-            hist.append(TrainLog(ep, float(tot.item()) / steps_per_epoch, time.perf_counter() - t0))
+            hist.append(TrainLog(ep, float(losses.sum().item()) / steps_per_epoch, time.perf_counter() - t0))
     torch.cuda.synchronize()
     net.step_count += epochs * steps_per_epoch
     return hist
