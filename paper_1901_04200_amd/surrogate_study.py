@@ -206,8 +206,14 @@ def train_surrogate(pb, n_train, train_paths, epochs, batch=4096, lr=2e-3, lr_fi
     # blocks (the 5x256 first layer is elementwise)
     rows = 6 * min(batch, n_train)
     flops = 3 * 2 * rows * (2 * 256 * 256 + 256 * pb.n_instr)
+    # epochs after the second logged one replay the captured epoch: their rate
+    # is the steady training step (the first epoch runs eagerly, the second is captured)
+    spe = n_train // min(batch, n_train)
+    replay = None
+    if len(hist) >= 3 and hist[-1].epoch > hist[1].epoch:
+        replay = (hist[-1].seconds - hist[1].seconds) / ((hist[-1].epoch - hist[1].epoch) * spe) * 1e3
     out["training"] = {"epochs": epochs, "seconds": t_fit, "loss_first": hist[0].loss, "loss_last": hist[-1].loss,
-                       "steps": steps, "gemm_flop_per_step": flops,
+                       "steps": steps, "ms_per_step_replayed": replay, "gemm_flop_per_step": flops,
                        "gemm_tflops": flops * steps / t_fit * 1e-12,
                        "bf16_peak_frac": flops * steps / t_fit / 2.5e15}
     log(f"surrogate: {epochs} epochs in {t_fit:.2f} s, loss {hist[0].loss:.4g} -> {hist[-1].loss:.4g}")
