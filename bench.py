@@ -162,6 +162,52 @@ def valu_issue_utilisation(ckpt_every):
     return value if ok else None
 
 
+FLOPS_PROFILE = os.path.join(ROOT, "profiles", "mc_kernels_heston_2p20x256_fp32_flops.md")
+
+
+def counted_flops(ckpt_every, path_steps, ms_pass2):
+    """FP32 flops of the Heston pass-2 kernel counted with SQ counters (adds,
+    multiplies and transcendentals one each, FMAs two, over 64 lanes) per
+    path-step, from the committed counter summary, and what they give over
+    the kernel's average duration against 157.3 TFLOP/s (the packed-FP32
+    peak) and 78.6 TFLOP/s (one FP32 operation per lane and cycle); None
+    when not taken or stale."""
+    from paper_1901_04200_amd import roofline
+    try:
+        lines = open(FLOPS_PROFILE).read().splitlines()
+    except OSError:
+        return None
+    value, ok = None, True
+    for ln in lines:
+        f = ln.split()
+        if len(f) == 4 and f[0] == "fp32_flops_per_path_step" and f[1:3] == ["k_pass2", f"K={ckpt_every}"]:
+            value = float(f[3])
+        elif len(f) == 3 and f[0] == "code-sha256":
+            ok = ok and os.path.exists(os.path.join(ROOT, f[1])) and code_hash(os.path.join(ROOT, f[1])) == f[2]
+    if value is None or not ok:
+        return None
+    tf = value * path_steps / (ms_pass2 * 1e-3) * 1e-12
+    return {"flops_per_path_step": value, "achieved_tflops": tf, "frac": tf / roofline.PEAK_FP32_TFLOPS,
+            "frac_nonpacked": tf / (roofline.PEAK_FP32_TFLOPS / 2)}
+
+
+def device_info():
+    """Name, architecture and compute units of device 0, and the clock the
+    runtime reports for it."""
+    import torch
+    pr = torch.cuda.get_device_properties(0)
+    info = {"name": pr.name, "arch": getattr(pr, "gcnArchName", None), "compute_units": pr.multi_processor_count}
+    try:
+        import ctypes
+        hip = ctypes.CDLL("libamdhip64.so")
+        v = ctypes.c_int(0)
+        if hip.hipDeviceGetAttribute(ctypes.byref(v), 5, 0) == 0:   # hipDeviceAttributeClockRate (kHz)
+            info["clock_khz"] = v.value
+    except OSError:
+        pass
+    return info
+
+
 GRID_VALU_PROFILE = os.path.join(ROOT, "profiles", "grid_kernels_valu_mix.md")
 
 
@@ -450,7 +496,9 @@ def copy_probe(nbytes):
 def timed_gradient(mc, theta_np, C, steps, warmup):
     """Time `steps` calibrate_gradient calls and `steps` calibrate_forward
     calls on one context (inputs resident on the device); returns the
-    timings, the library's per-pass kernel averages and the last outputs."""
+    timings, the library's per-pass kernel averages, the last outputs and
+    the spread of single steps (another `steps` steps, each between its own
+    events)."""
     import numpy as np
     import torch
     from paper_1901_04200_amd import capi
@@ -494,9 +542,19 @@ def timed_gradient(mc, theta_np, C, steps, warmup):
     ms_fwd = ev0.elapsed_time(ev1) / steps
     f_ms, f_n = capi.cal_timing_read(ctx, 0)
     capi.cal_timing_enable(ctx, False)
+    # the spread of single steps: each step of another `steps` bracketed by its own events
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    for a, b in evs:
+        a.record()
+        grad_step()
+        b.record()
+    torch.cuda.synchronize()
+    one = sorted(a.elapsed_time(b) for a, b in evs)
+    stats = {"n": steps, "median": float(np.median(one)), "min": one[0], "max": one[-1]}
     status = mc.status()
     return {"ms_step": ms_step, "wall": wall, "ms_fwd": ms_fwd, "pass1_avg": p1_ms / max(p1_n, 1),
-            "pass2_avg": p2_ms / max(p2_n, 1), "t_f": f_ms / max(f_n, 1), "status": status, "got": got}
+            "pass2_avg": p2_ms / max(p2_n, 1), "t_f": f_ms / max(f_n, 1), "status": status, "got": got,
+            "step_stats": stats}
 
 
 def theta0_leg(pb, th0, C, ckpt_every, ppl, steps, warmup):
@@ -629,6 +687,8 @@ def main():
             "tuning_ms": None if tune_table is None else {f"k{k}_ppl{q}": t * 1e3 for (k, q), t in tune_table},
             "threads_per_block": geo["threads"], "blocks": geo["blocks"],
         },
+        "ms_per_step_single": r["step_stats"],
+        "device": device_info(),
         "forward_value": path_steps / (r["ms_fwd"] * 1e-3),
         "ms_forward": r["ms_fwd"],
         "ms_pass1_kernel": r["pass1_avg"],
@@ -651,6 +711,7 @@ def main():
             "issue_slots_per_path_step": roofline.slots(w2),
             "issue_frac_cost_model": slots_frac,
             "issue_frac_counters": valu_issue_utilisation(geo["ckpt_every"]),
+            "counted_fp32": counted_flops(geo["ckpt_every"], path_steps, pass2_avg),
             "traffic": pass2_traffic(geo["ckpt_every"], ppl),
             "traffic_unit": "HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-scaled)",
             "traffic_algorithmic": roofline.pass2_bytes(pb.n_paths, geo["ckpt_every"], geo["blocks"], pb.n_instr,
