@@ -58,6 +58,7 @@ struct cal_ctx {
     int32_t *d_status = nullptr;
     double *d_part_y = nullptr;
     double *d_part_g = nullptr;
+    void *d_lv_rows = nullptr;     // local volatility: [N][nK] grid rows of pass 2 (path precision)
     double *d_part_j = nullptr;
     void *d_lamD = nullptr;
     void *d_ckpt = nullptr;
@@ -225,7 +226,8 @@ extern "C" int cal_destroy(cal_ctx *ctx)
     (void)hipDeviceSynchronize();
     void *bufs[] = {ctx->d_date_step, ctx->d_date_begin, ctx->d_strike, ctx->d_strike_f, ctx->d_disc, ctx->d_id,
                     ctx->d_status, ctx->d_part_y, ctx->d_part_g, ctx->d_part_j, ctx->d_lamD, ctx->d_ckpt,
-                    ctx->d_theta_ckpt, ctx->d_t_nodes, ctx->d_step_row, ctx->d_step_al, ctx->d_step_al_f};
+                    ctx->d_theta_ckpt, ctx->d_t_nodes, ctx->d_step_row, ctx->d_step_al, ctx->d_step_al_f,
+                    ctx->d_lv_rows};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
     for (auto &t : ctx->timed) {
@@ -308,7 +310,9 @@ extern "C" int cal_create(const cal_problem *pb, cal_ctx **out)
     A((void **)&c->d_id, sizeof(int32_t) * m);
     A((void **)&c->d_status, sizeof(int32_t));
     A((void **)&c->d_part_y, sizeof(double) * (size_t)c->nblocks * m);
-    A((void **)&c->d_part_g, sizeof(double) * (size_t)c->nblocks * c->M);
+    // local volatility: two partial columns per node (see launch_lv_reduce)
+    A((void **)&c->d_part_g, sizeof(double) * (size_t)c->nblocks * c->M * (c->model == CAL_LV ? 2 : 1));
+    if (c->model == CAL_LV) A(&c->d_lv_rows, c->real * (size_t)c->N * pb->n_k_nodes);
     A((void **)&c->d_part_j, sizeof(double) * (size_t)c->nblocks_tan * tan_w * c->max_batch);
     A(&c->d_lamD, c->real * m);
     A((void **)&c->d_theta_ckpt, sizeof(double) * c->M);
@@ -503,17 +507,28 @@ static int run_pass1(cal_ctx *c, const double *theta, bool store, hipStream_t st
     return CAL_OK;
 }
 
+// dG/dtheta from pass 2's partial columns
+static hipError_t reduce_grad(cal_ctx *c, double *d_grad, hipStream_t st)
+{
+    if (c->model == CAL_LV) return launch_lv_reduce(c->d_part_g, c->nblocks, c->M, d_grad, c->d_status, st);
+    return launch_reduce_sorted(c->d_part_g, c->nblocks, c->M, nullptr, 1.0, d_grad, c->d_status, st);
+}
+
 static int run_pass2(cal_ctx *c, const double *theta, bool from_ckpt, hipStream_t st)
 {
     Timed t(c, st, 1);
-    hipError_t e = c->model == CAL_LV
-                       ? launch_lv_pass2(c->dp, c->fp64, from_ckpt, theta, c->d_lamD, c->d_part_g, c->d_ckpt,
-                                         c->nblocks, st)
-                   : c->model == CAL_SLV
-                       ? launch_slv_pass2(c->dp, c->fp64, from_ckpt, theta, c->d_lamD, c->d_part_g, c->d_ckpt,
-                                          c->nblocks, st)
-                       : launch_pass2(c->dp, c->model, c->fp64, from_ckpt, theta, c->d_lamD, c->d_part_g, c->d_ckpt,
-                                      c->nblocks, st);
+    hipError_t e;
+    if (c->model == CAL_LV) {
+        e = launch_lv_rows(c->dp, c->fp64, theta, c->d_lv_rows, st);
+        if (e == hipSuccess)
+            e = launch_lv_pass2(c->dp, c->fp64, from_ckpt, theta, c->d_lv_rows, c->d_lamD, c->d_part_g, c->d_ckpt,
+                                c->nblocks, st);
+    } else if (c->model == CAL_SLV) {
+        e = launch_slv_pass2(c->dp, c->fp64, from_ckpt, theta, c->d_lamD, c->d_part_g, c->d_ckpt, c->nblocks, st);
+    } else {
+        e = launch_pass2(c->dp, c->model, c->fp64, from_ckpt, theta, c->d_lamD, c->d_part_g, c->d_ckpt, c->nblocks,
+                         st);
+    }
     t.done();
     if (e != hipSuccess) return hip_fail(c, e, "pass-2 launch");
     return CAL_OK;
@@ -568,7 +583,7 @@ static int vjp(cal_ctx *ctx, const double *d_theta, const double *d_lambda, doub
     int rc = run_pass2(ctx, d_theta, from_ckpt, st);
     if (rc) return rc;
     if (!from_ckpt) ctx->ckpt_valid = true;   // the re-run wrote every segment
-    e = launch_reduce_sorted(ctx->d_part_g, ctx->nblocks, ctx->M, nullptr, 1.0, d_grad, ctx->d_status, st);
+    e = reduce_grad(ctx, d_grad, st);
     if (e != hipSuccess) return hip_fail(ctx, e, "reduce launch");
     return CAL_OK;
 }
@@ -607,7 +622,7 @@ extern "C" int calibrate_gradient(cal_ctx *ctx, const double *d_theta, const dou
     rc = run_pass2(ctx, d_theta, store, st);
     if (rc) return rc;
     ctx->ckpt_valid = true;   // either pass wrote every segment
-    e = launch_reduce_sorted(ctx->d_part_g, ctx->nblocks, ctx->M, nullptr, 1.0, d_grad, ctx->d_status, st);
+    e = reduce_grad(ctx, d_grad, st);
     if (e != hipSuccess) return hip_fail(ctx, e, "reduce launch");
     return CAL_OK;
 }

@@ -91,8 +91,18 @@ int batch_blocks_per_cu(int model, bool fp64, int K, int max_m);
 // Local-volatility passes (lv_kernels.hip).
 hipError_t launch_lv_pass1(const DevProblem &pb, bool fp64, bool store_ckpt, const double *theta, double *partial,
                            void *ckpt, int64_t nblocks, hipStream_t stream);
-hipError_t launch_lv_pass2(const DevProblem &pb, bool fp64, bool from_ckpt, const double *theta, const void *lamD,
-                           double *partial, void *ckpt, int64_t nblocks, hipStream_t stream);
+// rows [N][nK] (path precision): the grid interpolated in time at every step,
+// from launch_lv_rows; partial: 2 nT nK columns of nblocks (see launch_lv_reduce)
+hipError_t launch_lv_pass2(const DevProblem &pb, bool fp64, bool from_ckpt, const double *theta, const void *rows,
+                           const void *lamD, double *partial, void *ckpt, int64_t nblocks, hipStream_t stream);
+// rows[n][k] = (1 - al_n) theta[a_n][k] + al_n theta[a_n + 1][k], n < N, k < nK
+hipError_t launch_lv_rows(const DevProblem &pb, bool fp64, const double *theta, void *rows, hipStream_t stream);
+// pass 2 stores each node's FP64 sums in two partial columns per workgroup
+// (the node row's own time cell and the cell below it):
+// out[k] = sum over workgroups b of (partial[k][b] + partial[M + k][b]),
+// k < M = nT nK, in a fixed order; status bit 2 for a non-finite sum
+hipError_t launch_lv_reduce(const double *partial, int64_t nblocks, int32_t M, double *out, int32_t *status,
+                            hipStream_t stream);
 size_t lv_lds_bytes(const DevProblem &pb, bool fp64, int pass);
 
 // Heston stochastic local volatility passes (slv_kernels.hip).
