@@ -497,11 +497,16 @@ static int run_pass1(cal_ctx *c, const double *theta, bool store, hipStream_t st
         if (ec != hipSuccess) return hip_fail(c, ec, "theta check launch");
     }
     Timed t(c, st, 0);
-    hipError_t e =
-        c->model == CAL_LV    ? launch_lv_pass1(c->dp, c->fp64, store, theta, c->d_part_y, c->d_ckpt, c->nblocks, st)
-        : c->model == CAL_SLV ? launch_slv_pass1(c->dp, c->fp64, store, theta, c->d_part_y, c->d_ckpt, c->nblocks, st)
-                              : launch_pass1(c->dp, c->model, c->fp64, store, theta, c->d_part_y, c->d_ckpt,
-                                             c->nblocks, st);
+    hipError_t e;
+    if (c->model == CAL_LV) {
+        e = launch_lv_rows(c->dp, c->fp64, theta, c->d_lv_rows, st);
+        if (e == hipSuccess)
+            e = launch_lv_pass1(c->dp, c->fp64, store, theta, c->d_lv_rows, c->d_part_y, c->d_ckpt, c->nblocks, st);
+    } else if (c->model == CAL_SLV) {
+        e = launch_slv_pass1(c->dp, c->fp64, store, theta, c->d_part_y, c->d_ckpt, c->nblocks, st);
+    } else {
+        e = launch_pass1(c->dp, c->model, c->fp64, store, theta, c->d_part_y, c->d_ckpt, c->nblocks, st);
+    }
     t.done();
     if (e != hipSuccess) return hip_fail(c, e, "pass-1 launch");
     return CAL_OK;

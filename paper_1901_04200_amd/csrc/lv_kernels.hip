@@ -33,22 +33,6 @@ __device__ __forceinline__ R exp_t(R x)
     else return exp(x);
 }
 
-// LDS carve-up of pass 1: [payoff sums: double [waves][m]][rows: R K*nK]
-template <typename R>
-struct LvLds {
-    double *dbl;
-    R *rows;
-};
-
-template <typename R>
-__device__ LvLds<R> carve(const DevProblem &pb, unsigned char *base, int ndbl)
-{
-    LvLds<R> L;
-    L.dbl = (double *)base;
-    L.rows = (R *)(base + sizeof(double) * ndbl);
-    return L;
-}
-
 // time weight al_n of step n in the path precision (host table, uniform)
 template <typename R>
 __device__ __forceinline__ R step_al(const DevProblem &pb, int n)
@@ -57,49 +41,12 @@ __device__ __forceinline__ R step_al(const DevProblem &pb, int n)
     else return ldc(pb.step_al, n);
 }
 
-// the time-interpolated rows of steps n0 .. n0 + K - 1 (those < N) into the
-// window, row n at L.rows + (n - n0) * nK; every thread calls it (uniform)
-template <typename R>
-__device__ void build_window(const DevProblem &pb, const double *theta, LvLds<R> &L, int n0)
-{
-    const int tid = threadIdx.x;
-    __syncthreads();   // the previous window is no longer read
-    const int total = pb.K * pb.nK;
-    for (int i = tid; i < total; i += kBlock) {
-        const int n = n0 + i / pb.nK, k = i % pb.nK;
-        if (n < pb.N) {
-            const int a = pb.step_row[n];
-            const double al = (double)step_al<R>(pb, n);
-            L.rows[i] = (R)((1.0 - al) * theta[a * pb.nK + k] + al * theta[(a + 1) * pb.nK + k]);
-        }
-    }
-    __syncthreads();
-}
-
 template <typename R>
 struct Cell {
     int b;
     R be, r0, r1, sig;
     bool inside;
 };
-
-template <typename R>
-__device__ __forceinline__ Cell<R> locate(const DevProblem &pb, const R *row, R S, R K0, R invdK, R Klast)
-{
-    Cell<R> c;
-    const R u = (S - K0) * invdK;
-    int b = (int)floor(u);
-    b = b < 0 ? 0 : (b > pb.nK - 2 ? pb.nK - 2 : b);
-    R be = u - (R)b;
-    be = be < (R)0 ? (R)0 : (be > (R)1 ? (R)1 : be);
-    c.b = b;
-    c.be = be;
-    c.r0 = row[b];
-    c.r1 = row[b + 1];
-    c.sig = c.r0 + be * (c.r1 - c.r0);
-    c.inside = S >= K0 && S <= Klast;
-    return c;
-}
 
 // The time-interpolated rows of every step, computed once per launch into a
 // table (the values build_window computes): rows[n][k].
@@ -162,15 +109,28 @@ __device__ __forceinline__ Cell<R> locate_lanes(const DevProblem &pb, R row, R S
     return c;
 }
 
+// Rows 4 c .. 4 c + 3 (the steps of Philox call c) into registers, node
+// `lane` of each, as rows_to_regs.
+template <typename R>
+__device__ __forceinline__ void call_rows(const DevProblem &pb, const R *__restrict__ rows, int c, R (&v)[4])
+{
+    const int k = min((int)(threadIdx.x & (kWave - 1)), pb.nK - 1);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) v[j] = rows[min(4 * c + j, pb.N - 1) * pb.nK + k];
+}
+
 // Pass 1.  A lane runs PPL paths side by side (independent dependency
 // chains, which hide each other's latency): path i of the lane in workgroup
-// blk is (blk * PPL + i) * kBlock + tid.
+// blk is (blk * PPL + i) * kBlock + tid.  The grid rows come from the table
+// into registers (see rows_to_regs), those of the next Philox call loaded
+// while the current one runs; LDS holds the waves' payoff sums.
 template <typename R, bool STORE, int PPL>
 __global__ __launch_bounds__(kBlock) void k_lv_pass1(DevProblem pb, const double *__restrict__ theta,
-                                                     double *__restrict__ partial, R *__restrict__ ckpt)
+                                                     const R *__restrict__ rowtab, double *__restrict__ partial,
+                                                     R *__restrict__ ckpt)
 {
     extern __shared__ __attribute__((aligned(16))) unsigned char lds_raw[];
-    LvLds<R> L = carve<R>(pb, lds_raw, kWavesPerBlock * pb.m);
+    double *sums = reinterpret_cast<double *>(lds_raw);   // [waves][m]
     const int tid = threadIdx.x;
     const int lane = tid & (kWave - 1);
     const int wave = tid / kWave;
@@ -192,12 +152,12 @@ __global__ __launch_bounds__(kBlock) void k_lv_pass1(DevProblem pb, const double
     int next = pb.ndates > 0 ? pb.date_step[0] : -1;
     const int cps = max(pb.K / 4, 1);   // Philox calls per segment (K is a multiple of 4)
     const int ncalls = (pb.N + 3) / 4;
-    int n0 = 0;                         // first step of the current segment and window
+    R rows[4], rows_next[4];
+    call_rows<R>(pb, rowtab, 0, rows);
     for (int call = 0; call < ncalls; ++call) {
-        if (call % cps == 0) {
-            n0 = call * 4;
-            build_window<R>(pb, theta, L, n0);
-            if constexpr (STORE) {
+        call_rows<R>(pb, rowtab, min(call + 1, ncalls - 1), rows_next);
+        if constexpr (STORE) {
+            if (call % cps == 0) {
 #pragma unroll
                 for (int i = 0; i < PPL; ++i)
                     if (active[i]) ckpt[(int64_t)(call / cps) * pb.P + p[i]] = x[i];
@@ -214,7 +174,7 @@ __global__ __launch_bounds__(kBlock) void k_lv_pass1(DevProblem pb, const double
 #pragma unroll
                 for (int i = 0; i < PPL; ++i) {
                     const R S = s0 * exp_t(x[i]);
-                    const Cell<R> c = locate<R>(pb, L.rows + (n - n0) * pb.nK, S, K0, invdK, Klast);
+                    const Cell<R> c = locate_lanes<R>(pb, rows[j], S, K0, invdK, Klast);
                     x[i] = x[i] + (rh - hh * c.sig * c.sig) + (sq * c.sig) * z[i][j];
                 }
                 if (n + 1 == next) {
@@ -222,19 +182,21 @@ __global__ __launch_bounds__(kBlock) void k_lv_pass1(DevProblem pb, const double
                     for (int i = 0; i < PPL; ++i) {
                         const double Sd = (double)(s0 * exp_t(x[i]));
                         payoff_sums(pb.strike, pb.disc, Sd, active[i], lane, pb.date_begin[d], pb.date_begin[d + 1],
-                                    L.dbl + wave * pb.m, i > 0);
+                                    sums + wave * pb.m, i > 0);
                     }
                     ++d;
                     next = d < pb.ndates ? pb.date_step[d] : -1;
                 }
             }
         }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) rows[j] = rows_next[j];
     }
     __syncthreads();
     for (int k = tid; k < pb.m; k += kBlock) {
-        double s = L.dbl[k];
+        double s = sums[k];
 #pragma unroll
-        for (int w = 1; w < kWavesPerBlock; ++w) s += L.dbl[w * pb.m + k];
+        for (int w = 1; w < kWavesPerBlock; ++w) s += sums[w * pb.m + k];
         partial[(int64_t)k * gridDim.x + blockIdx.x] = s;
     }
 }
@@ -501,26 +463,26 @@ __global__ __launch_bounds__(kBlock) void k_lv_pass2(DevProblem pb, const double
 }
 
 template <typename R, int PPL>
-hipError_t pass1_p(const DevProblem &pb, bool store, const double *theta, double *partial, void *ckpt, int64_t nb,
-                   hipStream_t st)
+hipError_t pass1_p(const DevProblem &pb, bool store, const double *theta, const void *rows, double *partial,
+                   void *ckpt, int64_t nb, hipStream_t st)
 {
     const size_t lds = lv_lds_bytes(pb, sizeof(R) == 8, 1);
     if (store)
-        hipLaunchKernelGGL((k_lv_pass1<R, true, PPL>), dim3((unsigned)nb), dim3(kBlock), lds, st, pb, theta, partial,
-                           (R *)ckpt);
+        hipLaunchKernelGGL((k_lv_pass1<R, true, PPL>), dim3((unsigned)nb), dim3(kBlock), lds, st, pb, theta,
+                           (const R *)rows, partial, (R *)ckpt);
     else
         hipLaunchKernelGGL((k_lv_pass1<R, false, PPL>), dim3((unsigned)nb), dim3(kBlock), lds, st, pb, theta,
-                           partial, (R *)ckpt);
+                           (const R *)rows, partial, (R *)ckpt);
     return hipGetLastError();
 }
 
 template <typename R>
-hipError_t pass1_t(const DevProblem &pb, bool store, const double *theta, double *partial, void *ckpt, int64_t nb,
-                   hipStream_t st)
+hipError_t pass1_t(const DevProblem &pb, bool store, const double *theta, const void *rows, double *partial,
+                   void *ckpt, int64_t nb, hipStream_t st)
 {
     switch (pb.ppl) {
-    case 1: return pass1_p<R, 1>(pb, store, theta, partial, ckpt, nb, st);
-    case 2: return pass1_p<R, 2>(pb, store, theta, partial, ckpt, nb, st);
+    case 1: return pass1_p<R, 1>(pb, store, theta, rows, partial, ckpt, nb, st);
+    case 2: return pass1_p<R, 2>(pb, store, theta, rows, partial, ckpt, nb, st);
     default: return hipErrorInvalidValue;
     }
 }
@@ -601,17 +563,15 @@ hipError_t launch_lv_reduce(const double *partial, int64_t nblocks, int32_t M, d
 size_t lv_lds_bytes(const DevProblem &pb, bool fp64, int pass)
 {
     const size_t real = fp64 ? 8 : 4;
-    if (pass == 2) return real * 2 * (size_t)pb.nK * kBlock;   // the node slices only
-    size_t o = sizeof(double) * (size_t)kWavesPerBlock * pb.m;
-    o += real * (size_t)pb.K * pb.nK;
-    return (o + 15) & ~(size_t)15;
+    if (pass == 2) return real * 2 * (size_t)pb.nK * kBlock;   // the node slices
+    return sizeof(double) * (size_t)kWavesPerBlock * pb.m;      // the waves' payoff sums
 }
 
-hipError_t launch_lv_pass1(const DevProblem &pb, bool fp64, bool store, const double *theta, double *partial,
-                           void *ckpt, int64_t nb, hipStream_t st)
+hipError_t launch_lv_pass1(const DevProblem &pb, bool fp64, bool store, const double *theta, const void *rows,
+                           double *partial, void *ckpt, int64_t nb, hipStream_t st)
 {
-    return fp64 ? pass1_t<double>(pb, store, theta, partial, ckpt, nb, st)
-                : pass1_t<float>(pb, store, theta, partial, ckpt, nb, st);
+    return fp64 ? pass1_t<double>(pb, store, theta, rows, partial, ckpt, nb, st)
+                : pass1_t<float>(pb, store, theta, rows, partial, ckpt, nb, st);
 }
 
 hipError_t launch_lv_rows(const DevProblem &pb, bool fp64, const double *theta, void *rows, hipStream_t st)

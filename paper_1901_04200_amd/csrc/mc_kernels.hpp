@@ -89,10 +89,11 @@ hipError_t launch_batch_step(const BatchLaunch &L, hipStream_t st);
 int batch_blocks_per_cu(int model, bool fp64, int K, int max_m);
 
 // Local-volatility passes (lv_kernels.hip).
-hipError_t launch_lv_pass1(const DevProblem &pb, bool fp64, bool store_ckpt, const double *theta, double *partial,
-                           void *ckpt, int64_t nblocks, hipStream_t stream);
 // rows [N][nK] (path precision): the grid interpolated in time at every step,
-// from launch_lv_rows; partial: 2 nT nK columns of nblocks (see launch_lv_reduce)
+// from launch_lv_rows; pass 2's partial: 2 nT nK columns of nblocks (see
+// launch_lv_reduce)
+hipError_t launch_lv_pass1(const DevProblem &pb, bool fp64, bool store_ckpt, const double *theta, const void *rows,
+                           double *partial, void *ckpt, int64_t nblocks, hipStream_t stream);
 hipError_t launch_lv_pass2(const DevProblem &pb, bool fp64, bool from_ckpt, const double *theta, const void *rows,
                            const void *lamD, double *partial, void *ckpt, int64_t nblocks, hipStream_t stream);
 // rows[n][k] = (1 - al_n) theta[a_n][k] + al_n theta[a_n + 1][k], n < N, k < nK
