@@ -391,6 +391,10 @@ def lv_leg(reps):
     capi.cal_timing_enable(mct.ctx, True)
     ms_tuned = time_ms(lambda: capi.calibrate_gradient(mct.ctx, th, C, Ey, G, g), reps)
     p2t = capi.cal_timing_read(mct.ctx, 1)
+    capi.cal_timing_enable(mct.ctx, True)
+    time_ms(lambda: capi.calibrate_forward(mct.ctx, th, Ey), reps)
+    ft = capi.cal_timing_read(mct.ctx, 0)
+    capi.cal_timing_enable(mct.ctx, False)
     status |= mct.status()
     mct.close()
     ps = pb.n_paths * pb.n_steps
@@ -398,7 +402,8 @@ def lv_leg(reps):
     tuned = {"ckpt_every": kt, "paths_per_lane": pplt,
              "tuning_ms": {f"k{kk}_ppl{pp}": t * 1e3 for (kk, pp), t in table},
              "ms_per_step": ms_tuned, "paths_steps_per_s": ps / (ms_tuned * 1e-3),
-             "ms_pass2_kernel": p2t[0] / p2t[1],
+             "ms_pass2_kernel": p2t[0] / p2t[1], "ms_forward_kernel": ft[0] / ft[1],
+             "kr_over_kf": costmodel.kr_over_kf(ft[0] / ft[1], p2t[0] / p2t[1]),
              "roofline": grid_roofline("lv", f"k_lv_pass2 (FP32, K={kt}, {pplt} path(s) per lane)", kt, ps,
                                        p2t[0] / p2t[1], pplt)}
     return {"workload": "local volatility: 2^22 paths x 256 steps over 2 years, bilinear 10 x 20 grid (M = 200), "

@@ -168,6 +168,40 @@ def test_lv_edge_shapes(orc):
             assert g_err(g, go) <= 1e-9
 
 
+def test_lv_widest_spot_grids(orc):
+    """Spot grids at the limits of the layout: pass 2 reads a step's two grid
+    nodes from the lanes that hold them (node k in lane k, up to 64 nodes) and
+    keeps only its node slices (2 nK values per lane) in LDS.  nK = 64 in
+    FP32 (every lane holds a node; 128 KB of slices), nK = 40 in FP64 (the
+    slices fill the 160 KB of LDS exactly); against the oracle, FP64 to its
+    bounds, FP32 to its bounds where the one-path share is within the gate.
+    nK = 41 in FP64 needs more LDS than a workgroup has and is refused."""
+    from paper_1901_04200_amd import capi
+    for prec, n_k, P, N, k, ppl in (("fp64", 40, 1000, 24, 8, 1), ("fp32", 64, (1 << 14) + 9, 40, 16, 2)):
+        pb, g0, gt, eps, _ = W.lv_problem(n_paths=P, n_steps=N, n_t=3, n_k=n_k)
+        C = np.linspace(2.0, 9.0, pb.n_instr)
+        Eo, Go, go = orc.gradient(pb, g0, C)
+        for mode in ("store", "rerun"):
+            say(f"  lv wide grid {prec} nK={n_k} P={P} N={N} K={k} ppl={ppl} {mode}")
+            Ey_f, Ey, G, g = run(pb, g0, C, prec, ckpt_every=k, ckpt_mode=mode, paths_per_lane=ppl)
+            say(f"    Ey {ey_err(Ey, Eo):.2e} grad {g_err(g, go):.2e}")
+            if prec == "fp64":
+                assert ey_err(Ey_f, Eo) <= 1e-12 and ey_err(Ey, Eo) <= 1e-12
+                assert g_err(g, go) <= 1e-9
+            else:
+                assert ey_err(Ey_f, Eo) <= 1e-5 and ey_err(Ey, Eo) <= 1e-5
+                share = PY.gradient_shares(orc, pb, g0, C, Eo)
+                ok = share <= PY.SHARE_GATE
+                scale = np.maximum(np.abs(go), 1e-3 * np.max(np.abs(go)))
+                err = np.abs(g - go) / scale
+                say(f"    gated components {int(ok.sum())}/{len(ok)}, max error there {err[ok].max():.2e}")
+                assert ok.sum() >= len(ok) // 4
+                assert err[ok].max() <= 1e-4
+    pb = W.lv_problem(n_paths=256, n_steps=8, n_t=2, n_k=41)[0]
+    with pytest.raises(capi.CalError, match="LDS"):
+        MonteCarloCalibration(pb, precision="fp64")
+
+
 def test_memory_budget_picks_spacing():
     pb = W.lv_problem()[0]     # 2^22 paths x 256 steps, one state variable
     assert AG.checkpoint_bytes(pb, "fp32", 16) == 16 * (1 << 22) * 4
