@@ -70,7 +70,13 @@ int mlp_forward(mlp_ctx *ctx, const float *d_theta, int32_t B, float *d_Y, float
  * be drawn from a resident data set without gathering them first.
  * Labels are given in price units: d_Ylab [B x n_out], d_Jlab
  * [B x n_out x n_in].  B must be a multiple of 128.  d_loss[1] (FP64) and
- * d_grad [num_params] (FP32, packed like the parameters) are written. */
+ * d_grad [num_params] (FP32, packed like the parameters) are written.
+ * For n_in <= 7 the weight and bias gradients of each layer run on a second
+ * stream the context owns, forked from `stream` by events as soon as the
+ * layer's adjoints exist and joined back to it before the call returns: all
+ * the call's work is ordered on `stream` as if it ran there (and the call can
+ * be captured into a graph on `stream`); two calls on one context must not
+ * overlap. */
 int mlp_loss_grad(mlp_ctx *ctx, const float *d_theta, const float *d_Ylab, const float *d_Jlab, const float *d_jw,
                   const int32_t *d_idx, int32_t B, float w, double *d_loss, float *d_grad, void *stream);
 
