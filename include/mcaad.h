@@ -103,7 +103,11 @@ typedef struct cal_ctx cal_ctx;
  *                       step n uses row a = #{t_nodes <= n h}, capped at nT-1)
  *   n_k_nodes (nK), k_nodes[nK] : LV and SLV spot nodes, 2..64, uniformly spaced
  *                       (within 1e-9 relative), linear in S, flat outside;
- *                       theta[(5 +) a*nK + k] is the value at (t_a, K_k)
+ *                       theta[(5 +) a*nK + k] is the value at (t_a, K_k);
+ *                       LV's reverse pass holds 2*nK*256 values of the path
+ *                       precision in one workgroup's LDS, so in FP64 nK is
+ *                       at most 40 on a 160 KB device (cal_create refuses
+ *                       more with CAL_EUNSUPPORTED)
  * Random numbers: normal q of path p is Box-Muller of the uniforms
  * ((w >> 9) + 0.5) 2^-23 of Philox4x32-10 counter (q/4, p, inst, 0), key
  * (seed lo, seed hi); q = n*d + j for normal j of step n (d = 2 for Heston
@@ -140,7 +144,9 @@ typedef struct {
 int cal_validate(const cal_problem *pb, char *msg, int32_t msg_len);
 
 /* Validate, then allocate the context and all its device workspace on the
- * current device.  *out receives the context (NULL on error). */
+ * current device.  *out receives the context (NULL on error).  For LV and
+ * SLV it also checks the kernels' LDS need against the current device's
+ * per-workgroup limit and returns CAL_EUNSUPPORTED when it does not fit. */
 int cal_create(const cal_problem *pb, cal_ctx **out);
 
 /* Free the context and its workspace (synchronises the device first).
