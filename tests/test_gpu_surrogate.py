@@ -205,17 +205,33 @@ def test_adam_step_matches_reference():
 
 
 def test_calibration_gradient_kernel():
-    """G = 1/2 |y - C|^2 and J^T (y - C) from the network's own outputs."""
+    """G = 1/2 |y - C|^2 and J^T (y - C): exactly those of the network's own
+    outputs, and within the bounds that the forward tolerance implies of the
+    oracle's."""
     net = S.MLP(5, 128, 7, max_batch=128)
     net.set_params(net.pack(rand_params([5, 128, 128, 128, 7], 4)))
     th = torch.as_tensor(np.random.default_rng(5).uniform(-1, 1, (9, 5)), dtype=torch.float32, device="cuda")
     C = torch.linspace(-1.0, 1.0, 7, dtype=torch.float64, device="cuda")
+    params = rand_params([5, 128, 128, 128, 7], 4)
     G, g = net.calibration_gradient(th, C)
     Y, J = net.forward(th)
     r = Y.double().cpu().numpy() - C.cpu().numpy()
     np.testing.assert_allclose(G.cpu().numpy(), 0.5 * np.sum(r * r, axis=1), rtol=1e-12)
     np.testing.assert_allclose(g.cpu().numpy(), np.einsum("bij,bi->bj", J.double().cpu().numpy(), r), rtol=1e-10,
                                atol=1e-12)
+    # against the oracle: with every output within ey of the oracle's and every
+    # Jacobian entry within ej (the forward tolerance, 2e-2 of the largest
+    # magnitude), G_b = 1/2 |r_b|^2 is off by at most sum_i (|r_i| ey + ey^2 / 2)
+    # and g_bj = sum_i J_bij r_bi by at most sum_i (ej |r_i| + |J_ij| ey + ej ey)
+    Yo, Jo = MO.forward_tangent(device_view(params), th.double().cpu().numpy())
+    ro = Yo - C.cpu().numpy()
+    ey, ej = 2e-2 * np.max(np.abs(Yo)), 2e-2 * np.max(np.abs(Jo))
+    Go, go = 0.5 * np.sum(ro * ro, axis=1), np.einsum("bij,bi->bj", Jo, ro)
+    G_tol = np.sum(np.abs(ro) * ey + 0.5 * ey * ey, axis=1)
+    g_tol = np.einsum("bij,bi->bj", np.abs(Jo), np.full_like(ro, ey)) + ej * np.sum(np.abs(ro) + ey, axis=1)[:, None]
+    dG, dg = np.abs(G.cpu().numpy() - Go), np.abs(g.cpu().numpy() - go)
+    say(f"  calibration gradient vs oracle: G {np.max(dG / G_tol):.2f}, g {np.max(dg / g_tol):.2f} of the bounds")
+    assert np.all(dG <= G_tol) and np.all(dg <= g_tol)
     # into preallocated buffers: the same values, twice in a row
     bufs = net.calibration_buffers(9)
     for _ in range(2):
