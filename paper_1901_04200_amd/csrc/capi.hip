@@ -287,7 +287,11 @@ extern "C" int cal_create(const cal_problem *pb, cal_ctx **out)
         probe.nT = pb->n_t_nodes;
         probe.nK = pb->n_k_nodes;
         int max_lds = 0;
-        (void)hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, c->device);
+        if (hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, c->device) != hipSuccess ||
+            max_lds <= 0) {
+            delete c;
+            return fail(nullptr, CAL_EHIP, "device query failed (LDS bytes per workgroup)");
+        }
         const size_t need = c->model == CAL_LV
                                 ? std::max(lv_lds_bytes(probe, c->fp64, 1), lv_lds_bytes(probe, c->fp64, 2))
                                 : std::max(slv_lds_bytes(probe, c->fp64, 1), slv_lds_bytes(probe, c->fp64, 2));
@@ -940,7 +944,10 @@ extern "C" int calb_create(const cal_problem *problems, int32_t n_inst, calb_ctx
     }
     calb_ctx *c = new calb_ctx();
     (void)hipGetDevice(&c->device);
-    (void)hipDeviceGetAttribute(&c->cus, hipDeviceAttributeMultiprocessorCount, c->device);
+    if (hipDeviceGetAttribute(&c->cus, hipDeviceAttributeMultiprocessorCount, c->device) != hipSuccess || c->cus <= 0) {
+        delete c;
+        return bfail(nullptr, CAL_EHIP, "device query failed (compute units)");
+    }
     c->model = problems[0].model;
     c->fp64 = problems[0].precision == CAL_FP64;
     c->n_inst = n_inst;
