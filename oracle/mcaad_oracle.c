@@ -31,8 +31,8 @@
  * so both precisions see the same uniforms) and pairs of uniforms to normals by
  * Box-Muller: rho = sqrt(-2 ln u0), z0 = rho cos(2 pi u1), z1 = rho sin(2 pi u1).
  *
- * Models (all step the log-price x = ln(S/S0): the paper's Euler scheme read
- * as log-Euler; payoffs are discounted calls):
+ * Models (0 to 3 step the log-price x = ln(S/S0): the paper's Euler scheme read
+ * as log-Euler; 4 takes it literally on S; payoffs are discounted calls):
  *   0  Black-Scholes GBM, theta = (sigma)
  *   1  Heston with full truncation, theta = (kappa, theta_bar, xi, rho, v0);
  *      the paper's test model with the leverage function set to one
@@ -41,6 +41,10 @@
  *      dS/S = r dt + L(t,S) sqrt(v) dW1 with Heston's v, theta = (kappa,
  *      theta_bar, xi, rho, v0, leverage node values L[a][k]); L piecewise
  *      constant in t, linear across the spot nodes
+ *   4  Black-Scholes GBM with the Euler scheme applied to the SDE as written
+ *      in S (section "Test on the Heston SLV model calibration": a standard
+ *      Euler discretisation of dS = mu S dt + sigma S dW), theta = (sigma):
+ *      S_{n+1} = S_n (1 + r h + sigma sqrt(h) z_n); the state is S itself
  *
  * Sums over paths are taken in path order with Neumaier compensation.
  * Per-path work runs in parallel (OpenMP) into per-path buffers; only the
@@ -60,7 +64,7 @@
 #define ORC_EINVAL (-1)
 #define ORC_ENOMEM (-2)
 
-enum { ORC_BS = 0, ORC_HESTON = 1, ORC_LV = 2, ORC_SLV = 3 };
+enum { ORC_BS = 0, ORC_HESTON = 1, ORC_LV = 2, ORC_SLV = 3, ORC_BSE = 4 };
 
 typedef struct {
     int32_t model;
@@ -174,7 +178,7 @@ static int consts_make(const orc_problem *pb, orc_consts *c)
     int N = pb->n_steps, m = pb->n_instr;
     for (int i = 0; i < m; ++i)
         if (pb->instr_step[i] < 1 || pb->instr_step[i] > N) return ORC_EINVAL;
-    if (pb->model == ORC_BS && pb->n_params != 1) return ORC_EINVAL;
+    if ((pb->model == ORC_BS || pb->model == ORC_BSE) && pb->n_params != 1) return ORC_EINVAL;
     if (pb->model == ORC_HESTON && pb->n_params != 5) return ORC_EINVAL;
     if (pb->model == ORC_LV) {
         if (pb->n_t_nodes < 2 || pb->n_k_nodes < 2 || !pb->t_nodes || !pb->k_nodes) return ORC_EINVAL;
@@ -184,7 +188,7 @@ static int consts_make(const orc_problem *pb, orc_consts *c)
         if (pb->n_t_nodes < 1 || pb->n_k_nodes < 2 || !pb->t_nodes || !pb->k_nodes) return ORC_EINVAL;
         if (pb->n_params != 5 + pb->n_t_nodes * pb->n_k_nodes) return ORC_EINVAL;
     }
-    if (pb->model < 0 || pb->model > 3) return ORC_EINVAL;
+    if (pb->model < 0 || pb->model > 4) return ORC_EINVAL;
     if (!(pb->sqrt_eps >= 0.0)) return ORC_EINVAL;
     c->h = pb->t_max / N;
     c->sq = sqrt(c->h);
@@ -213,6 +217,18 @@ static int consts_make(const orc_problem *pb, orc_consts *c)
 static void consts_free(orc_consts *c)
 {
     free(c->date_begin); free(c->ids); free(c->disc);
+}
+
+/* The spot price of state x: x itself for model 4 (Euler on S), S0 e^x otherwise. */
+static double spot_of(const orc_problem *pb, const orc_consts *c, double x)
+{
+    return pb->model == ORC_BSE ? x : c->s0 * exp(x);
+}
+
+/* The state at step 0: S0 for model 4, log-price 0 otherwise. */
+static double state0(const orc_problem *pb, const orc_consts *c)
+{
+    return pb->model == ORC_BSE ? c->s0 : 0.0;
 }
 
 /* Diffusion coefficient of the variance, s(v+) with v+ = max(v, 0).
@@ -342,7 +358,7 @@ static void path_forward(const orc_problem *pb, const orc_consts *c, const doubl
 {
     orc_rng g; rng_init(&g, pb, p);
     const double h = c->h, sq = c->sq, r = c->r;
-    double x = 0.0;
+    double x = state0(pb, c);
     const int hv = pb->model == ORC_HESTON || pb->model == ORC_SLV;   /* has a variance process */
     double v = hv ? th[4] : 0.0;
     const double rhop = hv ? sqrt(1.0 - th[3] * th[3]) : 0.0;
@@ -372,6 +388,10 @@ static void path_forward(const orc_problem *pb, const orc_consts *c, const doubl
             double xn = x + (r - 0.5 * L * L * vp) * h + L * s * sq * z1;
             double vn = v + kap * (thb - vp) * h + xi * s * sq * w;
             x = xn; v = vn;
+        } else if (pb->model == ORC_BSE) {
+            double sig = th[0];
+            double z = rng_normal(&g, (uint32_t)n);
+            x = x * (1.0 + r * h + sig * sq * z);
         } else {
             double z = rng_normal(&g, (uint32_t)n);
             double S = c->s0 * exp(x);
@@ -381,7 +401,7 @@ static void path_forward(const orc_problem *pb, const orc_consts *c, const doubl
         }
         for (int k = c->date_begin[n + 1]; k < c->date_begin[n + 2]; ++k) {
             int i = c->ids[k];
-            double S = c->s0 * exp(x);
+            double S = spot_of(pb, c, x);
             double pay = S - c->strike[i];
             y[i] = c->disc[i] * (pay > 0.0 ? pay : 0.0);
         }
@@ -406,7 +426,7 @@ static void path_reverse(const orc_problem *pb, const orc_consts *c, const doubl
     const double rhop = hv ? sqrt(1.0 - th[3] * th[3]) : 0.0;
 
     /* forward, recording the states and normals of every step */
-    xs[0] = 0.0;
+    xs[0] = state0(pb, c);
     vs[0] = hv ? th[4] : 0.0;
     for (int n = 0; n < N; ++n) {
         double x = xs[n];
@@ -438,6 +458,11 @@ static void path_reverse(const orc_problem *pb, const orc_consts *c, const doubl
             z1s[n] = z1; z2s[n] = z2;
             xs[n + 1] = x + (r - 0.5 * L * L * vp) * h + L * s * sq * z1;
             vs[n + 1] = v + kap * (thb - vp) * h + xi * s * sq * w;
+        } else if (pb->model == ORC_BSE) {
+            double sig = th[0];
+            double z = rng_normal(&g, (uint32_t)n);
+            z1s[n] = z;
+            xs[n + 1] = x * (1.0 + r * h + sig * sq * z);
         } else {
             double z = rng_normal(&g, (uint32_t)n);
             z1s[n] = z;
@@ -452,11 +477,13 @@ static void path_reverse(const orc_problem *pb, const orc_consts *c, const doubl
     for (int j = 0; j < M; ++j) thbar[j] = 0.0;
     double xb = 0.0, vb = 0.0;  /* adjoints of x_{n+1}, v_{n+1} */
     for (int n = N - 1; n >= 0; --n) {
-        /* payoff adjoints enter at the maturity step n+1: dy_i/dx = D_i 1{S>K_i} S */
-        double Sn1 = c->s0 * exp(xs[n + 1]);
+        /* payoff adjoints enter at the maturity step n+1: dy_i/dx = D_i 1{S>K_i} S
+         * for the log-price state, D_i 1{S>K_i} for the spot itself (model 4) */
+        double Sn1 = spot_of(pb, c, xs[n + 1]);
+        double dSdx = pb->model == ORC_BSE ? 1.0 : Sn1;
         for (int k = c->date_begin[n + 1]; k < c->date_begin[n + 2]; ++k) {
             int i = c->ids[k];
-            if (Sn1 > c->strike[i]) xb += lam[i] * c->disc[i] * Sn1;
+            if (Sn1 > c->strike[i]) xb += lam[i] * c->disc[i] * dSdx;
         }
         if (pb->model == ORC_BS) {
             double sig = th[0];
@@ -503,6 +530,11 @@ static void path_reverse(const orc_problem *pb, const orc_consts *c, const doubl
             thbar[5 + cell.a * nK + cell.b + 1] += Lbar * cell.be;
             xb = a + Lbar * slv_dlev_dS(pb, th + 5, cell) * S;
             vb = b + (v > 0.0 ? vpbar : 0.0);
+        } else if (pb->model == ORC_BSE) {
+            /* S_{n+1} = S_n (1 + r h + sig sq z) */
+            double sig = th[0], z = z1s[n];
+            thbar[0] += xb * xs[n] * sq * z;
+            xb = xb * (1.0 + r * h + sig * sq * z);
         } else {
             double x = xs[n];
             double S = c->s0 * exp(x);
@@ -532,7 +564,7 @@ static void path_tangent(const orc_problem *pb, const orc_consts *c, const doubl
     double *vd = work + M;    /* dv/dtheta_j */
     double *sd = work + 2 * M;/* dsigma/dtheta_j (LV), dL/dtheta_j (SLV) */
     orc_rng g; rng_init(&g, pb, p);
-    double x = 0.0, v = 0.0;
+    double x = state0(pb, c), v = 0.0;
     for (int j = 0; j < M; ++j) { xd[j] = 0.0; vd[j] = 0.0; }
     double rhop = 0.0;
     if (pb->model == ORC_HESTON || pb->model == ORC_SLV) { v = th[4]; vd[4] = 1.0; rhop = sqrt(1.0 - th[3] * th[3]); }
@@ -595,6 +627,12 @@ static void path_tangent(const orc_problem *pb, const orc_consts *c, const doubl
             double xn = x + (r - 0.5 * L * L * vp) * h + L * s * sq * z1;
             double vn = v + kap * (thb - vp) * h + xi * s * sq * w;
             x = xn; v = vn;
+        } else if (pb->model == ORC_BSE) {
+            double sig = th[0];
+            double z = rng_normal(&g, (uint32_t)n);
+            double f = 1.0 + r * h + sig * sq * z;
+            xd[0] = xd[0] * f + x * sq * z;
+            x = x * f;
         } else {
             double z = rng_normal(&g, (uint32_t)n);
             double S = c->s0 * exp(x);
@@ -613,11 +651,12 @@ static void path_tangent(const orc_problem *pb, const orc_consts *c, const doubl
         }
         for (int k = c->date_begin[n + 1]; k < c->date_begin[n + 2]; ++k) {
             int i = c->ids[k];
-            double S = c->s0 * exp(x);
+            double S = spot_of(pb, c, x);
+            double dSdx = pb->model == ORC_BSE ? 1.0 : S;
             double pay = S - c->strike[i];
             y[i] = c->disc[i] * (pay > 0.0 ? pay : 0.0);
             for (int j = 0; j < M; ++j)
-                dy[(size_t)i * M + j] = pay > 0.0 ? c->disc[i] * S * xd[j] : 0.0;
+                dy[(size_t)i * M + j] = pay > 0.0 ? c->disc[i] * dSdx * xd[j] : 0.0;
         }
     }
 }
@@ -633,7 +672,7 @@ static void path_forward_cstep(const orc_problem *pb, const orc_consts *c, const
     for (int j = 0; j < M; ++j) thc[j] = th[j] + (j == jdir ? hc * I : 0.0);
     orc_rng g; rng_init(&g, pb, p);
     const double h = c->h, sq = c->sq, r = c->r;
-    double complex x = 0.0;
+    double complex x = state0(pb, c);
     const int hv = pb->model == ORC_HESTON || pb->model == ORC_SLV;
     double complex v = hv ? thc[4] : 0.0;
     double complex rhop = hv ? csqrt(1.0 - thc[3] * thc[3]) : 0.0;
@@ -669,6 +708,10 @@ static void path_forward_cstep(const orc_problem *pb, const orc_consts *c, const
             double complex xn = x + (r - 0.5 * L * L * vp) * h + L * s * sq * z1;
             double complex vn = v + kap * (thb - vp) * h + xi * s * sq * w;
             x = xn; v = vn;
+        } else if (pb->model == ORC_BSE) {
+            double complex sig = thc[0];
+            double z = rng_normal(&g, (uint32_t)n);
+            x = x * (1.0 + r * h + sig * sq * z);
         } else {
             double z = rng_normal(&g, (uint32_t)n);
             double complex S = c->s0 * cexp(x);
@@ -686,7 +729,7 @@ static void path_forward_cstep(const orc_problem *pb, const orc_consts *c, const
         }
         for (int k = c->date_begin[n + 1]; k < c->date_begin[n + 2]; ++k) {
             int i = c->ids[k];
-            double complex S = c->s0 * cexp(x);
+            double complex S = pb->model == ORC_BSE ? x : c->s0 * cexp(x);
             double complex pay = S - c->strike[i];
             y[i] = creal(pay) > 0.0 ? c->disc[i] * pay : 0.0;
         }

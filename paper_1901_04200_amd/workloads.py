@@ -22,8 +22,9 @@ MODEL_BS = 0
 MODEL_HESTON = 1
 MODEL_LV = 2
 MODEL_SLV = 3
+MODEL_BS_S = 4   # Black-Scholes with the Euler scheme applied to S itself
 
-MODEL_NAMES = {MODEL_BS: "bs", MODEL_HESTON: "heston", MODEL_LV: "lv", MODEL_SLV: "slv"}
+MODEL_NAMES = {MODEL_BS: "bs", MODEL_HESTON: "heston", MODEL_LV: "lv", MODEL_SLV: "slv", MODEL_BS_S: "bs_s"}
 
 # Heston parameter box: kappa, theta_bar, xi, rho, v0
 HESTON_LO = np.array([0.5, 0.01, 0.1, -0.9, 0.01])
@@ -78,10 +79,13 @@ def bs_vega(s0, k, r, t, sigma):
     return s0 * norm.pdf(d1) * math.sqrt(t)
 
 
-def bs_problem(n_paths: int = 1 << 14, n_steps: int = 16, seed: int = 1):
-    """Black-Scholes GBM, one parameter sigma, four calls K=80..110 at T=1."""
+def bs_problem(n_paths: int = 1 << 14, n_steps: int = 16, seed: int = 1, euler_on_s: bool = False):
+    """Black-Scholes GBM, one parameter sigma, four calls K=80..110 at T=1;
+    euler_on_s: the Euler scheme on S as the SDE is written (model 4)
+    instead of on log S."""
     strikes = np.array([80.0, 90.0, 100.0, 110.0])
-    pb = Problem(model=MODEL_BS, n_params=1, n_steps=n_steps, n_paths=n_paths, t_max=1.0,
+    pb = Problem(model=MODEL_BS_S if euler_on_s else MODEL_BS, n_params=1, n_steps=n_steps, n_paths=n_paths,
+                 t_max=1.0,
                  instr_step=np.full(4, n_steps, dtype=np.int32), instr_strike=strikes,
                  s0=100.0, rate=0.02, seed=seed)
     theta = np.array([0.20])
