@@ -50,6 +50,11 @@ extern "C" {
 #define CAL_SLV 3     /* Heston stochastic local volatility (the paper's test model): dS/S = r dt +
                          L(t, S) sqrt(v) dW1, v as Heston; theta = (kappa, theta_bar, xi, rho, v0,
                          L[a][k]); L piecewise constant in t, linear across the spot nodes */
+#define CAL_BS_EULER_S 4  /* Black-Scholes GBM, theta = (sigma), with the paper's Euler scheme taken
+                             literally on the SDE as written in S (section "Test on the Heston SLV
+                             model calibration"): S_{n+1} = S_n (1 + r h + sigma sqrt(h) z_n); forward,
+                             gradient and vector-Jacobian product only (no tangent mode, batching or
+                             calibrate_gradient_static: CAL_EUNSUPPORTED) */
 
 /* precision of the path state */
 #define CAL_FP32 0

@@ -13,7 +13,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIBDIR = os.path.join(HERE, "lib")
 LIB = os.path.join(LIBDIR, "libmcaad.so")
 
-SOURCES = ["mc_kernels.hip", "lv_kernels.hip", "slv_kernels.hip", "capi.hip", "mlp.hip"]
+SOURCES = ["mc_kernels.hip", "lv_kernels.hip", "slv_kernels.hip", "bse_kernels.hip", "capi.hip", "mlp.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 

@@ -14,6 +14,7 @@
 #include <vector>
 
 #include "../../include/mcaad.h"
+#include "bse_kernels.hpp"
 #include "mc_device.hpp"
 #include "mc_kernels.hpp"
 
@@ -91,7 +92,8 @@ static std::string validate(const cal_problem *pb, int *code)
 {
     *code = CAL_EINVAL;
     if (!pb) return "null problem";
-    if (pb->model != CAL_BS && pb->model != CAL_HESTON && pb->model != CAL_LV && pb->model != CAL_SLV)
+    if (pb->model != CAL_BS && pb->model != CAL_HESTON && pb->model != CAL_LV && pb->model != CAL_SLV &&
+        pb->model != CAL_BS_EULER_S)
         return "unknown model";
     if (pb->precision != CAL_FP32 && pb->precision != CAL_FP64) return "unknown precision";
     if (pb->n_instr < 1 || pb->n_instr > kMaxInstr) return "n_instr must be in 1..2048";
@@ -120,7 +122,8 @@ static std::string validate(const cal_problem *pb, int *code)
         return "local volatility runs one or two paths per lane";
     }
     if (pb->max_batch < 0 || pb->max_batch > 65535) return "max_batch must be in 0..65535";
-    if (pb->model == CAL_BS && pb->n_params != 1) return "Black-Scholes takes n_params = 1";
+    if ((pb->model == CAL_BS || pb->model == CAL_BS_EULER_S) && pb->n_params != 1)
+        return "Black-Scholes takes n_params = 1";
     if (pb->model == CAL_HESTON && pb->n_params != 5) return "Heston takes n_params = 5";
     if (pb->model == CAL_LV || pb->model == CAL_SLV) {
         const bool lv = pb->model == CAL_LV;
@@ -508,6 +511,8 @@ static int run_pass1(cal_ctx *c, const double *theta, bool store, hipStream_t st
             e = launch_lv_pass1(c->dp, c->fp64, store, theta, c->d_lv_rows, c->d_part_y, c->d_ckpt, c->nblocks, st);
     } else if (c->model == CAL_SLV) {
         e = launch_slv_pass1(c->dp, c->fp64, store, theta, c->d_part_y, c->d_ckpt, c->nblocks, st);
+    } else if (c->model == CAL_BS_EULER_S) {
+        e = launch_bse_pass1(c->dp, c->fp64, store, theta, c->d_part_y, c->d_ckpt, c->nblocks, st);
     } else {
         e = launch_pass1(c->dp, c->model, c->fp64, store, theta, c->d_part_y, c->d_ckpt, c->nblocks, st);
     }
@@ -534,6 +539,8 @@ static int run_pass2(cal_ctx *c, const double *theta, bool from_ckpt, hipStream_
                                 c->nblocks, st);
     } else if (c->model == CAL_SLV) {
         e = launch_slv_pass2(c->dp, c->fp64, from_ckpt, theta, c->d_lamD, c->d_part_g, c->d_ckpt, c->nblocks, st);
+    } else if (c->model == CAL_BS_EULER_S) {
+        e = launch_bse_pass2(c->dp, c->fp64, from_ckpt, theta, c->d_lamD, c->d_part_g, c->d_ckpt, c->nblocks, st);
     } else {
         e = launch_pass2(c->dp, c->model, c->fp64, from_ckpt, theta, c->d_lamD, c->d_part_g, c->d_ckpt, c->nblocks,
                          st);
@@ -583,7 +590,8 @@ static int vjp(cal_ctx *ctx, const double *d_theta, const double *d_lambda, doub
     if (!d_theta || !d_lambda || !d_grad) return fail(ctx, CAL_EINVAL, "null device pointer");
     if (from_ckpt && !ctx->ckpt_valid)
         return fail(ctx, CAL_EINVAL, "no stored checkpoints on this context (no completed storing sweep yet)");
-    hipError_t e = launch_check_theta(ctx->dp, d_theta, ctx->model, st);
+    // sigma's domain is the same under both Black-Scholes schemes
+    hipError_t e = launch_check_theta(ctx->dp, d_theta, ctx->model == CAL_BS_EULER_S ? CAL_BS : ctx->model, st);
     if (e == hipSuccess)
         e = launch_lambda(ctx->dp, ctx->fp64, d_lambda, ctx->d_lamD, from_ckpt ? ctx->d_theta_ckpt : nullptr, d_theta,
                           st);
@@ -781,8 +789,8 @@ extern "C" int calibrate_jacobian_batch(cal_ctx *ctx, const double *d_theta, int
     int rc = check_ctx(ctx);
     if (rc) return rc;
     if (!d_theta || !d_Ey || !d_J) return fail(ctx, CAL_EINVAL, "null device pointer");
-    if (ctx->model == CAL_LV || ctx->model == CAL_SLV)
-        return fail(ctx, CAL_EUNSUPPORTED, "tangent mode serves Black-Scholes and Heston");
+    if (ctx->model != CAL_BS && ctx->model != CAL_HESTON)
+        return fail(ctx, CAL_EUNSUPPORTED, "tangent mode serves Black-Scholes (log-Euler) and Heston");
     if (n_inst < 1 || n_inst > ctx->max_batch) return fail(ctx, CAL_EINVAL, "n_inst outside 1..max_batch");
     if ((size_t)ctx->m * (ctx->M + 1) * kWavesPerBlock * sizeof(double) > 64 * 1024)
         return fail(ctx, CAL_EUNSUPPORTED, "m * (M + 1) too large for the tangent kernel's LDS");
@@ -937,8 +945,8 @@ extern "C" int calb_create(const cal_problem *problems, int32_t n_inst, calb_ctx
         int code;
         std::string msg = validate(&problems[i], &code);
         if (code != CAL_OK) return bfail(nullptr, code, "instance " + std::to_string(i) + ": " + msg);
-        if (problems[i].model == CAL_LV || problems[i].model == CAL_SLV)
-            return bfail(nullptr, CAL_EUNSUPPORTED, "batches take BS or Heston");
+        if (problems[i].model != CAL_BS && problems[i].model != CAL_HESTON)
+            return bfail(nullptr, CAL_EUNSUPPORTED, "batches take BS (log-Euler) or Heston");
         if (problems[i].model != problems[0].model || problems[i].precision != problems[0].precision)
             return bfail(nullptr, CAL_EINVAL, "all instances of a batch share model and precision");
     }

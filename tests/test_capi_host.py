@@ -58,6 +58,11 @@ def test_validate_accepts_the_workloads(L):
     # the smoothed square root exists in the oracle only
     rc, msg = _ok(pb2.with_(sqrt_eps=1e-4))
     assert rc == capi.CAL_EUNSUPPORTED and "sqrt_eps" in msg
+    # Black-Scholes with the Euler scheme on S: one parameter, like log-Euler
+    pbs, _, _ = W.bs_problem(euler_on_s=True)
+    assert _ok(pbs, precision=capi.CAL_FP64)[0] == capi.CAL_OK
+    rc, msg = _ok(pbs.with_(n_params=2))
+    assert rc == capi.CAL_EINVAL and "n_params" in msg
 
 
 @pytest.mark.parametrize("change,expect", [
