@@ -105,6 +105,12 @@ void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t ou
     out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
 }
 
+/* The same for n counters (ctr and out [n][4]) under one key, one after another. */
+void orc_philox_many(const uint32_t *ctr, int64_t n, const uint32_t key[2], uint32_t *out)
+{
+    for (int64_t i = 0; i < n; ++i) orc_philox4x32_10(ctr + 4 * i, key, out + 4 * i);
+}
+
 static double orc_uniform(uint32_t w)
 {
     return ((double)(w >> 9) + 0.5) * (1.0 / 8388608.0);

@@ -44,6 +44,9 @@ def lib():
         pp = C.POINTER(_Problem)
         L.orc_philox4x32_10.argtypes = [C.POINTER(C.c_uint32), C.POINTER(C.c_uint32), C.POINTER(C.c_uint32)]
         L.orc_philox4x32_10.restype = None
+        L.orc_philox_many.argtypes = [C.POINTER(C.c_uint32), C.c_int64, C.POINTER(C.c_uint32),
+                                      C.POINTER(C.c_uint32)]
+        L.orc_philox_many.restype = None
         L.orc_normals.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32, C.c_int32, dp]
         L.orc_normals.restype = None
         L.orc_forward.argtypes = [pp, dp, dp, dp]
@@ -118,6 +121,16 @@ def philox(ctr, key):
     o = (C.c_uint32 * 4)()
     lib().orc_philox4x32_10(c, k, o)
     return [int(o[i]) for i in range(4)]
+
+
+def philox_many(ctr: np.ndarray, key) -> np.ndarray:
+    """Philox4x32-10 of n counters ([n, 4] u32) under one key: [n, 4] u32."""
+    c = np.ascontiguousarray(ctr, dtype=np.uint32)
+    k = (C.c_uint32 * 2)(*[int(v) & 0xFFFFFFFF for v in key])
+    out = np.empty_like(c)
+    u32p = C.POINTER(C.c_uint32)
+    lib().orc_philox_many(c.ctypes.data_as(u32p), c.shape[0], k, out.ctypes.data_as(u32p))
+    return out
 
 
 def normals(seed: int, inst: int, path: int, q0: int, n: int) -> np.ndarray:

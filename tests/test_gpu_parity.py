@@ -77,6 +77,23 @@ def test_philox_words_bitwise(orc):
     np.testing.assert_array_equal(got, ref)
 
 
+def test_philox_million_pairs_bitwise(orc):
+    """2^20 (counter, key) pairs, bit for bit: 16 random keys (and the
+    all-zero and all-one keys) with 2^16 random counters each."""
+    rng = np.random.default_rng(4)
+    keys = [(0, 0), (2 ** 32 - 1, 2 ** 32 - 1)] + [tuple(int(v) for v in rng.integers(0, 2 ** 32, 2)) for _ in range(14)]
+    n = 1 << 16
+    say(f"philox: {len(keys)} keys x {n} counters")
+    for k0, k1 in keys:
+        ctr = rng.integers(0, 2 ** 32, size=(n, 4), dtype=np.uint64).astype(np.uint32)
+        d_ctr = torch.tensor(ctr.view(np.int32), device="cuda")
+        d_out = torch.empty_like(d_ctr)
+        capi.cal_philox(d_ctr, k0, k1, d_out)
+        torch.cuda.synchronize()
+        got = d_out.cpu().numpy().view(np.uint32).reshape(-1, 4)
+        np.testing.assert_array_equal(got, orc.philox_many(ctr, (k0, k1)))
+
+
 def _normals(precision, seed, inst, path0, npaths, q0, nq):
     dt = torch.float64 if precision == capi.CAL_FP64 else torch.float32
     out = torch.empty(npaths * nq, dtype=dt, device="cuda")
