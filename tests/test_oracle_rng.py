@@ -62,7 +62,7 @@ def test_philox_counter_and_key_sensitivity(orc):
 
 def test_normals_law(orc):
     from scipy import stats
-    z = np.concatenate([orc.normals(7, 0, p, 0, 4096) for p in range(1024)])  # 2^22 draws
+    z = np.concatenate([orc.normals(7, 0, p, 0, 4096) for p in range(4096)])  # 2^24 draws
     n = len(z)
     # the smallest uniform is 2^-24, so |z| <= sqrt(48 ln 2)
     assert np.abs(z).max() <= np.sqrt(48 * np.log(2)) + 1e-12
