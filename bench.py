@@ -296,6 +296,42 @@ def e2_sweep(n_paths, reps=5):
     return rows
 
 
+def bs_schemes_leg(reps):
+    """Black-Scholes at 2^20 paths x 256 steps (four calls at T = 1, FP32
+    state, K = 16) with the paper's Euler scheme on S as the SDE is written
+    and with the log-Euler scheme, timed side by side: gradient step,
+    forward pass and K_R/K_F of each."""
+    import torch
+    from paper_1901_04200_amd import capi, costmodel
+    from paper_1901_04200_amd import workloads as W
+    from paper_1901_04200_amd.mc import MonteCarloCalibration
+    out = {"workload": "Black-Scholes: 2^20 paths x 256 steps, 4 calls (K = 80..110, T = 1), FP32 state, "
+                       "FP64 sums, K = 16"}
+    for name, euler_on_s in (("euler_on_s", True), ("log_euler", False)):
+        pb, th, C = W.bs_problem(n_paths=1 << 20, n_steps=256, euler_on_s=euler_on_s)
+        mc = MonteCarloCalibration(pb, ckpt_every=16)
+        thd = torch.tensor(th, device="cuda")
+        Cd = torch.tensor(C, device="cuda")
+        Ey = torch.empty(pb.n_instr, dtype=torch.float64, device="cuda")
+        G = torch.empty(1, dtype=torch.float64, device="cuda")
+        g = torch.empty(1, dtype=torch.float64, device="cuda")
+        capi.calibrate_gradient(mc.ctx, thd, Cd, Ey, G, g)
+        capi.cal_timing_enable(mc.ctx, True)
+        ms = time_ms(lambda: capi.calibrate_gradient(mc.ctx, thd, Cd, Ey, G, g), reps)
+        p2 = capi.cal_timing_read(mc.ctx, 1)
+        capi.cal_timing_enable(mc.ctx, True)
+        ms_f = time_ms(lambda: capi.calibrate_forward(mc.ctx, thd, Ey), reps)
+        f = capi.cal_timing_read(mc.ctx, 0)
+        capi.cal_timing_enable(mc.ctx, False)
+        status = mc.status()
+        mc.close()
+        t2, tf = p2[0] / p2[1], f[0] / f[1]
+        out[name] = {"ms_per_step": ms, "paths_steps_per_s": pb.n_paths * pb.n_steps / (ms * 1e-3),
+                     "ms_forward": ms_f, "ms_pass2_kernel": t2, "ms_forward_kernel": tf,
+                     "kr_over_kf": costmodel.kr_over_kf(tf, t2), "status": status}
+    return out
+
+
 def slv_leg(reps):
     """Heston stochastic local volatility (the paper's test model): 2^20
     paths x 256 steps, 5 Heston parameters + a 10 x 20 leverage grid, 200
@@ -604,7 +640,7 @@ def main():
     ap.add_argument("--cpu-min-seconds", type=float, default=4.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the extra legs")
-    ap.add_argument("--extras", default="theta0,rerun,slv,lv,e2_sweep,batched,surrogate_vs_mc",
+    ap.add_argument("--extras", default="theta0,rerun,bs_schemes,slv,lv,e2_sweep,batched,surrogate_vs_mc",
                     help="comma-separated extra legs to run")
     ap.add_argument("--sweep-paths", type=int, default=1 << 20)
     ap.add_argument("--batch-instances", type=int, default=256)
@@ -732,6 +768,7 @@ def main():
     if not args.no_extras:
         legs = (("theta0", lambda: theta0_leg(pb, th0, C, ckpt_every, ppl, args.steps, args.warmup)),
                 ("rerun", lambda: rerun_leg(pb, theta_np, C, ckpt_every, ppl, args.steps, args.warmup, t_f)),
+                ("bs_schemes", lambda: bs_schemes_leg(max(5, args.steps // 2))),
                 ("slv", lambda: slv_leg(max(5, args.steps // 2))),
                 ("lv", lambda: lv_leg(max(5, args.steps // 2))),
                 ("e2_sweep", lambda: e2_sweep(args.sweep_paths)),
