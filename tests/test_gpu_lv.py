@@ -128,6 +128,38 @@ def test_autograd_two_forwards_then_backward(lv_small):
     mc.close()
 
 
+def test_autograd_calibration_with_torch_lbfgs(lv_small):
+    """The wrapper inside an ordinary PyTorch calibration loop:
+    torch.optim.LBFGS (strong Wolfe line search) on log theta, so the node
+    values stay positive, with G = 1/2 |Ey - C|^2 differentiated through
+    MonteCarloPrices, to targets priced at a second surface on the same
+    streams (the exact optimum has G = 0): G falls below 1e-4 G(theta0)."""
+    pb, g0, gt, _, _ = lv_small
+    mc = AG.make(pb, "fp32")
+    C = mc.forward(gt)
+    u = torch.tensor(np.log(g0), dtype=torch.float64, device="cuda", requires_grad=True)
+    opt = torch.optim.LBFGS([u], lr=1.0, max_iter=100, history_size=10, line_search_fn="strong_wolfe",
+                            tolerance_grad=0.0, tolerance_change=0.0)
+    calls = [0]
+
+    def closure():
+        opt.zero_grad()
+        G = 0.5 * torch.sum((AG.mc_prices(torch.exp(u), mc) - C) ** 2)
+        G.backward()
+        calls[0] += 1
+        return G
+
+    with torch.no_grad():
+        G0 = float(0.5 * torch.sum((mc.forward(g0) - C) ** 2))
+    opt.step(closure)
+    with torch.no_grad():
+        G = float(0.5 * torch.sum((mc.forward(torch.exp(u)) - C) ** 2))
+    assert mc.status() == 0
+    mc.close()
+    say(f"lv fp32 torch L-BFGS through the wrapper: G {G0:.4g} -> {G:.3g} in {calls[0]} forward/backward calls")
+    assert G <= 1e-4 * G0
+
+
 @pytest.mark.parametrize("k", [8, 16, 32])
 def test_lv_two_paths_per_lane(orc, k):
     """Two paths side by side per lane (a ragged last workgroup of 512
