@@ -458,6 +458,37 @@ def test_edge_shapes_fp64(orc, P, N, steps, k):
             assert g_err(r["g"], g) <= 1e-10
 
 
+@pytest.mark.parametrize("model", ["bs", "heston"])
+def test_maximum_sizes_fp64(orc, model):
+    """The largest instrument table the library takes (2048 calls: 128
+    strikes at each of 16 maturity dates) and the longest sweep (65536
+    steps), FP64 against the oracle.  Over 65536 steps FP64 rounding adds up
+    to about N u = 7e-12 relative per path (u = 2^-53), so the bounds there
+    are 1e-10 on the prices and 1e-9 on the gradient."""
+    mdl = W.MODEL_BS if model == "bs" else W.MODEL_HESTON
+    th = np.array([0.3]) if model == "bs" else np.array([2.0, 0.05, 0.4, -0.6, 0.04])
+    steps = np.repeat(np.arange(4, 65, 4, dtype=np.int32), 128)
+    strikes = np.tile(np.linspace(60.0, 140.0, 128), 16)
+    C = np.linspace(1.0, 20.0, steps.size)
+    pb = W.Problem(model=mdl, n_params=len(th), n_steps=64, n_paths=300, t_max=1.0, instr_step=steps,
+                   instr_strike=strikes, seed=5)
+    say(f"maximum sizes {model}: m = {pb.n_instr}")
+    r = run_all(pb, th, C, "fp64", ckpt_every=8)
+    Eo, Go, go = orc.gradient(pb, th, C)
+    assert ey_err(r["Ey"], Eo) <= 1e-12 and g_err(r["g"], go) <= 1e-10
+    N = 65536
+    pb = W.Problem(model=mdl, n_params=len(th), n_steps=N, n_paths=64, t_max=2.0,
+                   instr_step=np.array([N // 3, N // 2, N], dtype=np.int32), instr_strike=np.array([90.0, 100.0, 110.0]),
+                   seed=6)
+    C = np.array([12.0, 9.0, 6.0])
+    say(f"maximum sizes {model}: N = {N}")
+    r = run_all(pb, th, C, "fp64", ckpt_every=8)
+    Eo, Go, go = orc.gradient(pb, th, C)
+    ey, eg = ey_err(r["Ey"], Eo), g_err(r["g"], go)
+    say(f"  N = {N}: Ey {ey:.2e} grad {eg:.2e}")
+    assert ey <= 1e-10 and eg <= 1e-9
+
+
 def test_single_instrument_first_step(orc):
     pb = W.Problem(model=W.MODEL_HESTON, n_params=5, n_steps=8, n_paths=300, t_max=0.1,
                    instr_step=np.array([1], dtype=np.int32), instr_strike=np.array([100.0]), seed=3)
