@@ -489,6 +489,28 @@ def test_maximum_sizes_fp64(orc, model):
     assert ey <= 1e-10 and eg <= 1e-9
 
 
+@pytest.mark.parametrize("name,th", [
+    ("xi = 0 (deterministic variance)", [2.0, 0.05, 0.0, -0.5, 0.04]),
+    ("v0 = theta_bar = 0 (variance stays at zero)", [1.5, 0.0, 0.3, -0.5, 0.0]),
+    ("kappa = 0 (no mean reversion)", [0.0, 0.05, 0.4, -0.3, 0.04]),
+    ("rho = -0.999", [2.0, 0.05, 0.4, -0.999, 0.04]),
+])
+def test_degenerate_heston_parameters_fp64(orc, name, th):
+    """The edges of the Heston domain: where the variance's square root is
+    zero the reverse sweep drops its branch (the kernels select it away, the
+    oracle takes the derivative of the plain square root as 0 there)."""
+    pb, _, _, _ = W.heston_problem(n_paths=1000, n_steps=64, t_max=0.5)
+    th = np.array(th)
+    C = np.linspace(2.0, 12.0, pb.n_instr)
+    say(f"heston fp64 degenerate: {name}")
+    r = run_all(pb, th, C, "fp64", ckpt_every=8)
+    Eo, Go, go = orc.gradient(pb, th, C)
+    ey, eg = ey_err(r["Ey"], Eo), g_err(r["g"], go)
+    say(f"  Ey {ey:.2e} grad {eg:.2e}")
+    assert np.all(np.isfinite(r["g"]))
+    assert ey <= 1e-12 and eg <= 1e-10
+
+
 def test_single_instrument_first_step(orc):
     pb = W.Problem(model=W.MODEL_HESTON, n_params=5, n_steps=8, n_paths=300, t_max=0.1,
                    instr_step=np.array([1], dtype=np.int32), instr_strike=np.array([100.0]), seed=3)
