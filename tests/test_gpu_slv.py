@@ -172,3 +172,24 @@ def test_slv_paths_per_lane(orc):
             say(f"  ppl={ppl} K={k} {prec}: Ey {ey_err(Ey, Eo):.2e} grad {g_err(g, go):.2e}")
             assert ey_err(Ey, Eo) <= tol_y
             assert g_err(g, go) <= tol_g
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_unit_leverage_is_heston(slv_small, precision):
+    """Two independent kernels on the same streams: with every leverage node
+    at 1 the SLV sweep is the Heston sweep operation for operation (L s z1'
+    = s z1', (h/2) L^2 v+ = (h/2) v+, no spot slope), so the prices are
+    bitwise Heston's, and the Heston part of the gradient differs only by the
+    association of the reverse step's terms (1e-12 FP64, 1e-6 FP32
+    relative per component; both at K = 8, so the FP32 segment sums cover the
+    same steps)."""
+    pb, th0, _, C, _ = slv_small
+    th = np.concatenate([th0[:5], np.ones(pb.n_params - 5)])
+    hp = pb.with_(model=W.MODEL_HESTON, n_params=5, t_nodes=None, k_nodes=None)
+    say(f"slv with unit leverage vs heston, {precision}")
+    _, Ey_s, G_s, g_s = run(pb, th, C, precision, ckpt_every=8)
+    _, Ey_h, G_h, g_h = run(hp, th[:5], C, precision, ckpt_every=8)
+    np.testing.assert_array_equal(Ey_s, Ey_h)
+    eg = g_err(g_s[:5], g_h)
+    say(f"  Heston part of the gradient: {eg:.2e}")
+    assert eg <= (1e-12 if precision == "fp64" else 1e-6)
