@@ -314,3 +314,22 @@ def test_lv_iid_nodes_gated(orc, precision):
     else:
         assert ey_err(Ey, Eo) <= 1e-5 and ey_err(Ey_f, Eo) <= 1e-5
         assert np.median(rel) <= 1e-2          # stated above; guards against regressions only
+
+
+def test_constant_grid_is_black_scholes(lv_small):
+    """Two independent kernels on the same streams: a local-volatility grid
+    constant at sigma0 is Black-Scholes at sigma0, and its bilinear weights
+    (flat outside the nodes) sum to one, so the node gradient adds up to
+    dG/dsigma.  The two sweeps take the log-price step in different but
+    equivalent forms, so they agree to FP64 rounding (1e-12 on the prices,
+    1e-10 on the summed gradient)."""
+    pb, _, _, C, _ = lv_small
+    sig = 0.2
+    bp = pb.with_(model=W.MODEL_BS, n_params=1, t_nodes=None, k_nodes=None)
+    say("lv constant grid vs black-scholes, fp64")
+    _, Ey_l, _, g_l = run(pb, np.full(pb.n_params, sig), C, "fp64")
+    _, Ey_b, _, g_b = run(bp, np.array([sig]), C, "fp64")
+    ey = ey_err(Ey_l, Ey_b)
+    eg = abs(g_l.sum() - g_b[0]) / abs(g_b[0])
+    say(f"  prices {ey:.2e}, summed gradient {eg:.2e}")
+    assert ey <= 1e-12 and eg <= 1e-10
