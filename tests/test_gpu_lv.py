@@ -234,6 +234,22 @@ def test_lv_widest_spot_grids(orc):
         MonteCarloCalibration(pb, precision="fp64")
 
 
+def test_lv_longest_time_grid(orc):
+    """64 time nodes (the limit) over 256 steps: a time cell every 4 steps,
+    so every checkpoint segment spans several cells (the reverse sweep's
+    general branch, a slice flush inside the segment), FP64 against the
+    oracle in both checkpoint modes."""
+    pb, g0, gt, eps, _ = W.lv_problem(n_paths=1000, n_steps=256, n_t=64, n_k=6)
+    C = np.linspace(2.0, 9.0, pb.n_instr)
+    Eo, Go, go = orc.gradient(pb, g0, C)
+    for k in (8, 32):
+        for mode in ("store", "rerun"):
+            say(f"  lv nT=64 nK=6 fp64 K={k} {mode}")
+            Ey_f, Ey, G, g = run(pb, g0, C, "fp64", ckpt_every=k, ckpt_mode=mode)
+            assert ey_err(Ey_f, Eo) <= 1e-12 and ey_err(Ey, Eo) <= 1e-12
+            assert g_err(g, go) <= 1e-9
+
+
 def test_memory_budget_picks_spacing():
     pb = W.lv_problem()[0]     # 2^22 paths x 256 steps, one state variable
     assert AG.checkpoint_bytes(pb, "fp32", 16) == 16 * (1 << 22) * 4

@@ -193,3 +193,18 @@ def test_unit_leverage_is_heston(slv_small, precision):
     eg = g_err(g_s[:5], g_h)
     say(f"  Heston part of the gradient: {eg:.2e}")
     assert eg <= (1e-12 if precision == "fp64" else 1e-6)
+
+
+def test_slv_longest_time_grid(orc):
+    """64 leverage rows (the limit) over 256 steps: the row changes every 4
+    steps, inside every checkpoint segment; FP64 against the oracle in both
+    checkpoint modes."""
+    pb, th0, tht, eps, _ = W.slv_problem(n_paths=1000, n_steps=256, n_t=64, n_k=6)
+    C = np.linspace(2.0, 9.0, pb.n_instr)
+    Eo, Go, go = orc.gradient(pb, th0, C)
+    for k in (8, 32):
+        for mode in ("store", "rerun"):
+            say(f"  slv nT=64 nK=6 fp64 K={k} {mode}")
+            Ey_f, Ey, G, g = run(pb, th0, C, "fp64", ckpt_every=k, ckpt_mode=mode)
+            assert ey_err(Ey_f, Eo) <= 1e-12 and ey_err(Ey, Eo) <= 1e-12
+            assert g_err(g, go) <= 1e-9
