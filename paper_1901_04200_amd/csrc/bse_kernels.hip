@@ -139,7 +139,9 @@ __global__ __launch_bounds__(kBlock) void k_bse_pass2(DevProblem pb, const doubl
             // inactive lanes (past the last path) run a harmless path from S0
             // and add nothing; they read no checkpoint, since in the re-run mode
             // another workgroup may still be writing the one they would share
-            R S = active ? ckpt[(int64_t)seg * pb.P + p] : (R)pb.s0;
+            // (the index is clamped as well, so the address stays inside the
+            // buffer whatever form the compiler gives the selection)
+            R S = active ? ckpt[(int64_t)seg * pb.P + (active ? p : 0)] : (R)pb.s0;
             int dlo = dhi;
             while (dlo > 0 && ldc(pb.date_step, dlo - 1) > n0) --dlo;
             int d = dlo;
