@@ -85,7 +85,7 @@ typedef struct cal_ctx cal_ctx;
  * Problem description (all pointers are host pointers, read during
  * cal_validate / cal_create only).
  *   model, precision  : see above
- *   n_params (M)      : 1 (BS), 5 (Heston), nT*nK (LV), 5 + nT*nK (SLV)
+ *   n_params (M)      : 1 (BS, BS_EULER_S), 5 (Heston), nT*nK (LV), 5 + nT*nK (SLV)
  *   n_instr  (m)      : number of calls, 1..2048
  *   n_steps  (N)      : Euler steps over [0, t_max], 1..65536
  *   n_paths  (P)      : 1..2^32; path p uses Philox counter word 1 = p
