@@ -200,7 +200,7 @@ int calibrate_gradient(cal_ctx *ctx, const double *d_theta, const double *d_C, d
 
 /* Forward tangent mode over the same paths: d_Ey[m] and the Jacobian
  * d_J[m*M] (row-major, J[i*M + j] = dE y_i/dtheta_j).  Heston and BS (the
- * grid models return CAL_EUNSUPPORTED).  By
+ * grid models and CAL_BS_EULER_S return CAL_EUNSUPPORTED).  By
  * the paper's eq. 0711A the same numbers follow from m reverse sweeps; with
  * M < m the tangent sweep is the cheaper route to the whole matrix. */
 int calibrate_jacobian(cal_ctx *ctx, const double *d_theta, double *d_Ey, double *d_J, void *stream);
