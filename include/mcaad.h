@@ -274,7 +274,7 @@ int cal_normals(int32_t precision, uint64_t seed, uint32_t inst, uint32_t path0,
  * Persistent workgroups take (instance, 256-path block) items from a queue
  * ordered longest instance first, so uneven instances share the GPU; each
  * instance's results are bitwise those of its own cal_create context.
- * All instances share model (BS or Heston) and precision; checkpoints are
+ * All instances share model (BS with log-Euler, or Heston) and precision; checkpoints are
  * stored by pass 1.
  *
  * Device arrays of a batch: d_theta [n_inst * M]; d_C and d_Ey concatenated
