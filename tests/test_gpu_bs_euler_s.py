@@ -142,3 +142,20 @@ def test_unsupported_entry_points_refuse():
     with pytest.raises(capi.CalError) as e:
         capi.calibrate_gradient_static(pb, t(th), t(C), Ey, G, g, status, precision=capi.CAL_FP64)
     assert e.value.code == capi.CAL_EUNSUPPORTED
+
+
+def test_autograd_backward_is_the_adjoint():
+    """theta.grad of G = 1/2 |Ey - C|^2 through the torch.autograd wrapper
+    equals calibrate_gradient's gradient on the same context (FP32)."""
+    from paper_1901_04200_amd import autograd as AG
+    pb, th0, C = W.bs_problem(n_paths=(1 << 16) + 5, n_steps=64, euler_on_s=True)
+    mc = AG.make(pb, "fp32")
+    th = torch.tensor(th0, dtype=torch.float64, device="cuda", requires_grad=True)
+    Ct = torch.as_tensor(C, device="cuda")
+    G = 0.5 * torch.sum((AG.mc_prices(th, mc) - Ct) ** 2)
+    G.backward()
+    _, G2, g2 = mc.gradient(th0, Ct)
+    assert mc.status() == 0
+    mc.close()
+    assert abs(G.item() - G2.item()) <= 1e-12 * G2.item()
+    assert abs(th.grad.item() - g2.item()) <= 1e-12 * abs(g2.item())
