@@ -69,7 +69,7 @@ def _mc_errors(pb, P, ho, g_ref, C, seeds):
     return np.array(errs)
 
 
-def run(n_train=1 << 14, train_paths=1 << 14, n_heldout=32, ref_paths=1 << 26, epochs=200, batch=4096,
+def run(n_train=1 << 14, train_paths=1 << 14, n_heldout=64, ref_paths=1 << 26, epochs=200, batch=4096,
         lr=2e-3, lr_final=5e-5, w=1.0, seeds_mc=4, n_gain=16, g_frac=1e-3, max_iter=200, uniform_variant=True,
         log=print):
     import torch
